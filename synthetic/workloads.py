@@ -1,0 +1,296 @@
+"""Seeded synthetic inputs with the shapes of the paper's workloads.
+
+The paper (Section 4.1) studies a layered 2-D elastic half-space with a point
+moment-tensor source, surface receivers and a uniform prior on the seven
+source parameters.  No dataset is involved; every input here is drawn from
+numpy's PCG64 generator with a fixed seed.
+
+Coordinates: x runs from the left edge (node i at x = i*h) and z is depth
+(node k at z = k*h, k = 0 is the free surface).  Parameter order follows the
+paper's theta = (x_s, z_s, t_s, omega_s, m_xx, m_xz, m_zz) (Section 2.1); for
+the Gaussian-derivative wavelet the frequency slot holds f in Hz.
+
+Media are described by nodal density and Lame parameters (lambda, mu), the
+quantities in the paper's stress law (Section 2.1); velocities are only the
+way the workloads are specified.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+PARAM_NAMES = ("x", "z", "t0", "f", "Mxx", "Mxz", "Mzz")
+CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")
+
+
+@dataclasses.dataclass
+class Grid:
+    nx: int
+    nz: int
+    h: float
+    dt: float
+    nsteps: int
+
+    @property
+    def lx(self) -> float:
+        return (self.nx - 1) * self.h
+
+    @property
+    def lz(self) -> float:
+        return (self.nz - 1) * self.h
+
+    @property
+    def nt(self) -> int:
+        """Recorded time levels t_m = m*dt, m = 0..nsteps."""
+        return self.nsteps + 1
+
+
+@dataclasses.dataclass
+class Medium:
+    """Nodal density and Lame parameters.
+
+    kind == "layered": arrays of shape [nz] (properties vary with depth only).
+    kind == "nodal":   arrays of shape [nz, nx].
+    """
+    kind: str
+    rho: np.ndarray
+    lam: np.ndarray
+    mu: np.ndarray
+
+    def nodal(self, nx: int):
+        if self.kind == "nodal":
+            return self.rho, self.lam, self.mu
+        rep = lambda a: np.repeat(a[:, None], nx, axis=1)  # noqa: E731
+        return rep(self.rho), rep(self.lam), rep(self.mu)
+
+    def vp_max(self) -> float:
+        return float(np.max(np.sqrt((self.lam + 2 * self.mu) / self.rho)))
+
+
+@dataclasses.dataclass
+class Workload:
+    """One design query: a grid, a medium, receivers, a prior box, samples."""
+    name: str
+    grid: Grid
+    medium: Medium
+    receivers: np.ndarray          # int32 surface node indices (x index)
+    lo: np.ndarray                 # prior box, paper parameter order
+    hi: np.ndarray
+    theta: Optional[np.ndarray]    # [S, 7] prior draws (None: quadrature)
+    weights: Optional[np.ndarray]  # [S] Monte Carlo weights 1/S
+    stf: str = "gauss_deriv"
+    rel_step: float = 1e-4
+    noise_rel: float = 1e-3
+    smolyak_level: Optional[int] = None
+    greedy_kmax: Optional[int] = None
+
+    @property
+    def theta_bar(self) -> np.ndarray:
+        return 0.5 * (self.lo + self.hi)
+
+
+def cfl_dt(h: float, vp_max: float, cfl: float = 0.5) -> float:
+    return cfl * h / vp_max
+
+
+def _lame(rho, vp, vs):
+    rho = np.asarray(rho, dtype=np.float64)
+    vp = np.asarray(vp, dtype=np.float64)
+    vs = np.asarray(vs, dtype=np.float64)
+    mu = rho * vs * vs
+    lam = rho * vp * vp - 2.0 * mu
+    return lam, mu
+
+
+def homogeneous_medium(nz: int, rho: float, vp: float, vs: float) -> Medium:
+    lam, mu = _lame(rho, vp, vs)
+    one = np.ones(nz)
+    return Medium("layered", rho * one, lam * one, mu * one)
+
+
+def layered_medium(nz: int, h: float, interfaces, rho, vp, vs) -> Medium:
+    """Layer j holds nodes whose depth z = k*h satisfies
+    interfaces[j-1] <= z < interfaces[j]; interfaces sit on nodes."""
+    z = np.arange(nz) * h
+    layer = np.searchsorted(np.asarray(interfaces, dtype=np.float64), z,
+                            side="right")
+    rho_n = np.asarray(rho, dtype=np.float64)[layer]
+    lam_l, mu_l = _lame(rho, vp, vs)
+    return Medium("layered", rho_n, np.asarray(lam_l)[layer],
+                  np.asarray(mu_l)[layer])
+
+
+def random_layers_medium(rng: np.random.Generator, nz: int, h: float,
+                         nlayers: int, vp_lo=1500.0, vp_hi=4500.0,
+                         rho=2500.0) -> Medium:
+    lz = (nz - 1) * h
+    interfaces = np.sort(rng.uniform(0.0, lz, nlayers - 1))
+    vp = rng.uniform(vp_lo, vp_hi, nlayers)
+    vs = vp / math.sqrt(3.0)
+    return layered_medium(nz, h, interfaces, np.full(nlayers, rho), vp, vs)
+
+
+def _gaussian_random_field(rng, nz, nx, h, corr_len):
+    """Stationary field with squared-exponential covariance exp(-r^2/(2 l^2)),
+    made by filtering white noise with a Gaussian kernel in Fourier space."""
+    noise = rng.standard_normal((nz, nx))
+    kz = np.fft.fftfreq(nz, d=h) * 2 * np.pi
+    kx = np.fft.fftfreq(nx, d=h) * 2 * np.pi
+    k2 = kz[:, None] ** 2 + kx[None, :] ** 2
+    # kernel std s = l/sqrt(2) gives covariance exp(-r^2 / (2 l^2)).
+    s = corr_len / math.sqrt(2.0)
+    filt = np.exp(-0.5 * k2 * s * s)
+    g = np.real(np.fft.ifft2(np.fft.fft2(noise) * filt))
+    return g / np.max(np.abs(g))
+
+
+def nodal_perturbed_medium(rng: np.random.Generator, nz: int, nx: int,
+                           h: float, nlayers: int = 6, amp: float = 0.05,
+                           corr_len: float = 200.0, rho: float = 2500.0,
+                           ) -> Medium:
+    """Random layers whose velocities are scaled by (1 + amp*g(x, z)),
+    g a Gaussian random field normalised to max|g| = 1."""
+    lz = (nz - 1) * h
+    interfaces = np.sort(rng.uniform(0.0, lz, nlayers - 1))
+    vp_l = rng.uniform(1500.0, 4500.0, nlayers)
+    z = np.arange(nz) * h
+    layer = np.searchsorted(interfaces, z, side="right")
+    vp = vp_l[layer][:, None] * np.ones((1, nx))
+    g = _gaussian_random_field(rng, nz, nx, h, corr_len)
+    vp = vp * (1.0 + amp * g)
+    vs = vp / math.sqrt(3.0)
+    rho_n = np.full((nz, nx), rho)
+    lam, mu = _lame(rho_n, vp, vs)
+    return Medium("nodal", rho_n, lam, mu)
+
+
+def prior_box(grid: Grid, t0=(0.1, 0.3), f=(5.0, 10.0), m=(1e13, 1e14)):
+    """Uniform prior: source in the lower half of the box and at least 4
+    cells away from the rigid sides and bottom."""
+    h = grid.h
+    lo = np.array([4 * h, 0.5 * grid.lz, t0[0], f[0], m[0], m[0], m[0]])
+    hi = np.array([grid.lx - 4 * h, grid.lz - 4 * h, t0[1], f[1],
+                   m[1], m[1], m[1]])
+    return lo, hi
+
+
+def draw_uniform(rng: np.random.Generator, lo, hi, n: int) -> np.ndarray:
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    return lo + (hi - lo) * rng.random((n, lo.size))
+
+
+def equispaced_receivers(nx: int, nr: int) -> np.ndarray:
+    r = np.arange(nr)
+    return np.floor((r + 1) * (nx - 1) / (nr + 1) + 0.5).astype(np.int32)
+
+
+def candidate_receivers(nx: int, nc: int = 201) -> np.ndarray:
+    c = np.arange(nc)
+    return (4 + np.floor(c * (nx - 9) / (nc - 1) + 0.5)).astype(np.int32)
+
+
+def random_receivers(rng: np.random.Generator, nx: int, nr: int) -> np.ndarray:
+    """nr distinct non-corner surface nodes, sorted."""
+    pick = rng.choice(np.arange(1, nx - 1), size=nr, replace=False)
+    return np.sort(pick).astype(np.int32)
+
+
+def _mc(theta):
+    return np.full(theta.shape[0], 1.0 / theta.shape[0])
+
+
+def config(name: str, nsample: Optional[int] = None, seed: Optional[int] = None,
+           grid_override: Optional[tuple] = None) -> List[Workload]:
+    """The five workloads, as lists of design queries.
+
+    c1: 64^2, h=20, 400 steps, homogeneous, 5 receivers, 8 samples.
+    c2: 512^2, h=10, 2000 steps, two layers, 21 receivers, 256 samples.
+    c3: 4096 single-sample queries on grids {256,384,512}^2 with
+        {1000,1500,2000} steps and random 4-layer media.
+    c4: a stream of design queries (grid 256..1024, 500..4000 steps,
+        5..101 random receivers, 64..512 samples); see serving_queries().
+    c5: 2048x1024, 4000 steps, nodal 6-layer medium with a 5 % Gaussian
+        random-field perturbation, 201 candidate receivers, sparse grid
+        level 3, greedy to 40 receivers.
+    grid_override = (nx, nz, nsteps) shrinks a config for tests.
+    """
+    idx = CONFIG_NAMES.index(name)
+    rng = np.random.Generator(np.random.PCG64(idx if seed is None else seed))
+    if name == "c1":
+        nx, nz, nsteps, h = 64, 64, 400, 20.0
+        if grid_override:
+            nx, nz, nsteps = grid_override
+        med = homogeneous_medium(nz, 2500.0, 3000.0, 1730.0)
+        grid = Grid(nx, nz, h, cfl_dt(h, med.vp_max()), nsteps)
+        lo, hi = prior_box(grid)
+        theta = draw_uniform(rng, lo, hi, nsample or 8)
+        return [Workload("c1", grid, med, equispaced_receivers(nx, 5), lo, hi,
+                         theta, _mc(theta))]
+    if name == "c2":
+        nx, nz, nsteps, h = 512, 512, 2000, 10.0
+        if grid_override:
+            nx, nz, nsteps = grid_override
+        lz = (nz - 1) * h
+        zint = rng.uniform(0.15, 0.45) * lz
+        med = layered_medium(nz, h, [zint], [2500.0, 2500.0], [2000.0, 3500.0],
+                             [1150.0, 2000.0])
+        grid = Grid(nx, nz, h, cfl_dt(h, med.vp_max()), nsteps)
+        lo, hi = prior_box(grid)
+        theta = draw_uniform(rng, lo, hi, nsample or 256)
+        return [Workload("c2", grid, med, equispaced_receivers(nx, 21), lo, hi,
+                         theta, _mc(theta))]
+    if name == "c3":
+        out = []
+        for _ in range(nsample or 4096):
+            n = int(rng.choice([256, 384, 512]))
+            nsteps = int(rng.choice([1000, 1500, 2000]))
+            nx = nz = n
+            if grid_override:
+                nx, nz, nsteps = grid_override
+            h = 10.0
+            med = random_layers_medium(rng, nz, h, 4)
+            grid = Grid(nx, nz, h, cfl_dt(h, med.vp_max()), nsteps)
+            lo, hi = prior_box(grid)
+            theta = draw_uniform(rng, lo, hi, 1)
+            out.append(Workload("c3", grid, med, equispaced_receivers(nx, 21),
+                                lo, hi, theta, _mc(theta)))
+        return out
+    if name == "c4":
+        return serving_queries(rng, nsample or 128, grid_override)
+    if name == "c5":
+        nx, nz, nsteps, h = 2048, 1024, 4000, 10.0
+        if grid_override:
+            nx, nz, nsteps = grid_override
+        med = nodal_perturbed_medium(rng, nz, nx, h)
+        grid = Grid(nx, nz, h, cfl_dt(h, med.vp_max()), nsteps)
+        lo, hi = prior_box(grid)
+        return [Workload("c5", grid, med, candidate_receivers(nx, 201), lo, hi,
+                         None, None, smolyak_level=3, greedy_kmax=40)]
+    raise ValueError(name)
+
+
+def serving_queries(rng: np.random.Generator, nquery: int,
+                    grid_override: Optional[tuple] = None) -> List[Workload]:
+    out = []
+    for _ in range(nquery):
+        n = int(rng.integers(256 // 64, 1024 // 64 + 1)) * 64
+        nsteps = int(rng.integers(500, 4001))
+        nr = int(rng.integers(5, 102))
+        ns = int(rng.integers(64, 513))
+        nx = nz = n
+        if grid_override:
+            nx, nz, nsteps = grid_override
+            ns = max(1, ns // 64)
+            nr = min(nr, nx - 2)
+        h = 10.0
+        med = random_layers_medium(rng, nz, h, 4)
+        grid = Grid(nx, nz, h, cfl_dt(h, med.vp_max()), nsteps)
+        lo, hi = prior_box(grid)
+        theta = draw_uniform(rng, lo, hi, ns)
+        out.append(Workload("c4", grid, med, random_receivers(rng, nx, nr),
+                            lo, hi, theta, _mc(theta)))
+    return out
