@@ -1,0 +1,150 @@
+#!/usr/bin/env python
+"""Throughput of the Laplace-EIG hot path on one MI355X.
+
+One step = one whole design query of the paper-shaped Monte Carlo workload:
+512 x 512 grid (h = 10 m), 2000 leapfrog steps, two-layer medium, 21 surface
+receivers, 256 prior samples -> noise level from the nominal solve at the
+prior mean, 256 x (1 + 2*7) forward solves, central-difference Jacobians,
+H_1, scaled Cholesky log-dets, D^_KL and the Monte Carlo EIG.  Inputs are
+resident on the device before the timed region.
+
+value = sample-EIG evaluations per second (D^_KL(theta_s) values, each from
+15 solves + H_1 + log-det).  The stencil launches are timed live with HIP
+events by the library (eig_ctx_stencil_stats) for the roofline figure.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("EIG evals/s and grid-pt updates/s (HBM GB/s % peak) at ≤1e-3 nat err; "
+          "p50/p99")
+HBM_PEAK_GBS = 8000.0
+
+
+def _cpu_baseline(wl, theta_s, dkl_gpu_s):
+    """The oracle, untuned, on one prior sample (15 solves + its own sigma
+    solve) spread over the host cores."""
+    from oracle import pipeline as opipe
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    ref = opipe.query(wl, theta=theta_s[None, :], weights=[1.0], threads=threads)
+    t = time.perf_counter() - t0
+    err = abs(float(ref["dkl"][0]) - float(dkl_gpu_s))
+    cores = min(threads, 15)
+    return ({"value": 1.0 / t, "unit": "sample-EIG evals/s", "cores": cores,
+             "kind": "oracle",
+             "sample": "1 prior sample of the timed workload (1 sigma solve + 15 solves "
+                       f"at 512x512x2000, FP64), {t:.1f} s wall"}, err)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(samples would shard across GPUs with one all-reduce of the "
+              "per-design sums; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_1502_07873_amd import Context
+    from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
+
+    wl = synthetic.config("c2", nsample=args.samples)[0]
+    g = grid_tuple(wl.grid)
+    dev = torch.device("cuda", 0)
+    med = device_medium(wl.medium.kind, wl.medium.rho, wl.medium.lam, wl.medium.mu)
+    ctx = Context(0, 200 << 30)
+    stream = torch.cuda.current_stream(dev)
+
+    def one_step():
+        return run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, wl.theta, wl.weights)
+
+    print(f"[bench] workload c2 S={len(wl.theta)} grid={g} warmup={args.warmup} "
+          f"steps={args.steps}", flush=True)
+    for w in range(args.warmup):
+        one_step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w} done", flush=True)
+    ctx.stencil_stats(reset=True)
+    torch.cuda.synchronize()
+    lat = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record(stream)
+    t0 = time.perf_counter()
+    out = None
+    for k in range(args.steps):
+        out = one_step()
+        ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        lat.append(ev[k].elapsed_time(ev[k + 1]))
+        print(f"[bench] step {k} {lat[-1]:.1f} ms", flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = ev[0].elapsed_time(ev[-1])
+    st = ctx.stencil_stats()
+    S = len(wl.theta)
+    value = S * args.steps / (total_ms / 1e3)
+    avg_launch_ms = st["ms"] / max(st["launches"], 1)
+    bytes_per_launch = st["bytes"] / max(st["launches"], 1)
+    achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
+    dkl = out["dkl"].cpu().numpy()
+    eig = float(out["eig"].cpu()[0])
+    status_ok = int(out["status"].abs().sum()) == 0 and int(out["chol_status"].abs().sum()) == 0
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "sample-EIG evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 wavefields / f64 Jacobian-Hessian-logdet",
+        "data": "synthetic",
+        "config": {"workload": "c2 Monte Carlo query: 512x512 grid, h=10 m, 2000 steps, "
+                               "two-layer medium, 21 receivers, "
+                               f"{S} prior samples x 15 solves (+1 sigma solve)",
+                   "samples": S, "solves_per_step": 15 * S + 1,
+                   "grid": [wl.grid.nx, wl.grid.nz], "nsteps": wl.grid.nsteps},
+        "eig_nats": eig,
+        "status_ok": status_ok,
+        "grid_pt_updates_per_s": st["updates"] / (total_ms / 1e3),
+        "stencil": {"launches": st["launches"], "avg_launch_ms": avg_launch_ms,
+                    "bytes_per_launch": bytes_per_launch,
+                    "time_frac_of_step": st["ms"] / total_ms},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                       "p99": float(np.percentile(lat, 99))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, 1 sample)", flush=True)
+        cb, err = _cpu_baseline(wl, wl.theta[0], dkl[0])
+        line["cpu_baseline"] = cb
+        line["sampled_err_nats"] = err
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,257 @@
+/*
+ * eigseis — Laplace expected-information-gain design for 2-D seismic source
+ * inversion on AMD MI355X (gfx950).  C ABI.
+ *
+ * Method: Long, Motamed & Tempone, "Fast Bayesian optimal experimental
+ * design for seismic source inversion".  For every prior sample theta of the
+ * seven source parameters the library runs one nominal and 2*7 perturbed
+ * forward solves of the 2-D elastic wave equation (Section 3.3.1), forms the
+ * central-difference receiver Jacobian, the Gauss-Newton Hessian H_1
+ * (Theorem 2), its scaled Cholesky log-determinant (Section 3.3.3), the
+ * Laplace KL estimate D^_KL (Theorem 4), and the Monte Carlo or sparse-
+ * quadrature average over samples (Section 3.3.4) for each receiver design.
+ *
+ * Conventions (all entry points):
+ *  - Return 0 on success, a negative EIG_E* code otherwise; eig_last_error()
+ *    then holds a message (thread-local).  No C++ exception crosses the ABI.
+ *  - Argument errors are found synchronously, before any work is enqueued.
+ *    Work is enqueued on `stream` (a hipStream_t; NULL = default stream);
+ *    device outputs are valid after the stream has been synchronised.
+ *  - Numerical failures found on the device (a non-positive-definite
+ *    Hessian, a non-finite wavefield) are reported per sample in `status`
+ *    (EIG_ENOTPD / EIG_ENONFINITE) and poison dependent results with NaN.
+ *  - "host" pointers are read before the call returns; "device" pointers are
+ *    caller-owned device memory, never freed or kept by the library after
+ *    the enqueued work completes.
+ *  - Units SI.  Coordinates: node (i, k) sits at x = i*h (from the left edge)
+ *    and depth z = k*h; k = 0 is the traction-free surface; the nodes of the
+ *    left (i = 0), right (i = nx-1) and bottom (k = nz-1) edges are rigid.
+ *  - theta, in the paper's order (Section 2.1):
+ *      [0] x_s  [1] z_s (depth)  [2] t_s  [3] frequency  [4] m_xx  [5] m_xz
+ *      [6] m_zz
+ *    For EIG_STF_GAUSS the frequency slot is omega (rad/s); for
+ *    EIG_STF_GAUSS_DERIV it is f (Hz) with omega = 2 pi f.
+ *  - Receiver traces: float [nsteps+1][nrec][2], level m at t_m = m*dt,
+ *    component 0 = x, 1 = depth.  Level 0 is the zero initial state.
+ *  - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef EIGSEIS_H
+#define EIGSEIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EIG_NTHETA 7
+
+/* error codes */
+#define EIG_OK 0
+#define EIG_EINVAL (-1)       /* invalid argument */
+#define EIG_ENOMEM (-2)       /* device allocation failed */
+#define EIG_EBUDGET (-3)      /* request does not fit the HBM budget */
+#define EIG_ENOTPD (-4)       /* Hessian not positive definite (status) */
+#define EIG_ENONFINITE (-5)   /* non-finite wavefield (status) */
+#define EIG_EHIP (-6)         /* HIP runtime error */
+#define EIG_EUNSUPPORTED (-7) /* valid but not supported */
+
+/* source time functions (Section 4.1 and its time derivative) */
+#define EIG_STF_GAUSS 0       /* omega/sqrt(2 pi) exp(-omega^2 (t-t_s)^2 / 2) */
+#define EIG_STF_GAUSS_DERIV 1 /* d/dt of the above with omega = 2 pi f      */
+
+/* media */
+#define EIG_MEDIUM_LAYERED 0  /* rho, lam, mu arrays of [nz] (depth only) */
+#define EIG_MEDIUM_NODAL 1    /* rho, lam, mu arrays of [nz][nx]          */
+
+/* priors */
+#define EIG_PRIOR_UNIFORM 0
+#define EIG_PRIOR_GAUSSIAN 1
+
+/* noise level for jacobian_fd */
+#define EIG_SIGMA_GIVEN 0        /* sigma[s] is the noise standard deviation */
+#define EIG_SIGMA_NOMINAL_PEAK 1 /* sigma_s = sigma[s] * max |nominal trace| */
+
+typedef struct eig_ctx eig_ctx;
+
+/* Uniform grid of Section 3.3.1 (spacing h in both directions) with the
+ * leapfrog time step dt and nsteps steps.  nx, nz >= 8. */
+typedef struct {
+    int32_t nx, nz;
+    double h, dt;
+    int32_t nsteps;
+} eig_grid;
+
+/* Density nu and Lame parameters (lambda, mu) of the paper's stress law
+ * (Section 2.1); device pointers to FP64 arrays, laid out per `kind`. */
+typedef struct {
+    int32_t kind;
+    const double* rho;
+    const double* lam;
+    const double* mu;
+} eig_medium;
+
+/* Receivers on surface nodes (Section 2.1: stations coincide with grid
+ * points): n distinct x-indices in 1..nx-2, host array. */
+typedef struct {
+    int32_t n;
+    const int32_t* ix;
+} eig_receivers;
+
+/* Prior density p(theta); h(theta) = log p(theta) enters D^_KL. */
+typedef struct {
+    int32_t kind;
+    double lo[EIG_NTHETA], hi[EIG_NTHETA];  /* uniform box, lo < hi */
+    double mean[EIG_NTHETA];                /* gaussian mean */
+    double cov[EIG_NTHETA * EIG_NTHETA];    /* gaussian covariance, SPD */
+} eig_prior;
+
+/* Create a context on HIP device `device`.  The context owns all internal
+ * device workspace (wavefields, internal traces, tables) and never holds more
+ * than hbm_budget_bytes of it.  Returns EIG_EINVAL for a bad device. */
+int eig_ctx_create(int device, size_t hbm_budget_bytes, eig_ctx** out);
+void eig_ctx_destroy(eig_ctx* ctx);
+/* Message for the last error on this thread ("" if none). */
+const char* eig_last_error(void);
+/* Device bytes currently held by the context's workspace. */
+size_t eig_ctx_workspace_bytes(const eig_ctx* ctx);
+/* Stencil timing since the last reset: device time from the first to the
+ * last stencil launch of every wave (HIP events on the call's stream), the
+ * number of stencil launches, the grid-point updates they performed
+ * (sum over solves of nx*nz per step) and their algorithmic HBM bytes (per
+ * update: read u^m and u^{m-1}, write u^{m+1}, 8 bytes each; plus 12 bytes
+ * of nodal coefficients for EIG_MEDIUM_NODAL).  Waits for the recorded
+ * events.  Any output pointer may be NULL; reset != 0 clears the counters
+ * after reading them. */
+int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* launches,
+                          double* updates, double* bytes);
+
+/*
+ * forward_solve_batch — the parameter-to-observable map g_r(t_m; theta)
+ * (Section 2.2, forward model; Section 3.3.1, full-discrete scheme) for
+ * nsolve independent solves of possibly different grids and media.
+ *
+ *   grid, medium, rec: host arrays [nsolve]
+ *   theta:     host [nsolve][7]
+ *   dev_param: host [nsolve] or NULL.  -1 (or NULL): nominal solve, forcing
+ *              F(theta).  j in 0..6: deviation solve driven by the FP64
+ *              forcing difference F(theta + dev_step[s] e_j) - F(theta); by
+ *              linearity of the discrete scheme its traces are
+ *              g(theta + dev_step e_j) - g(theta).
+ *   dev_step:  host [nsolve] (read only for deviation solves), nonzero.
+ *   traces:    host array [nsolve] of device pointers, each float
+ *              [grid.nsteps+1][rec.n][2]; fully overwritten.
+ * EIG_EINVAL if the 6x6 source stencil of theta (or of theta + step e_j)
+ * would touch a rigid node, a receiver is off the free surface or repeated,
+ * or a size is out of range.
+ */
+int forward_solve_batch(eig_ctx* ctx, int32_t nsolve, const eig_grid* grid,
+                        const eig_medium* medium, const double* theta,
+                        const int32_t* dev_param, const double* dev_step,
+                        int32_t stf_kind, const eig_receivers* rec,
+                        float* const* traces, void* stream);
+
+/*
+ * jacobian_fd — for each of nsample prior samples: 1 nominal + 2*7 perturbed
+ * solves, the central-difference receiver Jacobian
+ *   J_j = (g(theta + d_j e_j) - g(theta - d_j e_j)) / (2 d_j),
+ *   d_j = rel_step * |theta_j|,
+ * formed from deviation solves (see forward_solve_batch) in FP64, and the
+ * Gauss-Newton Hessian H_1 = sigma^-2 sum_{m,r,c} J^T J (Theorem 2, H_1, with
+ * C_eps = sigma^2 I; Section 3.3.2, H_I with the receiver-selection Hessian).
+ *
+ *   grid, medium, rec: host arrays [nsample] (each sample may differ; with
+ *              per_receiver != 0 all rec[s].n must be equal)
+ *   theta:     host [nsample][7]; every theta_j must be nonzero
+ *   sigma_mode/sigma: host [nsample]; EIG_SIGMA_GIVEN: sigma[s] > 0 is the
+ *              noise std; EIG_SIGMA_NOMINAL_PEAK: sigma_s = sigma[s] times the
+ *              largest |value| in sample s's nominal traces (device-side)
+ *   per_receiver: 0 -> H1 device [nsample][7][7];
+ *                 1 -> H1 device [nsample][nrec][7][7] (one H_1 per receiver;
+ *                      their sum over receivers is the full H_1)
+ *   nominal:   host array [nsample] of device pointers (float
+ *              [nsteps+1][nrec][2]) or NULL
+ *   J:         host array [nsample] of device pointers (double
+ *              [nsteps+1][nrec][2][7]) or NULL
+ *   status:    device [nsample] or NULL: 0, or EIG_ENONFINITE
+ */
+int jacobian_fd(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
+                const eig_medium* medium, const double* theta, double rel_step,
+                int32_t stf_kind, const eig_receivers* rec, int32_t sigma_mode,
+                const double* sigma, int32_t per_receiver, float* const* nominal,
+                double* const* J, double* H1, int32_t* status, void* stream);
+
+/*
+ * laplace_eig — Theorem 4 with the scaled Hessian of Section 3.3.3:
+ *   S = sqrt(diag H_1),  H~ = S^-1 H_1 S^-1 = L L^T,
+ *   log det H_1 = 2 sum log L_ii + 2 sum log S_ii,
+ *   D^_KL(theta_s) = -1/2 log((2 pi)^7 |H_1^-1|) - 7/2 - h(theta_s),
+ *   I = sum_s w_s D^_KL(theta_s)  (Monte Carlo or quadrature weights,
+ *       Section 3.3.4), all in FP64.
+ *
+ *   H1:     device [nsample][7][7] (symmetric)
+ *   prior:  host; theta: host [nsample][7] (needed for EIG_PRIOR_GAUSSIAN,
+ *           may be NULL for EIG_PRIOR_UNIFORM); w: host [nsample]
+ *   dkl:    device [nsample]; logdet: device [nsample] or NULL;
+ *   eig:    device [1]; status: device [nsample] or NULL (0 or EIG_ENOTPD).
+ *   A failed sample has dkl = NaN, which makes eig NaN.
+ */
+int laplace_eig(eig_ctx* ctx, int32_t nsample, const double* H1,
+                const eig_prior* prior, const double* theta, const double* w,
+                double* dkl, double* logdet, double* eig, int32_t* status,
+                void* stream);
+
+/*
+ * design_eval — expected information gain of each receiver design
+ * (Section 4.5: designs are receiver sets): for design d,
+ *   I(d) = sum_s w_s D^_KL( sum_{c : mask[d][c] != 0} H1r[s][c] ),
+ * where H1r holds one H_1 per candidate receiver (additive over receivers),
+ * as produced by jacobian_fd with per_receiver = 1.
+ *
+ *   H1r:  device [nsample][ncand][7][7];  mask: device uint8 [ndesign][ncand]
+ *   prior, theta, w: as for laplace_eig;  eig: device [ndesign]
+ */
+int design_eval(eig_ctx* ctx, int32_t nsample, int32_t ncand, const double* H1r,
+                int32_t ndesign, const uint8_t* mask, const eig_prior* prior,
+                const double* theta, const double* w, double* eig, void* stream);
+
+/*
+ * design_greedy — greedy receiver selection on the same objective: start
+ * from no receivers and kmax times add the candidate c maximising
+ * I(chosen + {c}); ties go to the lowest index; a candidate whose I is NaN is
+ * never chosen.  The search stays on the device.
+ *   order: device int32 [kmax] (chosen candidate per step, -1 once none is
+ *          left); curve: device [kmax] (I after each step, NaN after -1).
+ */
+int design_greedy(eig_ctx* ctx, int32_t nsample, int32_t ncand,
+                  const double* H1r, const eig_prior* prior, const double* theta,
+                  const double* w, int32_t kmax, int32_t* order, double* curve,
+                  void* stream);
+
+/*
+ * noise_sigma_peak — sigma = rel * max |u| over all free surface nodes
+ * (i = 1..nx-2), both components and all levels, of the nominal solve at
+ * theta (usually the prior mean).  Synchronous; writes *sigma_out (host).
+ */
+int noise_sigma_peak(eig_ctx* ctx, const eig_grid* grid, const eig_medium* medium,
+                     const double* theta, int32_t stf_kind, double rel,
+                     double* sigma_out, void* stream);
+
+/*
+ * sparse_grid_gl — sparse quadrature of Section 3.3.4 for a uniform prior on
+ * the box [lo, hi] (host arrays [dim]): Smolyak combination of 1-D
+ * Gauss-Legendre rules with m(i) = i points over the total-degree index set
+ * sum_n (i_n - 1) <= level, coincident nodes merged.  Weights sum to one and
+ * may be negative.  Host-only, synchronous.
+ *   nodes: host [capacity][dim]; weights: host [capacity]; *count receives
+ *   the number of nodes (EIG_EINVAL, with *count set, if capacity is short).
+ *   dim in 1..16, level in 0..40.
+ */
+int sparse_grid_gl(int32_t dim, int32_t level, const double* lo, const double* hi,
+                   int32_t capacity, double* nodes, double* weights, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EIGSEIS_H */

@@ -1,0 +1,159 @@
+// Receiver Jacobian and Gauss-Newton Hessian, FP64 on the device.
+//
+// From the 14 deviation solves of a sample (traces of g(theta +- d_j e_j) -
+// g(theta), FP32) the central differences J_j = (w+_j - w-_j) / (2 d_j) are
+// formed in FP64 and H_1 = sigma^-2 sum_{m,r,c} J^T J accumulated (paper
+// Theorem 2, H_1 with C_eps = sigma^2 I; Section 3.3.2, H_I, whose
+// receiver-selection Hessian is diagonal).  Every thread owns a fixed subset
+// of the (level, receiver) pairs and the 28 distinct products are reduced
+// with wavefront shuffles and LDS in a fixed order, so the result does not
+// depend on how solves were batched.
+#include "internal.h"
+
+namespace eig {
+
+namespace {
+
+constexpr int kTri = kNT * (kNT + 1) / 2;  // 28
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Per-sample status and noise level.  mode EIG_SIGMA_GIVEN: sigma = given;
+// EIG_SIGMA_NOMINAL_PEAK: sigma = given * max |nominal trace value|.
+__global__ void sample_check_kernel(const SampleDesc* __restrict__ samples,
+                                    const double* __restrict__ given, int mode,
+                                    double* __restrict__ sigma,
+                                    int32_t* __restrict__ status) {
+    const SampleDesc& sd = samples[blockIdx.x];
+    const int n = sd.nt * sd.nrec;
+    float mx = 0.f;
+    int bad = 0;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const float2 v = sd.nominal[e];
+        if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
+        mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    for (int j = 0; j < 2 * kNT && !bad; ++j)
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const float2 v = sd.dev[j][e];
+            if (!isfinite(v.x) || !isfinite(v.y)) { bad = 1; break; }
+        }
+    __shared__ float smx[256];
+    __shared__ int sbad[256];
+    smx[threadIdx.x] = mx;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + o]);
+            sbad[threadIdx.x] |= sbad[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double g = given[blockIdx.x];
+        sigma[blockIdx.x] = mode == EIG_SIGMA_NOMINAL_PEAK ? g * (double)smx[0] : g;
+        if (status) status[blockIdx.x] = sbad[0] ? EIG_ENONFINITE : EIG_OK;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+hessian_kernel(const SampleDesc* __restrict__ samples, int per_receiver,
+               int ngroup, const double* __restrict__ sigma, double* __restrict__ H1) {
+    const int s = blockIdx.x, g = blockIdx.y;
+    const SampleDesc& sd = samples[s];
+    const int nt = sd.nt, nrec = sd.nrec;
+    double acc[kTri];
+    for (int t = 0; t < kTri; ++t) acc[t] = 0.0;
+    double inv2d[kNT];
+    for (int j = 0; j < kNT; ++j) inv2d[j] = sd.inv2d[j];
+    const int count = per_receiver ? nt : nt * nrec;
+    for (int q = threadIdx.x; q < count; q += blockDim.x) {
+        const int e = per_receiver ? q * nrec + g : q;
+        double Jx[kNT], Jz[kNT];
+        for (int j = 0; j < kNT; ++j) {
+            const float2 p = sd.dev[2 * j][e];
+            const float2 n = sd.dev[2 * j + 1][e];
+            Jx[j] = ((double)p.x - (double)n.x) * inv2d[j];
+            Jz[j] = ((double)p.y - (double)n.y) * inv2d[j];
+        }
+        if (sd.J) {
+            double* o = sd.J + (size_t)e * 2 * kNT;
+            for (int j = 0; j < kNT; ++j) {
+                o[j] = Jx[j];
+                o[kNT + j] = Jz[j];
+            }
+        }
+        int t = 0;
+        for (int a = 0; a < kNT; ++a)
+            for (int b = a; b < kNT; ++b, ++t) acc[t] += Jx[a] * Jx[b] + Jz[a] * Jz[b];
+    }
+    __shared__ double part[kWavesPerBlock][kTri];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int t = 0; t < kTri; ++t) {
+        const double v = wave_sum(acc[t]);
+        if (lane == 0) part[wave][t] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kTri) {
+        const int t = threadIdx.x;
+        double v = 0.0;
+        for (int w = 0; w < kWavesPerBlock; ++w) v += part[w][t];
+        const double sg = sigma[s];
+        v /= sg * sg;
+        // map t back to (a, b)
+        int a = 0, base = 0;
+        while (t >= base + (kNT - a)) { base += kNT - a; ++a; }
+        const int b = a + (t - base);
+        double* H = H1 + ((size_t)s * ngroup + g) * kNT * kNT;
+        H[a * kNT + b] = v;
+        H[b * kNT + a] = v;
+    }
+}
+
+__global__ void surface_peak_kernel(const float2* __restrict__ tr, int count,
+                                    double rel, double* __restrict__ out) {
+    float mx = 0.f;
+    for (int e = threadIdx.x; e < count; e += blockDim.x) {
+        const float2 v = tr[e];
+        mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+        if (!isfinite(v.x) || !isfinite(v.y)) mx = __int_as_float(0x7fc00000);
+    }
+    __shared__ float smx[256];
+    smx[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const float a = smx[threadIdx.x], b = smx[threadIdx.x + o];
+            smx[threadIdx.x] = (isnan(a) || isnan(b)) ? __int_as_float(0x7fc00000) : fmaxf(a, b);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = rel * (double)smx[0];
+}
+
+}  // namespace
+
+void launch_sample_check(const SampleDesc* samples, int nsample, const double* given,
+                         int mode, double* sigma, int32_t* status, hipStream_t s) {
+    if (nsample <= 0) return;
+    sample_check_kernel<<<nsample, 256, 0, s>>>(samples, given, mode, sigma, status);
+}
+
+void launch_hessian(const SampleDesc* samples, int nsample, int per_receiver,
+                    int ngroup, const double* sigma, double* H1, hipStream_t s) {
+    if (nsample <= 0) return;
+    dim3 grid(nsample, ngroup);
+    hessian_kernel<<<grid, 64 * kWavesPerBlock, 0, s>>>(samples, per_receiver, ngroup,
+                                                         sigma, H1);
+}
+
+void launch_surface_peak(const float2* traces, int count, double rel, double* out,
+                         hipStream_t s) {
+    surface_peak_kernel<<<1, 256, 0, s>>>(traces, count, rel, out);
+}
+
+}  // namespace eig

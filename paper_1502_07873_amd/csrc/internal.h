@@ -1,0 +1,115 @@
+// Internal declarations shared by the eigseis kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/eigseis.h"
+
+namespace eig {
+
+constexpr int kNT = EIG_NTHETA;  // seven source parameters
+constexpr int kTileW = 64;       // columns per wave tile (one wavefront)
+constexpr int kTileRows = 32;    // rows a wave streams through
+constexpr int kWavesPerBlock = 4;
+constexpr int kSrcW = 7;         // source window: union of two 6x6 stencils
+constexpr int kCoefStride = 16;  // floats per row of a layered coefficient table
+
+// Coefficient slots of a layered table row (all pre-multiplied by
+// dt^2 / (rho_k h^2) except kFco = dt^2 / rho_k for the body force).
+enum CoefSlot {
+    kCxxU = 0,   // (u_{i+1} - 2u + u_{i-1})
+    kCzpU = 1,   // (u_{k+1} - u)
+    kCzmU = 2,   // (u - u_{k-1})
+    kCmpU = 3,   // Dx v at row k+1
+    kCmmU = 4,   // Dx v at row k-1
+    kCm0U = 5,   // Dx v at row k (traction-free row only)
+    kCxxV = 6,
+    kCzpV = 7,
+    kCzmV = 8,
+    kCmpV = 9,   // Dx u at row k+1
+    kCmmV = 10,  // Dx u at row k-1
+    kCm0V = 11,  // Dx u at row k (traction-free row only)
+    kFco = 12,
+};
+
+// Nodal media store, per node, (lambda, mu, dt^2/(rho h^2)) as three float
+// planes [3][nz][pitch]; the operator is assembled on the fly.
+
+// One forward solve as seen by the stencil kernel.
+struct SolveDesc {
+    float2* buf0;            // u at even levels (and u^{-1}) ...
+    float2* buf1;            // ... and odd levels; [nz][pitch] (x, depth)
+    const float* coef;       // layered: [nz][kCoefStride]; nodal: [3][nz][pitch]
+    const float* srcw;       // [2][kSrcW][kSrcW] forcing window
+    const float* srcs;       // [nsteps] forcing time series
+    const int32_t* recmap;   // [pitch]: receiver index of a surface column or -1
+    float2* traces;          // [nsteps+1][nrec]
+    int32_t nx, nz, pitch, nsteps;
+    int32_t start;           // launch index at which this solve takes step 0
+    int32_t nrec;
+    int32_t src_i0, src_k0;  // window corner (column, row)
+    int32_t nstrip, nchunk;  // tiles: nstrip across x, nchunk down the depth
+    int32_t tile0;           // first tile index of this solve
+    int32_t medium_kind;     // EIG_MEDIUM_*
+    float h2;                // h^2 (nodal media scale the body force by s h^2)
+};
+
+// One forcing table to build (FP64 arithmetic, FP32 result).
+struct SourceJob {
+    double theta[kNT];
+    double step;             // deviation step (unused for nominal)
+    double h, dt;
+    int32_t param;           // -1 nominal, else the perturbed parameter
+    int32_t kx, kz;          // cell of the unperturbed source
+    int32_t kx2, kz2;        // cell of the perturbed source
+    int32_t i0, k0;          // window corner
+    int32_t nsteps;
+    int32_t stf;
+    float* srcw;
+    float* srcs;
+};
+
+// Per-sample inputs of the Jacobian / Hessian assembly.
+struct SampleDesc {
+    const float2* dev[2 * kNT];  // deviation traces: +d_j at 2j, -d_j at 2j+1
+    const float2* nominal;
+    double inv2d[kNT];           // 1 / (2 d_j)
+    double* J;                   // optional output [nt][nrec][2][7]
+    int32_t nt, nrec;
+};
+
+// launchers (all asynchronous on `s`)
+void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+void launch_layered_coef(const double* rho, const double* lam, const double* mu,
+                         int nz, double h, double dt, float* coef, hipStream_t s);
+void launch_nodal_coef(const double* rho, const double* lam, const double* mu,
+                       int nx, int nz, int pitch, double h, double dt, float* coef,
+                       hipStream_t s);
+void launch_source_tables(const SourceJob* jobs, int njobs, int max_nsteps,
+                          hipStream_t s);
+void launch_stencil(const SolveDesc* descs, const int32_t* tile_solve,
+                    int ntiles, int step, int medium_kind, hipStream_t s);
+void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s);
+void launch_sample_check(const SampleDesc* samples, int nsample, const double* given,
+                         int mode, double* sigma, int32_t* status, hipStream_t s);
+void launch_hessian(const SampleDesc* samples, int nsample, int per_receiver,
+                    int ngroup, const double* sigma, double* H1, hipStream_t s);
+void launch_laplace(const double* H1, int nsample, const eig_prior* prior_dev,
+                    const double* theta, const double* w, double* dkl,
+                    double* logdet, int32_t* status, double* eig, hipStream_t s);
+void launch_design_eval(const double* H1r, int nsample, int ncand,
+                        const uint8_t* mask, int ndesign,
+                        const eig_prior* prior_dev, const double* theta,
+                        const double* w, double* work, double* eig, hipStream_t s);
+void launch_greedy_step(const double* H1r, int nsample, int ncand,
+                        const eig_prior* prior_dev, const double* theta,
+                        const double* w, double* Hcur, uint8_t* chosen,
+                        double* work, double* ival, int k, int32_t* order,
+                        double* curve, hipStream_t s);
+void launch_surface_peak(const float2* traces, int count, double rel,
+                         double* out, hipStream_t s);
+
+}  // namespace eig

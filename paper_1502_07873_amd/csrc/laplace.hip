@@ -1,0 +1,248 @@
+// Laplace KL estimate, quadrature averages and design search, FP64.
+//
+// D^_KL(theta) = -1/2 log((2 pi)^7 |H_1^-1|) - 7/2 - h(theta)   (Theorem 4)
+// with log det H_1 taken through the scaled Hessian of Section 3.3.3,
+// S = sqrt(diag H_1), H~ = S^-1 H_1 S^-1 = L L^T, so that the ~30 decades
+// spanned by the raw entries never reach the factorisation;
+// I = sum_s w_s D^_KL(theta_s) (Section 3.3.4, Monte Carlo or sparse
+// quadrature).  Designs are receiver subsets (Section 4.5); H_1 is additive
+// over receivers, so a design's H_1 is the sum of per-receiver Hessians.
+#include "internal.h"
+
+namespace eig {
+
+namespace {
+
+// log det of a symmetric 7x7 matrix (full storage) via the scaled Cholesky
+// factorisation; false if it is not positive definite or not finite.
+__device__ bool scaled_logdet(const double* H, double* out) {
+    double s[kNT];
+    double ld = 0.0;
+    for (int j = 0; j < kNT; ++j) {
+        const double d = H[j * kNT + j];
+        if (!(d > 0.0) || !isfinite(d)) return false;
+        s[j] = sqrt(d);
+        ld += 2.0 * log(s[j]);
+    }
+    double L[kNT][kNT];
+    for (int j = 0; j < kNT; ++j) {
+        double v = H[j * kNT + j] / (s[j] * s[j]);
+        for (int k = 0; k < j; ++k) v -= L[j][k] * L[j][k];
+        if (!(v > 0.0) || !isfinite(v)) return false;
+        L[j][j] = sqrt(v);
+        ld += 2.0 * log(L[j][j]);
+        for (int i = j + 1; i < kNT; ++i) {
+            double w = H[i * kNT + j] / (s[i] * s[j]);
+            for (int k = 0; k < j; ++k) w -= L[i][k] * L[j][k];
+            L[i][j] = w / L[j][j];
+        }
+    }
+    *out = ld;
+    return true;
+}
+
+// h(theta) = log p(theta).
+__device__ double log_prior(const eig_prior& pr, const double* th) {
+    if (pr.kind == EIG_PRIOR_UNIFORM) {
+        double v = 0.0;
+        for (int j = 0; j < kNT; ++j) v -= log(pr.hi[j] - pr.lo[j]);
+        return v;
+    }
+    // Gaussian: -1/2 r^T C^-1 r - 1/2 (7 log 2 pi + log det C), via C = L L^T
+    double L[kNT][kNT];
+    double ld = 0.0;
+    for (int j = 0; j < kNT; ++j) {
+        double v = pr.cov[j * kNT + j];
+        for (int k = 0; k < j; ++k) v -= L[j][k] * L[j][k];
+        L[j][j] = sqrt(v);
+        ld += 2.0 * log(L[j][j]);
+        for (int i = j + 1; i < kNT; ++i) {
+            double w = pr.cov[i * kNT + j];
+            for (int k = 0; k < j; ++k) w -= L[i][k] * L[j][k];
+            L[i][j] = w / L[j][j];
+        }
+    }
+    double y[kNT];
+    double q = 0.0;
+    for (int i = 0; i < kNT; ++i) {
+        double v = th[i] - pr.mean[i];
+        for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+        y[i] = v / L[i][i];
+        q += y[i] * y[i];
+    }
+    return -0.5 * q - 0.5 * (kNT * log(2.0 * M_PI) + ld);
+}
+
+__device__ bool dkl_of(const double* H, const eig_prior& pr, const double* th,
+                       double* dkl, double* logdet) {
+    double ld;
+    if (!scaled_logdet(H, &ld)) {
+        *dkl = __longlong_as_double(0x7ff8000000000000ULL);
+        *logdet = *dkl;
+        return false;
+    }
+    *logdet = ld;
+    *dkl = -0.5 * (kNT * log(2.0 * M_PI) - ld) - 0.5 * kNT - log_prior(pr, th);
+    return true;
+}
+
+__global__ void laplace_kernel(const double* __restrict__ H1, int nsample,
+                               const eig_prior* __restrict__ prior,
+                               const double* __restrict__ theta,
+                               double* __restrict__ dkl, double* __restrict__ logdet,
+                               int32_t* __restrict__ status) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsample) return;
+    double H[kNT * kNT];
+    for (int j = 0; j < kNT * kNT; ++j) H[j] = H1[(size_t)s * kNT * kNT + j];
+    double v, ld;
+    const bool ok = dkl_of(H, *prior, theta + (size_t)s * kNT, &v, &ld);
+    dkl[s] = v;
+    if (logdet) logdet[s] = ld;
+    if (status) status[s] = ok ? EIG_OK : EIG_ENOTPD;
+}
+
+// out[r] = sum_s w[s] * x[r * n + s] for every row r (one block per row),
+// summed in a fixed order: strided per-thread partials, then a tree.
+__global__ void weighted_rows_kernel(const double* __restrict__ x, int n,
+                                     const double* __restrict__ w,
+                                     double* __restrict__ out,
+                                     const uint8_t* __restrict__ skip) {
+    const int r = blockIdx.x;
+    __shared__ double part[256];
+    double v = 0.0;
+    for (int s = threadIdx.x; s < n; s += blockDim.x) v += w[s] * x[(size_t)r * n + s];
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[r] = (skip && skip[r]) ? __longlong_as_double(0x7ff8000000000000ULL) : part[0];
+}
+
+__global__ void design_dkl_kernel(const double* __restrict__ H1r, int nsample,
+                                  int ncand, const uint8_t* __restrict__ mask,
+                                  const eig_prior* __restrict__ prior,
+                                  const double* __restrict__ theta,
+                                  double* __restrict__ work) {
+    const int d = blockIdx.y;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsample) return;
+    double H[kNT * kNT];
+    for (int j = 0; j < kNT * kNT; ++j) H[j] = 0.0;
+    const uint8_t* md = mask + (size_t)d * ncand;
+    for (int c = 0; c < ncand; ++c) {
+        if (!md[c]) continue;
+        const double* src = H1r + ((size_t)s * ncand + c) * kNT * kNT;
+        for (int j = 0; j < kNT * kNT; ++j) H[j] += src[j];
+    }
+    double v, ld;
+    dkl_of(H, *prior, theta + (size_t)s * kNT, &v, &ld);
+    work[(size_t)d * nsample + s] = v;
+}
+
+__global__ void greedy_dkl_kernel(const double* __restrict__ H1r, int nsample,
+                                  int ncand, const eig_prior* __restrict__ prior,
+                                  const double* __restrict__ theta,
+                                  const double* __restrict__ Hcur,
+                                  const uint8_t* __restrict__ chosen,
+                                  double* __restrict__ work) {
+    const int c = blockIdx.y;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsample) return;
+    if (chosen[c]) {
+        work[(size_t)c * nsample + s] = 0.0;
+        return;
+    }
+    double H[kNT * kNT];
+    const double* src = H1r + ((size_t)s * ncand + c) * kNT * kNT;
+    const double* cur = Hcur + (size_t)s * kNT * kNT;
+    for (int j = 0; j < kNT * kNT; ++j) H[j] = cur[j] + src[j];
+    double v, ld;
+    dkl_of(H, *prior, theta + (size_t)s * kNT, &v, &ld);
+    work[(size_t)c * nsample + s] = v;
+}
+
+// Pick argmax over candidates not yet chosen with a finite value (ties to
+// the lowest index), record it, and add its Hessians to the running sum.
+__global__ void greedy_pick_kernel(const double* __restrict__ H1r, int nsample,
+                                   int ncand, const double* __restrict__ ival,
+                                   double* __restrict__ Hcur, uint8_t* __restrict__ chosen,
+                                   int k, int32_t* __restrict__ order,
+                                   double* __restrict__ curve) {
+    __shared__ double bv[256];
+    __shared__ int bc[256];
+    double best = -INFINITY;
+    int bi = -1;
+    for (int c = threadIdx.x; c < ncand; c += blockDim.x) {
+        const double v = ival[c];
+        if (chosen[c] || isnan(v)) continue;
+        if (bi < 0 || v > best) { best = v; bi = c; }
+    }
+    bv[threadIdx.x] = best;
+    bc[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const int c2 = bc[threadIdx.x + o];
+            const double v2 = bv[threadIdx.x + o];
+            const int c1 = bc[threadIdx.x];
+            const double v1 = bv[threadIdx.x];
+            if (c2 >= 0 && (c1 < 0 || v2 > v1 || (v2 == v1 && c2 < c1))) {
+                bv[threadIdx.x] = v2;
+                bc[threadIdx.x] = c2;
+            }
+        }
+        __syncthreads();
+    }
+    const int pick = bc[0];
+    if (threadIdx.x == 0) {
+        order[k] = pick;
+        curve[k] = pick >= 0 ? bv[0] : __longlong_as_double(0x7ff8000000000000ULL);
+        if (pick >= 0) chosen[pick] = 1;
+    }
+    if (pick < 0) return;
+    for (size_t e = threadIdx.x; e < (size_t)nsample * kNT * kNT; e += blockDim.x) {
+        const size_t s = e / (kNT * kNT), j = e % (kNT * kNT);
+        Hcur[e] += H1r[(s * ncand + pick) * kNT * kNT + j];
+    }
+}
+
+}  // namespace
+
+void launch_laplace(const double* H1, int nsample, const eig_prior* prior_dev,
+                    const double* theta, const double* w, double* dkl,
+                    double* logdet, int32_t* status, double* eig, hipStream_t s) {
+    if (nsample <= 0) return;
+    laplace_kernel<<<(nsample + 127) / 128, 128, 0, s>>>(H1, nsample, prior_dev, theta,
+                                                         dkl, logdet, status);
+    weighted_rows_kernel<<<1, 256, 0, s>>>(dkl, nsample, w, eig, nullptr);
+}
+
+void launch_design_eval(const double* H1r, int nsample, int ncand,
+                        const uint8_t* mask, int ndesign, const eig_prior* prior_dev,
+                        const double* theta, const double* w, double* work,
+                        double* eig, hipStream_t s) {
+    if (nsample <= 0 || ndesign <= 0) return;
+    dim3 grid((nsample + 127) / 128, ndesign);
+    design_dkl_kernel<<<grid, 128, 0, s>>>(H1r, nsample, ncand, mask, prior_dev, theta,
+                                           work);
+    weighted_rows_kernel<<<ndesign, 256, 0, s>>>(work, nsample, w, eig, nullptr);
+}
+
+void launch_greedy_step(const double* H1r, int nsample, int ncand,
+                        const eig_prior* prior_dev, const double* theta,
+                        const double* w, double* Hcur, uint8_t* chosen, double* work,
+                        double* ival, int k, int32_t* order, double* curve,
+                        hipStream_t s) {
+    dim3 grid((nsample + 127) / 128, ncand);
+    greedy_dkl_kernel<<<grid, 128, 0, s>>>(H1r, nsample, ncand, prior_dev, theta, Hcur,
+                                           chosen, work);
+    weighted_rows_kernel<<<ncand, 256, 0, s>>>(work, nsample, w, ival, chosen);
+    greedy_pick_kernel<<<1, 256, 0, s>>>(H1r, nsample, ncand, ival, Hcur, chosen, k,
+                                         order, curve);
+}
+
+}  // namespace eig

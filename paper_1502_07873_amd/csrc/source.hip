@@ -1,0 +1,182 @@
+// Device-side tables: medium coefficients (FP64 in, FP32 out) and the point
+// moment-tensor forcing f = S(t) M grad(delta(x - x_s)) of every solve.
+//
+// The singular source is discretised with the fourth-order, twice
+// continuously differentiable regularised delta and delta' of the paper
+// (Section 3.3.2, item 2) on the six nodes k-2..k+3 around the source cell,
+// and the 2-D gradient is their Cartesian product.  Tables are built in FP64;
+// for the perturbed solves of the central-difference Jacobian the difference
+// F(theta + step e_j) - F(theta) is formed in FP64 and only then rounded to
+// FP32, so the small perturbation is not lost to FP32 cancellation.
+#include "internal.h"
+
+namespace eig {
+
+namespace {
+
+// Regularised delta weights (times h) for node offset o in -2..3 and
+// alpha = (x_s - x_k)/h.
+__device__ double delta_w(double a, int o) {
+    const double a2 = a * a, a3 = a2 * a, a4 = a3 * a;
+    const double P = a4 * a * (5.0 / 3.0 + a * (-7.0 / 24.0 + a * (-17.0 / 12.0 + a * (9.0 / 8.0 - a / 4.0))));
+    switch (o) {
+        case -2: return a / 12.0 - a2 / 24.0 - a3 / 12.0 - 19.0 * a4 / 24.0 + P;
+        case -1: return -2.0 * a / 3.0 + 2.0 * a2 / 3.0 + a3 / 6.0 + 4.0 * a4 - 5.0 * P;
+        case 0: return 1.0 - 5.0 * a2 / 4.0 - 97.0 * a4 / 12.0 + 10.0 * P;
+        case 1: return 2.0 * a / 3.0 + 2.0 * a2 / 3.0 - a3 / 6.0 + 49.0 * a4 / 6.0 - 10.0 * P;
+        case 2: return -a / 12.0 - a2 / 24.0 + a3 / 12.0 - 33.0 * a4 / 8.0 + 5.0 * P;
+        case 3: return 5.0 * a4 / 6.0 - P;
+        default: return 0.0;
+    }
+}
+
+// Regularised delta' weights (times h^2).
+__device__ double ddelta_w(double a, int o) {
+    const double a2 = a * a, a3 = a2 * a, a4 = a3 * a;
+    const double R = a4 * (-25.0 / 12.0 + a * (-3.0 / 4.0 + a * (59.0 / 12.0 + a * (-4.0 + a))));
+    switch (o) {
+        case -2: return -1.0 / 12.0 + a / 12.0 + a2 / 4.0 + 2.0 * a3 / 3.0 + R;
+        case -1: return 2.0 / 3.0 - 4.0 * a / 3.0 - a2 / 2.0 - 7.0 * a3 / 2.0 - 5.0 * R;
+        case 0: return 5.0 * a / 2.0 + 22.0 * a3 / 3.0 + 10.0 * R;
+        case 1: return -2.0 / 3.0 - 4.0 * a / 3.0 + a2 / 2.0 - 23.0 * a3 / 3.0 - 10.0 * R;
+        case 2: return 1.0 / 12.0 + a / 12.0 - a2 / 4.0 + 4.0 * a3 + 5.0 * R;
+        case 3: return -5.0 * a3 / 6.0 - R;
+        default: return 0.0;
+    }
+}
+
+// Force density on node (ic, kr), component c, of the source theta whose
+// cell is (kx, kz): M grad(delta) with grad(delta) = (delta'(x) delta(z),
+// delta(x) delta'(z)).
+__device__ double source_weight(const double* th, int kx, int kz, double h, int ic,
+                                int kr, int c) {
+    const int ox = ic - kx, oz = kr - kz;
+    if (ox < -2 || ox > 3 || oz < -2 || oz > 3) return 0.0;
+    const double ax = th[0] / h - kx, az = th[1] / h - kz;
+    const double dx = delta_w(ax, ox) / h, dpx = ddelta_w(ax, ox) / (h * h);
+    const double dz = delta_w(az, oz) / h, dpz = ddelta_w(az, oz) / (h * h);
+    const double gx = dpx * dz, gz = dx * dpz;
+    return c == 0 ? th[4] * gx + th[5] * gz : th[5] * gx + th[6] * gz;
+}
+
+__device__ double wavelet(int kind, double t, double t0, double p) {
+    if (kind == EIG_STF_GAUSS) {
+        const double w = p;
+        return w / sqrt(2.0 * M_PI) * exp(-0.5 * w * w * (t - t0) * (t - t0));
+    }
+    const double w = 2.0 * M_PI * p;
+    const double g = w / sqrt(2.0 * M_PI) * exp(-0.5 * w * w * (t - t0) * (t - t0));
+    return -w * w * (t - t0) * g;
+}
+
+__global__ void source_kernel(const SourceJob* __restrict__ jobs) {
+    const SourceJob& J = jobs[blockIdx.x];
+    double th[kNT], tp[kNT];
+    for (int j = 0; j < kNT; ++j) th[j] = tp[j] = J.theta[j];
+    if (J.param >= 0) tp[J.param] = J.theta[J.param] + J.step;
+    const bool spatial = (J.param == 0 || J.param == 1 || J.param >= 4);
+    const bool temporal = (J.param == 2 || J.param == 3);
+    for (int e = threadIdx.x; e < 2 * kSrcW * kSrcW; e += blockDim.x) {
+        const int c = e / (kSrcW * kSrcW);
+        const int kk = (e / kSrcW) % kSrcW;
+        const int ii = e % kSrcW;
+        const int ic = J.i0 + ii, kr = J.k0 + kk;
+        double w = source_weight(th, J.kx, J.kz, J.h, ic, kr, c);
+        if (J.param >= 0 && spatial)
+            w = source_weight(tp, J.kx2, J.kz2, J.h, ic, kr, c) - w;
+        J.srcw[e] = (float)w;
+    }
+    for (int m = threadIdx.x; m < J.nsteps; m += blockDim.x) {
+        const double t = m * J.dt;
+        double S = wavelet(J.stf, t, th[2], th[3]);
+        if (J.param >= 0 && temporal) S = wavelet(J.stf, t, tp[2], tp[3]) - S;
+        J.srcs[m] = (float)S;
+    }
+}
+
+// Depth-only medium: one row of kCoefStride coefficients per depth index,
+// the operator of the stencil kernel written out per row (a = lambda+2mu).
+__global__ void layered_coef_kernel(const double* __restrict__ rho,
+                                    const double* __restrict__ lam,
+                                    const double* __restrict__ mu, int nz, double h,
+                                    double dt, float* __restrict__ coef) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nz) return;
+    double c[kCoefStride];
+    for (int j = 0; j < kCoefStride; ++j) c[j] = 0.0;
+    if (k < nz - 1) {
+        const double s = dt * dt / (rho[k] * h * h);
+        const double l0 = lam[k], m0 = mu[k], a0 = l0 + 2.0 * m0;
+        const double l1 = lam[k + 1], m1 = mu[k + 1], a1 = l1 + 2.0 * m1;
+        c[kCxxU] = s * a0;
+        c[kCxxV] = s * m0;
+        c[kFco] = dt * dt / rho[k];
+        if (k == 0) {
+            // traction-free row
+            c[kCzpU] = s * (m0 + m1);               // 2 mu_{1/2}
+            c[kCmpU] = s * 0.5 * (l0 + m1);
+            c[kCm0U] = s * 0.5 * (m0 - l0);
+            c[kCzpV] = s * (a0 + a1);               // 2 a_{1/2}
+            c[kCmpV] = s * 0.5 * (l1 + m0);
+            c[kCm0V] = s * 0.5 * (l0 - m0);
+        } else {
+            const double lm = lam[k - 1], mm = mu[k - 1], am = lm + 2.0 * mm;
+            c[kCzpU] = s * 0.5 * (m0 + m1);
+            c[kCzmU] = s * 0.5 * (mm + m0);
+            c[kCmpU] = s * 0.25 * (l0 + m1);
+            c[kCmmU] = s * 0.25 * (l0 + mm);
+            c[kCzpV] = s * 0.5 * (a0 + a1);
+            c[kCzmV] = s * 0.5 * (am + a0);
+            c[kCmpV] = s * 0.25 * (l1 + m0);
+            c[kCmmV] = s * 0.25 * (lm + m0);
+        }
+    }
+    for (int j = 0; j < kCoefStride; ++j) coef[(size_t)k * kCoefStride + j] = (float)c[j];
+}
+
+__global__ void nodal_coef_kernel(const double* __restrict__ rho,
+                                  const double* __restrict__ lam,
+                                  const double* __restrict__ mu, int nx, int nz,
+                                  int pitch, double h, double dt,
+                                  float* __restrict__ coef) {
+    const size_t plane = (size_t)nz * pitch;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < plane;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e / pitch), i = (int)(e % pitch);
+        float l = 0.f, m = 0.f, sc = 0.f;
+        if (i < nx) {
+            const size_t p = (size_t)k * nx + i;
+            l = (float)lam[p];
+            m = (float)mu[p];
+            sc = (float)(dt * dt / (rho[p] * h * h));
+        }
+        coef[e] = l;
+        coef[plane + e] = m;
+        coef[2 * plane + e] = sc;
+    }
+}
+
+}  // namespace
+
+void launch_source_tables(const SourceJob* jobs, int njobs, int /*max_nsteps*/,
+                          hipStream_t s) {
+    if (njobs <= 0) return;
+    source_kernel<<<njobs, 256, 0, s>>>(jobs);
+}
+
+void launch_layered_coef(const double* rho, const double* lam, const double* mu,
+                         int nz, double h, double dt, float* coef, hipStream_t s) {
+    layered_coef_kernel<<<(nz + 127) / 128, 128, 0, s>>>(rho, lam, mu, nz, h, dt, coef);
+}
+
+void launch_nodal_coef(const double* rho, const double* lam, const double* mu,
+                       int nx, int nz, int pitch, double h, double dt, float* coef,
+                       hipStream_t s) {
+    const size_t plane = (size_t)nz * pitch;
+    size_t blocks = (plane + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    nodal_coef_kernel<<<(unsigned)blocks, 256, 0, s>>>(rho, lam, mu, nx, nz, pitch, h,
+                                                        dt, coef);
+}
+
+}  // namespace eig

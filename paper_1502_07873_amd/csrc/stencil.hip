@@ -1,0 +1,382 @@
+// Leapfrog step of the 2-D elastic wave equation for many solves at once,
+// with the point-source forcing and the surface receivers fused in.
+//
+// Scheme (paper Section 3.3.1, full-discrete formulas): at every free node
+//   u^{m+1} = 2 u^m - u^{m-1} + dt^2/rho (A_h u^m + f^m),
+// A_h the second-order operator made of D+(a D-) terms for the normal
+// second derivatives and D0(c D0) terms for the mixed ones, with a
+// traction-free top row (depth 0) and rigid left, right and bottom edges.
+// The top-row closure is the one that makes A_h the negative gradient of a
+// discrete elastic energy with trapezoid weights (so the scheme conserves a
+// discrete energy); derived per node, it reads, with a = lambda + 2 mu and
+// Dx w_k = w_{i+1,k} - w_{i-1,k}:
+//   h^2 (A_h u)_x = a (u_{i+1} - 2u + u_{i-1}) + 2 mu_{1/2} (u_1 - u_0)
+//                   + 1/2 (lambda_0 + mu_1) Dx v_1 + 1/2 (mu_0 - lambda_0) Dx v_0
+//   h^2 (A_h u)_z = mu (v_{i+1} - 2v + v_{i-1}) + 2 a_{1/2} (v_1 - v_0)
+//                   + 1/2 (lambda_1 + mu_0) Dx u_1 + 1/2 (lambda_0 - mu_0) Dx u_0
+// (depth-only media; the nodal variant keeps every coefficient per node).
+//
+// Work decomposition: one wavefront owns a tile of 64 columns and up to
+// kTileRows rows of one solve and streams down the rows, keeping the rows
+// k-1, k, k+1 of u^m in registers; x-neighbours come from cross-lane moves,
+// the two edge lanes fetch the halo columns.  Every u^m value is read from
+// HBM once per step (tile halos hit L2), u^{m-1} is read once and u^{m+1}
+// written in place of it: 24 bytes of field traffic per grid-point update.
+// Depth-only coefficients are per-row scalars (SGPR loads).
+#include "internal.h"
+
+namespace eig {
+
+namespace {
+
+// Workgroups are dealt round-robin to the 8 XCDs; renumber them so that the
+// tiles a given XCD works on at one time are contiguous (same solve, shared
+// halos in that XCD's L2).  A bijection on [0, n) for any n.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+    const int x = b & 7, j = b >> 3, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + j;
+}
+
+// Value held by lane-1 (lane 0 receives `edge`) and by lane+1 (lane 63
+// receives `edge`).  DPP wave shifts keep the old value in the lane whose
+// source is outside the wavefront.
+__device__ __forceinline__ float from_left(float x, float edge) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(
+        __float_as_int(edge), __float_as_int(x), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right(float x, float edge) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(
+        __float_as_int(edge), __float_as_int(x), 0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+}
+
+// Pointers read out of a descriptor are generic; loads through them would be
+// FLAT instructions.  These accessors address global memory explicitly.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GAS __attribute__((address_space(1)))
+#else
+#define GAS
+#endif
+typedef float fv2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 ld2(const float2* p, size_t i) {
+    const fv2 v = ((const GAS fv2*)p)[i];
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(float2* p, size_t i, float2 v) {
+    fv2 w;
+    w.x = v.x;
+    w.y = v.y;
+    ((GAS fv2*)p)[i] = w;
+}
+__device__ __forceinline__ float ld1(const float* p, size_t i) {
+    return ((const GAS float*)p)[i];
+}
+__device__ __forceinline__ int ldi(const int32_t* p, size_t i) {
+    return ((const GAS int32_t*)p)[i];
+}
+
+// u^m at column i of row k, and the halo column for the two edge lanes
+// (zero elsewhere).  Every lane loads a valid address.
+__device__ __forceinline__ void load_row(const float2* Q, size_t off, int i,
+                                         int hc, bool hl, float2& c, float2& h) {
+    c = ld2(Q, off + i);
+    const float2 hv = ld2(Q, off + (hl ? hc : i));
+    h.x = hl ? hv.x : 0.f;
+    h.y = hl ? hv.y : 0.f;
+}
+
+struct RowU {
+    float u, v;     // centre
+    float dxu, dxv; // u_{i+1} - u_{i-1}
+    float sxu, sxv; // u_{i+1} + u_{i-1}
+};
+
+__device__ __forceinline__ RowU make_row(float2 c, float2 h) {
+    RowU r;
+    const float lu = from_left(c.x, h.x), ru = from_right(c.x, h.x);
+    const float lv = from_left(c.y, h.y), rv = from_right(c.y, h.y);
+    r.u = c.x; r.v = c.y;
+    r.dxu = ru - lu; r.dxv = rv - lv;
+    r.sxu = ru + lu; r.sxv = rv + lv;
+    return r;
+}
+
+__global__ void __launch_bounds__(256)
+stencil_layered(const SolveDesc* __restrict__ descs,
+                const int32_t* __restrict__ tile_solve, int ntiles, int step) {
+    const int lane = threadIdx.x & 63;
+    const int tile = __builtin_amdgcn_readfirstlane(
+        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
+    if (tile >= ntiles) return;
+    const SolveDesc* d = descs + __builtin_amdgcn_readfirstlane(tile_solve[tile]);
+    const int m = step - d->start;
+    if (m < 0 || m >= d->nsteps) return;
+    const int nx = d->nx, nz = d->nz, pitch = d->pitch;
+    const int local = tile - d->tile0;
+    const int strip = local % d->nstrip;
+    const int chunk = local / d->nstrip;
+    const int x0 = strip * kTileW;
+    const int i = x0 + lane;
+    const int kb = chunk * kTileRows;
+    const int ke = min(kb + kTileRows, nz - 1);  // rows [kb, ke) are free rows
+    const float2* Q = (m & 1) ? d->buf1 : d->buf0;  // u^m
+    float2* P = (m & 1) ? d->buf0 : d->buf1;        // u^{m-1} -> u^{m+1}
+    const float* coef = d->coef;
+
+    const bool upd = (i >= 1) && (i <= nx - 2);
+    const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + kTileW < nx);
+    const int hc = (lane == 0) ? x0 - 1 : x0 + kTileW;
+
+    // source window (wave-uniform test per row)
+    const int si0 = d->src_i0, sk0 = d->src_k0;
+    const bool src_cols = (si0 < x0 + kTileW) && (si0 + kSrcW > x0);
+    const int di = i - si0;
+    const bool src_lane = src_cols && di >= 0 && di < kSrcW;
+    const float sval = src_cols ? ld1(d->srcs, m) : 0.0f;
+    const float* srcw = d->srcw;
+    float2* traces = d->traces;
+    const int nrec = d->nrec;
+
+    int rec = -1;
+    if (kb == 0) rec = ldi(d->recmap, i);
+
+    RowU rm, rc, rn;
+    if (kb == 0) {
+        rm = RowU{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    } else {
+        float2 c, h;
+        load_row(Q, (size_t)(kb - 1) * pitch, i, hc, hl, c, h);
+        rm = make_row(c, h);
+    }
+    float2 cc, ch, cn, chn;
+    load_row(Q, (size_t)kb * pitch, i, hc, hl, cc, ch);
+    load_row(Q, (size_t)(kb + 1) * pitch, i, hc, hl, cn, chn);
+    float2 up = ld2(P, (size_t)kb * pitch + i);
+    rc = make_row(cc, ch);
+
+    for (int k = kb; k < ke; ++k) {
+        // prefetch the row after next and the next u^{m-1}
+        float2 cnn = make_float2(0.f, 0.f), chnn = cnn, upn = cnn;
+        if (k + 2 <= nz - 1) load_row(Q, (size_t)(k + 2) * pitch, i, hc, hl, cnn, chnn);
+        if (k + 1 < ke) upn = ld2(P, (size_t)(k + 1) * pitch + i);
+        rn = make_row(cn, chn);
+
+        const size_t cb = (size_t)k * kCoefStride;
+        float au = ld1(coef, cb + kCxxU) * (rc.sxu - 2.f * rc.u)
+                 + ld1(coef, cb + kCzpU) * (rn.u - rc.u)
+                 - ld1(coef, cb + kCzmU) * (rc.u - rm.u) + ld1(coef, cb + kCmpU) * rn.dxv
+                 - ld1(coef, cb + kCmmU) * rm.dxv + ld1(coef, cb + kCm0U) * rc.dxv;
+        float av = ld1(coef, cb + kCxxV) * (rc.sxv - 2.f * rc.v)
+                 + ld1(coef, cb + kCzpV) * (rn.v - rc.v)
+                 - ld1(coef, cb + kCzmV) * (rc.v - rm.v) + ld1(coef, cb + kCmpV) * rn.dxu
+                 - ld1(coef, cb + kCmmV) * rm.dxu + ld1(coef, cb + kCm0V) * rc.dxu;
+        const int dk = k - sk0;
+        if (src_lane && dk >= 0 && dk < kSrcW) {
+            const float f = ld1(coef, cb + kFco) * sval;
+            au += f * ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
+            av += f * ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
+        }
+        float2 nw;
+        nw.x = rc.u + ((rc.u - up.x) + au);
+        nw.y = rc.v + ((rc.v - up.y) + av);
+        if (upd) {
+            st2(P, (size_t)k * pitch + i, nw);
+            if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
+        }
+        rm = rc;
+        rc = rn;
+        cn = cnn;
+        chn = chnn;
+        up = upn;
+    }
+}
+
+// Nodal media: coef = three planes (lambda, mu, s = dt^2/(rho h^2)).
+struct RowN {
+    float u, v, hu, hv;   // centre and halo-column values of u^m
+    float lam, mu;        // centre nodal coefficients
+    float hlam, hmu;      // halo-column coefficients
+};
+
+__global__ void __launch_bounds__(256)
+stencil_nodal(const SolveDesc* __restrict__ descs,
+              const int32_t* __restrict__ tile_solve, int ntiles, int step) {
+    const int lane = threadIdx.x & 63;
+    const int tile = __builtin_amdgcn_readfirstlane(
+        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
+    if (tile >= ntiles) return;
+    const SolveDesc* d = descs + __builtin_amdgcn_readfirstlane(tile_solve[tile]);
+    const int m = step - d->start;
+    if (m < 0 || m >= d->nsteps) return;
+    const int nx = d->nx, nz = d->nz, pitch = d->pitch;
+    const int local = tile - d->tile0;
+    const int strip = local % d->nstrip;
+    const int chunk = local / d->nstrip;
+    const int x0 = strip * kTileW;
+    const int i = x0 + lane;
+    const int kb = chunk * kTileRows;
+    const int ke = min(kb + kTileRows, nz - 1);
+    const float2* Q = (m & 1) ? d->buf1 : d->buf0;
+    float2* P = (m & 1) ? d->buf0 : d->buf1;
+    const size_t plane = (size_t)nz * pitch;
+    const float* LAM = d->coef;
+    const float* MU = LAM + plane;
+    const float* SC = LAM + 2 * plane;
+
+    const bool upd = (i >= 1) && (i <= nx - 2);
+    const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + kTileW < nx);
+    const int hc = (lane == 0) ? x0 - 1 : x0 + kTileW;
+
+    const int si0 = d->src_i0, sk0 = d->src_k0;
+    const bool src_cols = (si0 < x0 + kTileW) && (si0 + kSrcW > x0);
+    const int di = i - si0;
+    const bool src_lane = src_cols && di >= 0 && di < kSrcW;
+    const float sval = src_cols ? ld1(d->srcs, m) : 0.0f;
+    const float* srcw = d->srcw;
+    float2* traces = d->traces;
+    const int nrec = d->nrec;
+    const float h2 = d->h2;
+    int rec = -1;
+    if (kb == 0) rec = ldi(d->recmap, i);
+
+    auto load = [=](int k) {
+        RowN r;
+        const size_t o = (size_t)k * pitch;
+        const int j = hl ? hc : i;
+        const float2 c = ld2(Q, o + i);
+        const float2 h = ld2(Q, o + j);
+        r.u = c.x; r.v = c.y;
+        r.lam = ld1(LAM, o + i);
+        r.mu = ld1(MU, o + i);
+        const float hlam = ld1(LAM, o + j), hmu = ld1(MU, o + j);
+        r.hu = hl ? h.x : 0.f;
+        r.hv = hl ? h.y : 0.f;
+        r.hlam = hl ? hlam : 0.f;
+        r.hmu = hl ? hmu : 0.f;
+        return r;
+    };
+
+    RowN rm, rc, rn;
+    if (kb == 0) {
+        rm = RowN{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    } else {
+        rm = load(kb - 1);
+    }
+    rc = load(kb);
+    rn = load(kb + 1);
+    float2 up = ld2(P, (size_t)kb * pitch + i);
+    float sc = ld1(SC, (size_t)kb * pitch + i);
+
+    for (int k = kb; k < ke; ++k) {
+        RowN rnn = RowN{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float2 upn = make_float2(0.f, 0.f);
+        float scn = 0.f;
+        if (k + 2 <= nz - 1) rnn = load(k + 2);
+        if (k + 1 < ke) {
+            upn = ld2(P, (size_t)(k + 1) * pitch + i);
+            scn = ld1(SC, (size_t)(k + 1) * pitch + i);
+        }
+        // x-direction neighbours of row k
+        const float uL = from_left(rc.u, rc.hu), uR = from_right(rc.u, rc.hu);
+        const float vL = from_left(rc.v, rc.hv), vR = from_right(rc.v, rc.hv);
+        const float ac = rc.lam + 2.f * rc.mu;
+        const float ah = rc.hlam + 2.f * rc.hmu;
+        const float aL = from_left(ac, ah), aR = from_right(ac, ah);
+        const float mL = from_left(rc.mu, rc.hmu), mR = from_right(rc.mu, rc.hmu);
+        float au = 0.5f * ((ac + aR) * (uR - rc.u) - (aL + ac) * (rc.u - uL));
+        float av = 0.5f * ((rc.mu + mR) * (vR - rc.v) - (mL + rc.mu) * (rc.v - vL));
+        // Dx of rows k+1 (and k-1 or k on the top row)
+        const float dxu_n = from_right(rn.u, rn.hu) - from_left(rn.u, rn.hu);
+        const float dxv_n = from_right(rn.v, rn.hv) - from_left(rn.v, rn.hv);
+        const float an = rn.lam + 2.f * rn.mu;
+        if (k == 0) {
+            const float dxu_c = uR - uL, dxv_c = vR - vL;
+            au += (rc.mu + rn.mu) * (rn.u - rc.u);
+            av += (ac + an) * (rn.v - rc.v);
+            // 1/2 [lam_{i+1,0} (v_{i+1,1}-v_{i+1,0}) - lam_{i-1,0} (...)]
+            const float p = rc.lam * (rn.v - rc.v), ph = rc.hlam * (rn.hv - rc.hv);
+            const float q = rc.mu * (rn.u - rc.u), qh = rc.hmu * (rn.hu - rc.hu);
+            au += 0.5f * (from_right(p, ph) - from_left(p, ph))
+                + 0.5f * (rc.mu * dxv_c + rn.mu * dxv_n);
+            av += 0.5f * (rc.lam * dxu_c + rn.lam * dxu_n)
+                + 0.5f * (from_right(q, qh) - from_left(q, qh));
+        } else {
+            const float am = rm.lam + 2.f * rm.mu;
+            au += 0.5f * ((rc.mu + rn.mu) * (rn.u - rc.u) - (rm.mu + rc.mu) * (rc.u - rm.u));
+            av += 0.5f * ((ac + an) * (rn.v - rc.v) - (am + ac) * (rc.v - rm.v));
+            const float dxu_m = from_right(rm.u, rm.hu) - from_left(rm.u, rm.hu);
+            const float dxv_m = from_right(rm.v, rm.hv) - from_left(rm.v, rm.hv);
+            // 1/4 [lam_{i+1,k} Dz v_{i+1} - lam_{i-1,k} Dz v_{i-1}], Dz w = w_{k+1} - w_{k-1}
+            const float p = rc.lam * (rn.v - rm.v), ph = rc.hlam * (rn.hv - rm.hv);
+            const float q = rc.mu * (rn.u - rm.u), qh = rc.hmu * (rn.hu - rm.hu);
+            au += 0.25f * (from_right(p, ph) - from_left(p, ph))
+                + 0.25f * (rn.mu * dxv_n - rm.mu * dxv_m);
+            av += 0.25f * (rn.lam * dxu_n - rm.lam * dxu_m)
+                + 0.25f * (from_right(q, qh) - from_left(q, qh));
+        }
+        au *= sc;
+        av *= sc;
+        const int dk = k - sk0;
+        if (src_lane && dk >= 0 && dk < kSrcW) {
+            // dt^2/rho f = s h^2 f
+            const float f = sc * h2 * sval;
+            au += f * ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
+            av += f * ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
+        }
+        float2 nw;
+        nw.x = rc.u + ((rc.u - up.x) + au);
+        nw.y = rc.v + ((rc.v - up.y) + av);
+        if (upd) {
+            st2(P, (size_t)k * pitch + i, nw);
+            if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
+        }
+        rm = rc;
+        rc = rn;
+        rn = rnn;
+        up = upn;
+        sc = scn;
+    }
+}
+
+__global__ void fill_zero_kernel(uint4* p, size_t n16, uint8_t* tail, size_t ntail) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n16; j += stride)
+        p[j] = make_uint4(0, 0, 0, 0);
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntail) tail[t] = 0;
+}
+
+__global__ void zero_level0_kernel(const SolveDesc* __restrict__ descs) {
+    const SolveDesc& d = descs[blockIdx.x];
+    for (int r = threadIdx.x; r < d.nrec; r += blockDim.x) d.traces[r] = make_float2(0.f, 0.f);
+}
+
+}  // namespace
+
+void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s) {
+    if (n > 0) zero_level0_kernel<<<n, 64, 0, s>>>(descs);
+}
+
+void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return;
+    // callers pass 16-byte aligned buffers; the remainder is cleared bytewise
+    const size_t n16 = bytes / 16;
+    const size_t ntail = bytes - n16 * 16;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 8192) blocks = 8192;
+    fill_zero_kernel<<<(unsigned)blocks, 256, 0, s>>>(
+        (uint4*)p, n16, (uint8_t*)p + n16 * 16, ntail);
+}
+
+void launch_stencil(const SolveDesc* descs, const int32_t* tile_solve, int ntiles,
+                    int step, int medium_kind, hipStream_t s) {
+    if (ntiles <= 0) return;
+    const int blocks = (ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (medium_kind == EIG_MEDIUM_NODAL)
+        stencil_nodal<<<blocks, 64 * kWavesPerBlock, 0, s>>>(descs, tile_solve, ntiles, step);
+    else
+        stencil_layered<<<blocks, 64 * kWavesPerBlock, 0, s>>>(descs, tile_solve, ntiles, step);
+}
+
+}  // namespace eig

@@ -1,0 +1,300 @@
+"""Thin ctypes binding of libeigseis.so (include/eigseis.h).
+
+Argument marshalling only: every step of the Laplace-EIG path runs in the
+library's HIP kernels.  Device arrays are torch tensors on the HIP device;
+host arrays are numpy arrays.  The library is loaded from this package's
+directory; if it is missing the import fails (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeigseis.so")
+
+NTHETA = 7
+EIG_OK = 0
+EIG_EINVAL = -1
+EIG_ENOMEM = -2
+EIG_EBUDGET = -3
+EIG_ENOTPD = -4
+EIG_ENONFINITE = -5
+EIG_EHIP = -6
+EIG_EUNSUPPORTED = -7
+STF_GAUSS = 0
+STF_GAUSS_DERIV = 1
+MEDIUM_LAYERED = 0
+MEDIUM_NODAL = 1
+PRIOR_UNIFORM = 0
+PRIOR_GAUSSIAN = 1
+SIGMA_GIVEN = 0
+SIGMA_NOMINAL_PEAK = 1
+
+STF_KINDS = {"gauss": STF_GAUSS, "gauss_deriv": STF_GAUSS_DERIV}
+
+
+class EigError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"eigseis error {code}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("h", ctypes.c_double),
+                ("dt", ctypes.c_double), ("nsteps", ctypes.c_int32)]
+
+
+class Medium(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("rho", ctypes.c_void_p),
+                ("lam", ctypes.c_void_p), ("mu", ctypes.c_void_p)]
+
+
+class Receivers(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("ix", ctypes.POINTER(ctypes.c_int32))]
+
+
+class Prior(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("lo", ctypes.c_double * NTHETA),
+                ("hi", ctypes.c_double * NTHETA), ("mean", ctypes.c_double * NTHETA),
+                ("cov", ctypes.c_double * (NTHETA * NTHETA))]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "eig_ctx_create": ([ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)], ctypes.c_int),
+        "eig_ctx_destroy": ([vp], None),
+        "eig_last_error": ([], ctypes.c_char_p),
+        "eig_ctx_workspace_bytes": ([vp], ctypes.c_size_t),
+        "eig_ctx_stencil_stats": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
+        "forward_solve_batch": ([vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
+        "jacobian_fd": ([vp, i32, vp, vp, vp, dbl, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp],
+                        ctypes.c_int),
+        "laplace_eig": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "design_eval": ([vp, i32, i32, vp, i32, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "design_greedy": ([vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
+        "noise_sigma_peak": ([vp, vp, vp, vp, i32, dbl, vp, vp], ctypes.c_int),
+        "sparse_grid_gl": ([i32, i32, vp, vp, i32, vp, vp, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+_lib = _load()
+EXPORTED = ("eig_ctx_create", "eig_ctx_destroy", "eig_last_error", "eig_ctx_workspace_bytes",
+            "eig_ctx_stencil_stats",
+            "forward_solve_batch", "jacobian_fd", "laplace_eig", "design_eval",
+            "design_greedy", "noise_sigma_peak", "sparse_grid_gl")
+
+
+def _check(rc: int):
+    if rc != EIG_OK:
+        raise EigError(rc, _lib.eig_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr_array(tensors):
+    if tensors is None:
+        return None
+    arr = (ctypes.c_void_p * len(tensors))(*[None if t is None else t.data_ptr()
+                                            for t in tensors])
+    return arr
+
+
+def make_prior(lo=None, hi=None, mean=None, cov=None) -> Prior:
+    p = Prior()
+    if mean is not None:
+        p.kind = PRIOR_GAUSSIAN
+        p.mean[:] = list(np.asarray(mean, dtype=np.float64))
+        p.cov[:] = list(np.asarray(cov, dtype=np.float64).ravel())
+    else:
+        p.kind = PRIOR_UNIFORM
+    if lo is not None:
+        p.lo[:] = list(np.asarray(lo, dtype=np.float64))
+        p.hi[:] = list(np.asarray(hi, dtype=np.float64))
+    return p
+
+
+def sparse_grid_gl(dim: int, level: int, lo=None, hi=None):
+    """Nodes [eta][dim] and weights [eta] of the Gauss-Legendre total-degree
+    sparse grid (host computation in the library)."""
+    count = ctypes.c_int32(0)
+    lo_a = None if lo is None else np.ascontiguousarray(lo, dtype=np.float64)
+    hi_a = None if hi is None else np.ascontiguousarray(hi, dtype=np.float64)
+    rc = _lib.sparse_grid_gl(dim, level, None if lo_a is None else _np_ptr(lo_a),
+                             None if hi_a is None else _np_ptr(hi_a), 0, None, None,
+                             ctypes.byref(count))
+    n = count.value
+    if rc != EIG_OK and n <= 0:
+        _check(rc)
+    nodes = np.empty((n, dim))
+    w = np.empty(n)
+    _check(_lib.sparse_grid_gl(dim, level, None if lo_a is None else _np_ptr(lo_a),
+                               None if hi_a is None else _np_ptr(hi_a), n, _np_ptr(nodes),
+                               _np_ptr(w), ctypes.byref(count)))
+    return nodes, w
+
+
+class Context:
+    """An eig_ctx on one HIP device with a workspace budget in bytes."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 64 << 30):
+        h = ctypes.c_void_p()
+        _check(_lib.eig_ctx_create(device, budget_bytes, ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.eig_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def workspace_bytes(self) -> int:
+        return _lib.eig_ctx_workspace_bytes(self._h)
+
+    def stencil_stats(self, reset: bool = False) -> dict:
+        """Device time (ms) from first to last stencil launch of each wave,
+        launch count, grid-point updates and algorithmic HBM bytes."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        upd = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(_lib.eig_ctx_stencil_stats(self._h, 1 if reset else 0, ctypes.byref(ms),
+                                          ctypes.byref(n), ctypes.byref(upd),
+                                          ctypes.byref(by)))
+        return {"ms": ms.value, "launches": n.value, "updates": upd.value,
+                "bytes": by.value}
+
+    # -- marshalling helpers ------------------------------------------------
+    @staticmethod
+    def _grids(grids):
+        arr = (Grid * len(grids))()
+        for k, g in enumerate(grids):
+            arr[k] = Grid(int(g[0]), int(g[1]), float(g[2]), float(g[3]), int(g[4]))
+        return arr
+
+    @staticmethod
+    def _media(media):
+        arr = (Medium * len(media))()
+        for k, (kind, rho, lam, mu) in enumerate(media):
+            arr[k] = Medium(kind, _ptr(rho), _ptr(lam), _ptr(mu))
+        return arr
+
+    @staticmethod
+    def _receivers(recs):
+        keep = [np.ascontiguousarray(r, dtype=np.int32) for r in recs]
+        arr = (Receivers * len(keep))()
+        for k, r in enumerate(keep):
+            arr[k] = Receivers(r.size, r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        return arr, keep
+
+    # -- entry points --------------------------------------------------------
+    def forward_solve_batch(self, grids, media, theta, receivers, traces,
+                            dev_param=None, dev_step=None, stf="gauss_deriv",
+                            stream=None):
+        """grids: [(nx, nz, h, dt, nsteps)]; media: [(kind, rho, lam, mu)]
+        with device float64 tensors; theta: [n][7]; receivers: [int arrays];
+        traces: [float32 device tensors [nsteps+1][nrec][2]]."""
+        n = len(grids)
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(n, NTHETA)
+        recs, keep = self._receivers(receivers)
+        dp = None if dev_param is None else np.ascontiguousarray(dev_param, dtype=np.int32)
+        ds = None if dev_step is None else np.ascontiguousarray(dev_step, dtype=np.float64)
+        _check(_lib.forward_solve_batch(
+            self._h, n, self._grids(grids), self._media(media), _np_ptr(th),
+            None if dp is None else _np_ptr(dp), None if ds is None else _np_ptr(ds),
+            STF_KINDS[stf], recs, _ptr_array(traces), _stream(stream)))
+        del keep
+
+    def jacobian_fd(self, grids, media, theta, receivers, sigma, H1,
+                    rel_step=1e-4, stf="gauss_deriv", sigma_mode=SIGMA_GIVEN,
+                    per_receiver=False, nominal=None, J=None, status=None,
+                    stream=None):
+        n = len(grids)
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(n, NTHETA)
+        sg = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (n,)))
+        recs, keep = self._receivers(receivers)
+        _check(_lib.jacobian_fd(
+            self._h, n, self._grids(grids), self._media(media), _np_ptr(th),
+            float(rel_step), STF_KINDS[stf], recs, int(sigma_mode), _np_ptr(sg),
+            1 if per_receiver else 0, _ptr_array(nominal), _ptr_array(J), _ptr(H1),
+            _ptr(status), _stream(stream)))
+        del keep
+
+    def laplace_eig(self, H1, prior: Prior, w, dkl, eig, theta=None, logdet=None,
+                    status=None, stream=None):
+        n = int(H1.shape[0])
+        wa = np.ascontiguousarray(w, dtype=np.float64)
+        th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+        _check(_lib.laplace_eig(self._h, n, _ptr(H1), ctypes.byref(prior),
+                                None if th is None else _np_ptr(th), _np_ptr(wa),
+                                _ptr(dkl), _ptr(logdet), _ptr(eig), _ptr(status),
+                                _stream(stream)))
+
+    def design_eval(self, H1r, mask, prior: Prior, w, eig, theta=None, stream=None):
+        ns, nc = int(H1r.shape[0]), int(H1r.shape[1])
+        nd = int(mask.shape[0])
+        wa = np.ascontiguousarray(w, dtype=np.float64)
+        th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+        _check(_lib.design_eval(self._h, ns, nc, _ptr(H1r), nd, _ptr(mask),
+                                ctypes.byref(prior), None if th is None else _np_ptr(th),
+                                _np_ptr(wa), _ptr(eig), _stream(stream)))
+
+    def design_greedy(self, H1r, prior: Prior, w, kmax, order, curve, theta=None,
+                      stream=None):
+        ns, nc = int(H1r.shape[0]), int(H1r.shape[1])
+        wa = np.ascontiguousarray(w, dtype=np.float64)
+        th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+        _check(_lib.design_greedy(self._h, ns, nc, _ptr(H1r), ctypes.byref(prior),
+                                  None if th is None else _np_ptr(th), _np_ptr(wa),
+                                  int(kmax), _ptr(order), _ptr(curve), _stream(stream)))
+
+    def noise_sigma_peak(self, grid, medium, theta, rel=1e-3, stf="gauss_deriv",
+                         stream=None) -> float:
+        out = ctypes.c_double(0.0)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        _check(_lib.noise_sigma_peak(self._h, self._grids([grid]), self._media([medium]),
+                                     _np_ptr(th), STF_KINDS[stf], float(rel),
+                                     ctypes.byref(out), _stream(stream)))
+        return out.value

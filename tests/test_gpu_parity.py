@@ -1,0 +1,262 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Tolerances (stated by the method's precision split: FP32 wavefields, FP64
+Jacobian/Hessian/log-det): receiver traces relative L2 <= 1e-5 per solve,
+Jacobian columns relative L2 <= 1e-3, D^_KL and EIG absolute <= 1e-3 nats.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import elastic, laplace, pipeline as opipe
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TRACE_TOL = 1e-5
+JAC_TOL = 1e-3
+NAT_TOL = 1e-3
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context
+    c = Context(0, 48 << 30)
+    yield c
+    c.close()
+
+
+def _dev_medium(med):
+    from paper_1502_07873_amd.query import device_medium
+    return device_medium(med.kind, med.rho, med.lam, med.mu)
+
+
+def _relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _forward(ctx, grid, medium, thetas, receivers, dev_param=None, dev_step=None,
+             stf="gauss_deriv"):
+    from paper_1502_07873_amd.query import grid_tuple
+    n = len(thetas)
+    g = grid_tuple(grid)
+    dm = _dev_medium(medium)
+    tr = [torch.empty((grid.nsteps + 1, len(receivers), 2), dtype=torch.float32,
+                      device="cuda") for _ in range(n)]
+    ctx.forward_solve_batch([g] * n, [dm] * n, np.asarray(thetas), [receivers] * n, tr,
+                            dev_param=dev_param, dev_step=dev_step, stf=stf)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy().astype(np.float64) for t in tr]
+
+
+def test_forward_traces_c1(ctx):
+    wl = synthetic.config("c1")[0]
+    _say(f"forward c1 {wl.grid}")
+    out = _forward(ctx, wl.grid, wl.medium, wl.theta, wl.receivers)
+    for s, th in enumerate(wl.theta):
+        ref = elastic.forward(wl.grid, wl.medium, th, wl.receivers)
+        assert np.all(out[s][0] == 0)
+        assert _relerr(out[s], ref) <= TRACE_TOL, (s, _relerr(out[s], ref))
+
+
+@pytest.mark.parametrize("case", ["ragged_layered", "ragged_nodal", "gauss_stf"])
+def test_forward_traces_ragged(ctx, case):
+    # grids that are not multiples of the 64x32 tile, receivers on the first
+    # and last free columns, sources at the prior-box margins
+    rng = np.random.default_rng(11)
+    nx, nz, h = 133, 71, 12.0
+    if case == "ragged_nodal":
+        med = synthetic.nodal_perturbed_medium(rng, nz, nx, h, nlayers=3, corr_len=60.0)
+    else:
+        med = synthetic.random_layers_medium(rng, nz, h, 4)
+    grid = synthetic.Grid(nx, nz, h, synthetic.cfl_dt(h, med.vp_max()), 333)
+    lo, hi = synthetic.prior_box(grid)
+    thetas = synthetic.draw_uniform(rng, lo, hi, 5)
+    thetas[0, 0], thetas[0, 1] = lo[0], hi[1]
+    thetas[1, 0], thetas[1, 1] = hi[0] - 1e-9, lo[1]
+    rec = np.array([1, 2, 40, 63, 64, 65, 100, nx - 2], dtype=np.int32)
+    stf = "gauss" if case == "gauss_stf" else "gauss_deriv"
+    if stf == "gauss":
+        thetas[:, 3] = rng.uniform(20, 40, len(thetas))
+    _say(f"forward {case} {grid}")
+    out = _forward(ctx, grid, med, thetas, rec, stf=stf)
+    for s, th in enumerate(thetas):
+        ref = elastic.forward(grid, med, th, rec, stf)
+        assert _relerr(out[s], ref) <= TRACE_TOL, (case, s, _relerr(out[s], ref))
+
+
+def test_deviation_solves_match_literal_differences(ctx):
+    wl = synthetic.config("c1", nsample=2)[0]
+    th = wl.theta[0]
+    d = elastic.fd_steps(th, 1e-4)
+    _say("deviation solves c1")
+    params = np.repeat(np.arange(7), 2).astype(np.int32)
+    steps = np.array([d[j] * s for j in range(7) for s in (1, -1)])
+    out = _forward(ctx, wl.grid, wl.medium, [th] * 14, wl.receivers, params, steps)
+    for q in range(14):
+        j = params[q]
+        tp = th.copy()
+        tp[j] += steps[q]
+        ref = (elastic.forward(wl.grid, wl.medium, tp, wl.receivers)
+               - elastic.forward(wl.grid, wl.medium, th, wl.receivers))
+        assert _relerr(out[q], ref) <= 1e-4, (q, _relerr(out[q], ref))
+
+
+def test_jacobian_hessian_eig_c1(ctx):
+    from paper_1502_07873_amd.query import grid_tuple, run_query
+    wl = synthetic.config("c1")[0]
+    _say("jacobian/H1/eig c1")
+    ref = opipe.query(wl, keep_J=True)
+    out = run_query(ctx, grid_tuple(wl.grid), _dev_medium(wl.medium), wl.receivers,
+                    wl.lo, wl.hi, wl.theta, wl.weights, sigma=ref["sigma"],
+                    keep_nominal=True, keep_J=True)
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().sum()) == 0
+    for s in range(len(wl.theta)):
+        Jg = out["J"][s].cpu().numpy()
+        for j in range(7):
+            e = _relerr(Jg[..., j], ref["J"][s][..., j])
+            assert e <= JAC_TOL, (s, j, e)
+    H = out["H1"].cpu().numpy()
+    relH = np.max(np.abs(H - ref["H1"]) / np.sqrt(np.abs(np.einsum("sii,sjj->sij",
+                                                                   ref["H1"], ref["H1"]))))
+    assert relH < 1e-3
+    dkl = out["dkl"].cpu().numpy()
+    assert np.max(np.abs(dkl - ref["dkl"])) <= NAT_TOL, np.abs(dkl - ref["dkl"])
+    assert abs(float(out["eig"].cpu()[0]) - ref["eig"]) <= NAT_TOL
+
+
+def test_noise_sigma_peak_c1(ctx):
+    from paper_1502_07873_amd.query import grid_tuple
+    wl = synthetic.config("c1")[0]
+    _say("noise sigma c1")
+    s_gpu = ctx.noise_sigma_peak(grid_tuple(wl.grid), _dev_medium(wl.medium), wl.theta_bar)
+    s_ref = elastic.noise_sigma(wl.grid, wl.medium, wl.theta_bar)
+    assert abs(s_gpu - s_ref) <= 1e-5 * s_ref
+
+
+def test_sigma_nominal_peak_mode(ctx):
+    from paper_1502_07873_amd import eigseis
+    from paper_1502_07873_amd.query import grid_tuple
+    wl = synthetic.config("c1", nsample=3)[0]
+    _say("sigma nominal-peak mode")
+    g = grid_tuple(wl.grid)
+    dm = _dev_medium(wl.medium)
+    S = len(wl.theta)
+    H1 = torch.empty((S, 7, 7), dtype=torch.float64, device="cuda")
+    ctx.jacobian_fd([g] * S, [dm] * S, wl.theta, [wl.receivers] * S, 1e-3, H1,
+                    sigma_mode=eigseis.SIGMA_NOMINAL_PEAK)
+    torch.cuda.synchronize()
+    for s in range(S):
+        nominal, J = elastic.jacobian_literal(wl.grid, wl.medium, wl.theta[s], wl.receivers)
+        sig = 1e-3 * np.max(np.abs(nominal))
+        Href = laplace.hessian_h1(J, sig)
+        ld_g = laplace.logdet_scaled(H1[s].cpu().numpy())[0]
+        ld_r = laplace.logdet_scaled(Href)[0]
+        assert abs(ld_g - ld_r) < 2e-3
+
+
+def test_per_receiver_design_eval_and_greedy(ctx):
+    from paper_1502_07873_amd import eigseis, make_prior
+    from paper_1502_07873_amd.query import grid_tuple, run_query
+    wl = synthetic.config("c1", nsample=4)[0]
+    rec = np.array([3, 9, 17, 25, 32, 40, 47, 55, 60], dtype=np.int32)
+    _say("per-receiver H1, design_eval, greedy")
+    # oracle per-receiver Hessians on the candidate set
+    H1r_ref = np.stack([opipe.sample_terms(
+        synthetic.Workload("c1", wl.grid, wl.medium, rec, wl.lo, wl.hi, None, None),
+        th, 0.5, per_receiver=True)[2] for th in wl.theta])
+    out = run_query(ctx, grid_tuple(wl.grid), _dev_medium(wl.medium), rec, wl.lo, wl.hi,
+                    wl.theta, wl.weights, sigma=0.5, per_receiver=True)
+    torch.cuda.synchronize()
+    H1r = out["H1"]
+    Hg = H1r.cpu().numpy()
+    scale = np.sqrt(np.abs(np.einsum("scii,scjj->scij", H1r_ref, H1r_ref)))
+    assert np.max(np.abs(Hg - H1r_ref) / scale) < 1e-3
+    prior = laplace.uniform_prior(wl.lo, wl.hi)
+    rng = np.random.default_rng(5)
+    masks = (rng.random((6, len(rec))) < 0.5).astype(np.uint8)
+    masks[0] = 1
+    masks[1] = 0
+    masks[1, 4] = 1
+    eig_ref = laplace.design_eval(H1r_ref, masks, wl.theta, wl.weights, prior)
+    eig_g = torch.empty(len(masks), dtype=torch.float64, device="cuda")
+    ctx.design_eval(H1r, torch.as_tensor(masks, device="cuda"), make_prior(wl.lo, wl.hi),
+                    wl.weights, eig_g, theta=wl.theta)
+    torch.cuda.synchronize()
+    eg = eig_g.cpu().numpy()
+    ok = ~np.isnan(eig_ref)
+    assert np.array_equal(ok, ~np.isnan(eg))
+    assert np.max(np.abs(eg[ok] - eig_ref[ok])) <= NAT_TOL
+    order_ref, curve_ref = laplace.greedy(H1r_ref, wl.theta, wl.weights, prior, 5)
+    order = torch.empty(5, dtype=torch.int32, device="cuda")
+    curve = torch.empty(5, dtype=torch.float64, device="cuda")
+    ctx.design_greedy(H1r, make_prior(wl.lo, wl.hi), wl.weights, 5, order, curve,
+                      theta=wl.theta)
+    torch.cuda.synchronize()
+    og, cg = order.cpu().numpy(), curve.cpu().numpy()
+    k = len(order_ref)
+    assert np.max(np.abs(cg[:k] - curve_ref)) <= NAT_TOL
+    # the chosen sequence must agree unless two candidates tie within tolerance
+    assert list(og[:k]) == list(order_ref) or np.max(np.abs(np.diff(curve_ref))) < 1e-6
+    del eigseis
+
+
+def test_alone_equals_in_batch(ctx):
+    from paper_1502_07873_amd.query import grid_tuple, run_query
+    wl = synthetic.config("c1", nsample=6)[0]
+    _say("alone vs batch")
+    g = grid_tuple(wl.grid)
+    dm = _dev_medium(wl.medium)
+    full = run_query(ctx, g, dm, wl.receivers, wl.lo, wl.hi, wl.theta, wl.weights, sigma=0.7)
+    one = run_query(ctx, g, dm, wl.receivers, wl.lo, wl.hi, wl.theta[3:4], [1.0], sigma=0.7)
+    torch.cuda.synchronize()
+    assert torch.equal(full["H1"][3], one["H1"][0])
+    assert float(full["dkl"][3]) == float(one["dkl"][0])
+
+
+def test_edge_cases(ctx):
+    from paper_1502_07873_amd import EigError
+    from paper_1502_07873_amd.query import grid_tuple
+    wl = synthetic.config("c1", nsample=1, grid_override=(40, 40, 0))[0]
+    _say("edge cases")
+    # zero steps: a single recorded level, all zero
+    out = _forward(ctx, wl.grid, wl.medium, wl.theta, wl.receivers)
+    assert out[0].shape == (1, len(wl.receivers), 2) and np.all(out[0] == 0)
+    g1 = synthetic.Grid(40, 40, wl.grid.h, wl.grid.dt, 1)
+    out = _forward(ctx, g1, wl.medium, wl.theta, wl.receivers)
+    ref = elastic.forward(g1, wl.medium, wl.theta[0], wl.receivers)
+    assert np.allclose(out[0], ref, rtol=1e-5, atol=0)
+    dm = _dev_medium(wl.medium)
+    g = grid_tuple(g1)
+    tr = [torch.empty((2, 2, 2), dtype=torch.float32, device="cuda")]
+    bad = wl.theta.copy()
+    bad[0, 0] = wl.grid.h * 2.5     # stencil reaches the rigid left edge
+    with pytest.raises(EigError):
+        ctx.forward_solve_batch([g], [dm], bad, [np.array([3, 5], np.int32)], tr)
+    with pytest.raises(EigError):   # repeated receiver
+        ctx.forward_solve_batch([g], [dm], wl.theta, [np.array([3, 3], np.int32)], tr)
+    with pytest.raises(EigError):   # receiver on the rigid corner
+        ctx.forward_solve_batch([g], [dm], wl.theta, [np.array([0, 5], np.int32)], tr)
+    H1 = torch.empty((1, 7, 7), dtype=torch.float64, device="cuda")
+    th0 = wl.theta.copy()
+    th0[0, 5] = 0.0                 # zero parameter: relative FD step undefined
+    with pytest.raises(EigError):
+        ctx.jacobian_fd([g], [dm], th0, [wl.receivers], 1.0, H1)
+    # a singular Hessian is flagged, not factored
+    from paper_1502_07873_amd import make_prior
+    Hs = torch.zeros((2, 7, 7), dtype=torch.float64, device="cuda")
+    Hs[0] = torch.eye(7, dtype=torch.float64)
+    dkl = torch.empty(2, dtype=torch.float64, device="cuda")
+    eig = torch.empty(1, dtype=torch.float64, device="cuda")
+    st = torch.empty(2, dtype=torch.int32, device="cuda")
+    ctx.laplace_eig(Hs, make_prior(wl.lo, wl.hi), [0.5, 0.5], dkl, eig, status=st)
+    torch.cuda.synchronize()
+    assert st.cpu().tolist() == [0, -4]
+    assert np.isnan(float(eig.cpu()[0]))
