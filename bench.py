@@ -185,6 +185,26 @@ def main():
                      "traffic": _measured_traffic(S)},
         "wall_s": wall,
     }
+    # the plain GPU path: the same kernels, one solve per launch
+    print("[bench] one-solve-per-launch GPU baseline (2 samples)", flush=True)
+    ctx1 = Context(0, 8 << 30)
+    ctx1.set_option("max_wave_solves", 1)
+    sig1 = ctx1.noise_sigma_peak(g, med, theta_bar, wl.noise_rel)
+    run_query(ctx1, g, med, wl.receivers, wl.lo, wl.hi, wl.theta[:1], [1.0], sigma=sig1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sig1 = ctx1.noise_sigma_peak(g, med, theta_bar, wl.noise_rel)
+    o1 = run_query(ctx1, g, med, wl.receivers, wl.lo, wl.hi, wl.theta[:2], [0.5, 0.5],
+                   sigma=sig1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = e0.elapsed_time(e1) / 1e3
+    line["baseline_one_solve_per_launch"] = {
+        "value": 2 / t1, "unit": "sample-EIG evals/s", "samples": 2,
+        "speedup_of_batched": value / (2 / t1),
+        "dkl_match": bool(np.allclose(o1["dkl"].cpu().numpy(), dkl[:2], rtol=0, atol=0))}
+    ctx1.close()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, 1 sample)", flush=True)
         cb, err = _cpu_baseline(wl, wl.theta[0], dkl[0])

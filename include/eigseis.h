@@ -127,6 +127,20 @@ size_t eig_ctx_workspace_bytes(const eig_ctx* ctx);
 int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* launches,
                           double* updates, double* bytes);
 
+/* Context options (take effect for later calls):
+ *   "stencil_variant"  -1: choose automatically (default), else force one of
+ *                      the stencil kernel variants (all give bitwise-identical
+ *                      fields; they differ in tile shape and speed)
+ *   "autotune"         1 (default): time the variants on the first steps of a
+ *                      new grid class and keep the fastest; 0: use
+ *                      "default_variant"
+ *   "default_variant"  variant used before/without tuning
+ *   "max_wave_solves"  0 (default): every solve of a wave advances in the same
+ *                      launches; n > 0: at most n solves per launch (n = 1 is
+ *                      the plain one-solve-at-a-time path)
+ * EIG_EINVAL for an unknown name or value. */
+int eig_ctx_set_option(eig_ctx* ctx, const char* name, int64_t value);
+
 /*
  * forward_solve_batch — the parameter-to-observable map g_r(t_m; theta)
  * (Section 2.2, forward model; Section 3.3.1, full-discrete scheme) for
@@ -250,6 +264,43 @@ int noise_sigma_peak(eig_ctx* ctx, const eig_grid* grid, const eig_medium* mediu
  */
 int sparse_grid_gl(int32_t dim, int32_t level, const double* lo, const double* hi,
                    int32_t capacity, double* nodes, double* weights, int32_t* count);
+
+/*
+ * Serving engine (continuous batching).  A server owns an HBM arena of
+ * `budget` bytes.  Submitted queries run the work of jacobian_fd (one H_1
+ * per sample, per_receiver = 0) followed by laplace_eig; their samples are
+ * admitted in groups of `group_samples` whenever arena memory and descriptor
+ * slots are free, and every stencil launch advances all admitted solves of
+ * all queries by one step, so later queries overlap earlier ones on the
+ * device.  Per-sample arithmetic is independent of the batch: a query's
+ * outputs are identical whether it runs alone or in a mix.
+ */
+typedef struct eig_server eig_server;
+int eig_server_create(eig_ctx* ctx, size_t budget, int32_t group_samples,
+                      eig_server** out);
+void eig_server_destroy(eig_server* srv);
+/* Queue a query (host inputs are copied; device outputs are caller-owned and
+ * must stay valid until eig_server_poll reports it done):
+ *   H1 device [nsample][7][7], dkl device [nsample], eig device [1],
+ *   status device [nsample] or NULL (0 / EIG_ENONFINITE),
+ *   chol_status device [nsample] or NULL (0 / EIG_ENOTPD).
+ * sigma_mode/sigma as for jacobian_fd (one value for all samples).
+ * EIG_EBUDGET if a single sample cannot fit the arena; *id receives a handle. */
+int eig_server_submit(eig_server* srv, const eig_grid* grid, const eig_medium* medium,
+                      int32_t nsample, const double* theta, double rel_step,
+                      int32_t stf_kind, const eig_receivers* rec, int32_t sigma_mode,
+                      double sigma, const eig_prior* prior, const double* w, double* H1,
+                      double* dkl, double* eig, int32_t* status, int32_t* chol_status,
+                      int64_t* id);
+/* Enqueue up to max_launches stencil launches on `stream`, retiring finished
+ * groups (Hessian kernels, then laplace for completed queries) and admitting
+ * waiting ones at segment boundaries.  *running = admitted groups left. */
+int eig_server_step(eig_server* srv, int32_t max_launches, void* stream, int32_t* running);
+/* *done = 1 once query `id`'s outputs are complete on the device (the handle
+ * is then released). */
+int eig_server_poll(eig_server* srv, int64_t id, int32_t* done);
+/* Queries still waiting for admission of samples, and admitted groups. */
+int eig_server_pending(eig_server* srv, int32_t* queued, int32_t* running);
 
 #ifdef __cplusplus
 }

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -36,185 +37,54 @@ int set_error(int code, const std::string& msg) {
 
 using namespace eig;
 
-#define HIP_TRY(expr)                                                                 \
-    do {                                                                              \
-        hipError_t e_ = (expr);                                                       \
-        if (e_ != hipSuccess)                                                         \
-            return set_error(EIG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+#include "host.h"
 
 namespace {
 
-constexpr int kStageRing = 4;
-constexpr size_t kAlign = 256;
+int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
+              const std::vector<eig_grid>& grids, const std::vector<MediumKey>& media,
+              const std::vector<RecSet>& recsets, char* base, size_t cap, hipStream_t s);
 
-size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
-
-}  // namespace
-
-struct eig_ctx {
-    int device = 0;
-    size_t budget = 0;
-    char* ws = nullptr;      // device workspace
-    size_t ws_size = 0;
-    void* stage[kStageRing] = {};  // pinned staging blobs
-    size_t stage_size[kStageRing] = {};
-    hipEvent_t stage_ev[kStageRing] = {};
-    bool stage_used[kStageRing] = {};
-    int stage_next = 0;
-    // stencil timing: event pairs per wave, launch / update / byte counters
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> timing;
-    int64_t launches = 0;
-    double updates = 0.0, bytes = 0.0;
-    double resolved_ms = 0.0;
-};
-
-namespace {
-
-// Make the device workspace at least `bytes` large (never above budget).
-int ensure_ws(eig_ctx* c, size_t bytes) {
-    if (bytes <= c->ws_size) return EIG_OK;
-    if (bytes > c->budget)
-        return set_error(EIG_EBUDGET, "request needs " + std::to_string(bytes) +
-                                          " bytes of device workspace, budget is " +
-                                          std::to_string(c->budget));
-    if (c->ws) {
-        HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipFree(c->ws));
-        c->ws = nullptr;
-        c->ws_size = 0;
+// All solves of a wave advance together; with max_wave_solves set, they run
+// in consecutive chunks of at most that many solves instead (the chunks
+// reuse the same workspace in stream order).
+int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
+             const std::vector<eig_grid>& grids, const std::vector<MediumKey>& media,
+             const std::vector<RecSet>& recsets, char* base, size_t cap, hipStream_t s) {
+    const size_t per = c->max_wave_solves > 0 ? (size_t)c->max_wave_solves : solves.size();
+    for (size_t i0 = 0; i0 < solves.size(); i0 += per) {
+        std::vector<SolveSpec> part(solves.begin() + i0,
+                                    solves.begin() + std::min(solves.size(), i0 + per));
+        const int rc = run_chunk(c, part, grids, media, recsets, base, cap, s);
+        if (rc) return rc;
     }
-    size_t want = std::min(c->budget, std::max(bytes, bytes + bytes / 4));
-    if (hipMalloc((void**)&c->ws, want) != hipSuccess) {
-        (void)hipGetLastError();
-        if (hipMalloc((void**)&c->ws, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            c->ws = nullptr;
-            return set_error(EIG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-        }
-        want = bytes;
-    }
-    c->ws_size = want;
     return EIG_OK;
 }
 
-// Upload a host blob into device memory `dst` through a pinned staging
-// buffer; a staging buffer is reused only after its previous copy finished.
-int upload(eig_ctx* c, void* dst, const std::vector<char>& blob, hipStream_t s) {
-    if (blob.empty()) return EIG_OK;
-    const int r = c->stage_next;
-    c->stage_next = (r + 1) % kStageRing;
-    if (c->stage_used[r]) HIP_TRY(hipEventSynchronize(c->stage_ev[r]));
-    if (c->stage_size[r] < blob.size()) {
-        if (c->stage[r]) HIP_TRY(hipHostFree(c->stage[r]));
-        c->stage[r] = nullptr;
-        c->stage_size[r] = 0;
-        const size_t sz = align_up(blob.size(), 1 << 20);
-        HIP_TRY(hipHostMalloc(&c->stage[r], sz, hipHostMallocDefault));
-        c->stage_size[r] = sz;
+size_t tiles_of(const eig_grid& g, const StencilVariant& v) {
+    return (size_t)((g.nx + v.cols - 1) / v.cols) * ((g.nz - 1 + v.rows - 1) / v.rows);
+}
+
+// Variants a wave may run for a medium kind: the forced one, else all of
+// that kind (tuned online per grid class).
+void stencil_candidates(const eig_ctx* c, int kind, std::vector<int>& out) {
+    out.clear();
+    if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == kind) {
+        out.push_back(c->forced_variant);
+        return;
     }
-    std::memcpy(c->stage[r], blob.data(), blob.size());
-    HIP_TRY(hipMemcpyAsync(dst, c->stage[r], blob.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(c->stage_ev[r], s));
-    c->stage_used[r] = true;
-    return EIG_OK;
-}
-
-// Host-side image of a device region: record (offset, bytes) pieces first,
-// fill them, then place the blob at a device base address.
-struct Blob {
-    std::vector<char> data;
-    size_t put(const void* p, size_t bytes) {
-        const size_t off = align_up(data.size());
-        data.resize(off + bytes);
-        if (bytes) std::memcpy(data.data() + off, p, bytes);
-        return off;
+    for (int v = 0; v < kNumVariants; ++v)
+        if (kVariants[v].medium_kind == kind) out.push_back(v);
+    if (!c->autotune) {
+        int keep = out[0];
+        for (int v : out)
+            if (v == c->default_variant) keep = v;
+        out.assign(1, keep);
     }
-};
-
-// Device workspace carving for one wave.
-struct Carve {
-    size_t off = 0;
-    size_t take(size_t bytes) {
-        const size_t o = align_up(off);
-        off = o + bytes;
-        return o;
-    }
-};
-
-int floor_cell(double x, double h) { return (int)std::floor(x / h); }
-
-bool valid_grid(const eig_grid& g) {
-    return g.nx >= 8 && g.nz >= 8 && g.nx <= 65536 && g.nz <= 65536 && g.h > 0 &&
-           g.dt > 0 && std::isfinite(g.h) && std::isfinite(g.dt) && g.nsteps >= 0 &&
-           g.nsteps < (1 << 28);
-}
-
-// Source stencil rows/columns kx-2..kx+3 must stay on free nodes.
-bool source_inside(double x, double z, const eig_grid& g) {
-    if (!std::isfinite(x) || !std::isfinite(z)) return false;
-    const int kx = floor_cell(x, g.h), kz = floor_cell(z, g.h);
-    return kx - 2 >= 1 && kx + 3 <= g.nx - 2 && kz - 2 >= 0 && kz + 3 <= g.nz - 2;
-}
-
-int pitch_of(int nx) { return (nx + kTileW - 1) / kTileW * kTileW; }
-
-struct SolveSpec {
-    int grid;      // index into caller's grid array
-    int medium;    // index into the deduplicated media
-    int recset;    // index into the receiver sets
-    double theta[kNT];
-    int param;     // -1 nominal
-    double step;
-    int stf;
-    float2* traces;  // destination (device)
-};
-
-struct MediumKey {
-    int kind;
-    const double *rho, *lam, *mu;
-    int nx, nz;
-    double h, dt;
-    bool operator<(const MediumKey& o) const {
-        return std::tie(kind, rho, lam, mu, nx, nz, h, dt) <
-               std::tie(o.kind, o.rho, o.lam, o.mu, o.nx, o.nz, o.h, o.dt);
-    }
-};
-
-struct RecSet {
-    std::vector<int32_t> ix;
-    int nx;
-};
-
-int check_receivers(const eig_receivers& r, const eig_grid& g) {
-    if (r.n < 0 || (r.n > 0 && !r.ix))
-        return set_error(EIG_EINVAL, "receivers: n < 0 or ix NULL");
-    std::vector<int32_t> v(r.ix, r.ix + r.n);
-    for (int32_t x : v)
-        if (x < 1 || x > g.nx - 2)
-            return set_error(EIG_EINVAL, "receiver index outside the free surface 1..nx-2");
-    std::sort(v.begin(), v.end());
-    if (std::adjacent_find(v.begin(), v.end()) != v.end())
-        return set_error(EIG_EINVAL, "receivers must be distinct");
-    return EIG_OK;
-}
-
-// Device bytes for one solve (fields + forcing tables), excluding traces.
-size_t solve_bytes(const eig_grid& g) {
-    const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
-    return align_up(field) * 2 + align_up(2 * kSrcW * kSrcW * sizeof(float)) +
-           align_up((size_t)std::max(g.nsteps, 1) * sizeof(float)) + 4 * kAlign;
-}
-
-size_t medium_bytes(const MediumKey& k) {
-    if (k.kind == EIG_MEDIUM_NODAL)
-        return align_up((size_t)3 * k.nz * pitch_of(k.nx) * sizeof(float)) + kAlign;
-    return align_up((size_t)k.nz * kCoefStride * sizeof(float)) + kAlign;
 }
 
 // Run a set of solves that fits the workspace region [base, base+cap).
-// `extra_off` bytes at the start of the region are reserved by the caller.
-int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
+int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
              const std::vector<eig_grid>& grids, const std::vector<MediumKey>& media,
              const std::vector<RecSet>& recsets, char* base, size_t cap,
              hipStream_t s) {
@@ -257,15 +127,21 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
         if (ka != kb) return ka < kb;
         return grids[solves[a].grid].nsteps > grids[solves[b].grid].nsteps;
     });
-    // the staging blob (receiver maps, descriptors, tile map, forcing jobs)
+    // stencil variants this wave may use, per medium kind
+    std::vector<int> cand_layered, cand_nodal;
+    stencil_candidates(c, EIG_MEDIUM_LAYERED, cand_layered);
+    stencil_candidates(c, EIG_MEDIUM_NODAL, cand_nodal);
+    // the staging blob (receiver maps, descriptors, tile maps, forcing jobs)
     // gets its device place first so descriptors can point into it
     size_t ntiles_total = 0;
     for (int i = 0; i < n; ++i) {
         const eig_grid& g = grids[solves[i].grid];
-        ntiles_total += (size_t)(pitch_of(g.nx) / kTileW) * ((g.nz - 1 + kTileRows - 1) / kTileRows);
+        const auto& cand = media[solves[i].medium].kind == EIG_MEDIUM_NODAL ? cand_nodal
+                                                                            : cand_layered;
+        for (int v : cand) ntiles_total += tiles_of(g, kVariants[v]);
     }
     size_t blob_bound = align_up((size_t)n * sizeof(SolveDesc)) +
-                        align_up(ntiles_total * sizeof(int32_t)) +
+                        align_up(ntiles_total * sizeof(int2)) + 16 * kAlign +
                         align_up((size_t)n * sizeof(SourceJob)) + 4 * kAlign;
     for (int r : rec_used) blob_bound += align_up((size_t)pitch_of(recsets[r].nx) * sizeof(int32_t));
     const size_t blob_dev = cv.take(blob_bound);
@@ -278,11 +154,17 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
         for (size_t q = 0; q < recsets[r].ix.size(); ++q) map[recsets[r].ix[q]] = (int32_t)q;
         o_rec[r] = blob.put(map.data(), map.size() * sizeof(int32_t));
     }
-    // descriptors and tiles
+    // descriptors, and per medium kind a group of solves with one tile map
+    // per candidate variant
     std::vector<SolveDesc> desc(n);
-    std::vector<int32_t> tiles;
     std::vector<SourceJob> jobs(n);
-    struct Group { int kind; int first_tile; std::vector<std::pair<int, int>> steps_tiles; };
+    struct Group {
+        int kind;
+        int first, last;               // solve range in launch order
+        std::vector<int> cand;         // candidate variants
+        std::vector<std::vector<int2>> tiles;                     // per candidate
+        std::vector<std::vector<std::pair<int, int>>> steps_tiles;  // per candidate
+    };
     std::vector<Group> groups;
     for (int oi = 0; oi < n; ++oi) {
         const int i = ord[oi];
@@ -303,8 +185,6 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
         d.nsteps = g.nsteps;
         d.start = 0;
         d.nrec = (int32_t)recsets[sp.recset].ix.size();
-        d.nstrip = d.pitch / kTileW;
-        d.nchunk = (g.nz - 1 + kTileRows - 1) / kTileRows;
         d.medium_kind = mk.kind;
         d.h2 = (float)(g.h * g.h);
         // forcing window: union of the nominal and perturbed 6x6 stencils
@@ -332,15 +212,32 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
         J.srcs = (float*)(base + ss[i]);
         d.src_i0 = J.i0;
         d.src_k0 = J.k0;
-        if (groups.empty() || groups.back().kind != mk.kind)
-            groups.push_back(Group{mk.kind, (int)tiles.size(), {}});
-        d.tile0 = (int)tiles.size() - groups.back().first_tile;
-        const int nt = d.nstrip * d.nchunk;
-        for (int t = 0; t < nt; ++t) tiles.push_back(oi);
-        groups.back().steps_tiles.push_back({g.nsteps, (int)tiles.size() - groups.back().first_tile});
+        if (groups.empty() || groups.back().kind != mk.kind) {
+            Group gr;
+            gr.kind = mk.kind;
+            gr.first = oi;
+            gr.cand = mk.kind == EIG_MEDIUM_NODAL ? cand_nodal : cand_layered;
+            gr.tiles.resize(gr.cand.size());
+            gr.steps_tiles.resize(gr.cand.size());
+            groups.push_back(gr);
+        }
+        Group& gr = groups.back();
+        gr.last = oi + 1;
+        for (size_t v = 0; v < gr.cand.size(); ++v) {
+            const StencilVariant& sv = kVariants[gr.cand[v]];
+            const int nstrip = (g.nx + sv.cols - 1) / sv.cols;
+            const int nchunk = (g.nz - 1 + sv.rows - 1) / sv.rows;
+            for (int ch = 0; ch < nchunk; ++ch)
+                for (int st = 0; st < nstrip; ++st)
+                    gr.tiles[v].push_back(make_int2(oi, (st << 16) | ch));
+            gr.steps_tiles[v].push_back({g.nsteps, (int)gr.tiles[v].size()});
+        }
     }
     const size_t o_desc = blob.put(desc.data(), desc.size() * sizeof(SolveDesc));
-    const size_t o_tile = blob.put(tiles.data(), tiles.size() * sizeof(int32_t));
+    std::vector<std::vector<size_t>> o_tiles(groups.size());
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+        for (auto& tv : groups[gi].tiles)
+            o_tiles[gi].push_back(blob.put(tv.data(), tv.size() * sizeof(int2)));
     const size_t o_jobs = blob.put(jobs.data(), jobs.size() * sizeof(SourceJob));
     if (blob.data.size() > blob_bound) return set_error(EIG_EBUDGET, "descriptor blob overflow");
     int rc = upload(c, bd, blob.data, s);
@@ -361,17 +258,41 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
     launch_zero_level0(ddesc, n, s);  // traces at t_0 (zero initial state)
     HIP_TRY(hipGetLastError());
     // time loop
-    const int32_t* dtile = (const int32_t*)(bd + o_tile);
     int max_steps = 0;
     for (const auto& g : groups)
-        for (const auto& st : g.steps_tiles) max_steps = std::max(max_steps, st.first);
-    // per group and solve: grid-point updates per step, in launch order
-    std::vector<std::vector<double>> upd_per_solve(groups.size());
-    {
-        int oi = 0;
-        for (size_t gi = 0; gi < groups.size(); ++gi)
-            for (size_t q = 0; q < groups[gi].steps_tiles.size(); ++q, ++oi)
-                upd_per_solve[gi].push_back((double)desc[oi].nx * desc[oi].nz);
+        for (const auto& st : g.steps_tiles[0]) max_steps = std::max(max_steps, st.first);
+    // per group: variant in use, and an online tuning window if this grid
+    // class has not been tuned yet (the tuning launches are real steps)
+    struct Tune {
+        bool active = false;
+        int begin = 0, reps = 2;
+        std::vector<hipEvent_t> ev;  // 2 per tuning launch
+        std::tuple<int, int, int> key;
+    };
+    std::vector<int> use(groups.size(), 0);
+    std::vector<Tune> tune(groups.size());
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        Group& g = groups[gi];
+        const SolveDesc& d0 = desc[g.first];
+        tune[gi].key = std::make_tuple(g.kind, d0.nx, d0.nz);
+        use[gi] = 0;
+        if (g.cand.size() > 1) {
+            auto it = c->tuned.find(tune[gi].key);
+            if (it != c->tuned.end()) {
+                for (size_t v = 0; v < g.cand.size(); ++v)
+                    if (g.cand[v] == it->second) use[gi] = (int)v;
+            } else {
+                const int need = 1 + (int)g.cand.size() * tune[gi].reps;
+                for (size_t v = 0; v < g.cand.size(); ++v)
+                    if (g.cand[v] == c->default_variant) use[gi] = (int)v;
+                if (max_steps >= need) {
+                    tune[gi].active = true;
+                    tune[gi].begin = 1;
+                    tune[gi].ev.resize(2 * g.cand.size() * tune[gi].reps);
+                    for (auto& e : tune[gi].ev) HIP_TRY(hipEventCreate(&e));
+                }
+            }
+        }
     }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (max_steps > 0) {
@@ -381,24 +302,54 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
     }
     for (int step = 0; step < max_steps; ++step) {
         for (size_t gi = 0; gi < groups.size(); ++gi) {
-            const auto& g = groups[gi];
+            Group& g = groups[gi];
+            Tune& tn = tune[gi];
+            int vi = use[gi];
+            int slot = -1;
+            const int ncand = (int)g.cand.size();
+            if (tn.active && step >= tn.begin && step < tn.begin + ncand * tn.reps) {
+                slot = step - tn.begin;
+                vi = slot % ncand;
+            }
             // running solves form a prefix (steps descending within a group)
             int ntile = 0;
             double upd = 0.0;
-            for (size_t q = 0; q < g.steps_tiles.size(); ++q) {
-                const auto& st = g.steps_tiles[q];
-                if (st.first > step) {
-                    ntile = st.second;
-                    upd += upd_per_solve[gi][q];
+            const auto& stv = g.steps_tiles[vi];
+            for (size_t q = 0; q < stv.size(); ++q) {
+                if (stv[q].first > step) {
+                    ntile = stv[q].second;
+                    const SolveDesc& dq = desc[g.first + q];
+                    upd += (double)dq.nx * dq.nz;
                 } else {
                     break;
                 }
             }
             if (ntile > 0) {
-                launch_stencil(ddesc, dtile + g.first_tile, ntile, step, g.kind, s);
+                if (slot >= 0) HIP_TRY(hipEventRecord(tn.ev[2 * slot], s));
+                launch_stencil(ddesc, (const int2*)(bd + o_tiles[gi][vi]), ntile, step,
+                               g.cand[vi], s);
+                if (slot >= 0) HIP_TRY(hipEventRecord(tn.ev[2 * slot + 1], s));
                 c->launches += 1;
                 c->updates += upd;
                 c->bytes += upd * (g.kind == EIG_MEDIUM_NODAL ? 36.0 : 24.0);
+            }
+            if (slot == ncand * tn.reps - 1) {
+                // end of the tuning window: pick the fastest variant
+                HIP_TRY(hipEventSynchronize(tn.ev.back()));
+                std::vector<double> tot(ncand, 0.0);
+                for (int q = 0; q < ncand * tn.reps; ++q) {
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, tn.ev[2 * q], tn.ev[2 * q + 1]));
+                    tot[q % ncand] += ms;
+                }
+                int best = 0;
+                for (int v = 1; v < ncand; ++v)
+                    if (tot[v] < tot[best]) best = v;
+                use[gi] = best;
+                c->tuned[tn.key] = g.cand[best];
+                for (auto& e : tn.ev) (void)hipEventDestroy(e);
+                tn.ev.clear();
+                tn.active = false;
             }
         }
     }
@@ -406,6 +357,8 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
         HIP_TRY(hipEventRecord(ev1, s));
         c->timing.push_back({ev0, ev1});
     }
+    for (auto& tn : tune)
+        for (auto& e : tn.ev) (void)hipEventDestroy(e);
     HIP_TRY(hipGetLastError());
     return EIG_OK;
 }
@@ -423,7 +376,7 @@ struct WaveSizer {
     size_t cost(const SolveSpec& sp) const {
         const eig_grid& g = grids[sp.grid];
         size_t b = solve_bytes(g) + sizeof(SolveDesc) + sizeof(SourceJob) + 64;
-        b += (size_t)((g.nz - 1 + kTileRows - 1) / kTileRows) * (pitch_of(g.nx) / kTileW) * 4;
+        for (int v = 0; v < kNumVariants; ++v) b += tiles_of(g, kVariants[v]) * sizeof(int2);
         if (!med_seen[sp.medium]) b += medium_bytes(media[sp.medium]);
         if (!rec_seen[sp.recset]) b += 2 * align_up((size_t)pitch_of(recsets[sp.recset].nx) * 4);
         return b;
@@ -469,6 +422,11 @@ int eig_ctx_create(int device, size_t hbm_budget_bytes, eig_ctx** out) {
     eig_ctx* c = new eig_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes;
+    if (const char* e = std::getenv("EIG_STENCIL_VARIANT")) {
+        const int v = std::atoi(e);
+        if (v >= 0 && v < kNumVariants) c->forced_variant = v;
+    }
+    if (const char* e = std::getenv("EIG_AUTOTUNE")) c->autotune = std::atoi(e) != 0;
     for (int r = 0; r < kStageRing; ++r) {
         if (hipEventCreateWithFlags(&c->stage_ev[r], hipEventDisableTiming) != hipSuccess) {
             delete c;
@@ -496,6 +454,27 @@ void eig_ctx_destroy(eig_ctx* c) {
 }
 
 size_t eig_ctx_workspace_bytes(const eig_ctx* c) { return c ? c->ws_size : 0; }
+
+int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
+    if (!c || !name) return set_error(EIG_EINVAL, "ctx or name is NULL");
+    const std::string n(name);
+    if (n == "stencil_variant") {
+        if (value < -1 || value >= kNumVariants) return set_error(EIG_EINVAL, "variant");
+        c->forced_variant = (int)value;
+    } else if (n == "autotune") {
+        c->autotune = value != 0;
+        if (!c->autotune) c->tuned.clear();
+    } else if (n == "default_variant") {
+        if (value < 0 || value >= kNumVariants) return set_error(EIG_EINVAL, "variant");
+        c->default_variant = (int)value;
+    } else if (n == "max_wave_solves") {
+        if (value < 0) return set_error(EIG_EINVAL, "max_wave_solves < 0");
+        c->max_wave_solves = value;
+    } else {
+        return set_error(EIG_EINVAL, "unknown option " + n);
+    }
+    return EIG_OK;
+}
 
 int eig_ctx_stencil_stats(eig_ctx* c, int32_t reset, double* ms, int64_t* launches,
                           double* updates, double* bytes) {

@@ -11,9 +11,8 @@
 namespace eig {
 
 constexpr int kNT = EIG_NTHETA;  // seven source parameters
-constexpr int kTileW = 64;       // columns per wave tile (one wavefront)
-constexpr int kTileRows = 32;    // rows a wave streams through
 constexpr int kWavesPerBlock = 4;
+constexpr int kPitchAlign = 128; // row pitch (nodes) is a multiple of the widest tile
 constexpr int kSrcW = 7;         // source window: union of two 6x6 stencils
 constexpr int kCoefStride = 16;  // floats per row of a layered coefficient table
 
@@ -51,8 +50,6 @@ struct SolveDesc {
     int32_t start;           // launch index at which this solve takes step 0
     int32_t nrec;
     int32_t src_i0, src_k0;  // window corner (column, row)
-    int32_t nstrip, nchunk;  // tiles: nstrip across x, nchunk down the depth
-    int32_t tile0;           // first tile index of this solve
     int32_t medium_kind;     // EIG_MEDIUM_*
     float h2;                // h^2 (nodal media scale the body force by s h^2)
 };
@@ -90,8 +87,17 @@ void launch_nodal_coef(const double* rho, const double* lam, const double* mu,
                        hipStream_t s);
 void launch_source_tables(const SourceJob* jobs, int njobs, int max_nsteps,
                           hipStream_t s);
-void launch_stencil(const SolveDesc* descs, const int32_t* tile_solve,
-                    int ntiles, int step, int medium_kind, hipStream_t s);
+// Stencil kernel variants: tile geometry (columns x rows per wavefront) and
+// the medium kind they serve.  All variants of a medium kind produce
+// bitwise-identical results; they differ only in speed.
+struct StencilVariant {
+    int cols, rows, medium_kind;
+};
+constexpr int kNumVariants = 7;
+extern const StencilVariant kVariants[kNumVariants];
+// tiles: (solve index, strip << 16 | chunk) per wavefront
+void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
+                    int variant, hipStream_t s);
 void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s);
 void launch_sample_check(const SampleDesc* samples, int nsample, const double* given,
                          int mode, double* sigma, int32_t* status, hipStream_t s);

@@ -68,6 +68,19 @@ __device__ __forceinline__ void st2(float2* p, size_t i, float2 v) {
     w.y = v.y;
     ((GAS fv2*)p)[i] = w;
 }
+typedef float fv4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld4(const float2* p, size_t i) {  // i even
+    const fv4 v = *(const GAS fv4*)((const GAS fv2*)p + i);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4(float2* p, size_t i, float4 v) {  // i even
+    fv4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *(GAS fv4*)((GAS fv2*)p + i) = w;
+}
 __device__ __forceinline__ float ld1(const float* p, size_t i) {
     return ((const GAS float*)p)[i];
 }
@@ -75,8 +88,86 @@ __device__ __forceinline__ int ldi(const int32_t* p, size_t i) {
     return ((const GAS int32_t*)p)[i];
 }
 
-// u^m at column i of row k, and the halo column for the two edge lanes
-// (zero elsewhere).  Every lane loads a valid address.
+// One row of u^m seen from one node: centre values and the sum and
+// difference of the x-neighbours.
+struct NodeRow {
+    float u, v;      // centre
+    float dxu, dxv;  // w_{i+1} - w_{i-1}
+    float sxu, sxv;  // w_{i+1} + w_{i-1}
+};
+
+__device__ __forceinline__ NodeRow node_row(float u, float v, float lu, float lv,
+                                            float ru, float rv) {
+    NodeRow r;
+    r.u = u;
+    r.v = v;
+    r.dxu = ru - lu;
+    r.dxv = rv - lv;
+    r.sxu = ru + lu;
+    r.sxv = rv + lv;
+    return r;
+}
+
+struct LayerCoef {
+    float c[kFco + 1];
+};
+
+// Row k of a depth-only coefficient table (wave-uniform: scalar loads).
+__device__ __forceinline__ LayerCoef load_coef(const float* coef, int k) {
+    LayerCoef r;
+    const size_t cb = (size_t)k * kCoefStride;
+#pragma unroll
+    for (int j = 0; j <= kFco; ++j) r.c[j] = ld1(coef, cb + j);
+    return r;
+}
+
+// u^{m+1} at one node of a depth-only medium.  Every stencil variant calls
+// this, so all of them produce bitwise-identical fields.
+__device__ __forceinline__ float2 layered_update(const LayerCoef& c, const NodeRow& rm,
+                                                 const NodeRow& rc, const NodeRow& rn,
+                                                 float upu, float upv, bool src, float fsv,
+                                                 float wu, float wv) {
+    float au = c.c[kCxxU] * (rc.sxu - 2.f * rc.u) + c.c[kCzpU] * (rn.u - rc.u)
+             - c.c[kCzmU] * (rc.u - rm.u) + c.c[kCmpU] * rn.dxv
+             - c.c[kCmmU] * rm.dxv + c.c[kCm0U] * rc.dxv;
+    float av = c.c[kCxxV] * (rc.sxv - 2.f * rc.v) + c.c[kCzpV] * (rn.v - rc.v)
+             - c.c[kCzmV] * (rc.v - rm.v) + c.c[kCmpV] * rn.dxu
+             - c.c[kCmmV] * rm.dxu + c.c[kCm0V] * rc.dxu;
+    if (src) {
+        au += fsv * wu;
+        av += fsv * wv;
+    }
+    float2 nw;
+    nw.x = rc.u + ((rc.u - upu) + au);
+    nw.y = rc.v + ((rc.v - upv) + av);
+    return nw;
+}
+
+// Wave-uniform tile decode: tile entry = (solve, strip << 16 | chunk).
+struct TileInfo {
+    const SolveDesc* d;
+    int m, x0, kb, ke;
+};
+
+__device__ __forceinline__ bool decode_tile(const SolveDesc* descs, const int2* tiles,
+                                            int ntiles, int step, int cols, int rows,
+                                            TileInfo& t) {
+    const int tile = __builtin_amdgcn_readfirstlane(
+        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
+    if (tile >= ntiles) return false;
+    const int2 te = tiles[tile];
+    const int sidx = __builtin_amdgcn_readfirstlane(te.x);
+    const int sc = __builtin_amdgcn_readfirstlane(te.y);
+    t.d = descs + sidx;
+    t.m = step - t.d->start;
+    if (t.m < 0 || t.m >= t.d->nsteps) return false;
+    t.x0 = (sc >> 16) * cols;
+    t.kb = (sc & 0xffff) * rows;
+    t.ke = min(t.kb + rows, t.d->nz - 1);  // rows [kb, ke) are free rows
+    return true;
+}
+
+// Variant 0: one node per lane (64 columns per wave), one row of prefetch.
 __device__ __forceinline__ void load_row(const float2* Q, size_t off, int i,
                                          int hc, bool hl, float2& c, float2& h) {
     c = ld2(Q, off + i);
@@ -85,64 +176,41 @@ __device__ __forceinline__ void load_row(const float2* Q, size_t off, int i,
     h.y = hl ? hv.y : 0.f;
 }
 
-struct RowU {
-    float u, v;     // centre
-    float dxu, dxv; // u_{i+1} - u_{i-1}
-    float sxu, sxv; // u_{i+1} + u_{i-1}
-};
-
-__device__ __forceinline__ RowU make_row(float2 c, float2 h) {
-    RowU r;
-    const float lu = from_left(c.x, h.x), ru = from_right(c.x, h.x);
-    const float lv = from_left(c.y, h.y), rv = from_right(c.y, h.y);
-    r.u = c.x; r.v = c.y;
-    r.dxu = ru - lu; r.dxv = rv - lv;
-    r.sxu = ru + lu; r.sxv = rv + lv;
-    return r;
+__device__ __forceinline__ NodeRow make_row(float2 c, float2 h) {
+    return node_row(c.x, c.y, from_left(c.x, h.x), from_left(c.y, h.y),
+                    from_right(c.x, h.x), from_right(c.y, h.y));
 }
 
 __global__ void __launch_bounds__(256)
-stencil_layered(const SolveDesc* __restrict__ descs,
-                const int32_t* __restrict__ tile_solve, int ntiles, int step) {
+stencil_layered_w1(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
+                   int ntiles, int step) {
+    TileInfo t;
+    if (!decode_tile(descs, tiles, ntiles, step, 64, 32, t)) return;
+    const SolveDesc* d = t.d;
     const int lane = threadIdx.x & 63;
-    const int tile = __builtin_amdgcn_readfirstlane(
-        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
-    if (tile >= ntiles) return;
-    const SolveDesc* d = descs + __builtin_amdgcn_readfirstlane(tile_solve[tile]);
-    const int m = step - d->start;
-    if (m < 0 || m >= d->nsteps) return;
+    const int m = t.m, x0 = t.x0, kb = t.kb, ke = t.ke;
     const int nx = d->nx, nz = d->nz, pitch = d->pitch;
-    const int local = tile - d->tile0;
-    const int strip = local % d->nstrip;
-    const int chunk = local / d->nstrip;
-    const int x0 = strip * kTileW;
     const int i = x0 + lane;
-    const int kb = chunk * kTileRows;
-    const int ke = min(kb + kTileRows, nz - 1);  // rows [kb, ke) are free rows
     const float2* Q = (m & 1) ? d->buf1 : d->buf0;  // u^m
     float2* P = (m & 1) ? d->buf0 : d->buf1;        // u^{m-1} -> u^{m+1}
     const float* coef = d->coef;
-
     const bool upd = (i >= 1) && (i <= nx - 2);
-    const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + kTileW < nx);
-    const int hc = (lane == 0) ? x0 - 1 : x0 + kTileW;
-
-    // source window (wave-uniform test per row)
+    const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + 64 < nx);
+    const int hc = (lane == 0) ? x0 - 1 : x0 + 64;
     const int si0 = d->src_i0, sk0 = d->src_k0;
-    const bool src_cols = (si0 < x0 + kTileW) && (si0 + kSrcW > x0);
+    const bool src_cols = (si0 < x0 + 64) && (si0 + kSrcW > x0);
     const int di = i - si0;
     const bool src_lane = src_cols && di >= 0 && di < kSrcW;
     const float sval = src_cols ? ld1(d->srcs, m) : 0.0f;
     const float* srcw = d->srcw;
     float2* traces = d->traces;
     const int nrec = d->nrec;
-
     int rec = -1;
     if (kb == 0) rec = ldi(d->recmap, i);
 
-    RowU rm, rc, rn;
+    NodeRow rm, rc, rn;
     if (kb == 0) {
-        rm = RowU{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        rm = NodeRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     } else {
         float2 c, h;
         load_row(Q, (size_t)(kb - 1) * pitch, i, hc, hl, c, h);
@@ -155,30 +223,20 @@ stencil_layered(const SolveDesc* __restrict__ descs,
     rc = make_row(cc, ch);
 
     for (int k = kb; k < ke; ++k) {
-        // prefetch the row after next and the next u^{m-1}
         float2 cnn = make_float2(0.f, 0.f), chnn = cnn, upn = cnn;
         if (k + 2 <= nz - 1) load_row(Q, (size_t)(k + 2) * pitch, i, hc, hl, cnn, chnn);
         if (k + 1 < ke) upn = ld2(P, (size_t)(k + 1) * pitch + i);
         rn = make_row(cn, chn);
-
-        const size_t cb = (size_t)k * kCoefStride;
-        float au = ld1(coef, cb + kCxxU) * (rc.sxu - 2.f * rc.u)
-                 + ld1(coef, cb + kCzpU) * (rn.u - rc.u)
-                 - ld1(coef, cb + kCzmU) * (rc.u - rm.u) + ld1(coef, cb + kCmpU) * rn.dxv
-                 - ld1(coef, cb + kCmmU) * rm.dxv + ld1(coef, cb + kCm0U) * rc.dxv;
-        float av = ld1(coef, cb + kCxxV) * (rc.sxv - 2.f * rc.v)
-                 + ld1(coef, cb + kCzpV) * (rn.v - rc.v)
-                 - ld1(coef, cb + kCzmV) * (rc.v - rm.v) + ld1(coef, cb + kCmpV) * rn.dxu
-                 - ld1(coef, cb + kCmmV) * rm.dxu + ld1(coef, cb + kCm0V) * rc.dxu;
+        const LayerCoef cf = load_coef(coef, k);
         const int dk = k - sk0;
-        if (src_lane && dk >= 0 && dk < kSrcW) {
-            const float f = ld1(coef, cb + kFco) * sval;
-            au += f * ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
-            av += f * ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
+        const bool src = src_lane && dk >= 0 && dk < kSrcW;
+        float wu = 0.f, wv = 0.f;
+        if (src) {
+            wu = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
+            wv = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
         }
-        float2 nw;
-        nw.x = rc.u + ((rc.u - up.x) + au);
-        nw.y = rc.v + ((rc.v - up.y) + av);
+        const float2 nw = layered_update(cf, rm, rc, rn, up.x, up.y, src, cf.c[kFco] * sval,
+                                         wu, wv);
         if (upd) {
             st2(P, (size_t)k * pitch + i, nw);
             if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
@@ -191,6 +249,133 @@ stencil_layered(const SolveDesc* __restrict__ descs,
     }
 }
 
+// Variants 1..: two nodes per lane (128 columns per wave) with 16-byte loads,
+// R rows per wave and D rows of prefetch.  Lane l owns columns x0+2l and
+// x0+2l+1; the left neighbour of the first and the right neighbour of the
+// second come from the adjacent lanes (DPP), lanes 0 and 63 load the halo.
+struct Raw2 {
+    float4 c;  // (u, v) of the two columns
+    float2 h;  // halo column (edge lanes only)
+};
+
+__device__ __forceinline__ Raw2 load_raw2(const float2* Q, size_t off, int i0, int hc,
+                                          bool hl) {
+    Raw2 r;
+    r.c = ld4(Q, off + i0);
+    r.h = make_float2(0.f, 0.f);
+    if (hl) r.h = ld2(Q, off + hc);
+    return r;
+}
+
+__device__ __forceinline__ void make_rows2(const Raw2& r, NodeRow& a, NodeRow& b) {
+    const float lu = from_left(r.c.z, r.h.x), lv = from_left(r.c.w, r.h.y);
+    const float ru = from_right(r.c.x, r.h.x), rv = from_right(r.c.y, r.h.y);
+    a = node_row(r.c.x, r.c.y, lu, lv, r.c.z, r.c.w);
+    b = node_row(r.c.z, r.c.w, r.c.x, r.c.y, ru, rv);
+}
+
+template <int R, int D>
+__global__ void __launch_bounds__(256)
+stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
+                   int ntiles, int step) {
+    TileInfo t;
+    if (!decode_tile(descs, tiles, ntiles, step, 128, R, t)) return;
+    const SolveDesc* d = t.d;
+    const int lane = threadIdx.x & 63;
+    const int m = t.m, x0 = t.x0, kb = t.kb, ke = t.ke;
+    const int nx = d->nx, nz = d->nz, pitch = d->pitch;
+    const int i0 = x0 + 2 * lane;
+    const float2* Q = (m & 1) ? d->buf1 : d->buf0;
+    float2* P = (m & 1) ? d->buf0 : d->buf1;
+    const float* coef = d->coef;
+    const bool upd0 = (i0 >= 1) && (i0 <= nx - 2);
+    const bool upd1 = (i0 + 1 <= nx - 2);
+    const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + 128 < nx);
+    const int hc = (lane == 0) ? x0 - 1 : x0 + 128;
+    const int si0 = d->src_i0, sk0 = d->src_k0;
+    const bool src_cols = (si0 < x0 + 128) && (si0 + kSrcW > x0);
+    const int di0 = i0 - si0, di1 = di0 + 1;
+    const bool s0 = src_cols && di0 >= 0 && di0 < kSrcW;
+    const bool s1 = src_cols && di1 >= 0 && di1 < kSrcW;
+    const float sval = src_cols ? ld1(d->srcs, m) : 0.0f;
+    const float* srcw = d->srcw;
+    float2* traces = d->traces;
+    const int nrec = d->nrec;
+    int rec0 = -1, rec1 = -1;
+    if (kb == 0) {
+        rec0 = ldi(d->recmap, i0);
+        rec1 = ldi(d->recmap, i0 + 1);
+    }
+
+    NodeRow am, bm, ac, bc, an, bn;
+    if (kb == 0) {
+        am = bm = NodeRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    } else {
+        make_rows2(load_raw2(Q, (size_t)(kb - 1) * pitch, i0, hc, hl), am, bm);
+    }
+    make_rows2(load_raw2(Q, (size_t)kb * pitch, i0, hc, hl), ac, bc);
+    // prefetch ring: raw rows k+1..k+D of u^m, rows k..k+D-1 of u^{m-1}
+    Raw2 q1, q2;
+    float4 p0, p1;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    q1 = load_raw2(Q, (size_t)(kb + 1) * pitch, i0, hc, hl);
+    p0 = ld4(P, (size_t)kb * pitch + i0);
+    if (D == 2) {
+        q2.c = z4;
+        q2.h = make_float2(0.f, 0.f);
+        if (kb + 2 <= nz - 1) q2 = load_raw2(Q, (size_t)(kb + 2) * pitch, i0, hc, hl);
+        p1 = z4;
+        if (kb + 1 < ke) p1 = ld4(P, (size_t)(kb + 1) * pitch + i0);
+    }
+
+    for (int k = kb; k < ke; ++k) {
+        Raw2 qn;
+        qn.c = z4;
+        qn.h = make_float2(0.f, 0.f);
+        float4 pn = z4;
+        if (k + 1 + D <= nz - 1) qn = load_raw2(Q, (size_t)(k + 1 + D) * pitch, i0, hc, hl);
+        if (k + D < ke) pn = ld4(P, (size_t)(k + D) * pitch + i0);
+        make_rows2(q1, an, bn);
+        const LayerCoef cf = load_coef(coef, k);
+        const float fsv = cf.c[kFco] * sval;
+        const int dk = k - sk0;
+        const bool row_src = dk >= 0 && dk < kSrcW;
+        const bool sa = s0 && row_src, sb = s1 && row_src;
+        float wua = 0.f, wva = 0.f, wub = 0.f, wvb = 0.f;
+        if (sa) {
+            wua = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di0);
+            wva = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di0);
+        }
+        if (sb) {
+            wub = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di1);
+            wvb = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di1);
+        }
+        const float2 na = layered_update(cf, am, ac, an, p0.x, p0.y, sa, fsv, wua, wva);
+        const float2 nb = layered_update(cf, bm, bc, bn, p0.z, p0.w, sb, fsv, wub, wvb);
+        // rigid and padding columns keep their zeros
+        const float4 o = make_float4(upd0 ? na.x : 0.f, upd0 ? na.y : 0.f,
+                                     upd1 ? nb.x : 0.f, upd1 ? nb.y : 0.f);
+        st4(P, (size_t)k * pitch + i0, o);
+        if (k == 0) {
+            if (rec0 >= 0) st2(traces, (size_t)(m + 1) * nrec + rec0, na);
+            if (rec1 >= 0) st2(traces, (size_t)(m + 1) * nrec + rec1, nb);
+        }
+        am = ac;
+        bm = bc;
+        ac = an;
+        bc = bn;
+        if (D == 2) {
+            q1 = q2;
+            q2 = qn;
+            p0 = p1;
+            p1 = pn;
+        } else {
+            q1 = qn;
+            p0 = pn;
+        }
+    }
+}
+
 // Nodal media: coef = three planes (lambda, mu, s = dt^2/(rho h^2)).
 struct RowN {
     float u, v, hu, hv;   // centre and halo-column values of u^m
@@ -199,23 +384,15 @@ struct RowN {
 };
 
 __global__ void __launch_bounds__(256)
-stencil_nodal(const SolveDesc* __restrict__ descs,
-              const int32_t* __restrict__ tile_solve, int ntiles, int step) {
+stencil_nodal(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
+              int ntiles, int step) {
+    TileInfo t;
+    if (!decode_tile(descs, tiles, ntiles, step, 64, 32, t)) return;
+    const SolveDesc* d = t.d;
     const int lane = threadIdx.x & 63;
-    const int tile = __builtin_amdgcn_readfirstlane(
-        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
-    if (tile >= ntiles) return;
-    const SolveDesc* d = descs + __builtin_amdgcn_readfirstlane(tile_solve[tile]);
-    const int m = step - d->start;
-    if (m < 0 || m >= d->nsteps) return;
+    const int m = t.m, x0 = t.x0, kb = t.kb, ke = t.ke;
     const int nx = d->nx, nz = d->nz, pitch = d->pitch;
-    const int local = tile - d->tile0;
-    const int strip = local % d->nstrip;
-    const int chunk = local / d->nstrip;
-    const int x0 = strip * kTileW;
     const int i = x0 + lane;
-    const int kb = chunk * kTileRows;
-    const int ke = min(kb + kTileRows, nz - 1);
     const float2* Q = (m & 1) ? d->buf1 : d->buf0;
     float2* P = (m & 1) ? d->buf0 : d->buf1;
     const size_t plane = (size_t)nz * pitch;
@@ -224,11 +401,11 @@ stencil_nodal(const SolveDesc* __restrict__ descs,
     const float* SC = LAM + 2 * plane;
 
     const bool upd = (i >= 1) && (i <= nx - 2);
-    const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + kTileW < nx);
-    const int hc = (lane == 0) ? x0 - 1 : x0 + kTileW;
+    const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + 64 < nx);
+    const int hc = (lane == 0) ? x0 - 1 : x0 + 64;
 
     const int si0 = d->src_i0, sk0 = d->src_k0;
-    const bool src_cols = (si0 < x0 + kTileW) && (si0 + kSrcW > x0);
+    const bool src_cols = (si0 < x0 + 64) && (si0 + kSrcW > x0);
     const int di = i - si0;
     const bool src_lane = src_cols && di >= 0 && di < kSrcW;
     const float sval = src_cols ? ld1(d->srcs, m) : 0.0f;
@@ -369,14 +546,30 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
         (uint4*)p, n16, (uint8_t*)p + n16 * 16, ntail);
 }
 
-void launch_stencil(const SolveDesc* descs, const int32_t* tile_solve, int ntiles,
-                    int step, int medium_kind, hipStream_t s) {
+const StencilVariant kVariants[kNumVariants] = {
+    {64, 32, EIG_MEDIUM_LAYERED},   // 0: one node per lane
+    {128, 32, EIG_MEDIUM_LAYERED},  // 1: two nodes per lane, prefetch 1
+    {128, 32, EIG_MEDIUM_LAYERED},  // 2: two nodes per lane, prefetch 2
+    {128, 64, EIG_MEDIUM_LAYERED},  // 3
+    {128, 16, EIG_MEDIUM_LAYERED},  // 4
+    {128, 64, EIG_MEDIUM_LAYERED},  // 5: prefetch 1
+    {64, 32, EIG_MEDIUM_NODAL},     // 6: nodal media
+};
+
+void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
+                    int variant, hipStream_t s) {
     if (ntiles <= 0) return;
     const int blocks = (ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (medium_kind == EIG_MEDIUM_NODAL)
-        stencil_nodal<<<blocks, 64 * kWavesPerBlock, 0, s>>>(descs, tile_solve, ntiles, step);
-    else
-        stencil_layered<<<blocks, 64 * kWavesPerBlock, 0, s>>>(descs, tile_solve, ntiles, step);
+    const int threads = 64 * kWavesPerBlock;
+    switch (variant) {
+        case 0: stencil_layered_w1<<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 1: stencil_layered_w2<32, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 2: stencil_layered_w2<32, 2><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 3: stencil_layered_w2<64, 2><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 4: stencil_layered_w2<16, 2><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 5: stencil_layered_w2<64, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        default: stencil_nodal<<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+    }
 }
 
 }  // namespace eig

@@ -75,6 +75,7 @@ def _load():
         "eig_last_error": ([], ctypes.c_char_p),
         "eig_ctx_workspace_bytes": ([vp], ctypes.c_size_t),
         "eig_ctx_stencil_stats": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
+        "eig_ctx_set_option": ([vp, ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
         "forward_solve_batch": ([vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "jacobian_fd": ([vp, i32, vp, vp, vp, dbl, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp],
                         ctypes.c_int),
@@ -83,6 +84,13 @@ def _load():
         "design_greedy": ([vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "noise_sigma_peak": ([vp, vp, vp, vp, i32, dbl, vp, vp], ctypes.c_int),
         "sparse_grid_gl": ([i32, i32, vp, vp, i32, vp, vp, vp], ctypes.c_int),
+        "eig_server_create": ([vp, ctypes.c_size_t, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "eig_server_destroy": ([vp], None),
+        "eig_server_submit": ([vp, vp, vp, i32, vp, dbl, i32, vp, i32, dbl, vp, vp, vp, vp, vp,
+                               vp, vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "eig_server_step": ([vp, i32, vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "eig_server_poll": ([vp, ctypes.c_int64, ctypes.POINTER(i32)], ctypes.c_int),
+        "eig_server_pending": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -93,9 +101,11 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("eig_ctx_create", "eig_ctx_destroy", "eig_last_error", "eig_ctx_workspace_bytes",
-            "eig_ctx_stencil_stats",
+            "eig_ctx_stencil_stats", "eig_ctx_set_option",
             "forward_solve_batch", "jacobian_fd", "laplace_eig", "design_eval",
-            "design_greedy", "noise_sigma_peak", "sparse_grid_gl")
+            "design_greedy", "noise_sigma_peak", "sparse_grid_gl", "eig_server_create",
+            "eig_server_destroy", "eig_server_submit", "eig_server_step", "eig_server_poll",
+            "eig_server_pending")
 
 
 def _check(rc: int):
@@ -192,6 +202,9 @@ class Context:
     @property
     def workspace_bytes(self) -> int:
         return _lib.eig_ctx_workspace_bytes(self._h)
+
+    def set_option(self, name: str, value: int):
+        _check(_lib.eig_ctx_set_option(self._h, name.encode(), int(value)))
 
     def stencil_stats(self, reset: bool = False) -> dict:
         """Device time (ms) from first to last stencil launch of each wave,
@@ -298,3 +311,56 @@ class Context:
                                      _np_ptr(th), STF_KINDS[stf], float(rel),
                                      ctypes.byref(out), _stream(stream)))
         return out.value
+
+
+class Server:
+    """Continuous-batching serving engine (eig_server_*) on a Context."""
+
+    def __init__(self, ctx: "Context", budget_bytes: int, group_samples: int = 16):
+        h = ctypes.c_void_p()
+        _check(_lib.eig_server_create(ctx._h, budget_bytes, group_samples, ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.eig_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, grid, medium, theta, receivers, prior: Prior, w, H1, dkl, eig,
+               sigma, sigma_mode=SIGMA_GIVEN, rel_step=1e-4, stf="gauss_deriv",
+               status=None, chol_status=None) -> int:
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        n = th.shape[0]
+        wa = np.ascontiguousarray(w, dtype=np.float64)
+        recs, keep = Context._receivers([receivers])
+        qid = ctypes.c_int64()
+        _check(_lib.eig_server_submit(
+            self._h, Context._grids([grid]), Context._media([medium]), n, _np_ptr(th),
+            float(rel_step), STF_KINDS[stf], recs, int(sigma_mode), float(sigma),
+            ctypes.byref(prior), _np_ptr(wa), _ptr(H1), _ptr(dkl), _ptr(eig), _ptr(status),
+            _ptr(chol_status), ctypes.byref(qid)))
+        del keep
+        return qid.value
+
+    def step(self, max_launches: int, stream=None) -> int:
+        running = ctypes.c_int32()
+        _check(_lib.eig_server_step(self._h, int(max_launches), _stream(stream),
+                                    ctypes.byref(running)))
+        return running.value
+
+    def poll(self, qid: int) -> bool:
+        done = ctypes.c_int32()
+        _check(_lib.eig_server_poll(self._h, int(qid), ctypes.byref(done)))
+        return bool(done.value)
+
+    def pending(self):
+        q, r = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.eig_server_pending(self._h, ctypes.byref(q), ctypes.byref(r)))
+        return q.value, r.value

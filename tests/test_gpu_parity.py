@@ -260,3 +260,81 @@ def test_edge_cases(ctx):
     torch.cuda.synchronize()
     assert st.cpu().tolist() == [0, -4]
     assert np.isnan(float(eig.cpu()[0]))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+def test_stencil_variants_bitwise_identical(variant, monkeypatch):
+    # every layered-medium stencil variant computes the same arithmetic per
+    # node, so the traces must agree bit for bit (and with the oracle)
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context
+    rng = np.random.default_rng(21)
+    nx, nz, h = 201, 83, 10.0
+    med = synthetic.random_layers_medium(rng, nz, h, 4)
+    grid = synthetic.Grid(nx, nz, h, synthetic.cfl_dt(h, med.vp_max()), 150)
+    lo, hi = synthetic.prior_box(grid)
+    thetas = synthetic.draw_uniform(rng, lo, hi, 3)
+    rec = np.array([1, 50, 63, 64, 127, 128, 129, nx - 2], dtype=np.int32)
+    _say(f"stencil variant {variant}")
+    outs = {}
+    for v in (0, variant):
+        monkeypatch.setenv("EIG_STENCIL_VARIANT", str(v))
+        c = Context(0, 4 << 30)
+        outs[v] = _forward(c, grid, med, thetas, rec)
+        c.close()
+    for s in range(len(thetas)):
+        assert np.array_equal(outs[0][s], outs[variant][s]), s
+        ref = elastic.forward(grid, med, thetas[s], rec)
+        assert _relerr(outs[variant][s], ref) <= TRACE_TOL
+
+
+def test_server_alone_equals_mix_and_matches_jacobian_path(ctx):
+    from paper_1502_07873_amd import eigseis, make_prior
+    from paper_1502_07873_amd.query import grid_tuple, run_query
+    _say("serving engine: alone vs mix")
+    wlA = synthetic.config("c1", nsample=5)[0]
+    rng = np.random.default_rng(3)
+    medB = synthetic.random_layers_medium(rng, 70, 15.0, 3)
+    gB = synthetic.Grid(90, 70, 15.0, synthetic.cfl_dt(15.0, medB.vp_max()), 260)
+    loB, hiB = synthetic.prior_box(gB)
+    thB = synthetic.draw_uniform(rng, loB, hiB, 7)
+    recB = synthetic.random_receivers(rng, 90, 11)
+    dA, dB = _dev_medium(wlA.medium), _dev_medium(medB)
+
+    def run(queries, stagger):
+        srv = eigseis.Server(ctx, 2 << 30, group_samples=2)
+        outs = []
+        for k, (g, med, th, rec, lo, hi) in enumerate(queries):
+            S = len(th)
+            o = {"H1": torch.empty((S, 7, 7), dtype=torch.float64, device="cuda"),
+                 "dkl": torch.empty(S, dtype=torch.float64, device="cuda"),
+                 "eig": torch.empty(1, dtype=torch.float64, device="cuda")}
+            o["id"] = srv.submit(grid_tuple(g), med, th, rec, make_prior(lo, hi),
+                                 np.full(S, 1.0 / S), o["H1"], o["dkl"], o["eig"], 0.9)
+            outs.append(o)
+            srv.step(stagger)      # later queries join while earlier ones run
+        left = list(outs)
+        for _ in range(100000):
+            if not left:
+                break
+            srv.step(64)
+            torch.cuda.synchronize()
+            left = [o for o in left if not srv.poll(o["id"])]
+        assert not left
+        srv.close()
+        return outs
+
+    qA = (wlA.grid, dA, wlA.theta, wlA.receivers, wlA.lo, wlA.hi)
+    qB = (gB, dB, thB, recB, loB, hiB)
+    alone = run([qA], 0)
+    mix = run([qB, qA, qB], 37)
+    assert torch.equal(alone[0]["H1"], mix[1]["H1"])
+    assert torch.equal(alone[0]["dkl"], mix[1]["dkl"])
+    assert torch.equal(alone[0]["eig"], mix[1]["eig"])
+    assert torch.equal(mix[0]["H1"], mix[2]["H1"])
+    ref = run_query(ctx, grid_tuple(wlA.grid), dA, wlA.receivers, wlA.lo, wlA.hi, wlA.theta,
+                    np.full(5, 0.2), sigma=0.9)
+    torch.cuda.synchronize()
+    assert torch.equal(ref["H1"], alone[0]["H1"])
+    assert torch.equal(ref["dkl"], alone[0]["dkl"])
