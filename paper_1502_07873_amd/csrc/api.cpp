@@ -73,12 +73,16 @@ void stencil_candidates(const eig_ctx* c, int kind, std::vector<int>& out) {
         out.push_back(c->forced_variant);
         return;
     }
-    for (int v = 0; v < kNumVariants; ++v)
-        if (kVariants[v].medium_kind == kind) out.push_back(v);
+    // one family per wave: two steps per launch (four field buffers) or one
+    const int steps = (kind == EIG_MEDIUM_LAYERED && c->temporal_blocking) ? 2 : 1;
+    for (int v = 1; v < kNumVariants; ++v)
+        if (kVariants[v].medium_kind == kind && kVariants[v].steps == steps) out.push_back(v);
+    if (out.empty()) out.push_back(kind == EIG_MEDIUM_NODAL ? 6 : 0);
     if (!c->autotune) {
+        const int want = steps == 2 ? c->default_variant_tb : c->default_variant;
         int keep = out[0];
         for (int v : out)
-            if (v == c->default_variant) keep = v;
+            if (v == want) keep = v;
         out.assign(1, keep);
     }
 }
@@ -103,8 +107,16 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     rec_used.erase(std::unique(rec_used.begin(), rec_used.end()), rec_used.end());
     std::map<int, size_t> med_off;
     for (int m : med_used) med_off[m] = cv.take(medium_bytes(media[m]));
-    // fields: one contiguous block for all solves (cleared with one launch)
-    std::vector<size_t> f0(n), f1(n), sw(n), ss(n);
+    // stencil variants this wave may use, per medium kind
+    std::vector<int> cand_layered, cand_nodal;
+    stencil_candidates(c, EIG_MEDIUM_LAYERED, cand_layered);
+    stencil_candidates(c, EIG_MEDIUM_NODAL, cand_nodal);
+    auto family_steps = [&](int kind) {
+        return kVariants[(kind == EIG_MEDIUM_NODAL ? cand_nodal : cand_layered)[0]].steps;
+    };
+    // fields: one contiguous block for all solves (cleared with one launch);
+    // two-steps-per-launch kernels rotate over four buffers per solve
+    std::vector<size_t> f0(n), f1(n), f2(n, 0), f3(n, 0), sw(n), ss(n);
     const size_t fields_begin = align_up(cv.off);
     cv.off = fields_begin;
     for (int i = 0; i < n; ++i) {
@@ -112,6 +124,10 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
         f0[i] = cv.take(field);
         f1[i] = cv.take(field);
+        if (family_steps(media[solves[i].medium].kind) == 2) {
+            f2[i] = cv.take(field);
+            f3[i] = cv.take(field);
+        }
     }
     const size_t fields_end = cv.off;
     for (int i = 0; i < n; ++i) {
@@ -127,10 +143,6 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         if (ka != kb) return ka < kb;
         return grids[solves[a].grid].nsteps > grids[solves[b].grid].nsteps;
     });
-    // stencil variants this wave may use, per medium kind
-    std::vector<int> cand_layered, cand_nodal;
-    stencil_candidates(c, EIG_MEDIUM_LAYERED, cand_layered);
-    stencil_candidates(c, EIG_MEDIUM_NODAL, cand_nodal);
     // the staging blob (receiver maps, descriptors, tile maps, forcing jobs)
     // gets its device place first so descriptors can point into it
     size_t ntiles_total = 0;
@@ -174,6 +186,8 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         SolveDesc& d = desc[oi];
         d.buf0 = (float2*)(base + f0[i]);
         d.buf1 = (float2*)(base + f1[i]);
+        d.buf2 = f2[i] ? (float2*)(base + f2[i]) : nullptr;
+        d.buf3 = f3[i] ? (float2*)(base + f3[i]) : nullptr;
         d.coef = (const float*)(base + med_off[sp.medium]);
         d.srcw = (const float*)(base + sw[i]);
         d.srcs = (const float*)(base + ss[i]);
@@ -258,33 +272,39 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     launch_zero_level0(ddesc, n, s);  // traces at t_0 (zero initial state)
     HIP_TRY(hipGetLastError());
     // time loop
+    // launches: ceil(steps / steps-per-launch) per group
     int max_steps = 0;
-    for (const auto& g : groups)
-        for (const auto& st : g.steps_tiles[0]) max_steps = std::max(max_steps, st.first);
+    for (const auto& g : groups) {
+        const int spl = kVariants[g.cand[0]].steps;
+        for (const auto& st : g.steps_tiles[0])
+            max_steps = std::max(max_steps, (st.first + spl - 1) / spl);
+    }
     // per group: variant in use, and an online tuning window if this grid
     // class has not been tuned yet (the tuning launches are real steps)
     struct Tune {
         bool active = false;
         int begin = 0, reps = 2;
         std::vector<hipEvent_t> ev;  // 2 per tuning launch
-        std::tuple<int, int, int> key;
+        std::tuple<int, int, int, int> key;
     };
     std::vector<int> use(groups.size(), 0);
     std::vector<Tune> tune(groups.size());
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         Group& g = groups[gi];
         const SolveDesc& d0 = desc[g.first];
-        tune[gi].key = std::make_tuple(g.kind, d0.nx, d0.nz);
+        tune[gi].key = std::make_tuple(g.kind, d0.nx, d0.nz, kVariants[g.cand[0]].steps);
         use[gi] = 0;
         if (g.cand.size() > 1) {
             auto it = c->tuned.find(tune[gi].key);
-            if (it != c->tuned.end()) {
+            if (it != c->tuned.end() &&
+                std::find(g.cand.begin(), g.cand.end(), it->second) != g.cand.end()) {
                 for (size_t v = 0; v < g.cand.size(); ++v)
                     if (g.cand[v] == it->second) use[gi] = (int)v;
             } else {
                 const int need = 1 + (int)g.cand.size() * tune[gi].reps;
                 for (size_t v = 0; v < g.cand.size(); ++v)
-                    if (g.cand[v] == c->default_variant) use[gi] = (int)v;
+                    if (g.cand[v] == c->default_variant || g.cand[v] == c->default_variant_tb)
+                        use[gi] = (int)v;
                 if (max_steps >= need) {
                     tune[gi].active = true;
                     tune[gi].begin = 1;
@@ -312,14 +332,15 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
                 vi = slot % ncand;
             }
             // running solves form a prefix (steps descending within a group)
+            const int spl = kVariants[g.cand[vi]].steps;
             int ntile = 0;
             double upd = 0.0;
             const auto& stv = g.steps_tiles[vi];
             for (size_t q = 0; q < stv.size(); ++q) {
-                if (stv[q].first > step) {
+                if (stv[q].first > step * spl) {
                     ntile = stv[q].second;
                     const SolveDesc& dq = desc[g.first + q];
-                    upd += (double)dq.nx * dq.nz;
+                    upd += (double)dq.nx * dq.nz * std::min(spl, stv[q].first - step * spl);
                 } else {
                     break;
                 }
@@ -467,6 +488,8 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
     } else if (n == "default_variant") {
         if (value < 0 || value >= kNumVariants) return set_error(EIG_EINVAL, "variant");
         c->default_variant = (int)value;
+    } else if (n == "temporal_blocking") {
+        c->temporal_blocking = value != 0;
     } else if (n == "max_wave_solves") {
         if (value < 0) return set_error(EIG_EINVAL, "max_wave_solves < 0");
         c->max_wave_solves = value;

@@ -56,9 +56,11 @@ struct eig_ctx {
     // stencil variant selection: forced (EIG_STENCIL_VARIANT), or tuned
     // online per (medium kind, nx, nz) and cached here
     int forced_variant = -1;
-    int default_variant = 2;
+    int default_variant = 4;      // one step per launch
+    int default_variant_tb = 9;   // two steps per launch
+    bool temporal_blocking = true;
     bool autotune = true;
-    std::map<std::tuple<int, int, int>, int> tuned;
+    std::map<std::tuple<int, int, int, int>, int> tuned;
     int64_t max_wave_solves = 0;  // 0: no limit (all solves of a wave per launch)
 };
 
@@ -195,7 +197,7 @@ inline int check_receivers(const eig_receivers& r, const eig_grid& g) {
 // Device bytes for one solve (fields + forcing tables), excluding traces.
 inline size_t solve_bytes(const eig_grid& g) {
     const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
-    return align_up(field) * 2 + align_up(2 * kSrcW * kSrcW * sizeof(float)) +
+    return align_up(field) * 4 + align_up(2 * kSrcW * kSrcW * sizeof(float)) +
            align_up((size_t)std::max(g.nsteps, 1) * sizeof(float)) + 4 * kAlign;
 }
 

@@ -41,6 +41,8 @@ enum CoefSlot {
 struct SolveDesc {
     float2* buf0;            // u at even levels (and u^{-1}) ...
     float2* buf1;            // ... and odd levels; [nz][pitch] (x, depth)
+    float2* buf2;            // two-steps-per-launch kernels rotate over four
+    float2* buf3;            // buffers: level l in buffer (l + 1) mod 4
     const float* coef;       // layered: [nz][kCoefStride]; nodal: [3][nz][pitch]
     const float* srcw;       // [2][kSrcW][kSrcW] forcing window
     const float* srcs;       // [nsteps] forcing time series
@@ -92,8 +94,9 @@ void launch_source_tables(const SourceJob* jobs, int njobs, int max_nsteps,
 // bitwise-identical results; they differ only in speed.
 struct StencilVariant {
     int cols, rows, medium_kind;
+    int steps;  // leapfrog steps per launch (2: four field buffers per solve)
 };
-constexpr int kNumVariants = 7;
+constexpr int kNumVariants = 12;
 extern const StencilVariant kVariants[kNumVariants];
 // tiles: (solve index, strip << 16 | chunk) per wavefront
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,

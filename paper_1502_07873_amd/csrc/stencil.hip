@@ -376,6 +376,232 @@ stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__
     }
 }
 
+// Two leapfrog steps per launch (temporal blocking), depth-only media.
+// Pass p takes u^{m-1}, u^m (m = 2p) to u^{m+1} and u^{m+2}; level l lives in
+// buffer (l + 1) mod 4, so a pass reads two buffers and writes the other
+// two, and no wave ever overwrites data a neighbouring wave still reads.
+// Each wave recomputes u^{m+1} on a one-node halo around its 128 x R tile
+// (the rows kb-1 and ke, and the columns x0-1 / x0+128 handled as a third
+// node by lanes 0 / 63), so field traffic is 32 bytes per node per two
+// updates instead of 48.  Both steps use the same per-node update as the
+// one-step kernels: the fields are bitwise identical.
+struct RawTB {
+    float4 c;  // (u, v) of the lane's two columns
+    float4 h;  // lanes 0 / 63: the two columns beyond the tile edge
+};
+
+__device__ __forceinline__ RawTB load_raw_tb(const float2* Q, size_t off, int i0, int hcol,
+                                             bool hl) {
+    RawTB r;
+    r.c = ld4(Q, off + i0);
+    r.h = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (hl) r.h = ld4(Q, off + hcol);
+    return r;
+}
+
+// Node rows of the lane's columns A = x0+2l, B = x0+2l+1 and of the halo
+// node T (lane 0: x0-1 with neighbours x0-2 | x0; lane 63: x0+128 with
+// neighbours x0+127 | x0+129; other lanes: unused).
+struct RowTB {
+    NodeRow a, b, t;
+};
+
+__device__ __forceinline__ RowTB make_row_tb(const RawTB& r, bool first) {
+    RowTB o;
+    const float eu = first ? r.h.z : r.h.x, ev = first ? r.h.w : r.h.y;
+    const float lu = from_left(r.c.z, eu), lv = from_left(r.c.w, ev);
+    const float ru = from_right(r.c.x, eu), rv = from_right(r.c.y, ev);
+    o.a = node_row(r.c.x, r.c.y, lu, lv, r.c.z, r.c.w);
+    o.b = node_row(r.c.z, r.c.w, r.c.x, r.c.y, ru, rv);
+    o.t = node_row(eu, ev, first ? r.h.x : r.c.z, first ? r.h.y : r.c.w,
+                   first ? r.c.x : r.h.z, first ? r.c.y : r.h.w);
+    return o;
+}
+
+__device__ __forceinline__ void make_rows_x(float2 xa, float2 xb, float2 xt, NodeRow& a,
+                                            NodeRow& b) {
+    a = node_row(xa.x, xa.y, from_left(xb.x, xt.x), from_left(xb.y, xt.y), xb.x, xb.y);
+    b = node_row(xb.x, xb.y, xa.x, xa.y, from_right(xa.x, xt.x), from_right(xa.y, xt.y));
+}
+
+template <int R>
+__global__ void __launch_bounds__(256)
+stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
+                    int ntiles, int pass) {
+    const int tile = __builtin_amdgcn_readfirstlane(
+        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
+    if (tile >= ntiles) return;
+    const int2 te = tiles[tile];
+    const SolveDesc* d = descs + __builtin_amdgcn_readfirstlane(te.x);
+    const int sc = __builtin_amdgcn_readfirstlane(te.y);
+    const int m = 2 * (pass - d->start);
+    if (m < 0 || m >= d->nsteps) return;
+    const bool two = m + 1 < d->nsteps;
+    const int lane = threadIdx.x & 63;
+    const bool first = lane == 0;
+    const int nx = d->nx, nz = d->nz, pitch = d->pitch;
+    const int x0 = (sc >> 16) * 128;
+    const int kb = (sc & 0xffff) * R;
+    const int ke = min(kb + R, nz - 1);
+    const int i0 = x0 + 2 * lane;
+    float2* const bufs[4] = {d->buf0, d->buf1, d->buf2, d->buf3};
+    const float2* prev = bufs[m & 3];
+    const float2* cur = bufs[(m + 1) & 3];
+    float2* out1 = bufs[(m + 2) & 3];
+    float2* out2 = bufs[(m + 3) & 3];
+    const float* coef = d->coef;
+    const bool updA = (i0 >= 1) && (i0 <= nx - 2);
+    const bool updB = (i0 + 1 <= nx - 2);
+    const int tcol = first ? x0 - 1 : x0 + 128;
+    const bool edge = (first && x0 > 0) || (lane == 63 && x0 + 128 < nx);
+    const bool updT = edge && tcol >= 1 && tcol <= nx - 2;
+    const int hcol = first ? x0 - 2 : x0 + 128;
+    // sources (windows tested per row; the halo node may be in the window)
+    const int si0 = d->src_i0, sk0 = d->src_k0;
+    const bool src_cols = (si0 < x0 + 130) && (si0 + kSrcW > x0 - 1);
+    const int dA = i0 - si0, dB = dA + 1, dT = tcol - si0;
+    const bool sA = src_cols && dA >= 0 && dA < kSrcW;
+    const bool sB = src_cols && dB >= 0 && dB < kSrcW;
+    const bool sT = src_cols && dT >= 0 && dT < kSrcW;
+    const float sval1 = src_cols ? ld1(d->srcs, m) : 0.f;
+    const float sval2 = (src_cols && two) ? ld1(d->srcs, m + 1) : 0.f;
+    const float* srcw = d->srcw;
+    float2* traces = d->traces;
+    const int nrec = d->nrec;
+    int recA = -1, recB = -1;
+    if (kb == 0) {
+        recA = ldi(d->recmap, i0);
+        recB = ldi(d->recmap, i0 + 1);
+    }
+    const NodeRow z = NodeRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const float2 z2 = make_float2(0.f, 0.f);
+
+    // step-1 rows [j0, j1] (tile rows plus a one-row halo inside the free rows)
+    const int j0 = kb > 0 ? kb - 1 : 0;
+    const int j1 = min(ke, nz - 2);
+    RowTB um, uc, un;
+    if (j0 >= 1) {
+        um = make_row_tb(load_raw_tb(cur, (size_t)(j0 - 1) * pitch, i0, hcol, edge), first);
+    } else {
+        um.a = um.b = um.t = z;
+    }
+    uc = make_row_tb(load_raw_tb(cur, (size_t)j0 * pitch, i0, hcol, edge), first);
+    RawTB rn = load_raw_tb(cur, (size_t)(j0 + 1) * pitch, i0, hcol, edge);
+    float4 pv = ld4(prev, (size_t)j0 * pitch + i0);
+    float2 pt = z2;
+    if (edge) pt = ld2(prev, (size_t)j0 * pitch + tcol);
+    // u^{m+1} rows k-1 and k for the second step
+    NodeRow a2m = z, b2m = z, a2c = z, b2c = z;
+
+    for (int j = j0; j <= j1; ++j) {
+        RawTB rnn;
+        rnn.c = make_float4(0.f, 0.f, 0.f, 0.f);
+        rnn.h = rnn.c;
+        float4 pvn = rnn.c;
+        float2 ptn = z2;
+        if (j + 2 <= nz - 1) rnn = load_raw_tb(cur, (size_t)(j + 2) * pitch, i0, hcol, edge);
+        if (j + 1 <= j1) {
+            pvn = ld4(prev, (size_t)(j + 1) * pitch + i0);
+            if (edge) ptn = ld2(prev, (size_t)(j + 1) * pitch + tcol);
+        }
+        un = make_row_tb(rn, first);
+        // first step at row j: u^{m+1} at A, B and the halo node
+        const LayerCoef cj = load_coef(coef, j);
+        const float f1 = cj.c[kFco] * sval1;
+        const int dk1 = j - sk0;
+        const bool row1 = dk1 >= 0 && dk1 < kSrcW;
+        float wua = 0.f, wva = 0.f, wub = 0.f, wvb = 0.f, wut = 0.f, wvt = 0.f;
+        if (sA && row1) {
+            wua = ld1(srcw, (0 * kSrcW + dk1) * kSrcW + dA);
+            wva = ld1(srcw, (1 * kSrcW + dk1) * kSrcW + dA);
+        }
+        if (sB && row1) {
+            wub = ld1(srcw, (0 * kSrcW + dk1) * kSrcW + dB);
+            wvb = ld1(srcw, (1 * kSrcW + dk1) * kSrcW + dB);
+        }
+        if (sT && row1) {
+            wut = ld1(srcw, (0 * kSrcW + dk1) * kSrcW + dT);
+            wvt = ld1(srcw, (1 * kSrcW + dk1) * kSrcW + dT);
+        }
+        float2 xa = layered_update(cj, um.a, uc.a, un.a, pv.x, pv.y, sA && row1, f1, wua, wva);
+        float2 xb = layered_update(cj, um.b, uc.b, un.b, pv.z, pv.w, sB && row1, f1, wub, wvb);
+        float2 xt = layered_update(cj, um.t, uc.t, un.t, pt.x, pt.y, sT && row1, f1, wut, wvt);
+        if (!updA) xa = z2;
+        if (!updB) xb = z2;
+        if (!updT) xt = z2;
+        if (j >= kb && j < ke) {
+            st4(out1, (size_t)j * pitch + i0, make_float4(xa.x, xa.y, xb.x, xb.y));
+            if (j == 0) {
+                if (recA >= 0) st2(traces, (size_t)(m + 1) * nrec + recA, xa);
+                if (recB >= 0) st2(traces, (size_t)(m + 1) * nrec + recB, xb);
+            }
+        }
+        NodeRow a2n, b2n;
+        make_rows_x(xa, xb, xt, a2n, b2n);
+        // second step at row k = j - 1
+        const int k = j - 1;
+        if (two && k >= kb) {
+            const LayerCoef ck = load_coef(coef, k);
+            const float f2 = ck.c[kFco] * sval2;
+            const int dk2 = k - sk0;
+            const bool row2 = dk2 >= 0 && dk2 < kSrcW;
+            float qua = 0.f, qva = 0.f, qub = 0.f, qvb = 0.f;
+            if (sA && row2) {
+                qua = ld1(srcw, (0 * kSrcW + dk2) * kSrcW + dA);
+                qva = ld1(srcw, (1 * kSrcW + dk2) * kSrcW + dA);
+            }
+            if (sB && row2) {
+                qub = ld1(srcw, (0 * kSrcW + dk2) * kSrcW + dB);
+                qvb = ld1(srcw, (1 * kSrcW + dk2) * kSrcW + dB);
+            }
+            float2 ya = layered_update(ck, a2m, a2c, a2n, um.a.u, um.a.v, sA && row2, f2, qua, qva);
+            float2 yb = layered_update(ck, b2m, b2c, b2n, um.b.u, um.b.v, sB && row2, f2, qub, qvb);
+            if (!updA) ya = z2;
+            if (!updB) yb = z2;
+            st4(out2, (size_t)k * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
+            if (k == 0) {
+                if (recA >= 0) st2(traces, (size_t)(m + 2) * nrec + recA, ya);
+                if (recB >= 0) st2(traces, (size_t)(m + 2) * nrec + recB, yb);
+            }
+        }
+        um = uc;
+        uc = un;
+        rn = rnn;
+        pv = pvn;
+        pt = ptn;
+        a2m = a2c;
+        b2m = b2c;
+        a2c = a2n;
+        b2c = b2n;
+    }
+    // bottom tile: the last free row's second step sees the rigid row (zeros)
+    if (two && ke == nz - 1 && ke - 1 >= kb) {
+        const int k = ke - 1;
+        const LayerCoef ck = load_coef(coef, k);
+        const float f2 = ck.c[kFco] * sval2;
+        const int dk2 = k - sk0;
+        const bool row2 = dk2 >= 0 && dk2 < kSrcW;
+        float qua = 0.f, qva = 0.f, qub = 0.f, qvb = 0.f;
+        if (sA && row2) {
+            qua = ld1(srcw, (0 * kSrcW + dk2) * kSrcW + dA);
+            qva = ld1(srcw, (1 * kSrcW + dk2) * kSrcW + dA);
+        }
+        if (sB && row2) {
+            qub = ld1(srcw, (0 * kSrcW + dk2) * kSrcW + dB);
+            qvb = ld1(srcw, (1 * kSrcW + dk2) * kSrcW + dB);
+        }
+        float2 ya = layered_update(ck, a2m, a2c, z, um.a.u, um.a.v, sA && row2, f2, qua, qva);
+        float2 yb = layered_update(ck, b2m, b2c, z, um.b.u, um.b.v, sB && row2, f2, qub, qvb);
+        if (!updA) ya = z2;
+        if (!updB) yb = z2;
+        st4(out2, (size_t)k * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
+        if (k == 0) {
+            if (recA >= 0) st2(traces, (size_t)(m + 2) * nrec + recA, ya);
+            if (recB >= 0) st2(traces, (size_t)(m + 2) * nrec + recB, yb);
+        }
+    }
+}
+
 // Nodal media: coef = three planes (lambda, mu, s = dt^2/(rho h^2)).
 struct RowN {
     float u, v, hu, hv;   // centre and halo-column values of u^m
@@ -547,13 +773,18 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
 }
 
 const StencilVariant kVariants[kNumVariants] = {
-    {64, 32, EIG_MEDIUM_LAYERED},   // 0: one node per lane
-    {128, 32, EIG_MEDIUM_LAYERED},  // 1: two nodes per lane, prefetch 1
-    {128, 32, EIG_MEDIUM_LAYERED},  // 2: two nodes per lane, prefetch 2
-    {128, 64, EIG_MEDIUM_LAYERED},  // 3
-    {128, 16, EIG_MEDIUM_LAYERED},  // 4
-    {128, 64, EIG_MEDIUM_LAYERED},  // 5: prefetch 1
-    {64, 32, EIG_MEDIUM_NODAL},     // 6: nodal media
+    {64, 32, EIG_MEDIUM_LAYERED, 1},   // 0: one node per lane
+    {128, 32, EIG_MEDIUM_LAYERED, 1},  // 1: two nodes per lane, prefetch 1
+    {128, 32, EIG_MEDIUM_LAYERED, 1},  // 2: two nodes per lane, prefetch 2
+    {128, 64, EIG_MEDIUM_LAYERED, 1},  // 3: prefetch 2
+    {128, 16, EIG_MEDIUM_LAYERED, 1},  // 4: prefetch 2
+    {128, 64, EIG_MEDIUM_LAYERED, 1},  // 5: prefetch 1
+    {64, 32, EIG_MEDIUM_NODAL, 1},     // 6: nodal media
+    {128, 8, EIG_MEDIUM_LAYERED, 1},   // 7: prefetch 2
+    {128, 16, EIG_MEDIUM_LAYERED, 1},  // 8: prefetch 1
+    {128, 16, EIG_MEDIUM_LAYERED, 2},  // 9: two steps per launch
+    {128, 32, EIG_MEDIUM_LAYERED, 2},  // 10: two steps per launch
+    {128, 64, EIG_MEDIUM_LAYERED, 2},  // 11: two steps per launch
 };
 
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
@@ -568,6 +799,11 @@ void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int s
         case 3: stencil_layered_w2<64, 2><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         case 4: stencil_layered_w2<16, 2><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         case 5: stencil_layered_w2<64, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 7: stencil_layered_w2<8, 2><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 8: stencil_layered_w2<16, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 9: stencil_layered_tb2<16><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 10: stencil_layered_tb2<32><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 11: stencil_layered_tb2<64><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         default: stencil_nodal<<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
     }
 }
