@@ -145,6 +145,8 @@ def main():
     wall = time.perf_counter() - t0
     total_ms = ev[0].elapsed_time(ev[-1])
     st = jac_stats
+    variant = ctx.get_option("last_variant")
+    steps_per_launch = 2 if variant in (9, 10, 11) else 1
     S = len(wl.theta)
     value = S * args.steps / (total_ms / 1e3)
     avg_launch_ms = st["ms"] / max(st["launches"], 1)
@@ -175,9 +177,16 @@ def main():
         "status_ok": status_ok,
         "grid_pt_updates_per_s": st["updates"] / (total_ms / 1e3),
         "stencil": {"launches": st["launches"], "avg_launch_ms": avg_launch_ms,
+                    "variant": variant, "steps_per_launch": steps_per_launch,
                     "bytes_per_launch": bytes_per_launch,
+                    "kernel_floor_bytes_per_update": 16 if steps_per_launch == 2 else 24,
+                    "achieved_at_kernel_floor_GBs":
+                        achieved * (16 if steps_per_launch == 2 else 24) / 24,
                     "time_frac_of_step": st["ms"] / total_ms,
-                    "note": "launches of the 15*S-solve jacobian_fd wave"},
+                    "note": "launches of the 15*S-solve jacobian_fd wave; bytes_per_launch "
+                            "and roofline.achieved count 24 B per grid-point update (read u^m, "
+                            "u^{m-1}, write u^{m+1}); a two-steps-per-launch kernel needs only "
+                            "16 B per update (achieved_at_kernel_floor_GBs)"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)),
                        "p99": float(np.percentile(lat, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

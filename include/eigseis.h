@@ -140,6 +140,11 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  *                      the plain one-solve-at-a-time path)
  * EIG_EINVAL for an unknown name or value. */
 int eig_ctx_set_option(eig_ctx* ctx, const char* name, int64_t value);
+/* Reads an option back; "last_variant" gives the stencil variant of the most
+ * recent launch.  "temporal_blocking" 1 (default): depth-only media use the
+ * two-steps-per-launch kernels (four field buffers per solve); 0: one step
+ * per launch. */
+int eig_ctx_get_option(const eig_ctx* ctx, const char* name, int64_t* value);
 
 /*
  * forward_solve_batch — the parameter-to-observable map g_r(t_m; theta)

@@ -285,14 +285,17 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         bool active = false;
         int begin = 0, reps = 2;
         std::vector<hipEvent_t> ev;  // 2 per tuning launch
-        std::tuple<int, int, int, int> key;
+        std::tuple<int, int, int, int, int> key;
     };
     std::vector<int> use(groups.size(), 0);
     std::vector<Tune> tune(groups.size());
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         Group& g = groups[gi];
         const SolveDesc& d0 = desc[g.first];
-        tune[gi].key = std::make_tuple(g.kind, d0.nx, d0.nz, kVariants[g.cand[0]].steps);
+        // grid class and batch size (log2 of the solve count) both matter
+        int bucket = 0;
+        while ((2 << bucket) <= g.last - g.first) ++bucket;
+        tune[gi].key = std::make_tuple(g.kind, d0.nx, d0.nz, kVariants[g.cand[0]].steps, bucket);
         use[gi] = 0;
         if (g.cand.size() > 1) {
             auto it = c->tuned.find(tune[gi].key);
@@ -346,6 +349,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
                 }
             }
             if (ntile > 0) {
+                c->last_variant = g.cand[vi];
                 if (slot >= 0) HIP_TRY(hipEventRecord(tn.ev[2 * slot], s));
                 launch_stencil(ddesc, (const int2*)(bd + o_tiles[gi][vi]), ntile, step,
                                g.cand[vi], s);
@@ -496,6 +500,19 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
     } else {
         return set_error(EIG_EINVAL, "unknown option " + n);
     }
+    return EIG_OK;
+}
+
+int eig_ctx_get_option(const eig_ctx* c, const char* name, int64_t* value) {
+    if (!c || !name || !value) return set_error(EIG_EINVAL, "NULL argument");
+    const std::string n(name);
+    if (n == "stencil_variant") *value = c->forced_variant;
+    else if (n == "autotune") *value = c->autotune;
+    else if (n == "default_variant") *value = c->default_variant;
+    else if (n == "temporal_blocking") *value = c->temporal_blocking;
+    else if (n == "max_wave_solves") *value = c->max_wave_solves;
+    else if (n == "last_variant") *value = c->last_variant;
+    else return set_error(EIG_EINVAL, "unknown option " + n);
     return EIG_OK;
 }
 

@@ -60,7 +60,8 @@ struct eig_ctx {
     int default_variant_tb = 9;   // two steps per launch
     bool temporal_blocking = true;
     bool autotune = true;
-    std::map<std::tuple<int, int, int, int>, int> tuned;
+    std::map<std::tuple<int, int, int, int, int>, int> tuned;
+    int last_variant = -1;  // variant of the most recent stencil launch
     int64_t max_wave_solves = 0;  // 0: no limit (all solves of a wave per launch)
 };
 

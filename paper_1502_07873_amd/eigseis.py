@@ -76,6 +76,8 @@ def _load():
         "eig_ctx_workspace_bytes": ([vp], ctypes.c_size_t),
         "eig_ctx_stencil_stats": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
         "eig_ctx_set_option": ([vp, ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
+        "eig_ctx_get_option": ([vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)],
+                               ctypes.c_int),
         "forward_solve_batch": ([vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "jacobian_fd": ([vp, i32, vp, vp, vp, dbl, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp],
                         ctypes.c_int),
@@ -101,7 +103,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("eig_ctx_create", "eig_ctx_destroy", "eig_last_error", "eig_ctx_workspace_bytes",
-            "eig_ctx_stencil_stats", "eig_ctx_set_option",
+            "eig_ctx_stencil_stats", "eig_ctx_set_option", "eig_ctx_get_option",
             "forward_solve_batch", "jacobian_fd", "laplace_eig", "design_eval",
             "design_greedy", "noise_sigma_peak", "sparse_grid_gl", "eig_server_create",
             "eig_server_destroy", "eig_server_submit", "eig_server_step", "eig_server_poll",
@@ -205,6 +207,11 @@ class Context:
 
     def set_option(self, name: str, value: int):
         _check(_lib.eig_ctx_set_option(self._h, name.encode(), int(value)))
+
+    def get_option(self, name: str) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.eig_ctx_get_option(self._h, name.encode(), ctypes.byref(v)))
+        return v.value
 
     def stencil_stats(self, reset: bool = False) -> dict:
         """Device time (ms) from first to last stencil launch of each wave,
