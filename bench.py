@@ -73,6 +73,45 @@ def _copy_calibration(nbytes=4 << 30, reps=4):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def _serving(ctx, updates_per_s, nquery=24, load=0.7, seed=3, overlap=True):
+    """A c4-shaped query stream served by the continuous-batching engine with
+    Poisson arrivals at `load` x the capacity implied by updates_per_s."""
+    import numpy as np
+
+    import synthetic
+    from paper_1502_07873_amd import eigseis
+    from paper_1502_07873_amd.query import device_medium, grid_tuple
+    from paper_1502_07873_amd.serve import Query, latency_stats, serve
+    rng = np.random.Generator(np.random.PCG64(seed))
+    wls = synthetic.serving_stream(rng, nquery, n_range=(256, 384), sample_range=(8, 32))
+    work = np.array([15 * len(w.theta) * w.grid.nx * w.grid.nz * w.grid.nsteps for w in wls])
+    rate = load * updates_per_s / work.mean()
+    arrivals = synthetic.poisson_arrivals(rng, nquery, rate)
+    qs = []
+    for w, t in zip(wls, arrivals):
+        med = device_medium(w.medium.kind, w.medium.rho, w.medium.lam, w.medium.mu)
+        qs.append(Query(grid_tuple(w.grid), med, w.theta, w.receivers, w.lo, w.hi, w.weights,
+                        w.noise_rel, eigseis.SIGMA_NOMINAL_PEAK, arrival=float(t)))
+    srv = eigseis.Server(ctx, 120 << 30, group_samples=16)
+    serve(srv, qs, launches_per_step=20, overlap=overlap)
+    srv.close()
+    st = latency_stats(qs)
+    span = max(q.t_done for q in qs) - min(q.t_submit for q in qs)
+    nsamp = sum(len(q.theta) for q in qs)
+    flagged = sum(int((q.status != 0).sum()) + int((q.chol_status != 0).sum()) for q in qs)
+    return {"discipline": "continuous batching" if overlap else "queue only (one query at a time)",
+            "queries": nquery, "offered_load": load, "arrival_rate_per_s": rate,
+            "latency_p50_s": st["p50_s"], "latency_p99_s": st["p99_s"],
+            "latency_mean_s": st["mean_s"], "span_s": span,
+            "design_eig_evals_per_s": nquery / span, "sample_eig_evals_per_s": nsamp / span,
+            "grid_pt_updates": float(work.sum()), "flagged_samples": flagged,
+            "samples": nsamp,
+            "workload": "c4-shaped stream: N in {256..384 step 64}^2, 500..2000 steps "
+                        "(raised to cover 1.5x the P travel time from the deepest source), "
+                        "5..101 random surface receivers, 8..32 samples, random 4-layer "
+                        "media; sigma = 1e-3 x each sample's nominal peak"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--samples", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
     args = ap.parse_args()
@@ -146,7 +186,7 @@ def main():
     total_ms = ev[0].elapsed_time(ev[-1])
     st = jac_stats
     variant = ctx.get_option("last_variant")
-    steps_per_launch = 2 if variant in (9, 10, 11) else 1
+    steps_per_launch = 2 if variant in (9, 10, 11, 12) else 1
     S = len(wl.theta)
     value = S * args.steps / (total_ms / 1e3)
     avg_launch_ms = st["ms"] / max(st["launches"], 1)
@@ -214,6 +254,13 @@ def main():
         "speedup_of_batched": value / (2 / t1),
         "dkl_match": bool(np.allclose(o1["dkl"].cpu().numpy(), dkl[:2], rtol=0, atol=0))}
     ctx1.close()
+    if not args.no_serving:
+        print("[bench] serving run (continuous batching, Poisson arrivals)", flush=True)
+        line["serving"] = _serving(ctx, line["grid_pt_updates_per_s"])
+        print("[bench] serving run, queue-only discipline", flush=True)
+        line["serving_queue_only"] = _serving(ctx, line["grid_pt_updates_per_s"], overlap=False)
+        line["latency_ms"]["serving_p50"] = line["serving"]["latency_p50_s"] * 1e3
+        line["latency_ms"]["serving_p99"] = line["serving"]["latency_p99_s"] * 1e3
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, 1 sample)", flush=True)
         cb, err = _cpu_baseline(wl, wl.theta[0], dkl[0])

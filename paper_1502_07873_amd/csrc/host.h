@@ -57,7 +57,7 @@ struct eig_ctx {
     // online per (medium kind, nx, nz) and cached here
     int forced_variant = -1;
     int default_variant = 4;      // one step per launch
-    int default_variant_tb = 9;   // two steps per launch
+    int default_variant_tb = 11;  // two steps per launch
     bool temporal_blocking = true;
     bool autotune = true;
     std::map<std::tuple<int, int, int, int, int>, int> tuned;

@@ -121,7 +121,8 @@ struct eig_server {
     size_t tile_cap = 0;
     int64_t launch = 0;
     int group_samples = 16;
-    int variant_layered = 2;
+    int variant_layered = 4;
+    int spl = 1;  // leapfrog steps per launch of the layered variant
     std::deque<SrvQuery*> queue;
     std::map<int64_t, std::unique_ptr<SrvQuery>> queries;
     std::vector<SrvGroup> groups;
@@ -162,6 +163,7 @@ int srv_admit(eig_server* v, hipStream_t s) {
         gr.bytes = bytes;
         gr.start = v->launch;
         gr.nsteps = q.grid.nsteps;
+        const bool four = q.medium.kind == EIG_MEDIUM_LAYERED && v->spl == 2;
         // carve the group's region
         char* base = v->mem + off;
         const eig_grid& g = q.grid;
@@ -173,10 +175,15 @@ int srv_admit(eig_server* v, hipStream_t s) {
         const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
         const size_t fields_begin = align_up(cv.off);
         cv.off = fields_begin;
-        std::vector<size_t> f0(gr.nslot), f1(gr.nslot), sw(gr.nslot), ss(gr.nslot), tr(gr.nslot);
+        std::vector<size_t> f0(gr.nslot), f1(gr.nslot), f2(gr.nslot, 0), f3(gr.nslot, 0);
+        std::vector<size_t> sw(gr.nslot), ss(gr.nslot), tr(gr.nslot);
         for (size_t k = 0; k < gr.nslot; ++k) {
             f0[k] = cv.take(field);
             f1[k] = cv.take(field);
+            if (four) {
+                f2[k] = cv.take(field);
+                f3[k] = cv.take(field);
+            }
         }
         const size_t fields_end = cv.off;
         for (size_t k = 0; k < gr.nslot; ++k) {
@@ -209,6 +216,8 @@ int srv_admit(eig_server* v, hipStream_t s) {
                 std::memset(&dd, 0, sizeof(dd));
                 dd.buf0 = (float2*)(base + f0[k]);
                 dd.buf1 = (float2*)(base + f1[k]);
+                dd.buf2 = four ? (float2*)(base + f2[k]) : nullptr;
+                dd.buf3 = four ? (float2*)(base + f3[k]) : nullptr;
                 dd.coef = (const float*)(base + o_coef);
                 dd.srcw = (const float*)(base + sw[k]);
                 dd.srcs = (const float*)(base + ss[k]);
@@ -308,10 +317,16 @@ int srv_finish_query(eig_server* v, SrvQuery& q, hipStream_t s) {
     return EIG_OK;
 }
 
+// launches a group needs in total
+int64_t group_launches(const eig_server* v, const SrvGroup& gr) {
+    const int spl = gr.q->medium.kind == EIG_MEDIUM_LAYERED ? v->spl : 1;
+    return (gr.nsteps + spl - 1) / spl;
+}
+
 int srv_retire(eig_server* v, hipStream_t s) {
     std::vector<SrvGroup> keep;
     for (auto& gr : v->groups) {
-        if (gr.start + gr.nsteps > v->launch) {
+        if (gr.start + group_launches(v, gr) > v->launch) {
             keep.push_back(gr);
             continue;
         }
@@ -386,7 +401,8 @@ int eig_server_create(eig_ctx* c, size_t budget, int32_t group_samples, eig_serv
     v->variant_layered = c->forced_variant >= 0 &&
                                  kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_LAYERED
                              ? c->forced_variant
-                             : c->default_variant;
+                             : (c->temporal_blocking ? c->default_variant_tb : c->default_variant);
+    v->spl = kVariants[v->variant_layered].steps;
     v->nslot_cap = 1 << 17;
     if (hipMalloc((void**)&v->mem, budget) != hipSuccess) {
         (void)hipGetLastError();
@@ -497,13 +513,15 @@ int eig_server_step(eig_server* v, int32_t max_launches, void* stream, int32_t* 
     while (done < max_launches && !v->groups.empty()) {
         if ((rc = srv_rebuild_tiles(v, s))) return rc;
         int64_t seg = max_launches - done;
-        double upd = 0.0;
-        for (const auto& gr : v->groups) {
-            seg = std::min(seg, gr.start + gr.nsteps - v->launch);
-            upd += (double)gr.q->grid.nx * gr.q->grid.nz * gr.nslot;
-        }
+        for (const auto& gr : v->groups)
+            seg = std::min(seg, gr.start + group_launches(v, gr) - v->launch);
         for (int64_t l = 0; l < seg; ++l) {
-            c->updates += upd;
+            for (const auto& gr : v->groups) {
+                const int spl = gr.q->medium.kind == EIG_MEDIUM_LAYERED ? v->spl : 1;
+                const int64_t left = gr.nsteps - spl * (v->launch - gr.start);
+                c->updates += (double)gr.q->grid.nx * gr.q->grid.nz * gr.nslot *
+                              (double)std::min<int64_t>(spl, left);
+            }
             for (size_t kk = 0; kk < v->kind_tiles.size(); ++kk) {
                 const size_t nt = v->kind_tiles[kk].second;
                 if (nt == 0) continue;

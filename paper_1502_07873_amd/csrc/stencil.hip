@@ -424,7 +424,7 @@ __device__ __forceinline__ void make_rows_x(float2 xa, float2 xb, float2 xt, Nod
     b = node_row(xb.x, xb.y, xa.x, xa.y, from_right(xa.x, xt.x), from_right(xa.y, xt.y));
 }
 
-template <int R>
+template <int R, int D>
 __global__ void __launch_bounds__(256)
 stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
                     int ntiles, int pass) {
@@ -486,24 +486,50 @@ stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict_
         um.a = um.b = um.t = z;
     }
     uc = make_row_tb(load_raw_tb(cur, (size_t)j0 * pitch, i0, hcol, edge), first);
-    RawTB rn = load_raw_tb(cur, (size_t)(j0 + 1) * pitch, i0, hcol, edge);
-    float4 pv = ld4(prev, (size_t)j0 * pitch + i0);
-    float2 pt = z2;
-    if (edge) pt = ld2(prev, (size_t)j0 * pitch + tcol);
+    // prefetch ring: raw u^m rows j+1..j+D, u^{m-1} rows j..j+D-1 (one row
+    // measured fastest: deeper rings cost more than the latency they hide)
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    RawTB rq[D];
+    float4 pq[D];
+    float2 tq[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        rq[q].c = z4;
+        rq[q].h = z4;
+        pq[q] = z4;
+        tq[q] = z2;
+        if (j0 + 1 + q <= nz - 1) rq[q] = load_raw_tb(cur, (size_t)(j0 + 1 + q) * pitch, i0, hcol, edge);
+        if (j0 + q <= j1) {
+            pq[q] = ld4(prev, (size_t)(j0 + q) * pitch + i0);
+            if (edge) tq[q] = ld2(prev, (size_t)(j0 + q) * pitch + tcol);
+        }
+    }
     // u^{m+1} rows k-1 and k for the second step
     NodeRow a2m = z, b2m = z, a2c = z, b2c = z;
 
     for (int j = j0; j <= j1; ++j) {
         RawTB rnn;
-        rnn.c = make_float4(0.f, 0.f, 0.f, 0.f);
-        rnn.h = rnn.c;
-        float4 pvn = rnn.c;
+        rnn.c = z4;
+        rnn.h = z4;
+        float4 pvn = z4;
         float2 ptn = z2;
-        if (j + 2 <= nz - 1) rnn = load_raw_tb(cur, (size_t)(j + 2) * pitch, i0, hcol, edge);
-        if (j + 1 <= j1) {
-            pvn = ld4(prev, (size_t)(j + 1) * pitch + i0);
-            if (edge) ptn = ld2(prev, (size_t)(j + 1) * pitch + tcol);
+        if (j + 1 + D <= nz - 1) rnn = load_raw_tb(cur, (size_t)(j + 1 + D) * pitch, i0, hcol, edge);
+        if (j + D <= j1) {
+            pvn = ld4(prev, (size_t)(j + D) * pitch + i0);
+            if (edge) ptn = ld2(prev, (size_t)(j + D) * pitch + tcol);
         }
+        const RawTB rn = rq[0];
+        const float4 pv = pq[0];
+        const float2 pt = tq[0];
+#pragma unroll
+        for (int q = 0; q + 1 < D; ++q) {
+            rq[q] = rq[q + 1];
+            pq[q] = pq[q + 1];
+            tq[q] = tq[q + 1];
+        }
+        rq[D - 1] = rnn;
+        pq[D - 1] = pvn;
+        tq[D - 1] = ptn;
         un = make_row_tb(rn, first);
         // first step at row j: u^{m+1} at A, B and the halo node
         const LayerCoef cj = load_coef(coef, j);
@@ -566,9 +592,6 @@ stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict_
         }
         um = uc;
         uc = un;
-        rn = rnn;
-        pv = pvn;
-        pt = ptn;
         a2m = a2c;
         b2m = b2c;
         a2c = a2n;
@@ -785,6 +808,7 @@ const StencilVariant kVariants[kNumVariants] = {
     {128, 16, EIG_MEDIUM_LAYERED, 2},  // 9: two steps per launch
     {128, 32, EIG_MEDIUM_LAYERED, 2},  // 10: two steps per launch
     {128, 64, EIG_MEDIUM_LAYERED, 2},  // 11: two steps per launch
+    {128, 128, EIG_MEDIUM_LAYERED, 2}, // 12: two steps per launch
 };
 
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
@@ -801,9 +825,10 @@ void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int s
         case 5: stencil_layered_w2<64, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         case 7: stencil_layered_w2<8, 2><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         case 8: stencil_layered_w2<16, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
-        case 9: stencil_layered_tb2<16><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
-        case 10: stencil_layered_tb2<32><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
-        case 11: stencil_layered_tb2<64><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 9: stencil_layered_tb2<16, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 10: stencil_layered_tb2<32, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 11: stencil_layered_tb2<64, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 12: stencil_layered_tb2<128, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         default: stencil_nodal<<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
     }
 }

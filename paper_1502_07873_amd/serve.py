@@ -40,9 +40,11 @@ class Query:
 
 
 def serve(server: eigseis.Server, queries, launches_per_step: int = 40,
-          max_inflight_steps: int = 2):
+          max_inflight_steps: int = 2, overlap: bool = True):
     """Runs the arrival process in real time.  Returns the queries with
-    t_submit / t_done filled in (seconds from the start)."""
+    t_submit / t_done filled in (seconds from the start).  overlap=False is
+    the queue-only discipline: a query is submitted only once the previous
+    one has completed (no continuous batching)."""
     pending = sorted(queries, key=lambda q: q.arrival)
     active = []
     inflight = collections.deque()
@@ -50,7 +52,7 @@ def serve(server: eigseis.Server, queries, launches_per_step: int = 40,
     i = 0
     while i < len(pending) or active:
         now = time.perf_counter() - t0
-        while i < len(pending) and pending[i].arrival <= now:
+        while i < len(pending) and pending[i].arrival <= now and (overlap or not active):
             q = pending[i]
             q.submit(server)
             q.t_submit = now
@@ -64,7 +66,7 @@ def serve(server: eigseis.Server, queries, launches_per_step: int = 40,
             inflight.append(ev)
             while len(inflight) > max_inflight_steps:
                 inflight.popleft().synchronize()
-        elif i < len(pending):
+        elif i < len(pending) and (overlap or not active):
             time.sleep(min(0.01, max(0.0, pending[i].arrival - now)))
         else:
             torch.cuda.synchronize()

@@ -10,5 +10,5 @@ from .workloads import (  # noqa: F401
     Grid, Medium, Workload, prior_box, draw_uniform, equispaced_receivers,
     candidate_receivers, random_receivers, homogeneous_medium, layered_medium,
     random_layers_medium, nodal_perturbed_medium, cfl_dt, config, CONFIG_NAMES,
-    PARAM_NAMES,
+    PARAM_NAMES, serving_stream, poisson_arrivals,
 )

@@ -294,3 +294,39 @@ def serving_queries(rng: np.random.Generator, nquery: int,
         out.append(Workload("c4", grid, med, random_receivers(rng, nx, nr),
                             lo, hi, theta, _mc(theta)))
     return out
+
+
+def serving_stream(rng: np.random.Generator, nquery: int, n_range=(256, 512),
+                   steps_range=(500, 2000), rec_range=(5, 101), sample_range=(16, 64),
+                   h: float = 10.0, cover_travel: bool = True) -> List[Workload]:
+    """A design-query stream shaped like c4 (random grid size, duration,
+    receiver count and positions, sample count; random 4-layer media) with
+    adjustable ranges, so a serving run can be sized to minutes.
+
+    With cover_travel, a drawn duration is raised where needed to 1.5 x the
+    vertical P travel time from the deepest prior source plus the latest
+    wavelet: otherwise no wave reaches the surface, every H_1 is singular and
+    the whole query only returns flags."""
+    out = []
+    for _ in range(nquery):
+        n = int(rng.integers(n_range[0] // 64, n_range[1] // 64 + 1)) * 64
+        nsteps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        nr = int(rng.integers(rec_range[0], rec_range[1] + 1))
+        ns = int(rng.integers(sample_range[0], sample_range[1] + 1))
+        med = random_layers_medium(rng, n, h, 4)
+        grid = Grid(n, n, h, cfl_dt(h, med.vp_max()), nsteps)
+        lo, hi = prior_box(grid)
+        if cover_travel:
+            vp = np.sqrt((med.lam + 2 * med.mu) / med.rho)
+            travel = float(np.sum(h / vp[: int(hi[1] / h) + 1]))
+            need = int(math.ceil((1.5 * travel + hi[2] + 2.0 / lo[3]) / grid.dt))
+            grid.nsteps = max(nsteps, need)
+        theta = draw_uniform(rng, lo, hi, ns)
+        out.append(Workload("c4", grid, med, random_receivers(rng, n, min(nr, n - 2)),
+                            lo, hi, theta, _mc(theta)))
+    return out
+
+
+def poisson_arrivals(rng: np.random.Generator, n: int, rate: float) -> np.ndarray:
+    """Arrival times (s) of a Poisson process with the given rate."""
+    return np.cumsum(rng.exponential(1.0 / rate, n))
