@@ -112,6 +112,103 @@ def _serving(ctx, updates_per_s, nquery=24, load=0.7, seed=3, overlap=True):
                         "media; sigma = 1e-3 x each sample's nominal peak"}
 
 
+def _bench_c3(ctx, nsample):
+    """Uneven batching: nsample single-sample queries with grids from
+    {256,384,512}^2 and 1000/1500/2000 steps, each with its own 4-layer
+    medium, all 15*nsample solves in one jacobian_fd call."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_1502_07873_amd import eigseis
+    from paper_1502_07873_amd.query import device_medium, grid_tuple
+    wls = synthetic.config("c3", nsample=nsample)
+    grids = [grid_tuple(w.grid) for w in wls]
+    media = [device_medium(w.medium.kind, w.medium.rho, w.medium.lam, w.medium.mu) for w in wls]
+    theta = np.concatenate([w.theta for w in wls])
+    recs = [w.receivers for w in wls]
+    H1 = torch.empty((nsample, 7, 7), dtype=torch.float64, device="cuda")
+    status = torch.empty(nsample, dtype=torch.int32, device="cuda")
+    updates = float(sum(15 * g[0] * g[1] * g[4] for g in grids))
+    ctx.stencil_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.jacobian_fd(grids, media, theta, recs, 1e-3, H1, sigma_mode=eigseis.SIGMA_NOMINAL_PEAK,
+                    status=status)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    st = ctx.stencil_stats(reset=True)
+    return {"workload": f"c3 uneven batch: {nsample} samples x 15 solves, grids "
+                        "{256,384,512}^2, 1000/1500/2000 steps, per-sample 4-layer media",
+            "solves": 15 * nsample, "seconds": t, "sample_eig_evals_per_s": nsample / t,
+            "grid_pt_updates_per_s": updates / t, "stencil_ms": st["ms"],
+            "stencil_GBs_24B": st["bytes"] / st["ms"] * 1e-6,
+            "launches": st["launches"], "variant": ctx.get_option("last_variant"),
+            "workspace_GB": ctx.workspace_bytes / 1e9,
+            "flagged": int((status != 0).sum())}
+
+
+def _bench_c5(ctx, reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40):
+    """Sparse quadrature + greedy design: (a) the full 2048x1024x4000 nodal
+    problem on `full_nodes` sparse-grid nodes (throughput); (b) the whole
+    pipeline (589 level-3 nodes, 201 candidates, greedy to kmax) on a
+    reduced grid, with the EIG-vs-count curve."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_1502_07873_amd import make_prior, sparse_grid_gl
+    from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
+    out = {}
+    wl = synthetic.config("c5")[0]
+    nodes, w = sparse_grid_gl(7, 3, wl.lo, wl.hi)
+    med = device_medium(wl.medium.kind, wl.medium.rho, wl.medium.lam, wl.medium.mu)
+    g = grid_tuple(wl.grid)
+    ctx.stencil_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, nodes[:full_nodes],
+                  w[:full_nodes], sigma=1.0, per_receiver=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    st = ctx.stencil_stats(reset=True)
+    upd = 15 * full_nodes * wl.grid.nx * wl.grid.nz * wl.grid.nsteps
+    out["full_size"] = {"grid": [wl.grid.nx, wl.grid.nz, wl.grid.nsteps],
+                        "sparse_grid_nodes_total": len(w), "nodes_run": full_nodes,
+                        "candidates": len(wl.receivers), "seconds": t,
+                        "grid_pt_updates_per_s": upd / t,
+                        "stencil_GBs_36B": st["bytes"] / max(st["ms"], 1e-9) * 1e-6,
+                        "sample_eig_evals_per_s": full_nodes / t,
+                        "projected_full_query_hours": len(w) * t / full_nodes / 3600}
+    wr = synthetic.config("c5", grid_override=reduced_grid)[0]
+    nodes, w = sparse_grid_gl(7, 3, wr.lo, wr.hi)
+    medr = device_medium(wr.medium.kind, wr.medium.rho, wr.medium.lam, wr.medium.mu)
+    gr = grid_tuple(wr.grid)
+    sigma = ctx.noise_sigma_peak(gr, medr, wr.theta_bar, wr.noise_rel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = run_query(ctx, gr, medr, wr.receivers, wr.lo, wr.hi, nodes, w, sigma=sigma,
+                  per_receiver=True)
+    order = torch.empty(kmax, dtype=torch.int32, device="cuda")
+    curve = torch.empty(kmax, dtype=torch.float64, device="cuda")
+    ctx.design_greedy(r["H1"], make_prior(wr.lo, wr.hi), w, kmax, order, curve, theta=nodes)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    cv = curve.cpu().numpy()
+    ks = np.arange(1, kmax + 1)
+    ok = np.isfinite(cv)
+    slope = float(np.polyfit(np.log(ks[ok][4:]), cv[ok][4:], 1)[0]) if ok.sum() > 6 else None
+    out["reduced_pipeline"] = {"grid": list(reduced_grid), "sparse_grid_nodes": len(w),
+                               "solves": 15 * len(w), "candidates": len(wr.receivers),
+                               "greedy_kmax": kmax, "seconds": t,
+                               "order": order.cpu().numpy().tolist(),
+                               "eig_curve": [float(x) for x in cv],
+                               "slope_d_eig_d_log_k": slope,
+                               "note": "Laplace EIG grows ~ (N_theta/2) log k for large "
+                                       "k when H1 grows in proportion to receiver count"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +217,8 @@ def main():
     ap.add_argument("--samples", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
+                    help="c2: the headline query (default); c3/c5: extra measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
     args = ap.parse_args()
@@ -139,6 +238,15 @@ def main():
     from paper_1502_07873_amd import Context
     from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
 
+    if args.workload != "c2":
+        ctx = Context(0, 200 << 30)
+        if args.workload == "c3":
+            res = _bench_c3(ctx, args.samples if args.samples != 256 else 4096)
+        else:
+            res = _bench_c5(ctx)
+        print(json.dumps({"workload": args.workload, **res}), flush=True)
+        ctx.close()
+        return
     wl = synthetic.config("c2", nsample=args.samples)[0]
     g = grid_tuple(wl.grid)
     dev = torch.device("cuda", 0)
