@@ -232,3 +232,108 @@ def noise_sigma(grid, medium, theta_bar, rel=1e-3, stf_kind="gauss_deriv"):
     all recorded levels, for the nominal solve at the prior mean."""
     tr = forward(grid, medium, theta_bar, surface_nodes(grid.nx), stf_kind)
     return rel * float(np.max(np.abs(tr)))
+
+
+# ---------------------------------------------------------------------------
+# Forward sensitivities (Algorithm 1, steps 1-3): solves driven by the
+# derivative of the discretised source with respect to each parameter.
+# ---------------------------------------------------------------------------
+# The regularised delta / delta' weights as polynomials in alpha: per node
+# offset -2..3 a printed base polynomial plus k_o times the common
+# polynomial (P for delta, R for delta'), k = (1, -5, 10, -10, 5, -1).
+_K = (1.0, -5.0, 10.0, -10.0, 5.0, -1.0)
+_D_BASE = ((0, 1 / 12, -1 / 24, -1 / 12, -19 / 24), (0, -2 / 3, 2 / 3, 1 / 6, 4),
+           (1, 0, -5 / 4, 0, -97 / 12), (0, 2 / 3, 2 / 3, -1 / 6, 49 / 6),
+           (0, -1 / 12, -1 / 24, 1 / 12, -33 / 8), (0, 0, 0, 0, 5 / 6))
+_D_COMMON = (0, 0, 0, 0, 0, 5 / 3, -7 / 24, -17 / 12, 9 / 8, -1 / 4)
+_DP_BASE = ((-1 / 12, 1 / 12, 1 / 4, 2 / 3), (2 / 3, -4 / 3, -1 / 2, -7 / 2),
+            (0, 5 / 2, 0, 22 / 3), (-2 / 3, -4 / 3, 1 / 2, -23 / 3),
+            (1 / 12, 1 / 12, -1 / 4, 4), (0, 0, 0, -5 / 6))
+_DP_COMMON = (0, 0, 0, 0, -25 / 12, -3 / 4, 59 / 12, -4, 1)
+
+
+def weight_polys():
+    """(delta polys times h, delta' polys times h^2), six numpy Polynomials
+    each, coefficients in increasing powers of alpha."""
+    P = np.polynomial.Polynomial
+    d = [P(b) + k * P(_D_COMMON) for b, k in zip(_D_BASE, _K)]
+    dp = [P(b) + k * P(_DP_COMMON) for b, k in zip(_DP_BASE, _K)]
+    return d, dp
+
+
+def dsource_window(theta: Sequence[float], h: float, j: int):
+    """Derivative of the spatial source window with respect to x_s (j = 0)
+    or z_s (j = 1): d/dx_s = (1/h) d/dalpha on that axis."""
+    d_polys, dp_polys = weight_polys()
+    xs, zs = theta[0], theta[1]
+    mxx, mxz, mzz = theta[4], theta[5], theta[6]
+    kx, ax = locate(xs, h)
+    kz, az = locate(zs, h)
+    ev = lambda ps, a, der: np.array([(p.deriv() if der else p)(a) for p in ps])  # noqa: E731
+    dx, dpx = ev(d_polys, ax, j == 0) / h, ev(dp_polys, ax, j == 0) / h**2
+    dz, dpz = ev(d_polys, az, j == 1) / h, ev(dp_polys, az, j == 1) / h**2
+    if j == 0:
+        dx, dpx = dx / h, dpx / h
+    else:
+        dz, dpz = dz / h, dpz / h
+    gx = np.outer(dz, dpx)
+    gz = np.outer(dpz, dx)
+    W = np.empty((2, 6, 6))
+    W[0] = mxx * gx + mxz * gz
+    W[1] = mxz * gx + mzz * gz
+    return kx - 2, kz - 2, W
+
+
+def dstf(t, t0: float, p: float, kind: str, wrt: str):
+    """Analytic derivative of stf with respect to t0 (wrt='t0') or to the
+    frequency parameter (wrt='p')."""
+    t = np.asarray(t, dtype=np.float64)
+    tau = t - t0
+    c = 1.0 / math.sqrt(2 * math.pi)
+    if kind == "gauss":
+        w = p
+        e = np.exp(-0.5 * w * w * tau * tau)
+        if wrt == "t0":
+            return c * w**3 * tau * e
+        return c * e * (1.0 - w * w * tau * tau)
+    if kind == "gauss_deriv":
+        w = 2 * math.pi * p
+        e = np.exp(-0.5 * w * w * tau * tau)
+        if wrt == "t0":
+            return c * w * e * (w**2 - w**4 * tau * tau)
+        # d/df = 2 pi d/domega of -c w^3 tau e
+        return 2 * math.pi * c * e * (-3 * w**2 * tau + w**4 * tau**3)
+    raise ValueError(kind)
+
+
+def sensitivity_term(grid, theta, j, stf_kind):
+    """Forcing d F / d theta_j as one separable term (window, series)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    t = np.arange(grid.nsteps) * grid.dt
+    if j in (0, 1):
+        i0, k0, W = dsource_window(theta, grid.h, j)
+        S = stf(t, theta[2], theta[3], stf_kind)
+    elif j in (2, 3):
+        i0, k0, W = source_window(theta, grid.h)
+        S = dstf(t, theta[2], theta[3], stf_kind, "t0" if j == 2 else "p")
+    else:
+        unit = theta.copy()
+        unit[4:] = 0.0
+        unit[j] = 1.0
+        i0, k0, W = source_window(unit, grid.h)
+        S = stf(t, theta[2], theta[3], stf_kind)
+    _check_window(i0, k0, grid.nx, grid.nz)
+    return (i0, k0, W, S)
+
+
+def jacobian_sensitivity(grid, medium, theta, receivers, stf_kind="gauss_deriv"):
+    """Receiver Jacobian from 7 sensitivity solves: column j is the solve
+    driven by dF/dtheta_j (the discrete scheme is linear in the forcing).
+    Returns (nominal traces, J[nsteps+1][nrec][2][7])."""
+    theta = np.asarray(theta, dtype=np.float64)
+    nominal = forward(grid, medium, theta, receivers, stf_kind)
+    J = np.empty(nominal.shape + (NTHETA,))
+    for j in range(NTHETA):
+        J[..., j] = solve_terms(grid, medium, [sensitivity_term(grid, theta, j, stf_kind)],
+                                receivers)
+    return nominal, J

@@ -131,3 +131,22 @@ def test_scaling_moments_adds_four_log_c(small):
         _, J = elastic.jacobian_literal(grid, med, th, rec)
         v.append(laplace.dkl_hat(laplace.hessian_h1(J, 0.1), th, prior)[0])
     assert abs(v[1] - v[0] - 4 * math.log(c)) < 1e-7
+
+
+def test_sensitivity_jacobian_matches_central_differences(small):
+    # Algorithm 1 steps 1-3 (solves driven by dF/dtheta_j) against the
+    # central differences: equal up to the O(d^2) truncation of the latter
+    grid, med, rec, theta = small
+    nom_s, Js = elastic.jacobian_sensitivity(grid, med, theta, rec)
+    nom_c, Jc = elastic.jacobian_literal(grid, med, theta, rec, rel_step=1e-4)
+    _, Jc2 = elastic.jacobian_literal(grid, med, theta, rec, rel_step=5e-5)
+    assert np.array_equal(nom_s, nom_c)
+    for j in range(7):
+        n = np.linalg.norm(Js[..., j])
+        e1 = np.linalg.norm(Js[..., j] - Jc[..., j]) / n
+        e2 = np.linalg.norm(Js[..., j] - Jc2[..., j]) / n
+        assert e2 < 2e-6, (j, e2)
+        if j < 4:   # nonlinear parameters: the gap is the O(d^2) truncation
+            assert 3.5 < e1 / e2 < 4.5, (j, e1, e2)
+        else:       # linear in the moments: exact up to rounding
+            assert e2 < 1e-9, (j, e2)

@@ -85,3 +85,39 @@ def test_gauss_wavelet_closed_forms():
     G = elastic.stf(t, t0, 2 * math.pi * f, "gauss")
     num = np.gradient(G, t, edge_order=2)
     assert np.max(np.abs(gd - num)) < 1e-4 * np.max(np.abs(gd))
+
+
+def test_weight_polynomial_tables_equal_printed_formulas():
+    d_polys, dp_polys = elastic.weight_polys()
+    for a in np.linspace(0, 0.999, 23):
+        assert np.max(np.abs(np.array([p(a) for p in d_polys]) - elastic.delta_1d(a, 1.0))) < 1e-14
+        assert np.max(np.abs(np.array([p(a) for p in dp_polys]) - elastic.ddelta_1d(a, 1.0))) < 1e-14
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.13, 0.5, 0.77, 0.999])
+def test_weight_derivatives_by_differentiated_moments(alpha):
+    # d/dx_s of sum_j w_j(x_s) (x_j - x_s)^p h = const gives
+    # sum_j w_j' (x_j - x_s)^p h = p sum_j w_j (x_j - x_s)^(p-1) h
+    d_polys, dp_polys = elastic.weight_polys()
+    xs_rel = (np.arange(-2, 4) - alpha) * H
+    for polys, scale in ((d_polys, 1 / H), (dp_polys, 1 / H**2)):
+        w = np.array([p(alpha) for p in polys]) * scale
+        dw = np.array([p.deriv()(alpha) for p in polys]) * scale / H   # d/dx_s
+        for p in range(1, 5):
+            lhs = H * np.sum(dw * xs_rel**p)
+            rhs = p * H * np.sum(w * xs_rel ** (p - 1))
+            assert abs(lhs - rhs) < 1e-10 * max(1.0, abs(rhs)), (p, lhs, rhs)
+        assert abs(H * np.sum(dw)) < 1e-10 * np.max(np.abs(dw)) * H
+
+
+@pytest.mark.parametrize("kind,p", [("gauss", 6.0), ("gauss_deriv", 7.5)])
+def test_wavelet_derivatives_match_differences(kind, p):
+    t = np.linspace(0, 1.2, 601)
+    t0 = 0.4
+    e = 1e-6
+    num_t0 = (elastic.stf(t, t0 + e, p, kind) - elastic.stf(t, t0 - e, p, kind)) / (2 * e)
+    num_p = (elastic.stf(t, t0, p + e, kind) - elastic.stf(t, t0, p - e, kind)) / (2 * e)
+    a_t0 = elastic.dstf(t, t0, p, kind, "t0")
+    a_p = elastic.dstf(t, t0, p, kind, "p")
+    assert np.max(np.abs(a_t0 - num_t0)) < 1e-6 * np.max(np.abs(a_t0))
+    assert np.max(np.abs(a_p - num_p)) < 1e-6 * np.max(np.abs(a_p))
