@@ -362,6 +362,28 @@ def main():
         "speedup_of_batched": value / (2 / t1),
         "dkl_match": bool(np.allclose(o1["dkl"].cpu().numpy(), dkl[:2], rtol=0, atol=0))}
     ctx1.close()
+    # the forward-sensitivity Jacobian (1 + 7 solves per sample) on the same query
+    print("[bench] forward-sensitivity Jacobian path (same samples)", flush=True)
+    sig = ctx.noise_sigma_peak(g, med, theta_bar, wl.noise_rel)
+    run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, wl.theta[:8], np.full(8, 1 / 8),
+              sigma=sig, jacobian="sensitivity")   # tunes the 8*S-solve bucket
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sig = ctx.noise_sigma_peak(g, med, theta_bar, wl.noise_rel)
+    os_ = run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, wl.theta, wl.weights,
+                    sigma=sig, jacobian="sensitivity")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ts = e0.elapsed_time(e1) / 1e3
+    line["sensitivity_path"] = {
+        "value": S / ts, "unit": "sample-EIG evals/s", "samples": S,
+        "solves_per_step": 8 * S + 1, "ms_per_step": ts * 1e3,
+        "speedup_over_central_differences": (S / ts) / value,
+        "eig_nats": float(os_["eig"].cpu()[0]),
+        "max_abs_dkl_diff_vs_central_differences":
+            float(np.max(np.abs(os_["dkl"].cpu().numpy() - dkl))),
+        "status_ok": int(os_["status"].abs().sum()) == 0}
     if not args.no_serving:
         print("[bench] serving run (continuous batching, Poisson arrivals)", flush=True)
         line["serving"] = _serving(ctx, line["grid_pt_updates_per_s"])

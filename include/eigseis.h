@@ -202,6 +202,30 @@ int jacobian_fd(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
                 double* const* J, double* H1, int32_t* status, void* stream);
 
 /*
+ * jacobian_sensitivity — the forward-sensitivity form of the same quantity
+ * (Algorithm 1, steps 1-5; the remark of Section 3.3.2 that H_I needs only
+ * N_theta primal solves): for each sample 1 nominal solve plus, for every
+ * parameter j, one solve whose forcing is dF/dtheta_j, the exact derivative of
+ * the discretised point source f = S(t) M grad(delta):
+ *   x_s, z_s: S(t) M grad(d delta/dx_s) from the differentiated regularised
+ *             delta/delta' weights (Section 3.3.2, item 2), FP64 tables;
+ *   t_0, f:   dS/dt_0, dS/df of the wavelet times M grad(delta);
+ *   M_j:      S(t) E_j grad(delta) with the unit symmetric tensor E_j.
+ * By linearity of the discrete solve in its forcing, each such solve's traces
+ * are the column J_j itself (no step size, no truncation error), and H_1 is
+ * assembled exactly as in jacobian_fd.  8 solves per sample instead of 15.
+ *
+ * Arguments, layouts, ownership and errors are those of jacobian_fd without
+ * rel_step, except that theta entries may be zero (no relative step is
+ * taken); the source's 6x6 stencil must avoid the rigid nodes.
+ */
+int jacobian_sensitivity(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
+                         const eig_medium* medium, const double* theta, int32_t stf_kind,
+                         const eig_receivers* rec, int32_t sigma_mode, const double* sigma,
+                         int32_t per_receiver, float* const* nominal, double* const* J,
+                         double* H1, int32_t* status, void* stream);
+
+/*
  * laplace_eig — Theorem 4 with the scaled Hessian of Section 3.3.3:
  *   S = sqrt(diag H_1),  H~ = S^-1 H_1 S^-1 = L L^T,
  *   log det H_1 = 2 sum log L_ii + 2 sum log S_ii,

@@ -1,7 +1,7 @@
 """Oracle composition of one design query (TEST INFRASTRUCTURE ONLY).
 
 Per prior sample: 1 nominal + 2*7 perturbed solves -> central-difference
-Jacobian -> H_1 -> D^_KL; then the weighted average over samples
+Jacobian (or 1 + 7 forward-sensitivity solves, Algorithm 1) -> H_1 -> D^_KL; then the weighted average over samples
 (Theorem 4 with the Monte Carlo or sparse-quadrature rule of Section 3.3.4).
 """
 from __future__ import annotations
@@ -19,9 +19,15 @@ def default_threads() -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
 
-def sample_terms(wl, theta, sigma, per_receiver=False):
-    nominal, J = elastic.jacobian_literal(wl.grid, wl.medium, theta, wl.receivers,
-                                          wl.rel_step, wl.stf)
+def sample_terms(wl, theta, sigma, per_receiver=False, jacobian="fd"):
+    if jacobian == "fd":
+        nominal, J = elastic.jacobian_literal(wl.grid, wl.medium, theta, wl.receivers,
+                                              wl.rel_step, wl.stf)
+    elif jacobian == "sensitivity":
+        nominal, J = elastic.jacobian_sensitivity(wl.grid, wl.medium, theta, wl.receivers,
+                                                  wl.stf)
+    else:
+        raise ValueError(jacobian)
     if per_receiver:
         H = laplace.hessian_h1_per_receiver(J, sigma)
     else:
@@ -30,7 +36,8 @@ def sample_terms(wl, theta, sigma, per_receiver=False):
 
 
 def query(wl, theta=None, weights=None, sigma: Optional[float] = None,
-          per_receiver=False, threads: Optional[int] = None, keep_J=False):
+          per_receiver=False, threads: Optional[int] = None, keep_J=False,
+          jacobian="fd"):
     """Runs the whole path for one workload query.  Returns a dict with sigma,
     nominal traces, (J), H1 [S][7][7] (or [S][R][7][7]), dkl [S], eig."""
     theta = wl.theta if theta is None else np.asarray(theta)
@@ -41,7 +48,7 @@ def query(wl, theta=None, weights=None, sigma: Optional[float] = None,
     prior = laplace.uniform_prior(wl.lo, wl.hi)
     nthr = threads or default_threads()
     with ThreadPoolExecutor(nthr) as pool:
-        res = list(pool.map(lambda th: sample_terms(wl, th, sigma, per_receiver),
+        res = list(pool.map(lambda th: sample_terms(wl, th, sigma, per_receiver, jacobian),
                             list(theta)))
     H = np.stack([r[2] for r in res])
     Htot = H.sum(axis=1) if per_receiver else H

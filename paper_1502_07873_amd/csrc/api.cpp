@@ -208,11 +208,12 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         J.h = g.h;
         J.dt = g.dt;
         J.param = sp.param;
+        J.deriv = sp.deriv;
         J.kx = floor_cell(sp.theta[0], g.h);
         J.kz = floor_cell(sp.theta[1], g.h);
         double tp[kNT];
         std::memcpy(tp, sp.theta, sizeof(tp));
-        if (sp.param >= 0) tp[sp.param] = sp.theta[sp.param] + sp.step;
+        if (sp.param >= 0 && !sp.deriv) tp[sp.param] = sp.theta[sp.param] + sp.step;
         J.kx2 = floor_cell(tp[0], g.h);
         J.kz2 = floor_cell(tp[1], g.h);
         J.i0 = std::min(J.kx, J.kx2) - 2;
@@ -616,18 +617,23 @@ int forward_solve_batch(eig_ctx* c, int32_t nsolve, const eig_grid* grid,
     return EIG_OK;
 }
 
-int jacobian_fd(eig_ctx* c, int32_t nsample, const eig_grid* grid,
-                const eig_medium* medium, const double* theta, double rel_step,
-                int32_t stf_kind, const eig_receivers* rec, int32_t sigma_mode,
-                const double* sigma, int32_t per_receiver, float* const* nominal,
-                double* const* J, double* H1, int32_t* status, void* stream) {
+// Jacobian columns of every sample and H_1, either from 2*7 central-difference
+// deviation solves (sensitivity == 0) or from 7 solves driven by dF/dtheta_j
+// (sensitivity == 1); both share waves, tables, checks and the Hessian pass.
+static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
+                         const eig_medium* medium, const double* theta, double rel_step,
+                         int sensitivity, int32_t stf_kind, const eig_receivers* rec,
+                         int32_t sigma_mode, const double* sigma, int32_t per_receiver,
+                         float* const* nominal, double* const* J, double* H1,
+                         int32_t* status, void* stream) {
     if (!c) return set_error(EIG_EINVAL, "ctx is NULL");
     if (nsample < 0) return set_error(EIG_EINVAL, "nsample < 0");
     if (nsample == 0) return EIG_OK;
     if (!grid || !medium || !theta || !rec || !sigma || !H1)
         return set_error(EIG_EINVAL, "NULL array argument");
-    if (!(rel_step > 0) || !std::isfinite(rel_step) || rel_step > 0.1)
+    if (!sensitivity && (!(rel_step > 0) || !std::isfinite(rel_step) || rel_step > 0.1))
         return set_error(EIG_EINVAL, "rel_step must be in (0, 0.1]");
+    const int per = sensitivity ? 1 + kNT : 1 + 2 * kNT;  // solves per sample
     if (stf_kind != EIG_STF_GAUSS && stf_kind != EIG_STF_GAUSS_DERIV)
         return set_error(EIG_EINVAL, "stf_kind");
     if (sigma_mode != EIG_SIGMA_GIVEN && sigma_mode != EIG_SIGMA_NOMINAL_PEAK)
@@ -649,10 +655,12 @@ int jacobian_fd(eig_ctx* c, int32_t nsample, const eig_grid* grid,
             return set_error(EIG_EINVAL, "sigma must be positive");
         const double* th = theta + (size_t)i * kNT;
         for (int j = 0; j < kNT; ++j) {
-            if (!std::isfinite(th[j]) || th[j] == 0.0)
+            if (!std::isfinite(th[j]) || (!sensitivity && th[j] == 0.0))
                 return set_error(EIG_EINVAL, "theta entries must be finite and nonzero");
         }
-        for (int j = 0; j < 2; ++j)
+        if (sensitivity && !source_inside(th[0], th[1], g))
+            return set_error(EIG_EINVAL, "source stencil touches a rigid node");
+        for (int j = 0; j < 2 && !sensitivity; ++j)
             for (int sg = -1; sg <= 1; ++sg) {
                 double x = th[0], z = th[1];
                 const double d = rel_step * std::fabs(th[j]);
@@ -681,9 +689,9 @@ int jacobian_fd(eig_ctx* c, int32_t nsample, const eig_grid* grid,
         }
     }
     const int ngroup = per_receiver ? nrec0 : 1;
-    // bytes of one sample beyond its solves: 15 trace arrays + descriptors
+    // bytes of one sample beyond its solves: one trace array per solve + descriptors
     auto sample_trace_bytes = [&](int i) {
-        return 15 * align_up((size_t)(grid[i].nsteps + 1) * rec[i].n * sizeof(float2));
+        return per * align_up((size_t)(grid[i].nsteps + 1) * rec[i].n * sizeof(float2));
     };
     int s0 = 0;
     while (s0 < nsample) {
@@ -698,10 +706,10 @@ int jacobian_fd(eig_ctx* c, int32_t nsample, const eig_grid* grid,
             sp.medium = med_of[s1];
             sp.recset = rec_of[s1];
             const size_t one = wsz.cost(sp);
-            const size_t more = 15 * one + sample_trace_bytes(s1) + sizeof(SampleDesc) +
+            const size_t more = per * one + sample_trace_bytes(s1) + sizeof(SampleDesc) +
                                 3 * kAlign + 2 * sizeof(double);
             if (s1 > s0 && wsz.bytes + extra + more > c->budget) break;
-            for (int q = 0; q < 15; ++q) wsz.add(sp);
+            for (int q = 0; q < per; ++q) wsz.add(sp);
             extra += sample_trace_bytes(s1) + sizeof(SampleDesc) + 3 * kAlign + 2 * sizeof(double);
             need = wsz.bytes + extra;
             ++s1;
@@ -711,9 +719,9 @@ int jacobian_fd(eig_ctx* c, int32_t nsample, const eig_grid* grid,
         // carve: [traces | sample descs | sigma given | sigma | solve region]
         Carve cv;
         const int ns = s1 - s0;
-        std::vector<std::array<size_t, 15>> toff(ns);
+        std::vector<std::array<size_t, 1 + 2 * kNT>> toff(ns);
         for (int q = 0; q < ns; ++q)
-            for (int k = 0; k < 15; ++k)
+            for (int k = 0; k < per; ++k)
                 toff[q][k] = cv.take((size_t)(grid[s0 + q].nsteps + 1) * rec[s0 + q].n * sizeof(float2));
         const size_t o_sd = cv.take(ns * sizeof(SampleDesc));
         const size_t o_given = cv.take(ns * sizeof(double));
@@ -742,7 +750,16 @@ int jacobian_fd(eig_ctx* c, int32_t nsample, const eig_grid* grid,
             sp.step = 0.0;
             sp.traces = nom;
             solves.push_back(sp);
-            for (int j = 0; j < kNT; ++j) {
+            for (int j = 0; j < kNT && sensitivity; ++j) {
+                SolveSpec pj = sp;
+                pj.param = j;
+                pj.deriv = 1;
+                pj.traces = (float2*)(c->ws + toff[q][1 + j]);
+                sd.dev[2 * j] = pj.traces;  // dev[2j+1] stays NULL: direct column
+                sd.inv2d[j] = 1.0;
+                solves.push_back(pj);
+            }
+            for (int j = 0; j < kNT && !sensitivity; ++j) {
                 const double d = rel_step * std::fabs(th[j]);
                 sd.inv2d[j] = 1.0 / (2.0 * d);
                 for (int sg = 0; sg < 2; ++sg) {
@@ -777,6 +794,24 @@ int jacobian_fd(eig_ctx* c, int32_t nsample, const eig_grid* grid,
         s0 = s1;
     }
     return EIG_OK;
+}
+
+int jacobian_fd(eig_ctx* c, int32_t nsample, const eig_grid* grid,
+                const eig_medium* medium, const double* theta, double rel_step,
+                int32_t stf_kind, const eig_receivers* rec, int32_t sigma_mode,
+                const double* sigma, int32_t per_receiver, float* const* nominal,
+                double* const* J, double* H1, int32_t* status, void* stream) {
+    return jacobian_core(c, nsample, grid, medium, theta, rel_step, 0, stf_kind, rec,
+                         sigma_mode, sigma, per_receiver, nominal, J, H1, status, stream);
+}
+
+int jacobian_sensitivity(eig_ctx* c, int32_t nsample, const eig_grid* grid,
+                         const eig_medium* medium, const double* theta, int32_t stf_kind,
+                         const eig_receivers* rec, int32_t sigma_mode, const double* sigma,
+                         int32_t per_receiver, float* const* nominal, double* const* J,
+                         double* H1, int32_t* status, void* stream) {
+    return jacobian_core(c, nsample, grid, medium, theta, 0.0, 1, stf_kind, rec, sigma_mode,
+                         sigma, per_receiver, nominal, J, H1, status, stream);
 }
 
 static int upload_small(eig_ctx* c, size_t off, const void* p, size_t bytes, hipStream_t s) {

@@ -2,7 +2,9 @@
 //
 // From the 14 deviation solves of a sample (traces of g(theta +- d_j e_j) -
 // g(theta), FP32) the central differences J_j = (w+_j - w-_j) / (2 d_j) are
-// formed in FP64 and H_1 = sigma^-2 sum_{m,r,c} J^T J accumulated (paper
+// formed in FP64 (or, from the 7 sensitivity solves of Algorithm 1, the
+// traces are the columns J_j themselves), and H_1 = sigma^-2 sum_{m,r,c}
+// J^T J accumulated (paper
 // Theorem 2, H_1 with C_eps = sigma^2 I; Section 3.3.2, H_I, whose
 // receiver-selection Hessian is diagonal).  Every thread owns a fixed subset
 // of the (level, receiver) pairs and the 28 distinct products are reduced
@@ -37,7 +39,7 @@ __global__ void sample_check_kernel(const SampleDesc* __restrict__ samples,
         mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
     for (int j = 0; j < 2 * kNT && !bad; ++j)
-        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        for (int e = threadIdx.x; e < n && sd.dev[j]; e += blockDim.x) {
             const float2 v = sd.dev[j][e];
             if (!isfinite(v.x) || !isfinite(v.y)) { bad = 1; break; }
         }
@@ -76,9 +78,14 @@ hessian_kernel(const SampleDesc* __restrict__ samples, int per_receiver,
         double Jx[kNT], Jz[kNT];
         for (int j = 0; j < kNT; ++j) {
             const float2 p = sd.dev[2 * j][e];
-            const float2 n = sd.dev[2 * j + 1][e];
-            Jx[j] = ((double)p.x - (double)n.x) * inv2d[j];
-            Jz[j] = ((double)p.y - (double)n.y) * inv2d[j];
+            if (sd.dev[2 * j + 1]) {
+                const float2 n = sd.dev[2 * j + 1][e];
+                Jx[j] = ((double)p.x - (double)n.x) * inv2d[j];
+                Jz[j] = ((double)p.y - (double)n.y) * inv2d[j];
+            } else {  // sensitivity solve: the traces are the column itself
+                Jx[j] = (double)p.x;
+                Jz[j] = (double)p.y;
+            }
         }
         if (sd.J) {
             double* o = sd.J + (size_t)e * 2 * kNT;

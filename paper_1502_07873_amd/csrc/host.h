@@ -162,6 +162,7 @@ struct SolveSpec {
     double theta[kNT];
     int param;     // -1 nominal
     double step;
+    int deriv;     // 1: forcing dF/dtheta_param (sensitivity solve)
     int stf;
     float2* traces;  // destination (device)
 };

@@ -67,13 +67,15 @@ struct SourceJob {
     int32_t i0, k0;          // window corner
     int32_t nsteps;
     int32_t stf;
+    int32_t deriv;           // 1: forcing dF/dtheta_param instead of a difference
     float* srcw;
     float* srcs;
 };
 
 // Per-sample inputs of the Jacobian / Hessian assembly.
 struct SampleDesc {
-    const float2* dev[2 * kNT];  // deviation traces: +d_j at 2j, -d_j at 2j+1
+    const float2* dev[2 * kNT];  // deviation traces: +d_j at 2j, -d_j at 2j+1;
+                                 // sensitivity traces at 2j with 2j+1 NULL
     const float2* nominal;
     double inv2d[kNT];           // 1 / (2 d_j)
     double* J;                   // optional output [nt][nrec][2][7]

@@ -45,6 +45,56 @@ __device__ double ddelta_w(double a, int o) {
     }
 }
 
+// d/dalpha of the delta weights (times h).
+__device__ double delta_w_da(double a, int o) {
+    const double a2 = a * a, a3 = a2 * a;
+    const double Pd = a3 * a * (25.0 / 3.0 + a * (-7.0 / 4.0 + a * (-119.0 / 12.0 + a * (9.0 - 9.0 * a / 4.0))));
+    switch (o) {
+        case -2: return 1.0 / 12.0 - a / 12.0 - a2 / 4.0 - 19.0 * a3 / 6.0 + Pd;
+        case -1: return -2.0 / 3.0 + 4.0 * a / 3.0 + a2 / 2.0 + 16.0 * a3 - 5.0 * Pd;
+        case 0: return -5.0 * a / 2.0 - 97.0 * a3 / 3.0 + 10.0 * Pd;
+        case 1: return 2.0 / 3.0 + 4.0 * a / 3.0 - a2 / 2.0 + 98.0 * a3 / 3.0 - 10.0 * Pd;
+        case 2: return -1.0 / 12.0 - a / 12.0 + a2 / 4.0 - 33.0 * a3 / 2.0 + 5.0 * Pd;
+        case 3: return 10.0 * a3 / 3.0 - Pd;
+        default: return 0.0;
+    }
+}
+
+// d/dalpha of the delta' weights (times h^2).
+__device__ double ddelta_w_da(double a, int o) {
+    const double a2 = a * a, a3 = a2 * a;
+    const double Rd = a3 * (-25.0 / 3.0 + a * (-15.0 / 4.0 + a * (59.0 / 2.0 + a * (-28.0 + 8.0 * a))));
+    switch (o) {
+        case -2: return 1.0 / 12.0 + a / 2.0 + 2.0 * a2 + Rd;
+        case -1: return -4.0 / 3.0 - a - 21.0 * a2 / 2.0 - 5.0 * Rd;
+        case 0: return 5.0 / 2.0 + 22.0 * a2 + 10.0 * Rd;
+        case 1: return -4.0 / 3.0 + a - 23.0 * a2 - 10.0 * Rd;
+        case 2: return 1.0 / 12.0 - a / 2.0 + 12.0 * a2 + 5.0 * Rd;
+        case 3: return -5.0 * a2 / 2.0 - Rd;
+        default: return 0.0;
+    }
+}
+
+// d/dx_s (axis 0) or d/dz_s (axis 1) of source_weight: on that axis the
+// weights are differentiated in alpha and divided by h.
+__device__ double dsource_weight(const double* th, int kx, int kz, double h, int ic, int kr,
+                                 int c, int axis) {
+    const int ox = ic - kx, oz = kr - kz;
+    if (ox < -2 || ox > 3 || oz < -2 || oz > 3) return 0.0;
+    const double ax = th[0] / h - kx, az = th[1] / h - kz;
+    double dx = delta_w(ax, ox) / h, dpx = ddelta_w(ax, ox) / (h * h);
+    double dz = delta_w(az, oz) / h, dpz = ddelta_w(az, oz) / (h * h);
+    if (axis == 0) {
+        dx = delta_w_da(ax, ox) / (h * h);
+        dpx = ddelta_w_da(ax, ox) / (h * h * h);
+    } else {
+        dz = delta_w_da(az, oz) / (h * h);
+        dpz = ddelta_w_da(az, oz) / (h * h * h);
+    }
+    const double gx = dpx * dz, gz = dx * dpz;
+    return c == 0 ? th[4] * gx + th[5] * gz : th[5] * gx + th[6] * gz;
+}
+
 // Force density on node (ic, kr), component c, of the source theta whose
 // cell is (kx, kz): M grad(delta) with grad(delta) = (delta'(x) delta(z),
 // delta(x) delta'(z)).
@@ -69,6 +119,21 @@ __device__ double wavelet(int kind, double t, double t0, double p) {
     return -w * w * (t - t0) * g;
 }
 
+// d/dt0 (wrt 0) or d/d(frequency parameter) (wrt 1) of the wavelet.
+__device__ double dwavelet(int kind, double t, double t0, double p, int wrt) {
+    const double tau = t - t0;
+    const double c = 1.0 / sqrt(2.0 * M_PI);
+    if (kind == EIG_STF_GAUSS) {
+        const double w = p;
+        const double e = exp(-0.5 * w * w * tau * tau);
+        return wrt == 0 ? c * w * w * w * tau * e : c * e * (1.0 - w * w * tau * tau);
+    }
+    const double w = 2.0 * M_PI * p;
+    const double e = exp(-0.5 * w * w * tau * tau);
+    if (wrt == 0) return c * w * e * (w * w - w * w * w * w * tau * tau);
+    return 2.0 * M_PI * c * e * (-3.0 * w * w * tau + w * w * w * w * tau * tau * tau);
+}
+
 __global__ void source_kernel(const SourceJob* __restrict__ jobs) {
     const SourceJob& J = jobs[blockIdx.x];
     double th[kNT], tp[kNT];
@@ -76,6 +141,32 @@ __global__ void source_kernel(const SourceJob* __restrict__ jobs) {
     if (J.param >= 0) tp[J.param] = J.theta[J.param] + J.step;
     const bool spatial = (J.param == 0 || J.param == 1 || J.param >= 4);
     const bool temporal = (J.param == 2 || J.param == 3);
+    if (J.deriv) {
+        // sensitivity forcing dF/dtheta_param (Algorithm 1, step 2)
+        double tu[kNT];
+        for (int j = 0; j < kNT; ++j) tu[j] = th[j];
+        if (J.param >= 4) {
+            tu[4] = tu[5] = tu[6] = 0.0;
+            tu[J.param] = 1.0;
+        }
+        for (int e = threadIdx.x; e < 2 * kSrcW * kSrcW; e += blockDim.x) {
+            const int c = e / (kSrcW * kSrcW);
+            const int kk = (e / kSrcW) % kSrcW;
+            const int ii = e % kSrcW;
+            const int ic = J.i0 + ii, kr = J.k0 + kk;
+            const double w = (J.param == 0 || J.param == 1)
+                                 ? dsource_weight(th, J.kx, J.kz, J.h, ic, kr, c, J.param)
+                                 : source_weight(tu, J.kx, J.kz, J.h, ic, kr, c);
+            J.srcw[e] = (float)w;
+        }
+        for (int m = threadIdx.x; m < J.nsteps; m += blockDim.x) {
+            const double t = m * J.dt;
+            const double S = temporal ? dwavelet(J.stf, t, th[2], th[3], J.param - 2)
+                                      : wavelet(J.stf, t, th[2], th[3]);
+            J.srcs[m] = (float)S;
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < 2 * kSrcW * kSrcW; e += blockDim.x) {
         const int c = e / (kSrcW * kSrcW);
         const int kk = (e / kSrcW) % kSrcW;

@@ -81,6 +81,8 @@ def _load():
         "forward_solve_batch": ([vp, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "jacobian_fd": ([vp, i32, vp, vp, vp, dbl, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp],
                         ctypes.c_int),
+        "jacobian_sensitivity": ([vp, i32, vp, vp, vp, i32, vp, i32, vp, i32, vp, vp, vp,
+                                  vp, vp], ctypes.c_int),
         "laplace_eig": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "design_eval": ([vp, i32, i32, vp, i32, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "design_greedy": ([vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
@@ -104,8 +106,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("eig_ctx_create", "eig_ctx_destroy", "eig_last_error", "eig_ctx_workspace_bytes",
             "eig_ctx_stencil_stats", "eig_ctx_set_option", "eig_ctx_get_option",
-            "forward_solve_batch", "jacobian_fd", "laplace_eig", "design_eval",
-            "design_greedy", "noise_sigma_peak", "sparse_grid_gl", "eig_server_create",
+            "forward_solve_batch", "jacobian_fd", "jacobian_sensitivity", "laplace_eig",
+            "design_eval", "design_greedy", "noise_sigma_peak", "sparse_grid_gl", "eig_server_create",
             "eig_server_destroy", "eig_server_submit", "eig_server_step", "eig_server_poll",
             "eig_server_pending")
 
@@ -280,6 +282,19 @@ class Context:
             float(rel_step), STF_KINDS[stf], recs, int(sigma_mode), _np_ptr(sg),
             1 if per_receiver else 0, _ptr_array(nominal), _ptr_array(J), _ptr(H1),
             _ptr(status), _stream(stream)))
+        del keep
+
+    def jacobian_sensitivity(self, grids, media, theta, receivers, sigma, H1,
+                             stf="gauss_deriv", sigma_mode=SIGMA_GIVEN, per_receiver=False,
+                             nominal=None, J=None, status=None, stream=None):
+        n = len(grids)
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(n, NTHETA)
+        sg = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (n,)))
+        recs, keep = self._receivers(receivers)
+        _check(_lib.jacobian_sensitivity(
+            self._h, n, self._grids(grids), self._media(media), _np_ptr(th),
+            STF_KINDS[stf], recs, int(sigma_mode), _np_ptr(sg), 1 if per_receiver else 0,
+            _ptr_array(nominal), _ptr_array(J), _ptr(H1), _ptr(status), _stream(stream)))
         del keep
 
     def laplace_eig(self, H1, prior: Prior, w, dkl, eig, theta=None, logdet=None,

@@ -1,7 +1,7 @@
 """One design query through the C ABI (marshalling only).
 
 sigma (noise_sigma_peak at the prior mean) -> jacobian_fd (1 + 2*7 solves per
-sample, J, H_1) -> laplace_eig (scaled log-det, D^_KL, weighted average), or
+sample, J, H_1) or jacobian_sensitivity (1 + 7 solves) -> laplace_eig (scaled log-det, D^_KL, weighted average), or
 design_eval / design_greedy on per-receiver Hessians.
 """
 from __future__ import annotations
@@ -25,7 +25,8 @@ def grid_tuple(g):
 
 def run_query(ctx: eigseis.Context, grid, medium, receivers, lo, hi, theta, weights,
               stf="gauss_deriv", rel_step=1e-4, noise_rel=1e-3, sigma=None,
-              per_receiver=False, keep_nominal=False, keep_J=False, stream=None):
+              per_receiver=False, keep_nominal=False, keep_J=False, stream=None,
+              jacobian="fd"):
     """Returns a dict of device tensors: H1, dkl, eig, status (and sigma)."""
     dev = torch.device("cuda", ctx.device)
     theta = np.ascontiguousarray(theta, dtype=np.float64)
@@ -42,9 +43,16 @@ def run_query(ctx: eigseis.Context, grid, medium, receivers, lo, hi, theta, weig
                 for _ in range(S)] if keep_nominal else None)
     J = ([torch.empty((g[4] + 1, R, 2, 7), dtype=torch.float64, device=dev)
           for _ in range(S)] if keep_J else None)
-    ctx.jacobian_fd([g] * S, [medium] * S, theta, [receivers] * S, sigma, H1,
-                    rel_step=rel_step, stf=stf, per_receiver=per_receiver,
-                    nominal=nominal, J=J, status=status, stream=stream)
+    if jacobian == "fd":
+        ctx.jacobian_fd([g] * S, [medium] * S, theta, [receivers] * S, sigma, H1,
+                        rel_step=rel_step, stf=stf, per_receiver=per_receiver,
+                        nominal=nominal, J=J, status=status, stream=stream)
+    elif jacobian == "sensitivity":
+        ctx.jacobian_sensitivity([g] * S, [medium] * S, theta, [receivers] * S, sigma, H1,
+                                 stf=stf, per_receiver=per_receiver, nominal=nominal, J=J,
+                                 status=status, stream=stream)
+    else:
+        raise ValueError(f"jacobian must be 'fd' or 'sensitivity', not {jacobian!r}")
     out = {"sigma": sigma, "H1": H1, "status": status}
     if nominal is not None:
         out["nominal"] = nominal

@@ -132,6 +132,113 @@ def test_jacobian_hessian_eig_c1(ctx):
     assert abs(float(out["eig"].cpu()[0]) - ref["eig"]) <= NAT_TOL
 
 
+SENS_TOL = 1e-4   # one FP32 solve per column, no difference taken
+
+
+def test_sensitivity_jacobian_hessian_eig_c1(ctx):
+    # Algorithm 1 steps 1-5 on the GPU vs the oracle's sensitivity solves
+    from paper_1502_07873_amd.query import grid_tuple, run_query
+    wl = synthetic.config("c1")[0]
+    _say("sensitivity jacobian/H1/eig c1")
+    ref = opipe.query(wl, keep_J=True, jacobian="sensitivity")
+    out = run_query(ctx, grid_tuple(wl.grid), _dev_medium(wl.medium), wl.receivers,
+                    wl.lo, wl.hi, wl.theta, wl.weights, sigma=ref["sigma"],
+                    keep_nominal=True, keep_J=True, jacobian="sensitivity")
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().sum()) == 0
+    worst = 0.0
+    for s in range(len(wl.theta)):
+        assert _relerr(out["nominal"][s].cpu().numpy(), ref["nominal"][s]) <= TRACE_TOL
+        Jg = out["J"][s].cpu().numpy()
+        for j in range(7):
+            e = _relerr(Jg[..., j], ref["J"][s][..., j])
+            worst = max(worst, e)
+            assert e <= SENS_TOL, (s, j, e)
+    _say(f"  worst column rel err {worst:.3e}")
+    H = out["H1"].cpu().numpy()
+    relH = np.max(np.abs(H - ref["H1"]) / np.sqrt(np.abs(np.einsum("sii,sjj->sij",
+                                                                   ref["H1"], ref["H1"]))))
+    assert relH < 1e-4
+    dkl = out["dkl"].cpu().numpy()
+    assert np.max(np.abs(dkl - ref["dkl"])) <= NAT_TOL, np.abs(dkl - ref["dkl"])
+    assert abs(float(out["eig"].cpu()[0]) - ref["eig"]) <= NAT_TOL
+
+
+@pytest.mark.parametrize("case", ["nodal_gauss", "layered_per_receiver"])
+def test_sensitivity_ragged(ctx, case):
+    # uneven grids in one call, zero moment entries (allowed here), sources on
+    # cell boundaries; per-receiver Hessians sum to the full one
+    from paper_1502_07873_amd.query import grid_tuple
+    _say(f"sensitivity ragged {case}")
+    rng = np.random.default_rng(11)
+    shapes = [(70, 45, 16.0, 260), (53, 61, 12.0, 311)]
+    grids, meds, dmeds, recs, thetas = [], [], [], [], []
+    for k, (nx, nz, h, nt) in enumerate(shapes):
+        if case == "nodal_gauss":
+            med = synthetic.nodal_perturbed_medium(rng, nz, nx, h, nlayers=3, corr_len=60.0)
+        else:
+            med = synthetic.random_layers_medium(rng, nz, h, 3)
+        grid = synthetic.Grid(nx, nz, h, synthetic.cfl_dt(h, med.vp_max()), nt)
+        x = (nx // 2 + (0.0 if k == 0 else 0.37)) * h
+        z = (nz - 9) * h if k == 0 else 15 * h
+        theta = np.array([x, z, 0.06, 12.0, 2e13, 0.0 if k == 0 else -1e13, 3e13])
+        grids.append(grid)
+        meds.append(med)
+        dmeds.append(_dev_medium(med))
+        recs.append(synthetic.equispaced_receivers(nx, 6))
+        thetas.append(theta)
+    stf = "gauss" if case == "nodal_gauss" else "gauss_deriv"
+    if stf == "gauss":
+        for th in thetas:
+            th[3] = 60.0   # angular frequency of the Gaussian
+    per = case == "layered_per_receiver"
+    S = len(grids)
+    R = len(recs[0])
+    sigma = 0.05
+    H1 = torch.empty((S, R, 7, 7) if per else (S, 7, 7), dtype=torch.float64, device="cuda")
+    J = [torch.empty((g.nsteps + 1, R, 2, 7), dtype=torch.float64, device="cuda")
+         for g in grids]
+    status = torch.empty(S, dtype=torch.int32, device="cuda")
+    ctx.jacobian_sensitivity([grid_tuple(g) for g in grids], dmeds, np.stack(thetas), recs,
+                             sigma, H1, stf=stf, per_receiver=per, J=J, status=status)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    for s in range(S):
+        _, Jr = elastic.jacobian_sensitivity(grids[s], meds[s], thetas[s], recs[s], stf)
+        assert np.max(np.abs(Jr)) > 0
+        Jg = J[s].cpu().numpy()
+        for j in range(7):
+            assert _relerr(Jg[..., j], Jr[..., j]) <= SENS_TOL, (s, j)
+        Hr = (laplace.hessian_h1_per_receiver(Jr, sigma) if per
+              else laplace.hessian_h1(Jr, sigma))
+        Hg = H1[s].cpu().numpy()
+        d = np.sqrt(np.abs(np.diagonal(Hr.sum(0) if per else Hr)))
+        assert np.max(np.abs(Hg - Hr)) <= 1e-4 * np.max(np.outer(d, d))
+
+
+def test_sensitivity_agrees_with_central_differences(ctx):
+    # both GPU Jacobians of one sample: equal up to the O(d^2) truncation of
+    # the central differences and FP32 rounding of the deviation traces
+    from paper_1502_07873_amd.query import grid_tuple, run_query
+    wl = synthetic.config("c1", nsample=2)[0]
+    _say("sensitivity vs central differences (GPU)")
+    kw = dict(sigma=0.01, keep_J=True)
+    g = grid_tuple(wl.grid)
+    dm = _dev_medium(wl.medium)
+    a = run_query(ctx, g, dm, wl.receivers, wl.lo, wl.hi, wl.theta, wl.weights,
+                  jacobian="sensitivity", **kw)
+    # at rel_step 1e-4 the oracle's own truncation gap is <= 1.1e-5 on these
+    # samples (1e-3 on the z column at rel_step 1e-3)
+    b = run_query(ctx, g, dm, wl.receivers, wl.lo, wl.hi, wl.theta, wl.weights,
+                  rel_step=1e-4, jacobian="fd", **kw)
+    torch.cuda.synchronize()
+    for s in range(2):
+        for j in range(7):
+            e = _relerr(b["J"][s].cpu().numpy()[..., j], a["J"][s].cpu().numpy()[..., j])
+            assert e <= JAC_TOL, (s, j, e)
+    assert np.max(np.abs(a["dkl"].cpu().numpy() - b["dkl"].cpu().numpy())) <= NAT_TOL
+
+
 def test_noise_sigma_peak_c1(ctx):
     from paper_1502_07873_amd.query import grid_tuple
     wl = synthetic.config("c1")[0]

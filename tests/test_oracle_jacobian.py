@@ -150,3 +150,15 @@ def test_sensitivity_jacobian_matches_central_differences(small):
             assert 3.5 < e1 / e2 < 4.5, (j, e1, e2)
         else:       # linear in the moments: exact up to rounding
             assert e2 < 1e-9, (j, e2)
+
+
+def test_pipeline_dkl_same_from_either_jacobian():
+    # the two Jacobians of Algorithm 1 (central differences, sensitivity
+    # solves) give the same D^_KL up to the O(d^2) truncation of the former
+    import synthetic
+    from oracle import pipeline
+    wl = synthetic.config("c1", nsample=4, grid_override=(48, 40, 160))[0]
+    a = pipeline.query(wl, sigma=0.01, jacobian="fd")
+    b = pipeline.query(wl, sigma=0.01, jacobian="sensitivity")
+    assert np.max(np.abs(a["dkl"] - b["dkl"])) < 1e-4
+    assert np.array_equal(a["nominal"], b["nominal"])
