@@ -217,6 +217,9 @@ def main():
     ap.add_argument("--samples", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed query: no one-solve baseline, sensitivity path, "
+                         "serving or CPU baseline (for counter runs)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
                     help="c2: the headline query (default); c3/c5: extra measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -342,6 +345,10 @@ def main():
                      "traffic": _measured_traffic(S)},
         "wall_s": wall,
     }
+    if args.headline_only:
+        print(json.dumps(line), flush=True)
+        ctx.close()
+        return
     # the plain GPU path: the same kernels, one solve per launch
     print("[bench] one-solve-per-launch GPU baseline (2 samples)", flush=True)
     ctx1 = Context(0, 8 << 30)
