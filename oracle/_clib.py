@@ -38,7 +38,8 @@ def lib():
         L.oracle_solve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_int, dp, dp, dp,
                                    ctypes.c_int, ip, ip, ctypes.c_int, ctypes.c_int,
-                                   dp, dp, ctypes.c_int, ip, ip, dp, dp, dp, dp]
+                                   dp, dp, ctypes.c_int, ip, ip, dp, dp, dp, dp,
+                                   ctypes.c_int]
         L.oracle_solve.restype = ctypes.c_int
         _lib = L
     return _lib

@@ -115,6 +115,9 @@ def _check_window(i0, k0, nx, nz, fw=6, fh=6):
         raise ValueError("source stencil touches a rigid edge or leaves the grid")
 
 
+BC_CODES = {"rigid": 0, "absorbing": 1}
+
+
 def solve_terms(grid, medium, terms, rec_i, rec_k=None, u0=None, um1=None,
                 want_final=False):
     """Leapfrog solve driven by sum_q S_q(t_m) W_q.
@@ -147,7 +150,7 @@ def solve_terms(grid, medium, terms, rec_i, rec_k=None, u0=None, um1=None,
         nterm, _ip(fi0), _ip(fk0), int(fw), int(fh), _dp(W), _dp(S),
         nrec, _ip(rec_i), _ip(rec_k), _dp(traces),
         nul if u0c is None else _dp(u0c), nul if um1c is None else _dp(um1c),
-        _dp(fin) if want_final else nul)
+        _dp(fin) if want_final else nul, BC_CODES[getattr(grid, "bc", "rigid")])
     if rc != 0:
         raise ValueError("oracle_solve rejected its arguments")
     return (traces, fin) if want_final else traces

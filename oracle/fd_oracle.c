@@ -28,7 +28,20 @@
  * differences inside and one-sided at the ends.  Inside the grid this gives
  * D+(a D-) second-derivative terms and D0(c D0) mixed terms; the traction-free
  * condition on the top row (depth 0) is natural.  Nodes on the left, right and
- * bottom edges are rigid (held at zero).
+ * bottom edges are either rigid (held at zero, bc = 0) or absorbing (bc = 1).
+ *
+ * Absorbing edges (paper eq. for the boundary condition on the artificial
+ * boundary, and its discrete form in Section 3.3.1): the first-order
+ * Clayton-Engquist relation  u_t = B sigma(u) n,  B = -(1/rho) (n n^T / c_p +
+ * t t^T / c_s),  n the outward normal and t the tangent, replaces the wave
+ * equation at every edge node (corners take the relation of their side
+ * column).  sigma(u) n is formed with the normal derivative one-sided into the
+ * grid and the tangential derivative central (one-sided at the ends of the
+ * edge), with the node's own lambda, mu, rho.  Time: the paper's centred
+ * difference u_t ~ (u^{m+1} - u^{m-1}) / (2 dt), with the node's own
+ * same-component term of B_h u taken at the mean of levels m+1 and m-1.
+ * (Taking it at level m, the literal explicit form, has a root of modulus
+ * c dt/h + sqrt(1 + (c dt/h)^2) > 1 and diverges within a few dozen steps.)
  *
  * The gradient is accumulated edge by edge and node by node (scatter form),
  * which is the energy definition written out; no per-node closed form is used.
@@ -121,6 +134,73 @@ static int is_rigid(int i, int k, int nx, int nz) {
     return i == 0 || i == nx - 1 || k == nz - 1;
 }
 
+/* First derivative of component c along x (dir 0) or depth (dir 1) at node
+ * (i, k): forward (+1), backward (-1) or central (0) difference, one-sided
+ * at the ends of the line whatever is asked. */
+static double ce_deriv(const double* u, int nx, int nz, double h, int c, int i, int k,
+                       int dir, int side) {
+    int n = dir == 0 ? nx : nz, j = dir == 0 ? i : k;
+    int j0, j1;
+    double den;
+    if (side > 0 || (side == 0 && j == 0)) { j0 = j; j1 = j + 1; den = h; }
+    else if (side < 0 || j == n - 1) { j0 = j - 1; j1 = j; den = h; }
+    else { j0 = j - 1; j1 = j + 1; den = 2 * h; }
+    if (j0 < 0 || j1 > n - 1) return 0.0;
+    double a = dir == 0 ? u[IDX(c, k, j0)] : u[IDX(c, j0, i)];
+    double b = dir == 0 ? u[IDX(c, k, j1)] : u[IDX(c, j1, i)];
+    return (b - a) / den;
+}
+
+/* B_h u at an edge node: -(1/rho) (n n^T / c_p + t t^T / c_s) sigma(u) n.
+ * rate[0..1] receives the x and depth components. */
+static void ce_rate(int nx, int nz, double h, const double* rho, const double* lam,
+                    const double* mu, const double* u, int i, int k, double rate[2]) {
+    size_t p = (size_t)k * nx + i;
+    double nxv, nzv;  /* outward normal in (x, depth) */
+    int sx = 0, sz = 0;   /* difference sides for x and depth derivatives */
+    if (i == 0) { nxv = -1; nzv = 0; sx = +1; }
+    else if (i == nx - 1) { nxv = 1; nzv = 0; sx = -1; }
+    else { nxv = 0; nzv = 1; sz = -1; }
+    double ux = ce_deriv(u, nx, nz, h, 0, i, k, 0, sx);
+    double vx = ce_deriv(u, nx, nz, h, 1, i, k, 0, sx);
+    double uz = ce_deriv(u, nx, nz, h, 0, i, k, 1, sz);
+    double vz = ce_deriv(u, nx, nz, h, 1, i, k, 1, sz);
+    double l = lam[p], m = mu[p], r = rho[p];
+    double sxx = (l + 2 * m) * ux + l * vz;
+    double szz = (l + 2 * m) * vz + l * ux;
+    double sxz = m * (uz + vx);
+    double tx = sxx * nxv + sxz * nzv, tz = sxz * nxv + szz * nzv;  /* sigma n */
+    double cp = sqrt((l + 2 * m) / r), cs = sqrt(m / r);
+    double tnx = -nzv, tnz = nxv;                                   /* tangent */
+    double tn = tx * nxv + tz * nzv, tt = tx * tnx + tz * tnz;
+    rate[0] = -(tn / cp * nxv + tt / cs * tnx) / r;
+    rate[1] = -(tn / cp * nzv + tt / cs * tnz) / r;
+}
+
+/* u^{m+1} at every edge node from u^m (cur) and u^{m-1} (prev), written to
+ * next.  The coefficient of the node's own component in B_h is found by
+ * applying the (linear) rule to a unit field at that node. */
+static void ce_step(int nx, int nz, double h, double dt, const double* rho,
+                    const double* lam, const double* mu, const double* cur,
+                    const double* prev, double* next, double* unit) {
+    for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < nx; ++i) {
+            if (!is_rigid(i, k, nx, nz)) continue;
+            double rate[2];
+            ce_rate(nx, nz, h, rho, lam, mu, cur, i, k, rate);
+            for (int c = 0; c < 2; ++c) {
+                double e[2];
+                unit[IDX(c, k, i)] = 1.0;
+                ce_rate(nx, nz, h, rho, lam, mu, unit, i, k, e);
+                unit[IDX(c, k, i)] = 0.0;
+                double d = e[c];  /* own same-component coefficient */
+                double off = rate[c] - d * cur[IDX(c, k, i)];
+                next[IDX(c, k, i)] = ((1.0 + dt * d) * prev[IDX(c, k, i)] + 2.0 * dt * off) /
+                                     (1.0 - dt * d);
+            }
+        }
+}
+
 /* out = A_h u at free nodes, 0 at rigid nodes. */
 void oracle_apply_operator(int nx, int nz, double h, const double* lam,
                            const double* mu, const double* u, double* out) {
@@ -141,7 +221,9 @@ void oracle_apply_operator(int nx, int nz, double h, const double* lam,
  * and scaled by the series S[q][m], m = 0..nsteps-1.  Receivers sample both
  * components at nodes (rec_i[r], rec_k[r]) for every level m = 0..nsteps:
  * traces[(m * nrec + r) * 2 + c].  u0/um1 (optional) give u^0 and u^{-1}
- * (zero when NULL); ufinal (optional) receives u^{nsteps}.
+ * (zero when NULL); ufinal (optional) receives u^{nsteps}.  bc: 0 rigid,
+ * 1 absorbing left/right/bottom edges.  Forcing windows and receivers must
+ * not touch edge nodes when bc = 1 (only free nodes carry the wave equation).
  * Returns 0, or -1 on invalid arguments.
  */
 int oracle_solve(int nx, int nz, double h, double dt, int nsteps,
@@ -149,8 +231,9 @@ int oracle_solve(int nx, int nz, double h, double dt, int nsteps,
                  int nterm, const int* fi0, const int* fk0, int fw, int fh,
                  const double* W, const double* S,
                  int nrec, const int* rec_i, const int* rec_k, double* traces,
-                 const double* u0, const double* um1, double* ufinal) {
+                 const double* u0, const double* um1, double* ufinal, int bc) {
     if (nx < 3 || nz < 3 || nsteps < 0 || h <= 0 || dt <= 0) return -1;
+    if (bc != 0 && bc != 1) return -1;
     for (int q = 0; q < nterm; ++q)
         if (fi0[q] < 0 || fk0[q] < 0 || fi0[q] + fw > nx || fk0[q] + fh > nz) return -1;
     for (int r = 0; r < nrec; ++r)
@@ -159,7 +242,10 @@ int oracle_solve(int nx, int nz, double h, double dt, int nsteps,
     double* prev = (double*)calloc(n, sizeof(double));
     double* cur = (double*)calloc(n, sizeof(double));
     double* acc = (double*)malloc(n * sizeof(double));
-    if (!prev || !cur || !acc) { free(prev); free(cur); free(acc); return -1; }
+    double* unit = (double*)calloc(n, sizeof(double));
+    if (!prev || !cur || !acc || !unit) {
+        free(prev); free(cur); free(acc); free(unit); return -1;
+    }
     if (u0) memcpy(cur, u0, n * sizeof(double));
     if (um1) memcpy(prev, um1, n * sizeof(double));
     for (int r = 0; r < nrec; ++r)
@@ -176,11 +262,16 @@ int oracle_solve(int nx, int nz, double h, double dt, int nsteps,
                         acc[IDX(c, fk0[q] + kk, fi0[q] + ii)] +=
                             s * Wq[((size_t)c * fh + kk) * fw + ii];
         }
+        /* edge nodes first: they need u^{m-1} before it is overwritten */
+        if (bc == 1) ce_step(nx, nz, h, dt, rho, lam, mu, cur, prev, prev, unit);
         for (int c = 0; c < 2; ++c)
             for (int k = 0; k < nz; ++k)
                 for (int i = 0; i < nx; ++i) {
                     size_t p = IDX(c, k, i);
-                    if (is_rigid(i, k, nx, nz)) { prev[p] = 0.0; continue; }
+                    if (is_rigid(i, k, nx, nz)) {
+                        if (bc == 0) prev[p] = 0.0;
+                        continue;
+                    }
                     prev[p] = 2.0 * cur[p] - prev[p] +
                               dt * dt / rho[(size_t)k * nx + i] * acc[p];
                 }
@@ -191,6 +282,6 @@ int oracle_solve(int nx, int nz, double h, double dt, int nsteps,
                     cur[IDX(c, rec_k[r], rec_i[r])];
     }
     if (ufinal) memcpy(ufinal, cur, n * sizeof(double));
-    free(prev); free(cur); free(acc);
+    free(prev); free(cur); free(acc); free(unit);
     return 0;
 }

@@ -33,6 +33,7 @@ class Grid:
     h: float
     dt: float
     nsteps: int
+    bc: str = "rigid"   # left/right/bottom edges: "rigid" or "absorbing"
 
     @property
     def lx(self) -> float:

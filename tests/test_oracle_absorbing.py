@@ -1,0 +1,129 @@
+"""Pins of the oracle's absorbing (first-order Clayton-Engquist) edges.
+
+The boundary relation u_t = B sigma(u) n is exact for a plane wave leaving
+the domain through the edge at normal incidence.  A snapshot of such a wave
+that is linear in space has exact discrete derivatives, so one step of the
+discrete rule must return exactly that wave's particle velocity; the rule's
+rate and its own-node coefficient are recovered from two one-step solves by
+algebra alone.  Away from normal incidence the condition is approximate:
+reflections must still be much weaker than those of rigid edges, and the
+field must decay once the source has stopped.
+"""
+import numpy as np
+import pytest
+
+from oracle import elastic
+from synthetic import Grid, homogeneous_medium
+
+RHO, VP, VS = 2500.0, 3000.0, 1730.0
+NX, NZ, H = 24, 20, 10.0
+DT = 0.4 * H / VP
+
+
+def _edges():
+    """Edge nodes by side (corners with their side column), and outward normals."""
+    left = [(0, k) for k in range(NZ)]
+    right = [(NX - 1, k) for k in range(NZ)]
+    bottom = [(i, NZ - 1) for i in range(1, NX - 1)]
+    return {"left": (left, np.array([-1.0, 0.0])), "right": (right, np.array([1.0, 0.0])),
+            "bottom": (bottom, np.array([0.0, 1.0]))}
+
+
+def _one_step(u0, um1):
+    med = homogeneous_medium(NZ, RHO, VP, VS)
+    g = Grid(NX, NZ, H, DT, 1, bc="absorbing")
+    _, fin = elastic.solve_terms(g, med, [], np.array([1], dtype=np.int32), u0=u0, um1=um1,
+                                 want_final=True)
+    return fin
+
+
+def _rate_and_own(L):
+    """Rate r = B_h u and own coefficient d of the rule at every node, from
+    u^1 for (u^-1, u^0) = (L, L) and (0, L)."""
+    ua = _one_step(L, L)
+    ub = _one_step(L, np.zeros_like(L))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        q = (ua - ub) / L
+        d = (q - 1.0) / (DT * (q + 1.0))
+        r = ub * (1.0 - DT * d) / (2.0 * DT) + d * L
+    return r, d
+
+
+@pytest.mark.parametrize("wave", ["P", "S"])
+@pytest.mark.parametrize("side", ["left", "right", "bottom"])
+def test_outgoing_plane_wave_snapshot_gives_its_particle_velocity(wave, side):
+    nodes, n = _edges()[side]
+    tau = np.array([-n[1], n[0]])
+    pol, c = (n, VP) if wave == "P" else (tau, VS)
+    s = 0.37   # particle speed of the wave
+    # u(x, t) = pol * f(t - n.x / c) with f' = s: at one instant u = -pol (n.x) s / c + const
+    kk, ii = np.meshgrid(np.arange(NZ), np.arange(NX), indexing="ij")
+    X, Z = ii * H, kk * H
+    proj = n[0] * X + n[1] * Z
+    L = np.stack([-pol[0] * proj * s / c, -pol[1] * proj * s / c]) + np.array([0.3, -0.2])[:, None, None]
+    r, d = _rate_and_own(L)
+    want = s * pol
+    for (i, k) in nodes:
+        if side != "bottom" and k in (0, NZ - 1):
+            continue  # corners: the tangential derivative is one-sided (still exact, checked below)
+        assert np.allclose(r[:, k, i], want, rtol=0, atol=1e-9 * s), (i, k, r[:, k, i], want)
+    # own coefficients: -c_p/h for the normal component, -c_s/h for the tangential one
+    for (i, k) in nodes:
+        for comp in range(2):
+            along_n = abs(n[comp]) == 1.0
+            expect = -(VP if along_n else VS) / H
+            if abs(L[comp, k, i]) > 1e-6:
+                assert abs(d[comp, k, i] - expect) < 1e-6 * abs(expect), (side, i, k, comp)
+    # corners too: every derivative of a linear field is exact
+    for (i, k) in nodes:
+        assert np.allclose(r[:, k, i], want, rtol=0, atol=1e-9 * s)
+
+
+def _ricker_case(nx, nz, pad_x, pad_z, bc, nsteps):
+    med = homogeneous_medium(nz, RHO, VP, VS)
+    g = Grid(nx, nz, 10.0, 0.45 * 10.0 / VP, nsteps, bc=bc)
+    theta = np.array([(pad_x + 40) * 10.0 + 3.0, 22 * 10.0 + 4.0, 0.03, 30.0, 1e13, 4e12, 2e13])
+    rec = np.arange(pad_x + 10, pad_x + 71, 6, dtype=np.int32)
+    return elastic.forward(g, med, theta, rec)
+
+
+def test_absorbing_edges_reflect_far_less_than_rigid_ones():
+    # 81 x 41 box vs the same box inside a domain large enough that nothing
+    # comes back within the window: the absorbing box's error is a small
+    # fraction of the rigid box's (first-order condition, all incidences)
+    nsteps = 900
+    ref = _ricker_case(81 + 2 * 120, 41 + 160, 120, 160, "rigid", nsteps)
+    rig = _ricker_case(81, 41, 0, 0, "rigid", nsteps)
+    ab = _ricker_case(81, 41, 0, 0, "absorbing", nsteps)
+    e_rig = np.linalg.norm(rig - ref) / np.linalg.norm(ref)
+    e_ab = np.linalg.norm(ab - ref) / np.linalg.norm(ref)
+    assert e_rig > 0.5
+    assert e_ab < 0.25 * e_rig, (e_ab, e_rig)
+    # before any wave reaches an edge the two boxes agree exactly
+    assert np.array_equal(rig[:60], ab[:60])
+
+
+def _envelope(f, t0, nsteps):
+    med = homogeneous_medium(41, RHO, VP, VS)
+    g = Grid(61, 41, 10.0, 0.45 * 10.0 / VP, nsteps, bc="absorbing")
+    theta = np.array([30 * 10.0 + 1.0, 25 * 10.0 + 2.0, t0, f, 1e13, 4e12, 2e13])
+    tr = elastic.forward(g, med, theta, np.arange(1, 60, dtype=np.int32))
+    assert np.isfinite(tr).all()
+    peak = np.abs(tr).max()
+    return np.array([np.abs(tr[m:m + 500]).max() / peak for m in range(0, nsteps + 1 - 500, 500)])
+
+
+def test_field_decays_after_the_source_stops():
+    # a wavelet resolved by >= 7 nodes per S wavelength leaves the box:
+    # geometric decay to 1e-8 of the peak within 6000 steps
+    env = _envelope(8.0, 0.15, 6000)
+    assert env[-1] < 1e-8, env
+    assert np.all(np.diff(np.log(env[1:])) < 0), env
+
+
+def test_underresolved_grid_modes_do_not_grow():
+    # at 40 Hz (4 nodes per S wavelength) near-Nyquist grid modes travel at
+    # almost zero group speed and leave slowly; nothing may grow
+    env = _envelope(40.0, 0.02, 20000)
+    assert env[-1] < 0.05, env
+    assert max(env[8:]) <= 1.5 * max(env[2:8]), env
