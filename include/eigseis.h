@@ -65,6 +65,12 @@ extern "C" {
 #define EIG_MEDIUM_LAYERED 0  /* rho, lam, mu arrays of [nz] (depth only) */
 #define EIG_MEDIUM_NODAL 1    /* rho, lam, mu arrays of [nz][nx]          */
 
+/* left, right and bottom edges of the grid (the top row is always the
+ * traction-free surface, eq. for the free-surface condition in Section 2.1) */
+#define EIG_BC_RIGID 0      /* edge nodes held at zero                        */
+#define EIG_BC_ABSORBING 1  /* first-order Clayton-Engquist condition (Section
+                             * 2.1 artificial boundary; Section 4.1 model)   */
+
 /* priors */
 #define EIG_PRIOR_UNIFORM 0
 #define EIG_PRIOR_GAUSSIAN 1
@@ -76,11 +82,21 @@ extern "C" {
 typedef struct eig_ctx eig_ctx;
 
 /* Uniform grid of Section 3.3.1 (spacing h in both directions) with the
- * leapfrog time step dt and nsteps steps.  nx, nz >= 8. */
+ * leapfrog time step dt and nsteps steps.  nx, nz >= 8.
+ *
+ * bc = EIG_BC_ABSORBING: every node of the left, right and bottom edges obeys
+ * u_t = B sigma(u) n, B = -(1/rho)(n n^T/c_p + t t^T/c_s) (n outward normal,
+ * t tangent, node's own rho, lambda, mu), instead of the wave equation; the
+ * normal derivative is one-sided into the grid, the tangential one central
+ * (one-sided at the ends of the edge, corners take their column's relation);
+ * time is the centred difference of Section 3.3.1 with the node's own
+ * same-component term taken at the mean of levels m+1 and m-1 (the fully
+ * explicit form diverges).  Such grids always run one step per launch. */
 typedef struct {
     int32_t nx, nz;
     double h, dt;
     int32_t nsteps;
+    int32_t bc;  /* EIG_BC_RIGID or EIG_BC_ABSORBING */
 } eig_grid;
 
 /* Density nu and Lame parameters (lambda, mu) of the paper's stress law

@@ -42,6 +42,8 @@ def query(wl, theta=None, weights=None, sigma: Optional[float] = None,
     nominal traces, (J), H1 [S][7][7] (or [S][R][7][7]), dkl [S], eig."""
     theta = wl.theta if theta is None else np.asarray(theta)
     weights = wl.weights if weights is None else np.asarray(weights)
+    if sigma is None and getattr(wl, "sigma", None) is not None:
+        sigma = wl.sigma
     if sigma is None:
         sigma = elastic.noise_sigma(wl.grid, wl.medium, wl.theta_bar,
                                     wl.noise_rel, wl.stf)

@@ -66,15 +66,17 @@ size_t tiles_of(const eig_grid& g, const StencilVariant& v) {
 }
 
 // Variants a wave may run for a medium kind: the forced one, else all of
-// that kind (tuned online per grid class).
-void stencil_candidates(const eig_ctx* c, int kind, std::vector<int>& out) {
+// that kind (tuned online per grid class).  Grids with absorbing edges run
+// one step per launch (their edge nodes are updated between steps).
+void stencil_candidates(const eig_ctx* c, int kind, bool one_step, std::vector<int>& out) {
     out.clear();
-    if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == kind) {
+    if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == kind &&
+        !(one_step && kVariants[c->forced_variant].steps != 1)) {
         out.push_back(c->forced_variant);
         return;
     }
     // one family per wave: two steps per launch (four field buffers) or one
-    const int steps = (kind == EIG_MEDIUM_LAYERED && c->temporal_blocking) ? 2 : 1;
+    const int steps = (kind == EIG_MEDIUM_LAYERED && c->temporal_blocking && !one_step) ? 2 : 1;
     for (int v = 1; v < kNumVariants; ++v)
         if (kVariants[v].medium_kind == kind && kVariants[v].steps == steps) out.push_back(v);
     if (out.empty()) out.push_back(kind == EIG_MEDIUM_NODAL ? 6 : 0);
@@ -107,13 +109,15 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     rec_used.erase(std::unique(rec_used.begin(), rec_used.end()), rec_used.end());
     std::map<int, size_t> med_off;
     for (int m : med_used) med_off[m] = cv.take(medium_bytes(media[m]));
-    // stencil variants this wave may use, per medium kind
-    std::vector<int> cand_layered, cand_nodal;
-    stencil_candidates(c, EIG_MEDIUM_LAYERED, cand_layered);
-    stencil_candidates(c, EIG_MEDIUM_NODAL, cand_nodal);
-    auto family_steps = [&](int kind) {
-        return kVariants[(kind == EIG_MEDIUM_NODAL ? cand_nodal : cand_layered)[0]].steps;
+    // stencil variants this wave may use, per solve class (medium kind, edges)
+    std::vector<int> cands[2][2];
+    for (int kind = 0; kind < 2; ++kind)
+        for (int bc = 0; bc < 2; ++bc)
+            stencil_candidates(c, kind, bc == EIG_BC_ABSORBING, cands[kind][bc]);
+    auto cand_of = [&](int i) -> const std::vector<int>& {
+        return cands[media[solves[i].medium].kind][grids[solves[i].grid].bc];
     };
+    auto family_steps = [&](int i) { return kVariants[cand_of(i)[0]].steps; };
     // fields: one contiguous block for all solves (cleared with one launch);
     // two-steps-per-launch kernels rotate over four buffers per solve
     std::vector<size_t> f0(n), f1(n), f2(n, 0), f3(n, 0), sw(n), ss(n);
@@ -124,7 +128,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
         f0[i] = cv.take(field);
         f1[i] = cv.take(field);
-        if (family_steps(media[solves[i].medium].kind) == 2) {
+        if (family_steps(i) == 2) {
             f2[i] = cv.take(field);
             f3[i] = cv.take(field);
         }
@@ -135,11 +139,14 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         sw[i] = cv.take(2 * kSrcW * kSrcW * sizeof(float));
         ss[i] = cv.take((size_t)std::max(g.nsteps, 1) * sizeof(float));
     }
-    // order: medium kind, then steps descending
+    // order: solve class (medium kind, edges), then steps descending
     std::vector<int> ord(n);
     for (int i = 0; i < n; ++i) ord[i] = i;
+    auto class_of = [&](int i) {
+        return 2 * media[solves[i].medium].kind + grids[solves[i].grid].bc;
+    };
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-        const int ka = media[solves[a].medium].kind, kb = media[solves[b].medium].kind;
+        const int ka = class_of(a), kb = class_of(b);
         if (ka != kb) return ka < kb;
         return grids[solves[a].grid].nsteps > grids[solves[b].grid].nsteps;
     });
@@ -148,9 +155,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     size_t ntiles_total = 0;
     for (int i = 0; i < n; ++i) {
         const eig_grid& g = grids[solves[i].grid];
-        const auto& cand = media[solves[i].medium].kind == EIG_MEDIUM_NODAL ? cand_nodal
-                                                                            : cand_layered;
-        for (int v : cand) ntiles_total += tiles_of(g, kVariants[v]);
+        for (int v : cand_of(i)) ntiles_total += tiles_of(g, kVariants[v]);
     }
     size_t blob_bound = align_up((size_t)n * sizeof(SolveDesc)) +
                         align_up(ntiles_total * sizeof(int2)) + 16 * kAlign +
@@ -171,7 +176,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     std::vector<SolveDesc> desc(n);
     std::vector<SourceJob> jobs(n);
     struct Group {
-        int kind;
+        int kind, bc, cls;
         int first, last;               // solve range in launch order
         std::vector<int> cand;         // candidate variants
         std::vector<std::vector<int2>> tiles;                     // per candidate
@@ -227,11 +232,13 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         J.srcs = (float*)(base + ss[i]);
         d.src_i0 = J.i0;
         d.src_k0 = J.k0;
-        if (groups.empty() || groups.back().kind != mk.kind) {
+        if (groups.empty() || groups.back().cls != class_of(i)) {
             Group gr;
             gr.kind = mk.kind;
+            gr.bc = g.bc;
+            gr.cls = class_of(i);
             gr.first = oi;
-            gr.cand = mk.kind == EIG_MEDIUM_NODAL ? cand_nodal : cand_layered;
+            gr.cand = cand_of(i);
             gr.tiles.resize(gr.cand.size());
             gr.steps_tiles.resize(gr.cand.size());
             groups.push_back(gr);
@@ -296,7 +303,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         // grid class and batch size (log2 of the solve count) both matter
         int bucket = 0;
         while ((2 << bucket) <= g.last - g.first) ++bucket;
-        tune[gi].key = std::make_tuple(g.kind, d0.nx, d0.nz, kVariants[g.cand[0]].steps, bucket);
+        tune[gi].key = std::make_tuple(g.cls, d0.nx, d0.nz, kVariants[g.cand[0]].steps, bucket);
         use[gi] = 0;
         if (g.cand.size() > 1) {
             auto it = c->tuned.find(tune[gi].key);
@@ -337,12 +344,13 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
             }
             // running solves form a prefix (steps descending within a group)
             const int spl = kVariants[g.cand[vi]].steps;
-            int ntile = 0;
+            int ntile = 0, nrun = 0;
             double upd = 0.0;
             const auto& stv = g.steps_tiles[vi];
             for (size_t q = 0; q < stv.size(); ++q) {
                 if (stv[q].first > step * spl) {
                     ntile = stv[q].second;
+                    nrun = (int)q + 1;
                     const SolveDesc& dq = desc[g.first + q];
                     upd += (double)dq.nx * dq.nz * std::min(spl, stv[q].first - step * spl);
                 } else {
@@ -355,6 +363,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
                 launch_stencil(ddesc, (const int2*)(bd + o_tiles[gi][vi]), ntile, step,
                                g.cand[vi], s);
                 if (slot >= 0) HIP_TRY(hipEventRecord(tn.ev[2 * slot + 1], s));
+                if (g.bc == EIG_BC_ABSORBING) launch_ce_edges(ddesc + g.first, nrun, step, s);
                 c->launches += 1;
                 c->updates += upd;
                 c->bytes += upd * (g.kind == EIG_MEDIUM_NODAL ? 36.0 : 24.0);

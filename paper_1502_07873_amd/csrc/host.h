@@ -143,7 +143,7 @@ inline int floor_cell(double x, double h) { return (int)std::floor(x / h); }
 inline bool valid_grid(const eig_grid& g) {
     return g.nx >= 8 && g.nz >= 8 && g.nx <= 65536 && g.nz <= 65536 && g.h > 0 &&
            g.dt > 0 && std::isfinite(g.h) && std::isfinite(g.dt) && g.nsteps >= 0 &&
-           g.nsteps < (1 << 28);
+           g.nsteps < (1 << 28) && (g.bc == EIG_BC_RIGID || g.bc == EIG_BC_ABSORBING);
 }
 
 // Source stencil rows/columns kx-2..kx+3 must stay on free nodes.

@@ -32,6 +32,9 @@ enum CoefSlot {
     kCmmV = 10,  // Dx u at row k-1
     kCm0V = 11,  // Dx u at row k (traction-free row only)
     kFco = 12,
+    kCeP = 13,   // c_p dt / h       (absorbing edges)
+    kCeS = 14,   // c_s dt / h
+    kCeL = 15,   // lambda dt / (rho c_p h)
 };
 
 // Nodal media store, per node, (lambda, mu, dt^2/(rho h^2)) as three float
@@ -104,6 +107,8 @@ extern const StencilVariant kVariants[kNumVariants];
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                     int variant, hipStream_t s);
 void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s);
+// Absorbing-edge update of level step+1 for descs[0..n) (one-step buffers).
+void launch_ce_edges(const SolveDesc* descs, int n, int step, hipStream_t s);
 void launch_sample_check(const SampleDesc* samples, int nsample, const double* given,
                          int mode, double* sigma, int32_t* status, hipStream_t s);
 void launch_hessian(const SampleDesc* samples, int nsample, int per_receiver,

@@ -442,6 +442,8 @@ int eig_server_submit(eig_server* v, const eig_grid* grid, const eig_medium* med
         return set_error(EIG_EINVAL, "eig_server_submit: NULL argument");
     if (nsample < 1) return set_error(EIG_EINVAL, "nsample < 1");
     if (!valid_grid(*grid)) return set_error(EIG_EINVAL, "grid");
+    if (grid->bc != EIG_BC_RIGID)
+        return set_error(EIG_EUNSUPPORTED, "the server runs rigid-edge grids only");
     if (medium->kind != EIG_MEDIUM_LAYERED && medium->kind != EIG_MEDIUM_NODAL)
         return set_error(EIG_EINVAL, "medium kind");
     if (!medium->rho || !medium->lam || !medium->mu)

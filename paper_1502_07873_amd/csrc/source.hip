@@ -222,6 +222,14 @@ __global__ void layered_coef_kernel(const double* __restrict__ rho,
             c[kCmmV] = s * 0.25 * (lm + m0);
         }
     }
+    // absorbing-edge coefficients, every row (the bottom row included)
+    {
+        const double a = lam[k] + 2.0 * mu[k];
+        const double cp = sqrt(a / rho[k]), cs = sqrt(mu[k] / rho[k]);
+        c[kCeP] = cp * dt / h;
+        c[kCeS] = cs * dt / h;
+        c[kCeL] = lam[k] * dt / (rho[k] * cp * h);
+    }
     for (int j = 0; j < kCoefStride; ++j) coef[(size_t)k * kCoefStride + j] = (float)c[j];
 }
 

@@ -352,10 +352,15 @@ stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__
         }
         const float2 na = layered_update(cf, am, ac, an, p0.x, p0.y, sa, fsv, wua, wva);
         const float2 nb = layered_update(cf, bm, bc, bn, p0.z, p0.w, sb, fsv, wub, wvb);
-        // rigid and padding columns keep their zeros
-        const float4 o = make_float4(upd0 ? na.x : 0.f, upd0 ? na.y : 0.f,
-                                     upd1 ? nb.x : 0.f, upd1 ? nb.y : 0.f);
-        st4(P, (size_t)k * pitch + i0, o);
+        // edge and padding columns are never written (absorbing edges are
+        // updated by their own kernel, rigid ones stay zero)
+        if (upd0 && upd1) {
+            st4(P, (size_t)k * pitch + i0, make_float4(na.x, na.y, nb.x, nb.y));
+        } else if (upd0) {
+            st2(P, (size_t)k * pitch + i0, na);
+        } else if (upd1) {
+            st2(P, (size_t)k * pitch + i0 + 1, nb);
+        }
         if (k == 0) {
             if (rec0 >= 0) st2(traces, (size_t)(m + 1) * nrec + rec0, na);
             if (rec1 >= 0) st2(traces, (size_t)(m + 1) * nrec + rec1, nb);

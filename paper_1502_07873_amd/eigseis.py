@@ -29,6 +29,9 @@ STF_GAUSS = 0
 STF_GAUSS_DERIV = 1
 MEDIUM_LAYERED = 0
 MEDIUM_NODAL = 1
+BC_RIGID = 0
+BC_ABSORBING = 1
+BC_CODES = {"rigid": BC_RIGID, "absorbing": BC_ABSORBING}
 PRIOR_UNIFORM = 0
 PRIOR_GAUSSIAN = 1
 SIGMA_GIVEN = 0
@@ -45,7 +48,7 @@ class EigError(RuntimeError):
 
 class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("h", ctypes.c_double),
-                ("dt", ctypes.c_double), ("nsteps", ctypes.c_int32)]
+                ("dt", ctypes.c_double), ("nsteps", ctypes.c_int32), ("bc", ctypes.c_int32)]
 
 
 class Medium(ctypes.Structure):
@@ -233,7 +236,8 @@ class Context:
     def _grids(grids):
         arr = (Grid * len(grids))()
         for k, g in enumerate(grids):
-            arr[k] = Grid(int(g[0]), int(g[1]), float(g[2]), float(g[3]), int(g[4]))
+            arr[k] = Grid(int(g[0]), int(g[1]), float(g[2]), float(g[3]), int(g[4]),
+                          int(g[5]) if len(g) > 5 else BC_RIGID)
         return arr
 
     @staticmethod

@@ -20,7 +20,7 @@ def device_medium(kind: str, rho, lam, mu, device="cuda"):
 
 
 def grid_tuple(g):
-    return (g.nx, g.nz, g.h, g.dt, g.nsteps)
+    return (g.nx, g.nz, g.h, g.dt, g.nsteps, eigseis.BC_CODES[getattr(g, "bc", "rigid")])
 
 
 def run_query(ctx: eigseis.Context, grid, medium, receivers, lo, hi, theta, weights,

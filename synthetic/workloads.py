@@ -87,6 +87,7 @@ class Workload:
     noise_rel: float = 1e-3
     smolyak_level: Optional[int] = None
     greedy_kmax: Optional[int] = None
+    sigma: Optional[float] = None  # fixed noise std (else noise_rel x peak)
 
     @property
     def theta_bar(self) -> np.ndarray:
@@ -272,6 +273,66 @@ def config(name: str, nsample: Optional[int] = None, seed: Optional[int] = None,
         return [Workload("c5", grid, med, candidate_receivers(nx, 201), lo, hi,
                          None, None, smolyak_level=3, greedy_kmax=40)]
     raise ValueError(name)
+
+
+# The paper's model problem (Section 4.1): a layer over a half-space in the
+# box [-10 km, 10 km] x [-15 km, 0], h = 200 m, dt = 0.025 s, T = 8 s,
+# stress-free top and first-order absorbing sides and bottom, the Gaussian
+# wavelet with frequency omega_s, C_eps = 1e-4 I.  Build frame: x = x_1 +
+# 10 km, depth z = -x_2, so m_xz = -m_{x1 x2}.
+LOH_NX, LOH_NZ, LOH_H, LOH_DT, LOH_NSTEPS = 101, 76, 200.0, 0.025, 320
+LOH_X0 = 10000.0   # build x of the paper's x_1 = 0
+
+
+def loh_medium(nz: int = LOH_NZ, h: float = LOH_H) -> Medium:
+    # top layer: depth <= 1000 m (nodes down to the interface node included)
+    return layered_medium(nz, h, [1000.0 + 0.5 * h], [2600.0, 2700.0],
+                          [4000.0, 6000.0], [2000.0, 3464.0])
+
+
+def loh_prior():
+    """The paper's uniform prior, in the build frame and parameter order."""
+    lo = np.array([LOH_X0 - 1000.0, 1000.0, 0.5, 3.0, 1e13, -1e15, 1e13])
+    hi = np.array([LOH_X0 + 1000.0, 3000.0, 1.5, 5.0, 1e15, -1e13, 1e15])
+    return lo, hi
+
+
+def loh_prior_mean_paper() -> np.ndarray:
+    """E[theta] of the paper's conditioning example, in the build frame."""
+    return np.array([LOH_X0, 2000.0, 1.0, 4.0, 1e14, -1e14, 1e14])
+
+
+def loh_receivers(x1) -> np.ndarray:
+    """Surface node indices of receivers at paper coordinates x_1 (metres)."""
+    return np.rint((np.asarray(x1, dtype=np.float64) + LOH_X0) / LOH_H).astype(np.int32)
+
+
+def loh_scenarios():
+    """Receiver arrays of the three scenarios (Section 4.5), as
+    {scenario: [(label, node indices), ...]}."""
+    out = {"I": [], "II": [], "III": []}
+    for nr in (3, 5, 9, 17, 41, 81):                 # fixed span [-8 km, 8 km]
+        d = 16000.0 / (nr - 1)
+        out["I"].append((f"NR={nr},dR={d:g}", loh_receivers(-8000.0 + d * np.arange(nr))))
+    for nr in range(1, 20, 2):                       # d_R = 1 km, symmetric
+        out["II"].append((f"NR={nr}", loh_receivers(1000.0 * (np.arange(nr) - (nr - 1) / 2))))
+    for d in range(200, 4001, 200):                  # 5 receivers, symmetric
+        out["III"].append((f"dR={d}", loh_receivers(float(d) * (np.arange(5) - 2))))
+    return out
+
+
+def loh_candidates() -> np.ndarray:
+    """Every surface node a scenario uses (x_1 in [-9 km, 9 km])."""
+    return loh_receivers(np.arange(-9000.0, 9000.1, LOH_H))
+
+
+def loh_workload(nsample: int = 256, seed: int = 5, nsteps: int = LOH_NSTEPS) -> Workload:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grid = Grid(LOH_NX, LOH_NZ, LOH_H, LOH_DT, nsteps, bc="absorbing")
+    lo, hi = loh_prior()
+    theta = draw_uniform(rng, lo, hi, nsample)
+    return Workload("loh2d", grid, loh_medium(), loh_candidates(), lo, hi, theta, _mc(theta),
+                    stf="gauss", sigma=0.01)
 
 
 def serving_queries(rng: np.random.Generator, nquery: int,

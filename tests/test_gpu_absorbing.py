@@ -1,0 +1,180 @@
+"""Absorbing (first-order Clayton-Engquist) edges on the GPU vs the oracle,
+through the C ABI, including the paper's model problem (Section 4.1) and
+its scenario designs (Section 4.5).  Tolerances as for rigid edges: traces
+relative L2 <= 1e-5 per solve, Jacobian columns <= 1e-3, D^_KL <= 1e-3 nats.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import elastic, laplace, pipeline as opipe
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TRACE_TOL = 1e-5
+JAC_TOL = 1e-3
+NAT_TOL = 1e-3
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context
+    c = Context(0, 16 << 30)
+    yield c
+    c.close()
+
+
+def _dev_medium(med):
+    from paper_1502_07873_amd.query import device_medium
+    return device_medium(med.kind, med.rho, med.lam, med.mu)
+
+
+def _relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _forward(ctx, cases, stf):
+    """cases: list of (grid, medium, theta, receivers); one call."""
+    from paper_1502_07873_amd.query import grid_tuple
+    tr = [torch.empty((g.nsteps + 1, len(r), 2), dtype=torch.float32, device="cuda")
+          for g, _, _, r in cases]
+    ctx.forward_solve_batch([grid_tuple(g) for g, _, _, _ in cases],
+                            [_dev_medium(m) for _, m, _, _ in cases],
+                            np.stack([t for _, _, t, _ in cases]), [r for _, _, _, r in cases],
+                            tr, stf=stf)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy().astype(np.float64) for t in tr]
+
+
+def test_model_problem_forward(ctx):
+    wl = synthetic.loh_workload(6)
+    _say("model problem forward (101x76x320, absorbing, gauss)")
+    cases = [(wl.grid, wl.medium, th, wl.receivers) for th in wl.theta]
+    out = _forward(ctx, cases, "gauss")
+    for s, th in enumerate(wl.theta):
+        ref = elastic.forward(wl.grid, wl.medium, th, wl.receivers, "gauss")
+        e = _relerr(out[s], ref)
+        assert e <= TRACE_TOL, (s, e)
+
+
+@pytest.mark.parametrize("kind", ["layered", "nodal"])
+def test_absorbing_ragged_and_mixed_with_rigid(ctx, kind):
+    # ragged grids (not tile multiples), waves reach every edge, a source next
+    # to the bottom edge, and rigid solves of the same shape in the same call
+    rng = np.random.default_rng(21)
+    cases, stfs = [], []
+    for (nx, nz, nt, bc) in [(133, 71, 600, "absorbing"), (70, 45, 500, "absorbing"),
+                             (133, 71, 600, "rigid"), (97, 40, 450, "absorbing")]:
+        h = 12.0
+        if kind == "nodal":
+            med = synthetic.nodal_perturbed_medium(rng, nz, nx, h, nlayers=3, corr_len=60.0)
+        else:
+            med = synthetic.random_layers_medium(rng, nz, h, 3)
+        grid = synthetic.Grid(nx, nz, h, synthetic.cfl_dt(h, med.vp_max()), nt, bc=bc)
+        lo, hi = synthetic.prior_box(grid)
+        th = synthetic.draw_uniform(rng, lo, hi, 1)[0]
+        th[2] = 0.05
+        if nz == 40:
+            th[1] = (nz - 5) * h + 0.3   # window rows nz-7..nz-2
+        cases.append((grid, med, th, np.array([1, 2, nx // 3, nx // 2, nx - 3, nx - 2],
+                                              dtype=np.int32)))
+    _say(f"absorbing ragged + rigid mix ({kind})")
+    out = _forward(ctx, cases, "gauss_deriv")
+    for s, (g, m, th, r) in enumerate(cases):
+        ref = elastic.forward(g, m, th, r, "gauss_deriv")
+        assert np.abs(ref).max() > 0
+        e = _relerr(out[s], ref)
+        assert e <= TRACE_TOL, (kind, s, g.bc, e)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 7, 8, 11])
+def test_absorbing_variants_bitwise_identical(variant):
+    # every one-step layered kernel gives the same bits; a forced two-step
+    # variant falls back to one step for absorbing grids
+    from paper_1502_07873_amd import Context
+    from paper_1502_07873_amd.query import grid_tuple
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    wl = synthetic.loh_workload(3)
+    _say(f"absorbing variant {variant}")
+    outs = []
+    for v in (variant, 1):
+        with Context(0, 4 << 30) as c:
+            c.set_option("stencil_variant", v)
+            tr = [torch.empty((wl.grid.nsteps + 1, len(wl.receivers), 2), dtype=torch.float32,
+                              device="cuda") for _ in range(3)]
+            c.forward_solve_batch([grid_tuple(wl.grid)] * 3, [_dev_medium(wl.medium)] * 3,
+                                  wl.theta, [wl.receivers] * 3, tr, stf="gauss")
+            torch.cuda.synchronize()
+            outs.append([t.cpu().numpy() for t in tr])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_model_problem_scenarios_design_eval(ctx):
+    # per-receiver H_1 over the 91 candidate nodes, then every scenario design
+    # of Section 4.5 through design_eval, vs the oracle on the same samples
+    from paper_1502_07873_amd import eigseis
+    from paper_1502_07873_amd.query import grid_tuple
+    wl = synthetic.loh_workload(4)
+    _say("model problem per-receiver H1 + scenario designs")
+    S, R = len(wl.theta), len(wl.receivers)
+    g = grid_tuple(wl.grid)
+    H1r = torch.empty((S, R, 7, 7), dtype=torch.float64, device="cuda")
+    status = torch.empty(S, dtype=torch.int32, device="cuda")
+    ctx.jacobian_fd([g] * S, [_dev_medium(wl.medium)] * S, wl.theta, [wl.receivers] * S,
+                    wl.sigma, H1r, stf="gauss", per_receiver=True, status=status)
+    ref = opipe.query(wl, per_receiver=True)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    Hg = H1r.cpu().numpy()
+    Hr = ref["H1"]
+    d = np.sqrt(np.abs(np.einsum("srii->sri", Hr)))
+    assert np.max(np.abs(Hg - Hr) / (d[..., :, None] * d[..., None, :] + 1e-300)) < 1e-3
+    pos = {int(ix): c for c, ix in enumerate(wl.receivers)}
+    masks, labels = [], []
+    for scen, designs in synthetic.loh_scenarios().items():
+        for lab, idx in designs:
+            mk = np.zeros(R, dtype=np.uint8)
+            mk[[pos[int(i)] for i in idx]] = 1
+            masks.append(mk)
+            labels.append(scen + ":" + lab)
+    masks = np.stack(masks)
+    prior = eigseis.make_prior(wl.lo, wl.hi)
+    eig = torch.empty(len(masks), dtype=torch.float64, device="cuda")
+    ctx.design_eval(H1r, torch.as_tensor(masks, device="cuda"), prior, wl.weights, eig,
+                    theta=wl.theta)
+    torch.cuda.synchronize()
+    pr = laplace.uniform_prior(wl.lo, wl.hi)
+    for q, mk in enumerate(masks):
+        Hd = Hr[:, mk.astype(bool)].sum(axis=1)
+        dk = np.array([laplace.dkl_hat(Hd[s], wl.theta[s], pr)[0] for s in range(S)])
+        want = laplace.eig_average(dk, wl.weights)
+        assert abs(float(eig[q]) - want) <= NAT_TOL, (labels[q], float(eig[q]), want)
+
+
+def test_model_problem_sensitivity(ctx):
+    from paper_1502_07873_amd.query import grid_tuple
+    wl = synthetic.loh_workload(2)
+    _say("model problem sensitivity Jacobian")
+    S = 2
+    rec = synthetic.loh_scenarios()["III"][4][1]
+    g = grid_tuple(wl.grid)
+    H1 = torch.empty((S, 7, 7), dtype=torch.float64, device="cuda")
+    J = [torch.empty((wl.grid.nsteps + 1, len(rec), 2, 7), dtype=torch.float64,
+                     device="cuda") for _ in range(S)]
+    ctx.jacobian_sensitivity([g] * S, [_dev_medium(wl.medium)] * S, wl.theta, [rec] * S,
+                             wl.sigma, H1, stf="gauss", J=J)
+    torch.cuda.synchronize()
+    for s in range(S):
+        _, Jr = elastic.jacobian_sensitivity(wl.grid, wl.medium, wl.theta[s], rec, "gauss")
+        for j in range(7):
+            e = _relerr(J[s].cpu().numpy()[..., j], Jr[..., j])
+            assert e <= 1e-4, (s, j, e)

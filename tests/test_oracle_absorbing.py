@@ -127,3 +127,27 @@ def test_underresolved_grid_modes_do_not_grow():
     env = _envelope(40.0, 0.02, 20000)
     assert env[-1] < 0.05, env
     assert max(env[8:]) <= 1.5 * max(env[2:8]), env
+
+
+def test_model_problem_inputs_and_stability():
+    # the paper's model problem: scenario arrays lie on the candidate nodes,
+    # prior sources keep their stencil on free nodes, and the oracle solve at
+    # the paper's dt (c_p dt / h = 0.75 in the half-space) stays bounded and
+    # settles once the waves have left
+    import synthetic
+    wl = synthetic.loh_workload(3)
+    cand = set(int(i) for i in wl.receivers)
+    sizes = {k: len(v) for k, v in synthetic.loh_scenarios().items()}
+    assert sizes == {"I": 6, "II": 10, "III": 20}
+    for designs in synthetic.loh_scenarios().values():
+        for _, idx in designs:
+            assert set(int(i) for i in idx) <= cand and len(set(idx)) == len(idx)
+    g = wl.grid
+    for corner in (wl.lo, wl.hi):
+        kx, kz = int(corner[0] // g.h), int(corner[1] // g.h)
+        assert kx - 2 >= 1 and kx + 3 <= g.nx - 2 and kz - 2 >= 0 and kz + 3 <= g.nz - 2
+    long = Grid(g.nx, g.nz, g.h, g.dt, 3200, bc="absorbing")
+    tr = elastic.forward(long, wl.medium, synthetic.loh_prior_mean_paper(), wl.receivers, "gauss")
+    pk = np.abs(tr).max()
+    env = [np.abs(tr[m:m + 320]).max() / pk for m in range(0, 3201 - 320, 320)]
+    assert np.isfinite(tr).all() and max(env[1:]) < 0.1 and env[-1] < 1e-3, env
