@@ -209,6 +209,115 @@ def _bench_c5(ctx, reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40):
     return out
 
 
+def _bench_loh2d(ctx, nmc=10000, level=5, nbatch=10):
+    """The paper's model problem (Section 4.1) and its scenarios (Section 4.5):
+    per-receiver H_1 over the 91 candidate surface nodes for M = nmc Monte
+    Carlo samples and for the level-`level` sparse grid (8583 nodes at level
+    5), every scenario design's EIG from the same solves, a 68 % interval
+    from batch means, and the conditioning of H_1 at the prior mean."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_1502_07873_amd import make_prior, sparse_grid_gl
+    from paper_1502_07873_amd.query import device_medium, grid_tuple
+    wl = synthetic.loh_workload(nmc)
+    g = grid_tuple(wl.grid)
+    med = device_medium(wl.medium.kind, wl.medium.rho, wl.medium.lam, wl.medium.mu)
+    R = len(wl.receivers)
+    pos = {int(ix): c for c, ix in enumerate(wl.receivers)}
+    designs = [(scen, lab, idx) for scen, ds in synthetic.loh_scenarios().items()
+               for lab, idx in ds]
+    masks = np.zeros((len(designs), R), dtype=np.uint8)
+    for q, (_, _, idx) in enumerate(designs):
+        masks[q, [pos[int(i)] for i in idx]] = 1
+    dmask = torch.as_tensor(masks, device="cuda")
+    prior = make_prior(wl.lo, wl.hi)
+
+    def per_receiver_h1(theta, jacobian):
+        S = len(theta)
+        H = torch.empty((S, R, 7, 7), dtype=torch.float64, device="cuda")
+        st = torch.empty(S, dtype=torch.int32, device="cuda")
+        fn = ctx.jacobian_fd if jacobian == "fd" else ctx.jacobian_sensitivity
+        fn([g] * S, [med] * S, theta, [wl.receivers] * S, wl.sigma, H, stf="gauss",
+           per_receiver=True, status=st)
+        return H, st
+
+    def design_eigs(H, theta, w):
+        e = torch.empty(len(designs), dtype=torch.float64, device="cuda")
+        ctx.design_eval(H, dmask, prior, w, e, theta=theta)
+        return e.cpu().numpy()
+
+    out = {"grid": [wl.grid.nx, wl.grid.nz, wl.grid.nsteps], "h": wl.grid.h,
+           "dt": wl.grid.dt, "edges": "absorbing (first-order Clayton-Engquist)",
+           "candidates": R, "designs": len(designs)}
+    # warm-up and tuning on a few samples
+    per_receiver_h1(wl.theta[:64], "fd")
+    torch.cuda.synchronize()
+    runs = {}
+    for jac in ("fd", "sensitivity"):
+        ctx.stencil_stats(reset=True)
+        t0 = time.perf_counter()
+        H, st = per_receiver_h1(wl.theta, jac)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        sst = ctx.stencil_stats(reset=True)
+        nsol = 15 if jac == "fd" else 8
+        upd = nsol * nmc * wl.grid.nx * wl.grid.nz * wl.grid.nsteps
+        eig = design_eigs(H, wl.theta, wl.weights)
+        bm = []
+        b = nmc // nbatch
+        for k in range(nbatch):
+            bm.append(design_eigs(H[k * b:(k + 1) * b].contiguous(), wl.theta[k * b:(k + 1) * b],
+                                  np.full(b, 1.0 / b)))
+        ci = np.std(np.stack(bm), axis=0, ddof=1) / np.sqrt(nbatch)
+        runs[jac] = {"seconds": t, "sample_eig_evals_per_s": nmc / t,
+                     "grid_pt_updates_per_s": upd / t, "solves": nsol * nmc,
+                     "stencil_avg_launch_ms": sst["ms"] / max(sst["launches"], 1),
+                     "stencil_launches": sst["launches"],
+                     "flagged_samples": int(st.abs().gt(0).sum())}
+        runs[jac]["eig"] = eig
+        runs[jac]["ci68"] = ci
+        del H
+    out["mc"] = {"samples": nmc, "batches_for_ci": nbatch,
+                 **{jac: {k: v for k, v in r.items() if k not in ("eig", "ci68")}
+                    for jac, r in runs.items()}}
+    # sparse quadrature
+    nodes, w = sparse_grid_gl(7, level, wl.lo, wl.hi)
+    t0 = time.perf_counter()
+    H, st = per_receiver_h1(nodes, "fd")
+    eig_sg = design_eigs(H, nodes, w)
+    torch.cuda.synchronize()
+    out["sparse"] = {"level": level, "nodes": len(w), "seconds": time.perf_counter() - t0,
+                     "flagged_nodes": int(st.abs().gt(0).sum())}
+    del H
+    curves = {}
+    for q, (scen, lab, _) in enumerate(designs):
+        curves.setdefault(scen, []).append(
+            {"design": lab, "eig_mc": float(runs["fd"]["eig"][q]),
+             "ci68_mc": float(runs["fd"]["ci68"][q]),
+             "eig_mc_sensitivity": float(runs["sensitivity"]["eig"][q]),
+             "eig_sparse": float(eig_sg[q])})
+    out["scenarios"] = curves
+    c3 = curves["III"]
+    out["scenario_III_best_dR"] = c3[int(np.argmax([c["eig_mc"] for c in c3]))]["design"]
+    c1 = [c["eig_mc"] for c in curves["I"]]
+    out["scenario_I_gain_3_to_17_vs_17_to_81"] = [c1[3] - c1[0], c1[5] - c1[3]]
+    # conditioning of H_1 at the prior mean (one array per scenario family)
+    th = synthetic.loh_prior_mean_paper()[None, :]
+    H, _ = per_receiver_h1(th, "fd")
+    Hr = H.cpu().numpy()[0]
+    conds = {}
+    for scen, lab in (("I", "NR=17,dR=1000"), ("III", "dR=1000"), ("I", "NR=81,dR=200")):
+        idx = next(i for s_, l_, i in designs if s_ == scen and l_ == lab)
+        H1 = Hr[[pos[int(i)] for i in idx]].sum(axis=0)
+        d = np.sqrt(np.diag(H1))
+        conds[f"{scen}:{lab}"] = {"cond_H1": float(np.linalg.cond(H1)),
+                                  "cond_scaled": float(np.linalg.cond(H1 / np.outer(d, d)))}
+    out["conditioning_at_prior_mean"] = conds
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,8 +329,9 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed query: no one-solve baseline, sensitivity path, "
                          "serving or CPU baseline (for counter runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
-                    help="c2: the headline query (default); c3/c5: extra measurements")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "loh2d"],
+                    help="c2: the headline query (default); c3/c5/loh2d: extra measurements "
+                         "(loh2d: the paper's model problem and scenarios)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
     args = ap.parse_args()
@@ -245,6 +355,8 @@ def main():
         ctx = Context(0, 200 << 30)
         if args.workload == "c3":
             res = _bench_c3(ctx, args.samples if args.samples != 256 else 4096)
+        elif args.workload == "loh2d":
+            res = _bench_loh2d(ctx, args.samples if args.samples != 256 else 10000)
         else:
             res = _bench_c5(ctx)
         print(json.dumps({"workload": args.workload, **res}), flush=True)
