@@ -27,6 +27,10 @@ if ROOT not in sys.path:
 METRIC = ("EIG evals/s and grid-pt updates/s (HBM GB/s % peak) at ≤1e-3 nat err; "
           "p50/p99")
 HBM_PEAK_GBS = 8000.0
+# FP32 vector issue rate without packed-FP32 instructions (which this build
+# never emits): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations/s; the
+# published 157.3 TFLOP/s counts an FMA as two flops on packed pairs.
+ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_layered_c2_traffic.json")
 
 
@@ -318,6 +322,90 @@ def _bench_loh2d(ctx, nmc=10000, level=5, nbatch=10):
     return out
 
 
+def _bench_nested(ctx, sizes=(1000, 10000, 100000, 400000), nlaplace=10000, sg_level=4):
+    """Section 4.4: the Laplace method (Theorem 4 on the three inferred
+    parameters, Monte Carlo and sparse quadrature) against the nested Monte
+    Carlo estimator with the outer samples reused as inner ones, on the
+    model problem with T = 1.25 s and two receivers.  Also times the
+    nested kernel (vector-ALU bound: an FP64 subtract and FMA per (n, m, k),
+    3 flops; alu_frac against the vector issue rate, which FP64 shares with
+    unpacked FP32 on this chip)."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_1502_07873_amd import make_prior, sparse_grid_gl
+    from paper_1502_07873_amd.query import device_medium, grid_tuple
+    grid, med, rec, lo, hi, tpl = synthetic.loh_nested_setup()
+    dm = device_medium(med.kind, med.rho, med.lam, med.mu)
+    g = grid_tuple(grid)
+    act = list(synthetic.LOH_NESTED_ACTIVE)
+    sigma = 0.01
+    K = (grid.nsteps + 1) * len(rec) * 2
+    rng = np.random.default_rng(44)
+    out = {"grid": [grid.nx, grid.nz, grid.nsteps], "receivers_x1": [-9000, 1000],
+           "inferred": ["depth", "omega_s", "m_xx"], "nobs": K, "sigma": sigma}
+    # Laplace, Monte Carlo
+    prior = make_prior(lo, hi, active=act)
+
+    def laplace(theta, w):
+        S = len(theta)
+        H1 = torch.empty((S, 7, 7), dtype=torch.float64, device="cuda")
+        ctx.jacobian_fd([g] * S, [dm] * S, theta, [rec] * S, sigma, H1, stf="gauss")
+        dkl = torch.empty(S, dtype=torch.float64, device="cuda")
+        eig = torch.empty(1, dtype=torch.float64, device="cuda")
+        ctx.laplace_eig(H1, prior, w, dkl, eig, theta=theta)
+        return float(eig.cpu()[0]), dkl.cpu().numpy()
+
+    th = synthetic.loh_nested_draws(rng, nlaplace)
+    t0 = time.perf_counter()
+    e_mc, dk = laplace(th, np.full(nlaplace, 1.0 / nlaplace))
+    out["laplace_mc"] = {"samples": nlaplace, "eig": e_mc,
+                         "ci68": float(np.std(dk, ddof=1) / np.sqrt(nlaplace)),
+                         "seconds": time.perf_counter() - t0}
+    # Laplace, sparse quadrature over the three inferred parameters
+    nodes3, w3 = sparse_grid_gl(3, sg_level, lo[act], hi[act])
+    thq = np.repeat(tpl[None, :], len(w3), axis=0)
+    thq[:, act] = nodes3
+    e_sg, _ = laplace(thq, w3)
+    out["laplace_sparse"] = {"level": sg_level, "nodes": len(w3), "eig": e_sg}
+    # nested Monte Carlo, reuse
+    res = []
+    for N in sizes:
+        th = synthetic.loh_nested_draws(rng, N)
+        gtr = torch.empty((N, K), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.forward_solve_batch([g] * N, [dm] * N, th, [rec] * N, list(gtr), stf="gauss")
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        noise = torch.randn((N, K), generator=torch.Generator(device="cuda").manual_seed(N),
+                            device="cuda", dtype=torch.float32)
+        lr = torch.empty(N, dtype=torch.float64, device="cuda")
+        eig = torch.empty(1, dtype=torch.float64, device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.nested_mc_eig(gtr, noise, gtr, sigma, lr, eig)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        pairs = float(N) * N * K
+        v = float(eig.cpu()[0])
+        res.append({"N=M": N, "eig": v, "log_M": float(np.log(N)),
+                    "ci68": float(lr.std().item() / np.sqrt(N)),
+                    "rel_diff_vs_laplace_mc": (v - e_mc) / e_mc,
+                    "forward_seconds": t_fwd, "kernel_ms": ms,
+                    "pair_elements_per_s": pairs / (ms * 1e-3),
+                    "fp64_TFLOPs": 3 * pairs / (ms * 1e-3) / 1e12,
+                    "alu_frac": 2 * pairs / (ms * 1e-3) / ALU_PEAK_OPS})
+        print(f"[bench] nested N=M={N}: {v:.4f} nats, kernel {ms:.1f} ms", flush=True)
+        del gtr, noise
+    out["nested_reuse"] = res
+    out["note"] = ("with reuse each log ratio is at most log M, so the nested estimate "
+                   "approaches the Laplace value from below as M grows past exp(EIG)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,7 +417,7 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed query: no one-solve baseline, sensitivity path, "
                          "serving or CPU baseline (for counter runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "loh2d"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "loh2d", "nested"],
                     help="c2: the headline query (default); c3/c5/loh2d: extra measurements "
                          "(loh2d: the paper's model problem and scenarios)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -357,6 +445,8 @@ def main():
             res = _bench_c3(ctx, args.samples if args.samples != 256 else 4096)
         elif args.workload == "loh2d":
             res = _bench_loh2d(ctx, args.samples if args.samples != 256 else 10000)
+        elif args.workload == "nested":
+            res = _bench_nested(ctx)
         else:
             res = _bench_c5(ctx)
         print(json.dumps({"workload": args.workload, **res}), flush=True)

@@ -115,12 +115,18 @@ typedef struct {
     const int32_t* ix;
 } eig_receivers;
 
-/* Prior density p(theta); h(theta) = log p(theta) enters D^_KL. */
+/* Prior density p(theta); h(theta) = log p(theta) enters D^_KL.
+ * active: bit j set = theta_j is inferred (0 means all seven).  Parameters
+ * outside the mask are known: D^_KL then takes the active sub-block of H_1,
+ * N_theta = the number of active parameters, and h is the prior's marginal
+ * over them (uniform: the sub-box; Gaussian: the sub-mean and sub-covariance),
+ * as in the reduced-parameter experiments of Sections 4.3 and 4.4. */
 typedef struct {
     int32_t kind;
     double lo[EIG_NTHETA], hi[EIG_NTHETA];  /* uniform box, lo < hi */
     double mean[EIG_NTHETA];                /* gaussian mean */
     double cov[EIG_NTHETA * EIG_NTHETA];    /* gaussian covariance, SPD */
+    int32_t active;                         /* bitmask of inferred parameters */
 } eig_prior;
 
 /* Create a context on HIP device `device`.  The context owns all internal
@@ -240,6 +246,30 @@ int jacobian_sensitivity(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
                          const eig_receivers* rec, int32_t sigma_mode, const double* sigma,
                          int32_t per_receiver, float* const* nominal, double* const* J,
                          double* H1, int32_t* status, void* stream);
+
+/*
+ * nested_mc_eig — the direct double-loop sample average of the expected
+ * information gain (the estimator the introduction calls prohibitively
+ * expensive, compared with the Laplace method in Section 4.4).  For outer
+ * samples n with model outputs g_n (data y_n = g_n + sigma e_n) and inner
+ * prior samples m with outputs g_m, C_eps = sigma^2 I:
+ *   logratio_n = -|e_n|^2/2 - log( (1/M) sum_m exp(-|y_n - g_m|^2 / (2 sigma^2)) )
+ *   eig        = (1/N) sum_n logratio_n
+ * (Gaussian normalisers cancel).  Reusing the outer samples as the inner
+ * ones, as the paper does, is the caller's choice (g_inner == g_outer).
+ *
+ *   g_outer: device float [nouter][nobs] (e.g. traces [nt][nrec][2] per solve)
+ *   noise:   device float [nouter][nobs], standard normal draws (the caller's)
+ *   g_inner: device float [ninner][nobs]
+ *   sigma > 0; logratio: device double [nouter]; eig: device double [1] or NULL
+ * y_n, distances, sums and log-sum-exp in FP64 (the FP32 inputs are exact in
+ * FP64); context workspace: 16 bytes per outer sample per inner-range split
+ * (splits only when nouter is small).  Errors: EIG_EINVAL for non-positive sizes or sigma, NULL
+ * arrays.
+ */
+int nested_mc_eig(eig_ctx* ctx, int32_t nouter, int32_t ninner, int32_t nobs,
+                  const float* g_outer, const float* noise, const float* g_inner,
+                  double sigma, double* logratio, double* eig, void* stream);
 
 /*
  * laplace_eig — Theorem 4 with the scaled Hessian of Section 3.3.3:

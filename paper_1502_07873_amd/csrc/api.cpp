@@ -823,6 +823,24 @@ int jacobian_sensitivity(eig_ctx* c, int32_t nsample, const eig_grid* grid,
                          sigma, per_receiver, nominal, J, H1, status, stream);
 }
 
+int nested_mc_eig(eig_ctx* c, int32_t nouter, int32_t ninner, int32_t nobs,
+                  const float* g_outer, const float* noise, const float* g_inner,
+                  double sigma, double* logratio, double* eig, void* stream) {
+    if (!c) return set_error(EIG_EINVAL, "ctx is NULL");
+    if (nouter <= 0 || ninner <= 0 || nobs <= 0)
+        return set_error(EIG_EINVAL, "nested_mc_eig sizes must be positive");
+    if (!g_outer || !noise || !g_inner || !logratio)
+        return set_error(EIG_EINVAL, "NULL array argument");
+    if (!(sigma > 0) || !std::isfinite(sigma)) return set_error(EIG_EINVAL, "sigma");
+    HIP_TRY(hipSetDevice(c->device));
+    const int rc = ensure_ws(c, nested_workspace(nouter, ninner));
+    if (rc) return rc;
+    launch_nested(g_outer, noise, g_inner, nouter, ninner, nobs, sigma, logratio, eig,
+                  (double*)c->ws, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return EIG_OK;
+}
+
 static int upload_small(eig_ctx* c, size_t off, const void* p, size_t bytes, hipStream_t s) {
     std::vector<char> v(bytes);
     std::memcpy(v.data(), p, bytes);
@@ -831,6 +849,8 @@ static int upload_small(eig_ctx* c, size_t off, const void* p, size_t bytes, hip
 
 static int check_prior(const eig_prior* prior) {
     if (!prior) return set_error(EIG_EINVAL, "prior is NULL");
+    if (prior->active < 0 || prior->active >= (1 << kNT))
+        return set_error(EIG_EINVAL, "prior active mask");
     if (prior->kind == EIG_PRIOR_UNIFORM) {
         for (int j = 0; j < kNT; ++j)
             if (!(prior->hi[j] > prior->lo[j])) return set_error(EIG_EINVAL, "prior box lo < hi");

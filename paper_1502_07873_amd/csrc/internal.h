@@ -107,6 +107,13 @@ extern const StencilVariant kVariants[kNumVariants];
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                     int variant, hipStream_t s);
 void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s);
+// Nested Monte Carlo log ratios (and their mean when eig != NULL); work
+// holds nested_workspace() bytes of per-split partial sums.
+int nested_splits(int nouter, int ninner);
+size_t nested_workspace(int nouter, int ninner);
+void launch_nested(const float* gout, const float* noise, const float* gin, int nouter,
+                   int ninner, int nobs, double sigma, double* logratio, double* eig,
+                   double* work, hipStream_t s);
 // Absorbing-edge update of level step+1 for descs[0..n) (one-step buffers).
 void launch_ce_edges(const SolveDesc* descs, int n, int step, hipStream_t s);
 void launch_sample_check(const SampleDesc* samples, int nsample, const double* given,

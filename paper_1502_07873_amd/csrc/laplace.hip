@@ -1,6 +1,7 @@
 // Laplace KL estimate, quadrature averages and design search, FP64.
 //
-// D^_KL(theta) = -1/2 log((2 pi)^7 |H_1^-1|) - 7/2 - h(theta)   (Theorem 4)
+// D^_KL(theta) = -1/2 log((2 pi)^N |H_1^-1|) - N/2 - h(theta)   (Theorem 4;
+// N = 7, or the number of inferred parameters when the prior marks a subset)
 // with log det H_1 taken through the scaled Hessian of Section 3.3.3,
 // S = sqrt(diag H_1), H~ = S^-1 H_1 S^-1 = L L^T, so that the ~30 decades
 // spanned by the raw entries never reach the factorisation;
@@ -13,26 +14,27 @@ namespace eig {
 
 namespace {
 
-// log det of a symmetric 7x7 matrix (full storage) via the scaled Cholesky
-// factorisation; false if it is not positive definite or not finite.
-__device__ bool scaled_logdet(const double* H, double* out) {
+// log det of a symmetric n x n matrix (full storage, row stride n, n <= 7)
+// via the scaled Cholesky factorisation; false if it is not positive
+// definite or not finite.
+__device__ bool scaled_logdet(const double* H, int n, double* out) {
     double s[kNT];
     double ld = 0.0;
-    for (int j = 0; j < kNT; ++j) {
-        const double d = H[j * kNT + j];
+    for (int j = 0; j < n; ++j) {
+        const double d = H[j * n + j];
         if (!(d > 0.0) || !isfinite(d)) return false;
         s[j] = sqrt(d);
         ld += 2.0 * log(s[j]);
     }
     double L[kNT][kNT];
-    for (int j = 0; j < kNT; ++j) {
-        double v = H[j * kNT + j] / (s[j] * s[j]);
+    for (int j = 0; j < n; ++j) {
+        double v = H[j * n + j] / (s[j] * s[j]);
         for (int k = 0; k < j; ++k) v -= L[j][k] * L[j][k];
         if (!(v > 0.0) || !isfinite(v)) return false;
         L[j][j] = sqrt(v);
         ld += 2.0 * log(L[j][j]);
-        for (int i = j + 1; i < kNT; ++i) {
-            double w = H[i * kNT + j] / (s[i] * s[j]);
+        for (int i = j + 1; i < n; ++i) {
+            double w = H[i * n + j] / (s[i] * s[j]);
             for (int k = 0; k < j; ++k) w -= L[i][k] * L[j][k];
             L[i][j] = w / L[j][j];
         }
@@ -41,48 +43,63 @@ __device__ bool scaled_logdet(const double* H, double* out) {
     return true;
 }
 
-// h(theta) = log p(theta).
-__device__ double log_prior(const eig_prior& pr, const double* th) {
+// Indices of the inferred parameters (all seven when the mask is 0).
+__device__ int active_set(const eig_prior& pr, int* idx) {
+    const int act = pr.active ? pr.active : (1 << kNT) - 1;
+    int n = 0;
+    for (int j = 0; j < kNT; ++j)
+        if ((act >> j) & 1) idx[n++] = j;
+    return n;
+}
+
+// h(theta) = log p(theta), the prior's marginal over the active parameters.
+__device__ double log_prior(const eig_prior& pr, const double* th, const int* idx, int n) {
     if (pr.kind == EIG_PRIOR_UNIFORM) {
         double v = 0.0;
-        for (int j = 0; j < kNT; ++j) v -= log(pr.hi[j] - pr.lo[j]);
+        for (int a = 0; a < n; ++a) v -= log(pr.hi[idx[a]] - pr.lo[idx[a]]);
         return v;
     }
-    // Gaussian: -1/2 r^T C^-1 r - 1/2 (7 log 2 pi + log det C), via C = L L^T
+    // Gaussian: -1/2 r^T C^-1 r - 1/2 (n log 2 pi + log det C), via C = L L^T
     double L[kNT][kNT];
     double ld = 0.0;
-    for (int j = 0; j < kNT; ++j) {
-        double v = pr.cov[j * kNT + j];
+    for (int j = 0; j < n; ++j) {
+        double v = pr.cov[idx[j] * kNT + idx[j]];
         for (int k = 0; k < j; ++k) v -= L[j][k] * L[j][k];
         L[j][j] = sqrt(v);
         ld += 2.0 * log(L[j][j]);
-        for (int i = j + 1; i < kNT; ++i) {
-            double w = pr.cov[i * kNT + j];
+        for (int i = j + 1; i < n; ++i) {
+            double w = pr.cov[idx[i] * kNT + idx[j]];
             for (int k = 0; k < j; ++k) w -= L[i][k] * L[j][k];
             L[i][j] = w / L[j][j];
         }
     }
     double y[kNT];
     double q = 0.0;
-    for (int i = 0; i < kNT; ++i) {
-        double v = th[i] - pr.mean[i];
+    for (int i = 0; i < n; ++i) {
+        double v = th[idx[i]] - pr.mean[idx[i]];
         for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
         y[i] = v / L[i][i];
         q += y[i] * y[i];
     }
-    return -0.5 * q - 0.5 * (kNT * log(2.0 * M_PI) + ld);
+    return -0.5 * q - 0.5 * (n * log(2.0 * M_PI) + ld);
 }
 
+// Theorem 4 on the active sub-block of a full 7x7 H_1.
 __device__ bool dkl_of(const double* H, const eig_prior& pr, const double* th,
                        double* dkl, double* logdet) {
+    int idx[kNT];
+    const int n = active_set(pr, idx);
+    double Hs[kNT * kNT];
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) Hs[a * n + b] = H[idx[a] * kNT + idx[b]];
     double ld;
-    if (!scaled_logdet(H, &ld)) {
+    if (!scaled_logdet(Hs, n, &ld)) {
         *dkl = __longlong_as_double(0x7ff8000000000000ULL);
         *logdet = *dkl;
         return false;
     }
     *logdet = ld;
-    *dkl = -0.5 * (kNT * log(2.0 * M_PI) - ld) - 0.5 * kNT - log_prior(pr, th);
+    *dkl = -0.5 * (n * log(2.0 * M_PI) - ld) - 0.5 * n - log_prior(pr, th, idx, n);
     return true;
 }
 

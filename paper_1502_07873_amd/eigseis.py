@@ -63,7 +63,7 @@ class Receivers(ctypes.Structure):
 class Prior(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("lo", ctypes.c_double * NTHETA),
                 ("hi", ctypes.c_double * NTHETA), ("mean", ctypes.c_double * NTHETA),
-                ("cov", ctypes.c_double * (NTHETA * NTHETA))]
+                ("cov", ctypes.c_double * (NTHETA * NTHETA)), ("active", ctypes.c_int32)]
 
 
 def _load():
@@ -86,6 +86,7 @@ def _load():
                         ctypes.c_int),
         "jacobian_sensitivity": ([vp, i32, vp, vp, vp, i32, vp, i32, vp, i32, vp, vp, vp,
                                   vp, vp], ctypes.c_int),
+        "nested_mc_eig": ([vp, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
         "laplace_eig": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "design_eval": ([vp, i32, i32, vp, i32, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "design_greedy": ([vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
@@ -109,7 +110,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("eig_ctx_create", "eig_ctx_destroy", "eig_last_error", "eig_ctx_workspace_bytes",
             "eig_ctx_stencil_stats", "eig_ctx_set_option", "eig_ctx_get_option",
-            "forward_solve_batch", "jacobian_fd", "jacobian_sensitivity", "laplace_eig",
+            "forward_solve_batch", "jacobian_fd", "jacobian_sensitivity", "nested_mc_eig", "laplace_eig",
             "design_eval", "design_greedy", "noise_sigma_peak", "sparse_grid_gl", "eig_server_create",
             "eig_server_destroy", "eig_server_submit", "eig_server_step", "eig_server_poll",
             "eig_server_pending")
@@ -146,8 +147,10 @@ def _ptr_array(tensors):
     return arr
 
 
-def make_prior(lo=None, hi=None, mean=None, cov=None) -> Prior:
+def make_prior(lo=None, hi=None, mean=None, cov=None, active=None) -> Prior:
+    """active: indices of the inferred parameters (None: all seven)."""
     p = Prior()
+    p.active = 0 if active is None else sum(1 << int(j) for j in active)
     if mean is not None:
         p.kind = PRIOR_GAUSSIAN
         p.mean[:] = list(np.asarray(mean, dtype=np.float64))
@@ -300,6 +303,18 @@ class Context:
             STF_KINDS[stf], recs, int(sigma_mode), _np_ptr(sg), 1 if per_receiver else 0,
             _ptr_array(nominal), _ptr_array(J), _ptr(H1), _ptr(status), _stream(stream)))
         del keep
+
+    def nested_mc_eig(self, g_outer, noise, g_inner, sigma, logratio, eig=None, stream=None):
+        """g_outer/noise [N][K], g_inner [M][K] device float32 (contiguous)."""
+        n, k = int(g_outer.shape[0]), int(g_outer.shape[1])
+        m = int(g_inner.shape[0])
+        for t in (g_outer, noise, g_inner):
+            if not t.is_contiguous() or str(t.dtype) != "torch.float32":
+                raise ValueError("nested_mc_eig needs contiguous float32 tensors")
+        if tuple(noise.shape) != (n, k) or int(g_inner.shape[1]) != k:
+            raise ValueError("nested_mc_eig shape mismatch")
+        _check(_lib.nested_mc_eig(self._h, n, m, k, _ptr(g_outer), _ptr(noise), _ptr(g_inner),
+                                  float(sigma), _ptr(logratio), _ptr(eig), _stream(stream)))
 
     def laplace_eig(self, H1, prior: Prior, w, dkl, eig, theta=None, logdet=None,
                     status=None, stream=None):

@@ -335,6 +335,30 @@ def loh_workload(nsample: int = 256, seed: int = 5, nsteps: int = LOH_NSTEPS) ->
                     stf="gauss", sigma=0.01)
 
 
+# Section 4.4: the Laplace method against the nested Monte Carlo estimator
+# on the model problem with T = 1.25 s, two receivers at x_1 = -9 km and
+# 1 km, x_1 = -1 km, t_s = 1 s, m_{x1x2} = m_{x2x2} = 1e14 known, and the
+# depth, omega_s and m_{x1x1} inferred (the priors of Section 4.3).
+LOH_NESTED_ACTIVE = (1, 3, 4)
+
+
+def loh_nested_setup(nsteps: int = 50):
+    """(grid, medium, receivers, lo, hi, template theta) of the comparison."""
+    grid = Grid(LOH_NX, LOH_NZ, LOH_H, LOH_DT, nsteps, bc="absorbing")
+    lo, hi = loh_prior()
+    template = np.array([LOH_X0 - 1000.0, 2000.0, 1.0, 4.0, 1e14, -1e14, 1e14])
+    return grid, loh_medium(), loh_receivers([-9000.0, 1000.0]), lo, hi, template
+
+
+def loh_nested_draws(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n prior draws of the three inferred parameters, the rest fixed."""
+    _, _, _, lo, hi, template = loh_nested_setup()
+    th = np.repeat(template[None, :], n, axis=0)
+    for j in LOH_NESTED_ACTIVE:
+        th[:, j] = rng.uniform(lo[j], hi[j], n)
+    return th
+
+
 def serving_queries(rng: np.random.Generator, nquery: int,
                     grid_override: Optional[tuple] = None) -> List[Workload]:
     out = []
