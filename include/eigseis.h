@@ -272,6 +272,45 @@ int nested_mc_eig(eig_ctx* ctx, int32_t nouter, int32_t ninner, int32_t nobs,
                   double sigma, double* logratio, double* eig, void* stream);
 
 /*
+ * theorem3_eig — the O(N^-2) estimator of Theorem 3.  For each outer sample
+ * (theta*_s, noise e_s): data y_s = g(theta*_s) + sigma e_s; the MAP point
+ * theta^_s by Gauss-Newton from theta*_s (Theorem 1 puts it within
+ * O(N^-1/2)); at theta^_s
+ *   H_1 from the 7 forward-sensitivity solves (Algorithm 1, steps 1-5),
+ *   H_2 = -sum_{r,m} grad grad g o C_eps^-1 (y - g(theta^)) (Theorem 2) from one
+ *         dual solve (Algorithm 1, steps 6-10): with rigid edges the adjoint of
+ *         the leapfrog scheme is the same stencil run backward in time, driven
+ *         at the receivers by the residuals divided by the lumped mass
+ *         h^2/2 of a surface node; its field on the 7x7 forcing window is
+ *         contracted with the second derivatives of the discretised source,
+ *   and the integrand
+ *   -1/2 log((2 pi)^N |H^-1|) - N/2 - h(theta^) - 1/2 tr(H^-1 grad grad h),
+ *   H = H_1 + H_2 - grad grad h (active parameters of the prior only; the
+ *   others stay at theta*).
+ * Cost per sample: 1 + 8 (iters + 1) + 1 solves; the call synchronises the
+ * stream once per Gauss-Newton iteration (theta is updated on the host).
+ *
+ *   grid, medium, rec: host arrays [nsample]; rigid edges only
+ *              (EIG_EUNSUPPORTED otherwise)
+ *   theta_star: host [nsample][7]; noise: host array [nsample] of device
+ *              float pointers [nsteps+1][nrec][2] (standard normal draws)
+ *   sigma > 0: C_eps = sigma^2 I; prior: as for laplace_eig; w: host [nsample]
+ *   iters:     Gauss-Newton steps, 0..64 (0: theta^ = theta*)
+ *   theta_hat: host [nsample][7] (out); H1, H2: device [nsample][7][7] (out)
+ *   val:       device [nsample] integrands; eig: device [1] (sum w_s val_s)
+ *              or NULL; status: device [nsample] (EIG_ENOTPD if H is not
+ *              positive definite) or NULL
+ * Errors: EIG_EINVAL for bad arguments or an iterate whose source stencil
+ * leaves the free nodes, EIG_ENOTPD if a Gauss-Newton system is singular.
+ */
+int theorem3_eig(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
+                 const eig_medium* medium, const double* theta_star, int32_t stf_kind,
+                 const eig_receivers* rec, const float* const* noise, double sigma,
+                 const eig_prior* prior, const double* w, int32_t iters, double* theta_hat,
+                 double* H1, double* H2, double* val, double* eig, int32_t* status,
+                 void* stream);
+
+/*
  * laplace_eig — Theorem 4 with the scaled Hessian of Section 3.3.3:
  *   S = sqrt(diag H_1),  H~ = S^-1 H_1 S^-1 = L L^T,
  *   log det H_1 = 2 sum log L_ii + 2 sum log S_ii,

@@ -109,13 +109,16 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     rec_used.erase(std::unique(rec_used.begin(), rec_used.end()), rec_used.end());
     std::map<int, size_t> med_off;
     for (int m : med_used) med_off[m] = cv.take(medium_bytes(media[m]));
-    // stencil variants this wave may use, per solve class (medium kind, edges)
+    // stencil variants this wave may use, per solve class (medium kind,
+    // absorbing edges, dual solve): the last two need one step per launch
     std::vector<int> cands[2][2];
     for (int kind = 0; kind < 2; ++kind)
-        for (int bc = 0; bc < 2; ++bc)
-            stencil_candidates(c, kind, bc == EIG_BC_ABSORBING, cands[kind][bc]);
+        for (int one = 0; one < 2; ++one) stencil_candidates(c, kind, one != 0, cands[kind][one]);
+    auto one_step = [&](int i) {
+        return grids[solves[i].grid].bc == EIG_BC_ABSORBING || solves[i].rforce != nullptr;
+    };
     auto cand_of = [&](int i) -> const std::vector<int>& {
-        return cands[media[solves[i].medium].kind][grids[solves[i].grid].bc];
+        return cands[media[solves[i].medium].kind][one_step(i) ? 1 : 0];
     };
     auto family_steps = [&](int i) { return kVariants[cand_of(i)[0]].steps; };
     // fields: one contiguous block for all solves (cleared with one launch);
@@ -143,7 +146,8 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     std::vector<int> ord(n);
     for (int i = 0; i < n; ++i) ord[i] = i;
     auto class_of = [&](int i) {
-        return 2 * media[solves[i].medium].kind + grids[solves[i].grid].bc;
+        return 4 * media[solves[i].medium].kind + 2 * (solves[i].rforce != nullptr) +
+               grids[solves[i].grid].bc;
     };
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
         const int ka = class_of(a), kb = class_of(b);
@@ -206,6 +210,8 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         d.nrec = (int32_t)recsets[sp.recset].ix.size();
         d.medium_kind = mk.kind;
         d.h2 = (float)(g.h * g.h);
+        d.rforce = sp.rforce;
+        d.wrec = sp.wrec;
         // forcing window: union of the nominal and perturbed 6x6 stencils
         SourceJob& J = jobs[oi];
         std::memcpy(J.theta, sp.theta, sizeof(J.theta));
@@ -857,6 +863,337 @@ static int check_prior(const eig_prior* prior) {
     } else if (prior->kind != EIG_PRIOR_GAUSSIAN) {
         return set_error(EIG_EINVAL, "prior kind");
     }
+    return EIG_OK;
+}
+
+// Host side of the Gauss-Newton step on the active parameters:
+// (H_1 - grad grad h) step = -grad_data + grad h, through the diagonal
+// scaling of Section 3.3.3.  Returns false if the system is not SPD.
+static bool gn_step(const double* H1, const double* grad, const eig_prior& pr,
+                    const double* th, double* step) {
+    const int act = pr.active ? pr.active : (1 << kNT) - 1;
+    int idx[kNT], n = 0;
+    for (int j = 0; j < kNT; ++j)
+        if ((act >> j) & 1) idx[n++] = j;
+    double A[kNT][kNT], b[kNT];
+    for (int a = 0; a < n; ++a) {
+        b[a] = -grad[idx[a]];
+        for (int c = 0; c < n; ++c) A[a][c] = H1[idx[a] * kNT + idx[c]];
+    }
+    if (pr.kind == EIG_PRIOR_GAUSSIAN) {
+        // grad h = -Gamma^-1 (theta - mean), grad grad h = -Gamma^-1 (active block)
+        double C[kNT][kNT], Ci[kNT][kNT];
+        for (int a = 0; a < n; ++a)
+            for (int c = 0; c < n; ++c) C[a][c] = pr.cov[idx[a] * kNT + idx[c]];
+        // invert C by Gauss-Jordan (n <= 7, SPD)
+        double M[kNT][2 * kNT];
+        for (int a = 0; a < n; ++a)
+            for (int c = 0; c < 2 * n; ++c) M[a][c] = c < n ? C[a][c] : (c - n == a ? 1.0 : 0.0);
+        for (int p = 0; p < n; ++p) {
+            const double d = M[p][p];
+            if (!(d > 0.0)) return false;
+            for (int c = 0; c < 2 * n; ++c) M[p][c] /= d;
+            for (int r = 0; r < n; ++r)
+                if (r != p) {
+                    const double f = M[r][p];
+                    for (int c = 0; c < 2 * n; ++c) M[r][c] -= f * M[p][c];
+                }
+        }
+        for (int a = 0; a < n; ++a)
+            for (int c = 0; c < n; ++c) Ci[a][c] = M[a][c + n];
+        for (int a = 0; a < n; ++a) {
+            double g = 0.0;
+            for (int c = 0; c < n; ++c) {
+                A[a][c] += Ci[a][c];
+                g -= Ci[a][c] * (th[idx[c]] - pr.mean[idx[c]]);
+            }
+            b[a] += g;
+        }
+    }
+    double s[kNT];
+    for (int a = 0; a < n; ++a) {
+        if (!(A[a][a] > 0.0) || !std::isfinite(A[a][a])) return false;
+        s[a] = std::sqrt(A[a][a]);
+    }
+    double L[kNT][kNT];
+    for (int j = 0; j < n; ++j) {
+        double v = A[j][j] / (s[j] * s[j]);
+        for (int k = 0; k < j; ++k) v -= L[j][k] * L[j][k];
+        if (!(v > 0.0)) return false;
+        L[j][j] = std::sqrt(v);
+        for (int i = j + 1; i < n; ++i) {
+            double w = A[i][j] / (s[i] * s[j]);
+            for (int k = 0; k < j; ++k) w -= L[i][k] * L[j][k];
+            L[i][j] = w / L[j][j];
+        }
+    }
+    double y[kNT], x[kNT];
+    for (int i = 0; i < n; ++i) {
+        double v = b[i] / s[i];
+        for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+        y[i] = v / L[i][i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int k = i + 1; k < n; ++k) v -= L[k][i] * x[k];
+        x[i] = v / L[i][i];
+    }
+    for (int j = 0; j < kNT; ++j) step[j] = 0.0;
+    for (int a = 0; a < n; ++a) step[idx[a]] = x[a] / s[a];
+    return true;
+}
+
+int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_medium* medium,
+                 const double* theta_star, int32_t stf_kind, const eig_receivers* rec,
+                 const float* const* noise, double sigma, const eig_prior* prior,
+                 const double* w, int32_t iters, double* theta_hat, double* H1out,
+                 double* H2out, double* val, double* eig, int32_t* status, void* stream) {
+    if (!c) return set_error(EIG_EINVAL, "ctx is NULL");
+    if (nsample <= 0) return set_error(EIG_EINVAL, "nsample must be positive");
+    if (!grid || !medium || !theta_star || !rec || !noise || !w || !theta_hat || !H1out ||
+        !H2out || !val)
+        return set_error(EIG_EINVAL, "NULL array argument");
+    if (!(sigma > 0) || !std::isfinite(sigma)) return set_error(EIG_EINVAL, "sigma");
+    if (iters < 0 || iters > 64) return set_error(EIG_EINVAL, "iters must be in 0..64");
+    if (stf_kind != EIG_STF_GAUSS && stf_kind != EIG_STF_GAUSS_DERIV)
+        return set_error(EIG_EINVAL, "stf_kind");
+    int rc = check_prior(prior);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<eig_grid> grids(grid, grid + nsample);
+    std::vector<MediumKey> media;
+    std::map<MediumKey, int> seen;
+    std::vector<RecSet> recsets;
+    std::vector<int> med_of(nsample);
+    for (int i = 0; i < nsample; ++i) {
+        const eig_grid& g = grid[i];
+        if (!valid_grid(g)) return set_error(EIG_EINVAL, "grid " + std::to_string(i));
+        if (g.bc != EIG_BC_RIGID)
+            return set_error(EIG_EUNSUPPORTED,
+                             "theorem3_eig: the dual solve is the time-reversed stencil only "
+                             "with rigid edges");
+        if ((rc = validate_medium(medium[i]))) return rc;
+        if ((rc = check_receivers(rec[i], g))) return rc;
+        if (rec[i].n < 1) return set_error(EIG_EINVAL, "at least one receiver");
+        if (!noise[i]) return set_error(EIG_EINVAL, "noise pointer NULL");
+        const double* th = theta_star + (size_t)i * kNT;
+        for (int j = 0; j < kNT; ++j)
+            if (!std::isfinite(th[j])) return set_error(EIG_EINVAL, "theta not finite");
+        if (!source_inside(th[0], th[1], g))
+            return set_error(EIG_EINVAL, "source stencil touches a rigid node");
+        med_of[i] = medium_index(media, seen, medium[i], g);
+        recsets.push_back(RecSet{std::vector<int32_t>(rec[i].ix, rec[i].ix + rec[i].n), g.nx});
+    }
+    std::vector<double> th_cur(theta_star, theta_star + (size_t)nsample * kNT);
+    // per-sample device region: truth, nominal and 7 sensitivity traces, the
+    // dual's traces, injection and window record, descriptors, H1, grad, H2
+    auto sample_bytes = [&](int i) {
+        const size_t tr = align_up((size_t)(grid[i].nsteps + 1) * rec[i].n * sizeof(float2));
+        return 10 * tr + align_up((size_t)grid[i].nsteps * rec[i].n * sizeof(float2)) +
+               align_up((size_t)grid[i].nsteps * kSrcW * kSrcW * sizeof(float2)) +
+               align_up(sizeof(SampleDesc)) + align_up(sizeof(H2Job)) +
+               3 * align_up(kNT * kNT * sizeof(double)) + 4 * kAlign;
+    };
+    int s0 = 0;
+    while (s0 < nsample) {
+        int s1 = s0;
+        size_t need = 0;
+        WaveSizer wsz(grids, media, recsets);
+        size_t extra = 8 * kAlign + align_up(sizeof(eig_prior));
+        while (s1 < nsample) {
+            SolveSpec sp{};
+            sp.grid = s1;
+            sp.medium = med_of[s1];
+            sp.recset = s1;
+            const size_t one = wsz.cost(sp);
+            if (s1 > s0 && wsz.bytes + extra + 8 * one + sample_bytes(s1) > c->budget) break;
+            for (int q = 0; q < 8; ++q) wsz.add(sp);
+            extra += sample_bytes(s1) + 2 * sizeof(double);
+            need = wsz.bytes + extra;
+            ++s1;
+        }
+        if ((rc = ensure_ws(c, need))) return rc;
+        const int ns = s1 - s0;
+        Carve cv;
+        struct Off {
+            size_t ystar, nominal, sens[kNT], dtr, rf, wrec, H1, grad, H2;
+        };
+        std::vector<Off> off(ns);
+        for (int q = 0; q < ns; ++q) {
+            const int i = s0 + q;
+            const size_t tr = (size_t)(grid[i].nsteps + 1) * rec[i].n * sizeof(float2);
+            off[q].ystar = cv.take(tr);
+            off[q].nominal = cv.take(tr);
+            for (int j = 0; j < kNT; ++j) off[q].sens[j] = cv.take(tr);
+            off[q].dtr = cv.take(tr);
+            off[q].rf = cv.take((size_t)grid[i].nsteps * rec[i].n * sizeof(float2));
+            off[q].wrec = cv.take((size_t)grid[i].nsteps * kSrcW * kSrcW * sizeof(float2));
+            off[q].H1 = cv.take(kNT * kNT * sizeof(double));
+            off[q].grad = cv.take(kNT * sizeof(double));
+            off[q].H2 = cv.take(kNT * kNT * sizeof(double));
+        }
+        const size_t o_sd = cv.take(ns * sizeof(SampleDesc));
+        const size_t o_h2 = cv.take(ns * sizeof(H2Job));
+        const size_t o_sig = cv.take(ns * sizeof(double));
+        const size_t o_th = cv.take((size_t)ns * kNT * sizeof(double));
+        const size_t solve_base = align_up(cv.off);
+        char* ws = c->ws;
+        auto tp = [&](size_t o) { return (float2*)(ws + o); };
+        // sigma per sample (given)
+        {
+            std::vector<double> sg(ns, sigma);
+            if ((rc = upload_small(c, o_sig, sg.data(), ns * sizeof(double), s))) return rc;
+        }
+        auto base_spec = [&](int i, const double* th) {
+            SolveSpec sp{};
+            sp.grid = i;
+            sp.medium = med_of[i];
+            sp.recset = i;
+            std::memcpy(sp.theta, th, sizeof(sp.theta));
+            sp.param = -1;
+            sp.stf = stf_kind;
+            return sp;
+        };
+        // 1. truth traces g(theta*)
+        {
+            std::vector<SolveSpec> sol;
+            for (int q = 0; q < ns; ++q) {
+                SolveSpec sp = base_spec(s0 + q, theta_star + (size_t)(s0 + q) * kNT);
+                sp.traces = tp(off[q].ystar);
+                sol.push_back(sp);
+            }
+            if ((rc = run_wave(c, sol, grids, media, recsets, ws + solve_base,
+                               c->ws_size - solve_base, s)))
+                return rc;
+        }
+        // 2./3. Gauss-Newton from theta*, then H_1 and g at theta^
+        std::vector<double> hbuf((size_t)ns * (kNT * kNT + kNT));
+        for (int it = 0; it <= iters; ++it) {
+            std::vector<SolveSpec> sol;
+            std::vector<SampleDesc> sds(ns);
+            for (int q = 0; q < ns; ++q) {
+                const int i = s0 + q;
+                for (int j = 0; j < kNT; ++j)
+                    if (!std::isfinite(th_cur[(size_t)i * kNT + j]))
+                        return set_error(EIG_ENONFINITE, "Gauss-Newton diverged");
+                if (!source_inside(th_cur[(size_t)i * kNT], th_cur[(size_t)i * kNT + 1], grid[i]))
+                    return set_error(EIG_EINVAL,
+                                     "Gauss-Newton iterate left the grid's source region");
+                SolveSpec sp = base_spec(i, &th_cur[(size_t)i * kNT]);
+                sp.traces = tp(off[q].nominal);
+                sol.push_back(sp);
+                SampleDesc& sd = sds[q];
+                std::memset(&sd, 0, sizeof(sd));
+                sd.nt = grid[i].nsteps + 1;
+                sd.nrec = rec[i].n;
+                sd.nominal = tp(off[q].nominal);
+                sd.ystar = tp(off[q].ystar);
+                sd.noise = (const float2*)noise[i];
+                sd.grad = (double*)(ws + off[q].grad);
+                for (int j = 0; j < kNT; ++j) {
+                    SolveSpec pj = sp;
+                    pj.param = j;
+                    pj.deriv = 1;
+                    pj.traces = tp(off[q].sens[j]);
+                    sd.dev[2 * j] = pj.traces;
+                    sd.inv2d[j] = 1.0;
+                    sol.push_back(pj);
+                }
+            }
+            if ((rc = run_wave(c, sol, grids, media, recsets, ws + solve_base,
+                               c->ws_size - solve_base, s)))
+                return rc;
+            std::vector<char> blob(ns * sizeof(SampleDesc));
+            std::memcpy(blob.data(), sds.data(), blob.size());
+            if ((rc = upload(c, ws + o_sd, blob, s))) return rc;
+            // H1 of every sample into its own slot: one launch per sample keeps
+            // the output contiguous per sample
+            for (int q = 0; q < ns; ++q)
+                launch_hessian((const SampleDesc*)(ws + o_sd) + q, 1, 0, 1,
+                               (const double*)(ws + o_sig) + q, (double*)(ws + off[q].H1), s);
+            HIP_TRY(hipGetLastError());
+            if (it == iters) break;
+            for (int q = 0; q < ns; ++q) {
+                HIP_TRY(hipMemcpyAsync(&hbuf[(size_t)q * (kNT * kNT + kNT)], ws + off[q].H1,
+                                       kNT * kNT * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipMemcpyAsync(&hbuf[(size_t)q * (kNT * kNT + kNT) + kNT * kNT],
+                                       ws + off[q].grad, kNT * sizeof(double),
+                                       hipMemcpyDeviceToHost, s));
+            }
+            HIP_TRY(hipStreamSynchronize(s));
+            for (int q = 0; q < ns; ++q) {
+                const double* Hq = &hbuf[(size_t)q * (kNT * kNT + kNT)];
+                double* th = &th_cur[(size_t)(s0 + q) * kNT];
+                double step[kNT];
+                if (!gn_step(Hq, Hq + kNT * kNT, *prior, th, step))
+                    return set_error(EIG_ENOTPD, "Gauss-Newton system not positive definite");
+                for (int j = 0; j < kNT; ++j) th[j] += step[j];
+            }
+        }
+        // 4. dual solves driven by the weighted residuals at the receivers
+        {
+            std::vector<SolveSpec> sol;
+            std::vector<H2Job> jobs(ns);
+            for (int q = 0; q < ns; ++q) {
+                const int i = s0 + q;
+                const eig_grid& g = grid[i];
+                launch_dual_force(tp(off[q].ystar), (const float2*)noise[i], tp(off[q].nominal),
+                                  sigma, 2.0 / (g.h * g.h), g.nsteps, rec[i].n, tp(off[q].rf), s);
+                double th0[kNT];
+                std::memcpy(th0, &th_cur[(size_t)i * kNT], sizeof(th0));
+                SolveSpec sp = base_spec(i, th0);
+                sp.theta[4] = sp.theta[5] = sp.theta[6] = 0.0;  // no window forcing
+                sp.traces = tp(off[q].dtr);
+                sp.rforce = tp(off[q].rf);
+                sp.wrec = tp(off[q].wrec);
+                sol.push_back(sp);
+                H2Job& J = jobs[q];
+                std::memcpy(J.theta, th0, sizeof(J.theta));
+                J.h = g.h;
+                J.dt = g.dt;
+                J.nsteps = g.nsteps;
+                J.stf = stf_kind;
+                J.kx = floor_cell(th0[0], g.h);
+                J.kz = floor_cell(th0[1], g.h);
+                J.i0 = J.kx - 2;
+                J.k0 = J.kz - 2;
+                J.wrec = tp(off[q].wrec);
+                J.H2 = (double*)(ws + off[q].H2);
+            }
+            HIP_TRY(hipGetLastError());
+            if ((rc = run_wave(c, sol, grids, media, recsets, ws + solve_base,
+                               c->ws_size - solve_base, s)))
+                return rc;
+            std::vector<char> blob(ns * sizeof(H2Job));
+            std::memcpy(blob.data(), jobs.data(), blob.size());
+            if ((rc = upload(c, ws + o_h2, blob, s))) return rc;
+            launch_h2((const H2Job*)(ws + o_h2), ns, s);
+        }
+        // 5. outputs of the chunk
+        for (int q = 0; q < ns; ++q) {
+            HIP_TRY(hipMemcpyAsync(H1out + (size_t)(s0 + q) * kNT * kNT, ws + off[q].H1,
+                                   kNT * kNT * sizeof(double), hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(H2out + (size_t)(s0 + q) * kNT * kNT, ws + off[q].H2,
+                                   kNT * kNT * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        HIP_TRY(hipStreamSynchronize(s));  // the next chunk reuses the workspace
+        s0 = s1;
+    }
+    std::memcpy(theta_hat, th_cur.data(), th_cur.size() * sizeof(double));
+    // 6. Theorem 3 integrand and the weighted average
+    Carve cv;
+    const size_t o_pr = cv.take(sizeof(eig_prior));
+    const size_t o_th = cv.take((size_t)nsample * kNT * sizeof(double));
+    const size_t o_w = cv.take((size_t)nsample * sizeof(double));
+    if ((rc = ensure_ws(c, cv.off))) return rc;
+    if ((rc = upload_small(c, o_pr, prior, sizeof(eig_prior), s))) return rc;
+    if ((rc = upload_small(c, o_th, th_cur.data(), th_cur.size() * sizeof(double), s))) return rc;
+    if ((rc = upload_small(c, o_w, w, (size_t)nsample * sizeof(double), s))) return rc;
+    launch_theorem3(H1out, H2out, nsample, (const eig_prior*)(c->ws + o_pr),
+                    (const double*)(c->ws + o_th), (const double*)(c->ws + o_w), val, status,
+                    eig, s);
+    HIP_TRY(hipGetLastError());
     return EIG_OK;
 }
 

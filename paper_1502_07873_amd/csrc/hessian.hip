@@ -68,8 +68,10 @@ hessian_kernel(const SampleDesc* __restrict__ samples, int per_receiver,
     const int s = blockIdx.x, g = blockIdx.y;
     const SampleDesc& sd = samples[s];
     const int nt = sd.nt, nrec = sd.nrec;
-    double acc[kTri];
-    for (int t = 0; t < kTri; ++t) acc[t] = 0.0;
+    double acc[kTri + kNT];
+    for (int t = 0; t < kTri + kNT; ++t) acc[t] = 0.0;
+    const bool want_grad = sd.grad != nullptr && !per_receiver;
+    const double sgm = sigma[s];
     double inv2d[kNT];
     for (int j = 0; j < kNT; ++j) inv2d[j] = sd.inv2d[j];
     const int count = per_receiver ? nt : nt * nrec;
@@ -97,14 +99,26 @@ hessian_kernel(const SampleDesc* __restrict__ samples, int per_receiver,
         int t = 0;
         for (int a = 0; a < kNT; ++a)
             for (int b = a; b < kNT; ++b, ++t) acc[t] += Jx[a] * Jx[b] + Jz[a] * Jz[b];
+        if (want_grad) {
+            const float2 ys = sd.ystar[e], nm = sd.nominal[e], ns = sd.noise[e];
+            const double rx = ((double)ys.x - (double)nm.x) + sgm * (double)ns.x;
+            const double rz = ((double)ys.y - (double)nm.y) + sgm * (double)ns.y;
+            for (int j = 0; j < kNT; ++j) acc[kTri + j] += Jx[j] * rx + Jz[j] * rz;
+        }
     }
-    __shared__ double part[kWavesPerBlock][kTri];
+    __shared__ double part[kWavesPerBlock][kTri + kNT];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int t = 0; t < kTri; ++t) {
+    for (int t = 0; t < kTri + (want_grad ? kNT : 0); ++t) {
         const double v = wave_sum(acc[t]);
         if (lane == 0) part[wave][t] = v;
     }
     __syncthreads();
+    if (want_grad && threadIdx.x >= 64 && threadIdx.x < 64 + kNT) {
+        const int j = threadIdx.x - 64;
+        double v = 0.0;
+        for (int w = 0; w < kWavesPerBlock; ++w) v += part[w][kTri + j];
+        sd.grad[j] = -v / (sgm * sgm);
+    }
     if (threadIdx.x < kTri) {
         const int t = threadIdx.x;
         double v = 0.0;

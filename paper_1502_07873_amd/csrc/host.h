@@ -165,6 +165,8 @@ struct SolveSpec {
     int deriv;     // 1: forcing dF/dtheta_param (sensitivity solve)
     int stf;
     float2* traces;  // destination (device)
+    const float2* rforce = nullptr;  // dual solve: receiver injection [nsteps][nrec]
+    float2* wrec = nullptr;          // dual solve: window record [nsteps][49]
 };
 
 struct MediumKey {

@@ -57,6 +57,11 @@ struct SolveDesc {
     int32_t src_i0, src_k0;  // window corner (column, row)
     int32_t medium_kind;     // EIG_MEDIUM_*
     float h2;                // h^2 (nodal media scale the body force by s h^2)
+    // dual (adjoint) solves only, one-step kernels: force density added at the
+    // surface receivers at step m, [nsteps][nrec] (NULL otherwise), and the
+    // new level recorded on the forcing window, [nsteps][kSrcW * kSrcW]
+    const float2* rforce;
+    float2* wrec;
 };
 
 // One forcing table to build (FP64 arithmetic, FP32 result).
@@ -83,6 +88,22 @@ struct SampleDesc {
     double inv2d[kNT];           // 1 / (2 d_j)
     double* J;                   // optional output [nt][nrec][2][7]
     int32_t nt, nrec;
+    // optional misfit gradient (Gauss-Newton): data y = ystar + sigma noise,
+    // grad_j = -sum J_j (y - nominal) / sigma^2 written to grad[7]
+    const float2* ystar;
+    const float2* noise;
+    double* grad;
+};
+
+// One H_2 contraction (Theorem 2, through the dual solve of Section 3.3.2):
+// H_2 = - sum_n sum_window W psi^{N-n} d^2 F^n / dtheta dtheta.
+struct H2Job {
+    double theta[kNT];           // theta^ (the MAP point)
+    double h, dt;
+    int32_t nsteps, stf;
+    int32_t kx, kz, i0, k0;      // source cell and window corner
+    const float2* wrec;          // dual field on the window, level q at [q-1][49]
+    double* H2;                  // [7][7] output
 };
 
 // launchers (all asynchronous on `s`)
@@ -134,5 +155,15 @@ void launch_greedy_step(const double* H1r, int nsample, int ncand,
                         double* curve, hipStream_t s);
 void launch_surface_peak(const float2* traces, int count, double rel,
                          double* out, hipStream_t s);
+void launch_h2(const H2Job* jobs, int njobs, hipStream_t s);
+// rforce[s][r] = w_inv * ((ystar - ghat) + sigma noise)[N - s][r] / sigma^2,
+// s = 0..N-1, for one dual solve (traces [N+1][nrec]).
+void launch_dual_force(const float2* ystar, const float2* noise, const float2* ghat,
+                       double sigma, double w_inv, int nsteps, int nrec, float2* rforce,
+                       hipStream_t s);
+// Theorem 3 integrand per sample and the weighted average.
+void launch_theorem3(const double* H1, const double* H2, int nsample,
+                     const eig_prior* prior_dev, const double* theta_hat, const double* w,
+                     double* val, int32_t* status, double* eig, hipStream_t s);
 
 }  // namespace eig

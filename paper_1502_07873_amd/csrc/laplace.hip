@@ -103,6 +103,91 @@ __device__ bool dkl_of(const double* H, const eig_prior& pr, const double* th,
     return true;
 }
 
+// Cholesky of an n x n SPD matrix (row stride n); false if not SPD.
+__device__ bool chol_n(const double* A, int n, double L[kNT][kNT]) {
+    for (int j = 0; j < n; ++j) {
+        double v = A[j * n + j];
+        for (int k = 0; k < j; ++k) v -= L[j][k] * L[j][k];
+        if (!(v > 0.0) || !isfinite(v)) return false;
+        L[j][j] = sqrt(v);
+        for (int i = j + 1; i < n; ++i) {
+            double w = A[i * n + j];
+            for (int k = 0; k < j; ++k) w -= L[i][k] * L[j][k];
+            L[i][j] = w / L[j][j];
+        }
+    }
+    return true;
+}
+
+// x = A^-1 b from the Cholesky factor of A.
+__device__ void chol_solve(const double L[kNT][kNT], int n, const double* b, double* x) {
+    double y[kNT];
+    for (int i = 0; i < n; ++i) {
+        double v = b[i];
+        for (int k = 0; k < i; ++k) v -= L[i][k] * y[k];
+        y[i] = v / L[i][i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int k = i + 1; k < n; ++k) v -= L[k][i] * x[k];
+        x[i] = v / L[i][i];
+    }
+}
+
+// Theorem 3 at theta^: H = H_1 + H_2 - grad grad h on the active parameters,
+//   -1/2 log((2 pi)^N |H^-1|) - N/2 - h(theta^) - 1/2 tr(H^-1 grad grad h),
+// grad grad h = 0 for the uniform prior and -Gamma^-1 for the Gaussian one.
+__global__ void theorem3_kernel(const double* __restrict__ H1, const double* __restrict__ H2,
+                                int nsample, const eig_prior* __restrict__ prior,
+                                const double* __restrict__ theta, double* __restrict__ val,
+                                int32_t* __restrict__ status) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsample) return;
+    const eig_prior& pr = *prior;
+    int idx[kNT];
+    const int n = active_set(pr, idx);
+    double H[kNT * kNT];
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            const size_t o = (size_t)s * kNT * kNT + idx[a] * kNT + idx[b];
+            H[a * n + b] = H1[o] + H2[o];
+        }
+    double Gi[kNT * kNT];   // Gamma^-1 on the active parameters (Gaussian prior)
+    bool ok = true;
+    const bool gauss = pr.kind == EIG_PRIOR_GAUSSIAN;
+    if (gauss) {
+        double C[kNT * kNT], L[kNT][kNT];
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) C[a * n + b] = pr.cov[idx[a] * kNT + idx[b]];
+        ok = chol_n(C, n, L);
+        for (int c = 0; c < n && ok; ++c) {
+            double e[kNT] = {0, 0, 0, 0, 0, 0, 0}, x[kNT];
+            e[c] = 1.0;
+            chol_solve(L, n, e, x);
+            for (int a = 0; a < n; ++a) Gi[a * n + c] = x[a];
+        }
+        for (int a = 0; a < n * n && ok; ++a) H[a] += Gi[a];
+    }
+    double ld = 0.0;
+    ok = ok && scaled_logdet(H, n, &ld);
+    double tr = 0.0;   // tr(H^-1 Gamma^-1) = -tr(H^-1 grad grad h)
+    if (ok && gauss) {
+        double L[kNT][kNT];
+        ok = chol_n(H, n, L);
+        for (int c = 0; c < n && ok; ++c) {
+            double col[kNT], x[kNT];
+            for (int a = 0; a < n; ++a) col[a] = Gi[a * n + c];
+            chol_solve(L, n, col, x);
+            tr += x[c];
+        }
+    }
+    const double th_nan = __longlong_as_double(0x7ff8000000000000ULL);
+    val[s] = ok ? -0.5 * (n * log(2.0 * M_PI) - ld) - 0.5 * n -
+                      log_prior(pr, theta + (size_t)s * kNT, idx, n) + 0.5 * tr
+                : th_nan;
+    if (status) status[s] = ok ? EIG_OK : EIG_ENOTPD;
+}
+
 __global__ void laplace_kernel(const double* __restrict__ H1, int nsample,
                                const eig_prior* __restrict__ prior,
                                const double* __restrict__ theta,
@@ -236,6 +321,15 @@ void launch_laplace(const double* H1, int nsample, const eig_prior* prior_dev,
     laplace_kernel<<<(nsample + 127) / 128, 128, 0, s>>>(H1, nsample, prior_dev, theta,
                                                          dkl, logdet, status);
     weighted_rows_kernel<<<1, 256, 0, s>>>(dkl, nsample, w, eig, nullptr);
+}
+
+void launch_theorem3(const double* H1, const double* H2, int nsample,
+                     const eig_prior* prior_dev, const double* theta_hat, const double* w,
+                     double* val, int32_t* status, double* eig, hipStream_t s) {
+    if (nsample <= 0) return;
+    theorem3_kernel<<<(nsample + 127) / 128, 128, 0, s>>>(H1, H2, nsample, prior_dev,
+                                                          theta_hat, val, status);
+    if (eig) weighted_rows_kernel<<<1, 256, 0, s>>>(val, nsample, w, eig, nullptr);
 }
 
 void launch_design_eval(const double* H1r, int nsample, int ncand,

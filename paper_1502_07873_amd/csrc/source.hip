@@ -95,6 +95,59 @@ __device__ double dsource_weight(const double* th, int kx, int kz, double h, int
     return c == 0 ? th[4] * gx + th[5] * gz : th[5] * gx + th[6] * gz;
 }
 
+// d^2/dalpha^2 of the delta weights (times h).
+__device__ double delta_w_da2(double a, int o) {
+    const double a2 = a * a, a3 = a2 * a;
+    const double Pdd = a3 * (100.0 / 3.0 + a * (-35.0 / 4.0 + a * (-119.0 / 2.0 + a * (63.0 - 18.0 * a))));
+    switch (o) {
+        case -2: return -1.0 / 12.0 - a / 2.0 - 19.0 * a2 / 2.0 + Pdd;
+        case -1: return 4.0 / 3.0 + a + 48.0 * a2 - 5.0 * Pdd;
+        case 0: return -5.0 / 2.0 - 97.0 * a2 + 10.0 * Pdd;
+        case 1: return 4.0 / 3.0 - a + 98.0 * a2 - 10.0 * Pdd;
+        case 2: return -1.0 / 12.0 + a / 2.0 - 99.0 * a2 / 2.0 + 5.0 * Pdd;
+        case 3: return 10.0 * a2 - Pdd;
+        default: return 0.0;
+    }
+}
+
+// d^2/dalpha^2 of the delta' weights (times h^2).
+__device__ double ddelta_w_da2(double a, int o) {
+    const double a2 = a * a;
+    const double Rdd = a2 * (-25.0 + a * (-15.0 + a * (295.0 / 2.0 + a * (-168.0 + 56.0 * a))));
+    switch (o) {
+        case -2: return 1.0 / 2.0 + 4.0 * a + Rdd;
+        case -1: return -1.0 - 21.0 * a - 5.0 * Rdd;
+        case 0: return 44.0 * a + 10.0 * Rdd;
+        case 1: return 1.0 - 46.0 * a - 10.0 * Rdd;
+        case 2: return -1.0 / 2.0 + 24.0 * a + 5.0 * Rdd;
+        case 3: return -5.0 * a - Rdd;
+        default: return 0.0;
+    }
+}
+
+// delta (dp = false) or delta' (dp = true) weight of node offset o along one
+// axis, differentiated der times (0..2) in the source coordinate.
+__device__ double axis_weight(double a, int o, bool dp, int der, double h) {
+    double v;
+    if (!dp) v = der == 0 ? delta_w(a, o) : der == 1 ? delta_w_da(a, o) : delta_w_da2(a, o);
+    else v = der == 0 ? ddelta_w(a, o) : der == 1 ? ddelta_w_da(a, o) : ddelta_w_da2(a, o);
+    double sc = dp ? h * h : h;
+    for (int q = 0; q < der; ++q) sc *= h;
+    return v / sc;
+}
+
+// Window weight (component c) of M grad(delta), differentiated ox times in
+// x_s and oz times in z_s, for the moments m = (mxx, mxz, mzz).
+__device__ double window_weight(const double* th, const double* m, int kx, int kz, double h,
+                                int ic, int kr, int c, int ox, int oz) {
+    const int o1 = ic - kx, o2 = kr - kz;
+    if (o1 < -2 || o1 > 3 || o2 < -2 || o2 > 3) return 0.0;
+    const double ax = th[0] / h - kx, az = th[1] / h - kz;
+    const double gx = axis_weight(ax, o1, true, ox, h) * axis_weight(az, o2, false, oz, h);
+    const double gz = axis_weight(ax, o1, false, ox, h) * axis_weight(az, o2, true, oz, h);
+    return c == 0 ? m[0] * gx + m[1] * gz : m[1] * gx + m[2] * gz;
+}
+
 // Force density on node (ic, kr), component c, of the source theta whose
 // cell is (kx, kz): M grad(delta) with grad(delta) = (delta'(x) delta(z),
 // delta(x) delta'(z)).
@@ -132,6 +185,24 @@ __device__ double dwavelet(int kind, double t, double t0, double p, int wrt) {
     const double e = exp(-0.5 * w * w * tau * tau);
     if (wrt == 0) return c * w * e * (w * w - w * w * w * w * tau * tau);
     return 2.0 * M_PI * c * e * (-3.0 * w * w * tau + w * w * w * w * tau * tau * tau);
+}
+
+// Second derivatives of the wavelet: wrt 0 = t0 t0, 1 = t0 p, 2 = p p.
+__device__ double d2wavelet(int kind, double t, double t0, double p, int wrt) {
+    const double tau = t - t0;
+    const double c = 1.0 / sqrt(2.0 * M_PI);
+    if (kind == EIG_STF_GAUSS) {
+        const double w = p, wt2 = w * w * tau * tau;
+        const double e = exp(-0.5 * wt2);
+        if (wrt == 0) return c * w * w * w * e * (wt2 - 1.0);
+        if (wrt == 1) return c * w * w * tau * e * (3.0 - wt2);
+        return c * w * tau * tau * e * (wt2 - 3.0);
+    }
+    const double w = 2.0 * M_PI * p, wt2 = w * w * tau * tau;
+    const double e = exp(-0.5 * wt2);
+    if (wrt == 0) return c * w * w * w * w * w * tau * e * (3.0 - wt2);
+    if (wrt == 1) return 2.0 * M_PI * c * w * w * e * (wt2 * wt2 - 6.0 * wt2 + 3.0);
+    return 4.0 * M_PI * M_PI * c * w * tau * e * (-wt2 * wt2 + 7.0 * wt2 - 6.0);
 }
 
 __global__ void source_kernel(const SourceJob* __restrict__ jobs) {
@@ -255,6 +326,96 @@ __global__ void nodal_coef_kernel(const double* __restrict__ rho,
     }
 }
 
+// H_2 of one sample from the dual field on the forcing window.  Threads
+// 0..97 own a (component, node) of the window and accumulate, over the
+// levels, the six time-series projections Psi_b = sum_n b(t_n) psi^{N-n}
+// (b = S, dS/dt0, dS/dp and the three second derivatives); then one thread
+// per (j, k) sums W_i a_jk(i) Psi_{b(jk)} over the window (fixed order).
+__global__ void __launch_bounds__(128) h2_kernel(const H2Job* __restrict__ jobs) {
+    const H2Job& J = jobs[blockIdx.x];
+    constexpr int kWin = kSrcW * kSrcW;
+    __shared__ double psi[2 * kWin][6];
+    const int e = threadIdx.x;
+    const int N = J.nsteps;
+    if (e < 2 * kWin) {
+        const int comp = e / kWin, node = e % kWin;
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int n = 0; n < N; ++n) {
+            const float2 pv = J.wrec[(size_t)(N - 1 - n) * kWin + node];  // psi^{N-n}
+            const double p = comp == 0 ? pv.x : pv.y;
+            const double t = n * J.dt;
+            acc[0] += p * wavelet(J.stf, t, J.theta[2], J.theta[3]);
+            acc[1] += p * dwavelet(J.stf, t, J.theta[2], J.theta[3], 0);
+            acc[2] += p * dwavelet(J.stf, t, J.theta[2], J.theta[3], 1);
+            acc[3] += p * d2wavelet(J.stf, t, J.theta[2], J.theta[3], 0);
+            acc[4] += p * d2wavelet(J.stf, t, J.theta[2], J.theta[3], 1);
+            acc[5] += p * d2wavelet(J.stf, t, J.theta[2], J.theta[3], 2);
+        }
+        for (int b = 0; b < 6; ++b) psi[e][b] = acc[b];
+    }
+    __syncthreads();
+    if (threadIdx.x < kNT * kNT) {
+        const int j = threadIdx.x / kNT, k = threadIdx.x % kNT;
+        if (j > k) return;
+        // spatial orders, moments and time series of d^2 F / dtheta_j dtheta_k
+        int ox = 0, oz = 0, b = -1;
+        double m[3] = {J.theta[4], J.theta[5], J.theta[6]};
+        const int a0 = j, a1 = k;
+        auto spatial = [](int q) { return q == 0 || q == 1; };
+        auto temporal = [](int q) { return q == 2 || q == 3; };
+        auto moment = [](int q) { return q >= 4; };
+        if (moment(a0) && moment(a1)) {
+            b = -1;
+        } else {
+            int tcount = 0, tfirst = -1;
+            for (int qi = 0; qi < 2; ++qi) {
+                const int q = qi == 0 ? a0 : a1;
+                if (spatial(q)) (q == 0 ? ox : oz) += 1;
+                if (temporal(q)) {
+                    if (tcount == 0) tfirst = q;
+                    ++tcount;
+                }
+                if (moment(q)) {
+                    m[0] = m[1] = m[2] = 0.0;
+                    m[q - 4] = 1.0;
+                }
+            }
+            if (tcount == 0) b = 0;
+            else if (tcount == 1) b = tfirst == 2 ? 1 : 2;
+            else b = (a0 == 2 && a1 == 2) ? 3 : (a0 == 3 && a1 == 3) ? 5 : 4;
+        }
+        double v = 0.0;
+        if (b >= 0) {
+            for (int q = 0; q < 2 * kWin; ++q) {
+                const int comp = q / kWin, node = q % kWin;
+                const int ic = J.i0 + node % kSrcW, kr = J.k0 + node / kSrcW;
+                const double Wq = J.h * J.h * (kr == 0 ? 0.5 : 1.0);
+                v += Wq * window_weight(J.theta, m, J.kx, J.kz, J.h, ic, kr, comp, ox, oz) *
+                     psi[q][b];
+            }
+            v = -v;
+        }
+        J.H2[j * kNT + k] = v;
+        J.H2[k * kNT + j] = v;
+    }
+}
+
+__global__ void dual_force_kernel(const float2* __restrict__ ystar,
+                                  const float2* __restrict__ noise,
+                                  const float2* __restrict__ ghat, double sigma, double w_inv,
+                                  int nsteps, int nrec, float2* __restrict__ rforce) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)nsteps * nrec) return;
+    const int s = (int)(e / nrec), r = (int)(e % nrec);
+    const size_t src = (size_t)(nsteps - s) * nrec + r;   // level N - s
+    const float2 y = ystar[src], g = ghat[src], z = noise[src];
+    const double sc = w_inv / (sigma * sigma);
+    float2 o;
+    o.x = (float)((((double)y.x - (double)g.x) + sigma * (double)z.x) * sc);
+    o.y = (float)((((double)y.y - (double)g.y) + sigma * (double)z.y) * sc);
+    rforce[e] = o;
+}
+
 }  // namespace
 
 void launch_source_tables(const SourceJob* jobs, int njobs, int /*max_nsteps*/,
@@ -276,6 +437,19 @@ void launch_nodal_coef(const double* rho, const double* lam, const double* mu,
     if (blocks > 4096) blocks = 4096;
     nodal_coef_kernel<<<(unsigned)blocks, 256, 0, s>>>(rho, lam, mu, nx, nz, pitch, h,
                                                         dt, coef);
+}
+
+void launch_h2(const H2Job* jobs, int njobs, hipStream_t s) {
+    if (njobs > 0) h2_kernel<<<njobs, 128, 0, s>>>(jobs);
+}
+
+void launch_dual_force(const float2* ystar, const float2* noise, const float2* ghat,
+                       double sigma, double w_inv, int nsteps, int nrec, float2* rforce,
+                       hipStream_t s) {
+    const size_t n = (size_t)nsteps * nrec;
+    if (n == 0) return;
+    dual_force_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ystar, noise, ghat, sigma,
+                                                                  w_inv, nsteps, nrec, rforce);
 }
 
 }  // namespace eig

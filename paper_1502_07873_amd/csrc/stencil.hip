@@ -207,6 +207,8 @@ stencil_layered_w1(const SolveDesc* __restrict__ descs, const int2* __restrict__
     const int nrec = d->nrec;
     int rec = -1;
     if (kb == 0) rec = ldi(d->recmap, i);
+    const float2* rfz = d->rforce;
+    float2* wrec = d->wrec;
 
     NodeRow rm, rc, rn;
     if (kb == 0) {
@@ -229,17 +231,25 @@ stencil_layered_w1(const SolveDesc* __restrict__ descs, const int2* __restrict__
         rn = make_row(cn, chn);
         const LayerCoef cf = load_coef(coef, k);
         const int dk = k - sk0;
-        const bool src = src_lane && dk >= 0 && dk < kSrcW;
-        float wu = 0.f, wv = 0.f;
+        const bool in_win = src_lane && dk >= 0 && dk < kSrcW;
+        bool src = in_win;
+        float wu = 0.f, wv = 0.f, fsv = cf.c[kFco] * sval;
         if (src) {
             wu = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
             wv = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
         }
-        const float2 nw = layered_update(cf, rm, rc, rn, up.x, up.y, src, cf.c[kFco] * sval,
-                                         wu, wv);
+        if (rfz && k == 0 && rec >= 0) {  // dual solve: receiver injection
+            const float2 rf = ld2(rfz, (size_t)m * nrec + rec);
+            src = true;
+            fsv = cf.c[kFco];
+            wu = rf.x;
+            wv = rf.y;
+        }
+        const float2 nw = layered_update(cf, rm, rc, rn, up.x, up.y, src, fsv, wu, wv);
         if (upd) {
             st2(P, (size_t)k * pitch + i, nw);
             if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
+            if (wrec && in_win) st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
         }
         rm = rc;
         rc = rn;
@@ -306,6 +316,8 @@ stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__
         rec0 = ldi(d->recmap, i0);
         rec1 = ldi(d->recmap, i0 + 1);
     }
+    const float2* rfz = d->rforce;
+    float2* wrec = d->wrec;
 
     NodeRow am, bm, ac, bc, an, bn;
     if (kb == 0) {
@@ -337,10 +349,11 @@ stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__
         if (k + D < ke) pn = ld4(P, (size_t)(k + D) * pitch + i0);
         make_rows2(q1, an, bn);
         const LayerCoef cf = load_coef(coef, k);
-        const float fsv = cf.c[kFco] * sval;
+        float fsa = cf.c[kFco] * sval, fsb = fsa;
         const int dk = k - sk0;
         const bool row_src = dk >= 0 && dk < kSrcW;
-        const bool sa = s0 && row_src, sb = s1 && row_src;
+        const bool wa = s0 && row_src, wb = s1 && row_src;
+        bool sa = wa, sb = wb;
         float wua = 0.f, wva = 0.f, wub = 0.f, wvb = 0.f;
         if (sa) {
             wua = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di0);
@@ -350,8 +363,29 @@ stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__
             wub = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di1);
             wvb = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di1);
         }
-        const float2 na = layered_update(cf, am, ac, an, p0.x, p0.y, sa, fsv, wua, wva);
-        const float2 nb = layered_update(cf, bm, bc, bn, p0.z, p0.w, sb, fsv, wub, wvb);
+        if (rfz && k == 0) {  // dual solve: receiver injection
+            if (rec0 >= 0) {
+                const float2 rf = ld2(rfz, (size_t)m * nrec + rec0);
+                sa = true;
+                fsa = cf.c[kFco];
+                wua = rf.x;
+                wva = rf.y;
+            }
+            if (rec1 >= 0) {
+                const float2 rf = ld2(rfz, (size_t)m * nrec + rec1);
+                sb = true;
+                fsb = cf.c[kFco];
+                wub = rf.x;
+                wvb = rf.y;
+            }
+        }
+        const float2 na = layered_update(cf, am, ac, an, p0.x, p0.y, sa, fsa, wua, wva);
+        const float2 nb = layered_update(cf, bm, bc, bn, p0.z, p0.w, sb, fsb, wub, wvb);
+        if (wrec) {
+            const size_t wb0 = (size_t)m * (kSrcW * kSrcW) + dk * kSrcW;
+            if (wa && upd0) st2(wrec, wb0 + di0, na);
+            if (wb && upd1) st2(wrec, wb0 + di1, nb);
+        }
         // edge and padding columns are never written (absorbing edges are
         // updated by their own kernel, rigid ones stay zero)
         if (upd0 && upd1) {
@@ -669,6 +703,8 @@ stencil_nodal(const SolveDesc* __restrict__ descs, const int2* __restrict__ tile
     const float h2 = d->h2;
     int rec = -1;
     if (kb == 0) rec = ldi(d->recmap, i);
+    const float2* rfz = d->rforce;
+    float2* wrec = d->wrec;
 
     auto load = [=](int k) {
         RowN r;
@@ -748,7 +784,12 @@ stencil_nodal(const SolveDesc* __restrict__ descs, const int2* __restrict__ tile
         au *= sc;
         av *= sc;
         const int dk = k - sk0;
-        if (src_lane && dk >= 0 && dk < kSrcW) {
+        const bool in_win = src_lane && dk >= 0 && dk < kSrcW;
+        if (rfz && k == 0 && rec >= 0) {  // dual solve: receiver injection
+            const float2 rf = ld2(rfz, (size_t)m * nrec + rec);
+            au += sc * h2 * rf.x;
+            av += sc * h2 * rf.y;
+        } else if (in_win) {
             // dt^2/rho f = s h^2 f
             const float f = sc * h2 * sval;
             au += f * ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
@@ -760,6 +801,7 @@ stencil_nodal(const SolveDesc* __restrict__ descs, const int2* __restrict__ tile
         if (upd) {
             st2(P, (size_t)k * pitch + i, nw);
             if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
+            if (wrec && in_win) st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
         }
         rm = rc;
         rc = rn;

@@ -87,6 +87,8 @@ def _load():
         "jacobian_sensitivity": ([vp, i32, vp, vp, vp, i32, vp, i32, vp, i32, vp, vp, vp,
                                   vp, vp], ctypes.c_int),
         "nested_mc_eig": ([vp, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "theorem3_eig": ([vp, i32, vp, vp, vp, i32, vp, vp, dbl, vp, vp, i32, vp, vp, vp, vp,
+                          vp, vp, vp], ctypes.c_int),
         "laplace_eig": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "design_eval": ([vp, i32, i32, vp, i32, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "design_greedy": ([vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
@@ -110,7 +112,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("eig_ctx_create", "eig_ctx_destroy", "eig_last_error", "eig_ctx_workspace_bytes",
             "eig_ctx_stencil_stats", "eig_ctx_set_option", "eig_ctx_get_option",
-            "forward_solve_batch", "jacobian_fd", "jacobian_sensitivity", "nested_mc_eig", "laplace_eig",
+            "forward_solve_batch", "jacobian_fd", "jacobian_sensitivity", "nested_mc_eig",
+            "theorem3_eig", "laplace_eig",
             "design_eval", "design_greedy", "noise_sigma_peak", "sparse_grid_gl", "eig_server_create",
             "eig_server_destroy", "eig_server_submit", "eig_server_step", "eig_server_poll",
             "eig_server_pending")
@@ -315,6 +318,24 @@ class Context:
             raise ValueError("nested_mc_eig shape mismatch")
         _check(_lib.nested_mc_eig(self._h, n, m, k, _ptr(g_outer), _ptr(noise), _ptr(g_inner),
                                   float(sigma), _ptr(logratio), _ptr(eig), _stream(stream)))
+
+    def theorem3_eig(self, grids, media, theta_star, receivers, noise, sigma, prior: Prior, w,
+                     H1, H2, val, eig=None, status=None, iters=5, stf="gauss_deriv",
+                     stream=None):
+        """Returns theta_hat [n][7] (numpy); H1/H2/val/eig/status are device
+        tensors filled asynchronously."""
+        n = len(grids)
+        th = np.ascontiguousarray(theta_star, dtype=np.float64).reshape(n, NTHETA)
+        wa = np.ascontiguousarray(np.broadcast_to(np.asarray(w, dtype=np.float64), (n,)))
+        out = np.zeros((n, NTHETA))
+        recs, keep = self._receivers(receivers)
+        _check(_lib.theorem3_eig(self._h, n, self._grids(grids), self._media(media), _np_ptr(th),
+                                 STF_KINDS[stf], recs, _ptr_array(noise), float(sigma),
+                                 ctypes.byref(prior), _np_ptr(wa), int(iters), _np_ptr(out),
+                                 _ptr(H1), _ptr(H2), _ptr(val), _ptr(eig), _ptr(status),
+                                 _stream(stream)))
+        del keep
+        return out
 
     def laplace_eig(self, H1, prior: Prior, w, dkl, eig, theta=None, logdet=None,
                     status=None, stream=None):
