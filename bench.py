@@ -406,6 +406,97 @@ def _bench_nested(ctx, sizes=(1000, 10000, 100000, 400000), nlaplace=10000, sg_l
     return out
 
 
+def _bench_estimators(ctx, sig_rels=(0.3, 0.6, 1.0), n_outer=4000, n_inner=200000,
+                      n_lap=2000, iters=5):
+    """Theorem 4 (O(1/N)), Theorem 3 (O(1/N^2)) and the nested double loop
+    with independent inner samples, on one low-information problem: the
+    64x64x400 homogeneous grid with rigid edges, two receivers, depth,
+    frequency and m_xx inferred under a Gaussian prior (width 1/10 of the
+    c1 box, draws clipped to the box), at several noise levels."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_1502_07873_amd import make_prior
+    from paper_1502_07873_amd.query import device_medium, grid_tuple
+    wl = synthetic.config("c1")[0]
+    grid, med = wl.grid, wl.medium
+    g = grid_tuple(grid)
+    dm = device_medium(med.kind, med.rho, med.lam, med.mu)
+    rec = np.array([16, 48], dtype=np.int32)
+    act = [1, 3, 4]
+    tpl = 0.5 * (wl.lo + wl.hi)
+    std = (wl.hi - wl.lo) / 10
+    cov = np.diag(std ** 2)
+    prior = make_prior(mean=tpl, cov=cov, active=act)
+    rng = np.random.default_rng(12)
+
+    def draws(n):
+        th = np.repeat(tpl[None, :], n, axis=0)
+        for j in act:
+            th[:, j] = np.clip(tpl[j] + std[j] * rng.standard_normal(n), wl.lo[j], wl.hi[j])
+        return th
+
+    K = (grid.nsteps + 1) * len(rec) * 2
+
+    def forward(th):
+        out = torch.empty((len(th), K), dtype=torch.float32, device="cuda")
+        ctx.forward_solve_batch([g] * len(th), [dm] * len(th), th, [rec] * len(th), list(out))
+        return out
+
+    peak = float(forward(tpl[None, :]).abs().max())
+    th_out, th_in, th_lap = draws(n_outer), draws(n_inner), draws(n_lap)
+    noise = torch.randn((n_outer, K), generator=torch.Generator(device="cuda").manual_seed(3),
+                        device="cuda", dtype=torch.float32)
+    t0 = time.perf_counter()
+    g_out, g_in = forward(th_out), forward(th_in)
+    torch.cuda.synchronize()
+    out = {"grid": [grid.nx, grid.nz, grid.nsteps], "receivers": rec.tolist(),
+           "inferred": ["depth", "f", "m_xx"], "prior": "gaussian, std = c1 box / 10",
+           "n_outer": n_outer, "n_inner": n_inner, "n_laplace": n_lap,
+           "forward_seconds": time.perf_counter() - t0, "levels": []}
+    for rel in sig_rels:
+        sigma = rel * peak
+        row = {"sigma_rel_peak": rel}
+        # Theorem 4
+        H1 = torch.empty((n_lap, 7, 7), dtype=torch.float64, device="cuda")
+        ctx.jacobian_fd([g] * n_lap, [dm] * n_lap, th_lap, [rec] * n_lap, sigma, H1)
+        dkl = torch.empty(n_lap, dtype=torch.float64, device="cuda")
+        e4 = torch.empty(1, dtype=torch.float64, device="cuda")
+        ctx.laplace_eig(H1, prior, np.full(n_lap, 1.0 / n_lap), dkl, e4, theta=th_lap)
+        d4 = dkl.cpu().numpy()
+        row["theorem4"] = {"eig": float(e4.cpu()[0]),
+                           "ci68": float(d4.std(ddof=1) / np.sqrt(n_lap))}
+        # Theorem 3 on the first n_lap outer samples and their noise
+        n3 = n_lap
+        H1t = torch.empty((n3, 7, 7), dtype=torch.float64, device="cuda")
+        H2t = torch.empty_like(H1t)
+        v3 = torch.empty(n3, dtype=torch.float64, device="cuda")
+        e3 = torch.empty(1, dtype=torch.float64, device="cuda")
+        st = torch.empty(n3, dtype=torch.int32, device="cuda")
+        t0 = time.perf_counter()
+        ctx.theorem3_eig([g] * n3, [dm] * n3, th_out[:n3], [rec] * n3, list(noise[:n3]), sigma,
+                         prior, np.full(n3, 1.0 / n3), H1t, H2t, v3, e3, st, iters=iters)
+        torch.cuda.synchronize()
+        v3n = v3.cpu().numpy()
+        ok = st.cpu().numpy() == 0
+        row["theorem3"] = {"eig": float(e3.cpu()[0]), "eig_ok_samples": float(v3n[ok].mean()),
+                           "ci68": float(v3n[ok].std(ddof=1) / np.sqrt(ok.sum())),
+                           "not_pd": int((~ok).sum()), "seconds": time.perf_counter() - t0}
+        # nested double loop, independent inner samples
+        lr = torch.empty(n_outer, dtype=torch.float64, device="cuda")
+        en = torch.empty(1, dtype=torch.float64, device="cuda")
+        ctx.nested_mc_eig(g_out, noise, g_in, sigma, lr, en)
+        lrn = lr.cpu().numpy()
+        row["nested"] = {"eig": float(en.cpu()[0]), "ci68": float(lrn.std(ddof=1) / np.sqrt(n_outer)),
+                         "eig_same_outer_as_theorem3": float(lrn[:n3][ok].mean())}
+        out["levels"].append(row)
+        print(f"[bench] sigma={rel} peak: thm4 {row['theorem4']['eig']:.3f} "
+              f"thm3 {row['theorem3']['eig_ok_samples']:.3f} nested {row['nested']['eig']:.3f}",
+              flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,7 +508,7 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed query: no one-solve baseline, sensitivity path, "
                          "serving or CPU baseline (for counter runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "loh2d", "nested"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "loh2d", "nested", "estimators"],
                     help="c2: the headline query (default); c3/c5/loh2d: extra measurements "
                          "(loh2d: the paper's model problem and scenarios)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -447,6 +538,8 @@ def main():
             res = _bench_loh2d(ctx, args.samples if args.samples != 256 else 10000)
         elif args.workload == "nested":
             res = _bench_nested(ctx)
+        elif args.workload == "estimators":
+            res = _bench_estimators(ctx)
         else:
             res = _bench_c5(ctx)
         print(json.dumps({"workload": args.workload, **res}), flush=True)
