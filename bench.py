@@ -49,20 +49,36 @@ def _measured_traffic(samples):
     return rec["traffic_bytes_per_launch"]
 
 
-def _cpu_baseline(wl, theta_s, dkl_gpu_s):
-    """The oracle, untuned, on one prior sample (15 solves + its own sigma
-    solve) spread over the host cores."""
+def _cpu_baseline(wl, theta_s, gpu):
+    """The oracle, untuned, on one prior sample: its own sigma solve, then
+    the 15 solves spread over the host cores (each single-threaded), H_1 and
+    D^_KL.  Also the error set against the GPU's outputs for that sample
+    (gpu: nominal traces, J, H1, dkl of the same sample and sigma)."""
+    import numpy as np
     from oracle import pipeline as opipe
     threads = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
-    ref = opipe.query(wl, theta=theta_s[None, :], weights=[1.0], threads=threads)
+    ref = opipe.query(wl, theta=theta_s[None, :], weights=[1.0], threads=threads, keep_J=True)
     t = time.perf_counter() - t0
-    err = abs(float(ref["dkl"][0]) - float(dkl_gpu_s))
     cores = min(threads, 15)
+    upd = 16.0 * wl.grid.nx * wl.grid.nz * wl.grid.nsteps
+    Jr, Jg = ref["J"][0], gpu["J"]
+    Hr, Hg = ref["H1"][0], gpu["H1"]
+    d = np.sqrt(np.abs(np.diag(Hr)))
+    errors = {
+        "trace_rel_l2": float(np.linalg.norm(gpu["nominal"] - ref["nominal"][0]) /
+                              np.linalg.norm(ref["nominal"][0])),
+        "jacobian_col_rel_l2_max": float(max(np.linalg.norm(Jg[..., j] - Jr[..., j]) /
+                                             np.linalg.norm(Jr[..., j]) for j in range(7))),
+        "scaled_hessian_max_abs": float(np.max(np.abs((Hg - Hr) / np.outer(d, d)))),
+        "dkl_abs": abs(float(ref["dkl"][0]) - float(gpu["dkl"])),
+        "eig_abs": abs(float(ref["eig"]) - float(gpu["dkl"])),
+        "sigma_rel": abs(gpu["sigma"] - ref["sigma"]) / ref["sigma"],
+        "sample": "prior sample 0 of the timed query (the oracle with its own sigma)"}
     return ({"value": 1.0 / t, "unit": "sample-EIG evals/s", "cores": cores,
-             "kind": "oracle",
-             "sample": "1 prior sample of the timed workload (1 sigma solve + 15 solves "
-                       f"at 512x512x2000, FP64), {t:.1f} s wall"}, err)
+             "kind": "oracle", "updates_per_s": upd / t, "updates_per_s_per_core": upd / t / cores,
+             "sample": "1 prior sample of the timed workload (1 sigma solve, then 15 solves "
+                       f"on {cores} threads, 512x512x2000, FP64), {t:.1f} s wall"}, errors)
 
 
 def _copy_calibration(nbytes=4 << 30, reps=4):
@@ -695,9 +711,17 @@ def main():
         line["latency_ms"]["serving_p99"] = line["serving"]["latency_p99_s"] * 1e3
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, 1 sample)", flush=True)
-        cb, err = _cpu_baseline(wl, wl.theta[0], dkl[0])
+        sig = ctx.noise_sigma_peak(g, med, theta_bar, wl.noise_rel)
+        o0 = run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, wl.theta[:1], [1.0], sigma=sig,
+                       keep_nominal=True, keep_J=True)
+        torch.cuda.synchronize()
+        gpu0 = {"nominal": o0["nominal"][0].cpu().numpy().astype(np.float64),
+                "J": o0["J"][0].cpu().numpy(), "H1": o0["H1"][0].cpu().numpy(),
+                "dkl": float(o0["dkl"].cpu()[0]), "sigma": sig}
+        cb, errs = _cpu_baseline(wl, wl.theta[0], gpu0)
         line["cpu_baseline"] = cb
-        line["sampled_err_nats"] = err
+        line["errors"] = errs
+        line["sampled_err_nats"] = errs["dkl_abs"]
     print(json.dumps(line), flush=True)
     ctx.close()
 

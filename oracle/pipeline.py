@@ -19,10 +19,10 @@ def default_threads() -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
 
-def sample_terms(wl, theta, sigma, per_receiver=False, jacobian="fd"):
+def sample_terms(wl, theta, sigma, per_receiver=False, jacobian="fd", pool=None):
     if jacobian == "fd":
         nominal, J = elastic.jacobian_literal(wl.grid, wl.medium, theta, wl.receivers,
-                                              wl.rel_step, wl.stf)
+                                              wl.rel_step, wl.stf, pool=pool)
     elif jacobian == "sensitivity":
         nominal, J = elastic.jacobian_sensitivity(wl.grid, wl.medium, theta, wl.receivers,
                                                   wl.stf)
@@ -49,9 +49,15 @@ def query(wl, theta=None, weights=None, sigma: Optional[float] = None,
                                     wl.noise_rel, wl.stf)
     prior = laplace.uniform_prior(wl.lo, wl.hi)
     nthr = threads or default_threads()
-    with ThreadPoolExecutor(nthr) as pool:
-        res = list(pool.map(lambda th: sample_terms(wl, th, sigma, per_receiver, jacobian),
-                            list(theta)))
+    if len(theta) < nthr and jacobian == "fd":
+        # few samples: spread each sample's 15 solves over the threads instead
+        # (each solve stays single-threaded; the C solver releases the GIL)
+        with ThreadPoolExecutor(nthr) as pool:
+            res = [sample_terms(wl, th, sigma, per_receiver, jacobian, pool) for th in theta]
+    else:
+        with ThreadPoolExecutor(nthr) as pool:
+            res = list(pool.map(lambda th: sample_terms(wl, th, sigma, per_receiver, jacobian),
+                                list(theta)))
     H = np.stack([r[2] for r in res])
     Htot = H.sum(axis=1) if per_receiver else H
     dkl = np.array([laplace.dkl_hat(Htot[s], theta[s], prior)[0]
