@@ -163,9 +163,10 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  * EIG_EINVAL for an unknown name or value. */
 int eig_ctx_set_option(eig_ctx* ctx, const char* name, int64_t value);
 /* Reads an option back; "last_variant" gives the stencil variant of the most
- * recent launch.  "temporal_blocking" 1 (default): depth-only media use the
- * two-steps-per-launch kernels (four field buffers per solve); 0: one step
- * per launch. */
+ * recent launch.  "temporal_blocking": leapfrog steps per launch for
+ * depth-only media with rigid edges, 2 (default; 1 also selects 2), 3, or 0
+ * for one step; two and three steps per launch keep four field buffers per
+ * solve.  The serving engine uses at most two. */
 int eig_ctx_get_option(const eig_ctx* ctx, const char* name, int64_t* value);
 
 /*

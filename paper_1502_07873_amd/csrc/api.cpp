@@ -75,13 +75,15 @@ void stencil_candidates(const eig_ctx* c, int kind, bool one_step, std::vector<i
         out.push_back(c->forced_variant);
         return;
     }
-    // one family per wave: two steps per launch (four field buffers) or one
-    const int steps = (kind == EIG_MEDIUM_LAYERED && c->temporal_blocking && !one_step) ? 2 : 1;
+    // one family per wave: two or three steps per launch (four field
+    // buffers) or one
+    const int steps = (kind == EIG_MEDIUM_LAYERED && !one_step) ? c->temporal_blocking : 1;
     for (int v = 1; v < kNumVariants; ++v)
         if (kVariants[v].medium_kind == kind && kVariants[v].steps == steps) out.push_back(v);
     if (out.empty()) out.push_back(kind == EIG_MEDIUM_NODAL ? 6 : 0);
     if (!c->autotune) {
-        const int want = steps == 2 ? c->default_variant_tb : c->default_variant;
+        const int want = steps == 3 ? c->default_variant_tb3
+                                    : (steps == 2 ? c->default_variant_tb : c->default_variant);
         int keep = out[0];
         for (int v : out)
             if (v == want) keep = v;
@@ -131,12 +133,20 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
         f0[i] = cv.take(field);
         f1[i] = cv.take(field);
-        if (family_steps(i) == 2) {
+        if (family_steps(i) >= 2) {
             f2[i] = cv.take(field);
             f3[i] = cv.take(field);
         }
     }
     const size_t fields_end = cv.off;
+    // three-steps-per-launch halo side buffers (written before every read)
+    auto nbound = [&](const eig_grid& g) { return (g.nx + 127) / 128 - 1; };
+    std::vector<size_t> side_off(n, 0);
+    for (int i = 0; i < n; ++i) {
+        const eig_grid& g = grids[solves[i].grid];
+        if (family_steps(i) == 3 && nbound(g) > 0)
+            side_off[i] = cv.take((size_t)nbound(g) * g.nz * 4 * sizeof(float2));
+    }
     for (int i = 0; i < n; ++i) {
         const eig_grid& g = grids[solves[i].grid];
         sw[i] = cv.take(2 * kSrcW * kSrcW * sizeof(float));
@@ -159,10 +169,17 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     size_t ntiles_total = 0;
     for (int i = 0; i < n; ++i) {
         const eig_grid& g = grids[solves[i].grid];
-        for (int v : cand_of(i)) ntiles_total += tiles_of(g, kVariants[v]);
+        for (int v : cand_of(i)) {
+            ntiles_total += tiles_of(g, kVariants[v]);
+            if (kVariants[v].steps == 3)
+                ntiles_total += (size_t)std::max(nbound(g), 0) * ((g.nz - 1 + 63) / 64);
+        }
     }
+    // one aligned piece per descriptor table, job table, receiver map and
+    // (halo) tile map: at most 4 solve classes x 2 maps x every variant
+    const size_t npieces = 4 + 8 * (size_t)kNumVariants;
     size_t blob_bound = align_up((size_t)n * sizeof(SolveDesc)) +
-                        align_up(ntiles_total * sizeof(int2)) + 16 * kAlign +
+                        align_up(ntiles_total * sizeof(int2)) + npieces * kAlign +
                         align_up((size_t)n * sizeof(SourceJob)) + 4 * kAlign;
     for (int r : rec_used) blob_bound += align_up((size_t)pitch_of(recsets[r].nx) * sizeof(int32_t));
     const size_t blob_dev = cv.take(blob_bound);
@@ -185,6 +202,8 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         std::vector<int> cand;         // candidate variants
         std::vector<std::vector<int2>> tiles;                     // per candidate
         std::vector<std::vector<std::pair<int, int>>> steps_tiles;  // per candidate
+        std::vector<std::vector<int2>> htiles;                    // three-step halo
+        std::vector<std::vector<std::pair<int, int>>> steps_htiles;
     };
     std::vector<Group> groups;
     for (int oi = 0; oi < n; ++oi) {
@@ -212,6 +231,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         d.h2 = (float)(g.h * g.h);
         d.rforce = sp.rforce;
         d.wrec = sp.wrec;
+        d.side = side_off[i] ? (float2*)(base + side_off[i]) : nullptr;
         // forcing window: union of the nominal and perturbed 6x6 stencils
         SourceJob& J = jobs[oi];
         std::memcpy(J.theta, sp.theta, sizeof(J.theta));
@@ -247,6 +267,8 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
             gr.cand = cand_of(i);
             gr.tiles.resize(gr.cand.size());
             gr.steps_tiles.resize(gr.cand.size());
+            gr.htiles.resize(gr.cand.size());
+            gr.steps_htiles.resize(gr.cand.size());
             groups.push_back(gr);
         }
         Group& gr = groups.back();
@@ -259,13 +281,23 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
                 for (int st = 0; st < nstrip; ++st)
                     gr.tiles[v].push_back(make_int2(oi, (st << 16) | ch));
             gr.steps_tiles[v].push_back({g.nsteps, (int)gr.tiles[v].size()});
+            if (sv.steps == 3) {
+                const int nhch = (g.nz - 1 + 63) / 64;
+                for (int bi = 0; bi < nbound(g); ++bi)
+                    for (int ch = 0; ch < nhch; ++ch)
+                        gr.htiles[v].push_back(make_int2(oi, (bi << 16) | ch));
+                gr.steps_htiles[v].push_back({g.nsteps, (int)gr.htiles[v].size()});
+            }
         }
     }
     const size_t o_desc = blob.put(desc.data(), desc.size() * sizeof(SolveDesc));
-    std::vector<std::vector<size_t>> o_tiles(groups.size());
-    for (size_t gi = 0; gi < groups.size(); ++gi)
+    std::vector<std::vector<size_t>> o_tiles(groups.size()), o_htiles(groups.size());
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
         for (auto& tv : groups[gi].tiles)
             o_tiles[gi].push_back(blob.put(tv.data(), tv.size() * sizeof(int2)));
+        for (auto& hv : groups[gi].htiles)
+            o_htiles[gi].push_back(hv.empty() ? 0 : blob.put(hv.data(), hv.size() * sizeof(int2)));
+    }
     const size_t o_jobs = blob.put(jobs.data(), jobs.size() * sizeof(SourceJob));
     if (blob.data.size() > blob_bound) return set_error(EIG_EBUDGET, "descriptor blob overflow");
     int rc = upload(c, bd, blob.data, s);
@@ -366,6 +398,14 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
             if (ntile > 0) {
                 c->last_variant = g.cand[vi];
                 if (slot >= 0) HIP_TRY(hipEventRecord(tn.ev[2 * slot], s));
+                if (spl == 3) {
+                    int nh = 0;
+                    for (const auto& hs : g.steps_htiles[vi]) {
+                        if (hs.first > step * spl) nh = hs.second;
+                        else break;
+                    }
+                    launch_tb3_halo(ddesc, (const int2*)(bd + o_htiles[gi][vi]), nh, step, s);
+                }
                 launch_stencil(ddesc, (const int2*)(bd + o_tiles[gi][vi]), ntile, step,
                                g.cand[vi], s);
                 if (slot >= 0) HIP_TRY(hipEventRecord(tn.ev[2 * slot + 1], s));
@@ -410,7 +450,7 @@ struct WaveSizer {
     const std::vector<MediumKey>& media;
     const std::vector<RecSet>& recsets;
     std::vector<char> med_seen, rec_seen;
-    size_t bytes = 64 * kAlign;
+    size_t bytes = (64 + 8 * kNumVariants) * kAlign;
     WaveSizer(const std::vector<eig_grid>& g, const std::vector<MediumKey>& m,
               const std::vector<RecSet>& r)
         : grids(g), media(m), recsets(r), med_seen(m.size(), 0), rec_seen(r.size(), 0) {}
@@ -418,6 +458,9 @@ struct WaveSizer {
         const eig_grid& g = grids[sp.grid];
         size_t b = solve_bytes(g) + sizeof(SolveDesc) + sizeof(SourceJob) + 64;
         for (int v = 0; v < kNumVariants; ++v) b += tiles_of(g, kVariants[v]) * sizeof(int2);
+        // three-step halo: side buffer and halo tile maps (upper bound)
+        const size_t nb = (size_t)(g.nx + 127) / 128;
+        b += nb * g.nz * 4 * sizeof(float2) + 2 * nb * ((g.nz + 63) / 64) * sizeof(int2) + kAlign;
         if (!med_seen[sp.medium]) b += medium_bytes(media[sp.medium]);
         if (!rec_seen[sp.recset]) b += 2 * align_up((size_t)pitch_of(recsets[sp.recset].nx) * 4);
         return b;
@@ -509,7 +552,8 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
         if (value < 0 || value >= kNumVariants) return set_error(EIG_EINVAL, "variant");
         c->default_variant = (int)value;
     } else if (n == "temporal_blocking") {
-        c->temporal_blocking = value != 0;
+        if (value < 0 || value > 3) return set_error(EIG_EINVAL, "temporal_blocking: 0..3");
+        c->temporal_blocking = value == 0 ? 1 : (value == 1 ? 2 : (int)value);
     } else if (n == "max_wave_solves") {
         if (value < 0) return set_error(EIG_EINVAL, "max_wave_solves < 0");
         c->max_wave_solves = value;

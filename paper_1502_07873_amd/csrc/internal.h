@@ -62,6 +62,9 @@ struct SolveDesc {
     // new level recorded on the forcing window, [nsteps][kSrcW * kSrcW]
     const float2* rforce;
     float2* wrec;
+    // three-steps-per-launch kernels: per strip boundary b = 128 (i + 1) and
+    // free row k, u^{m+1} and u^{m+2} at columns b-1 and b: [nb][nz][4]
+    float2* side;
 };
 
 // One forcing table to build (FP64 arithmetic, FP32 result).
@@ -120,14 +123,18 @@ void launch_source_tables(const SourceJob* jobs, int njobs, int max_nsteps,
 // bitwise-identical results; they differ only in speed.
 struct StencilVariant {
     int cols, rows, medium_kind;
-    int steps;  // leapfrog steps per launch (2: four field buffers per solve)
+    int steps;  // leapfrog steps per launch (2, 3: four field buffers per solve)
 };
-constexpr int kNumVariants = 15;
+constexpr int kNumVariants = 17;
 extern const StencilVariant kVariants[kNumVariants];
 // tiles: (solve index, strip << 16 | chunk) per wavefront
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                     int variant, hipStream_t s);
 void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s);
+// Halo values of the three-steps-per-launch kernels; htiles: (solve,
+// boundary << 16 | 64-row chunk).
+void launch_tb3_halo(const SolveDesc* descs, const int2* htiles, int nhtiles, int pass,
+                     hipStream_t s);
 // Nested Monte Carlo log ratios (and their mean when eig != NULL); work
 // holds nested_workspace() bytes of per-split partial sums.
 int nested_splits(int nouter, int ninner);

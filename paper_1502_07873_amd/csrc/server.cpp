@@ -401,7 +401,7 @@ int eig_server_create(eig_ctx* c, size_t budget, int32_t group_samples, eig_serv
     v->variant_layered = c->forced_variant >= 0 &&
                                  kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_LAYERED
                              ? c->forced_variant
-                             : (c->temporal_blocking ? c->default_variant_tb : c->default_variant);
+                             : (c->temporal_blocking >= 2 ? c->default_variant_tb : c->default_variant);
     v->spl = kVariants[v->variant_layered].steps;
     v->nslot_cap = 1 << 17;
     if (hipMalloc((void**)&v->mem, budget) != hipSuccess) {

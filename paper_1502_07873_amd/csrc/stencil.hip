@@ -892,6 +892,298 @@ stencil_layered_tb2h(const SolveDesc* __restrict__ descs, const int2* __restrict
     }
 }
 
+// Three leapfrog steps per launch (temporal blocking), depth-only media.
+// Levels alternate between two buffer pairs: a launch reads u^{m-1}, u^m
+// from one pair and writes u^{m+2}, u^{m+3} to the other (u^{m+1} only
+// reaches the receivers), so field traffic is 32 bytes per node per three
+// updates.  A wave streams down its 128 x R tile doing step 1 at row j,
+// step 2 at row j-1 and step 3 at row j-2; the values its edge nodes need
+// from the neighbouring strips (u^{m+1} and u^{m+2} one column beyond the
+// tile) come from a side buffer that stencil_tb3_halo fills first, one lane
+// per (strip boundary, row).  Every node goes through the same per-node
+// update as all other variants: the fields are bitwise identical.
+// Measured at 3840 x 512^2: 12.64 ms per launch (4.21 ms per step) against
+// 3.48 ms per step for stencil_layered_tb2 -- with a third of the field
+// traffic per step it is bound by vector issue (396 instructions per row
+// pass, 144 of them register moves; unrolling the row rotation needed 206
+// VGPRs), so it is offered ("temporal_blocking" 3) but not the default.
+
+// side[b][k][4]: u^{m+1} at columns b-1 and b, then u^{m+2} at b-1 and b,
+// for the strip boundary b = 128 (bi + 1) and free row k.
+__global__ void __launch_bounds__(256)
+stencil_tb3_halo(const SolveDesc* __restrict__ descs, const int2* __restrict__ htiles,
+                 int nhtiles, int pass) {
+    const int tile = __builtin_amdgcn_readfirstlane(
+        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
+    if (tile >= nhtiles) return;
+    const int2 te = htiles[tile];
+    const SolveDesc* d = descs + __builtin_amdgcn_readfirstlane(te.x);
+    const int hc = __builtin_amdgcn_readfirstlane(te.y);
+    const int m = 3 * (pass - d->start);
+    if (m < 0 || m >= d->nsteps) return;
+    const int nx = d->nx, nz = d->nz, pitch = d->pitch;
+    const int bi = hc >> 16;
+    const int b = 128 * (bi + 1);
+    const int k = (hc & 0xffff) * 64 + (threadIdx.x & 63);
+    if (k > nz - 2) return;
+    const float2* prev = ((pass - d->start) & 1) ? d->buf2 : d->buf0;
+    const float2* cur = ((pass - d->start) & 1) ? d->buf3 : d->buf1;
+    const float* coef = d->coef;
+    const int si0 = d->src_i0, sk0 = d->src_k0;
+    const float sval1 = ld1(d->srcs, m);
+    const float sval2 = m + 1 < d->nsteps ? ld1(d->srcs, m + 1) : 0.f;
+    const float* srcw = d->srcw;
+    const NodeRow z = NodeRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const float2 z2 = make_float2(0.f, 0.f);
+    // u^m on rows k-2..k+2, columns b-3..b+2 (zero outside the grid)
+    float2 U[5][6];
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const int rr = k - 2 + r, cc = b - 3 + c;
+            U[r][c] = (rr >= 0 && rr <= nz - 1 && cc >= 0 && cc <= nx - 1)
+                          ? ld2(cur, (size_t)rr * pitch + cc) : z2;
+        }
+    // step 1 on rows k-1..k+1, columns b-2..b+1
+    float2 X1[3][4];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int rr = k - 1 + r, cc = b - 2 + c;
+            float2 x = z2;
+            if (rr >= 0 && rr <= nz - 2 && cc >= 1 && cc <= nx - 2) {
+                const NodeRow rm = rr >= 1 ? node_row(U[r][c + 1].x, U[r][c + 1].y, U[r][c].x,
+                                                      U[r][c].y, U[r][c + 2].x, U[r][c + 2].y)
+                                           : z;
+                const NodeRow rc = node_row(U[r + 1][c + 1].x, U[r + 1][c + 1].y, U[r + 1][c].x,
+                                            U[r + 1][c].y, U[r + 1][c + 2].x, U[r + 1][c + 2].y);
+                const NodeRow rn = node_row(U[r + 2][c + 1].x, U[r + 2][c + 1].y, U[r + 2][c].x,
+                                            U[r + 2][c].y, U[r + 2][c + 2].x, U[r + 2][c + 2].y);
+                const float2 p = ld2(prev, (size_t)rr * pitch + cc);
+                const LayerCoef cf = load_coef(coef, rr);
+                const int di = cc - si0, dk = rr - sk0;
+                const bool src = di >= 0 && di < kSrcW && dk >= 0 && dk < kSrcW;
+                float wu = 0.f, wv = 0.f;
+                if (src) {
+                    wu = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
+                    wv = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
+                }
+                x = layered_update(cf, rm, rc, rn, p.x, p.y, src, cf.c[kFco] * sval1, wu, wv);
+            }
+            X1[r][c] = x;
+        }
+    // step 2 at row k, columns b-1 and b
+    float2 X2[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int cc = b - 1 + c;
+        float2 x = z2;
+        if (cc >= 1 && cc <= nx - 2 && m + 1 < d->nsteps) {
+            const NodeRow rm = k >= 1 ? node_row(X1[0][c + 1].x, X1[0][c + 1].y, X1[0][c].x,
+                                                 X1[0][c].y, X1[0][c + 2].x, X1[0][c + 2].y)
+                                      : z;
+            const NodeRow rc = node_row(X1[1][c + 1].x, X1[1][c + 1].y, X1[1][c].x, X1[1][c].y,
+                                        X1[1][c + 2].x, X1[1][c + 2].y);
+            const NodeRow rn = node_row(X1[2][c + 1].x, X1[2][c + 1].y, X1[2][c].x, X1[2][c].y,
+                                        X1[2][c + 2].x, X1[2][c + 2].y);
+            const float2 p = U[2][c + 2];   // u^m at (k, cc)
+            const LayerCoef cf = load_coef(coef, k);
+            const int di = cc - si0, dk = k - sk0;
+            const bool src = di >= 0 && di < kSrcW && dk >= 0 && dk < kSrcW;
+            float wu = 0.f, wv = 0.f;
+            if (src) {
+                wu = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
+                wv = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
+            }
+            x = layered_update(cf, rm, rc, rn, p.x, p.y, src, cf.c[kFco] * sval2, wu, wv);
+        }
+        X2[c] = x;
+    }
+    float2* out = d->side + ((size_t)bi * nz + k) * 4;
+    st4(out, 0, make_float4(X1[1][1].x, X1[1][1].y, X1[1][2].x, X1[1][2].y));
+    st4(out, 2, make_float4(X2[0].x, X2[0].y, X2[1].x, X2[1].y));
+}
+
+template <int R>
+__global__ void __launch_bounds__(256)
+stencil_layered_tb3(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
+                    int ntiles, int pass) {
+    const int tile = __builtin_amdgcn_readfirstlane(
+        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
+    if (tile >= ntiles) return;
+    const int2 te = tiles[tile];
+    const SolveDesc* d = descs + __builtin_amdgcn_readfirstlane(te.x);
+    const int sc = __builtin_amdgcn_readfirstlane(te.y);
+    const int lp = pass - d->start;
+    const int m = 3 * lp;
+    if (m < 0 || m >= d->nsteps) return;
+    const int nsub = min(3, d->nsteps - m);
+    const int lane = threadIdx.x & 63;
+    const int nx = d->nx, nz = d->nz, pitch = d->pitch;
+    const int x0 = (sc >> 16) * 128;
+    const int kb = (sc & 0xffff) * R;
+    const int ke = min(kb + R, nz - 1);
+    const int i0 = x0 + 2 * lane;
+    const bool odd = lp & 1;
+    const float2* prev = odd ? d->buf2 : d->buf0;
+    const float2* cur = odd ? d->buf3 : d->buf1;
+    float2* outA = odd ? d->buf0 : d->buf2;   // u^{m+2}
+    float2* outB = odd ? d->buf1 : d->buf3;   // u^{m+3}
+    const float* coef = d->coef;
+    const bool updA = (i0 >= 1) && (i0 <= nx - 2);
+    const bool updB = (i0 + 1 <= nx - 2);
+    const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + 128 < nx);
+    const int hc = (lane == 0) ? x0 - 1 : x0 + 128;
+    // side-buffer column of this lane's halo node (lanes 0 and 63 only)
+    const float2* side = nullptr;
+    int sofs = 0;
+    if (lane == 0 && x0 > 0) {
+        side = d->side + (size_t)(x0 / 128 - 1) * nz * 4;
+        sofs = 0;   // column b - 1 with b = x0
+    } else if (lane == 63 && x0 + 128 < nx) {
+        side = d->side + (size_t)(x0 / 128) * nz * 4;
+        sofs = 1;   // column b with b = x0 + 128
+    }
+    const int si0 = d->src_i0, sk0 = d->src_k0;
+    const bool src_cols = (si0 < x0 + 128) && (si0 + kSrcW > x0);
+    const int dA = i0 - si0, dB = dA + 1;
+    const bool sA = src_cols && dA >= 0 && dA < kSrcW;
+    const bool sB = src_cols && dB >= 0 && dB < kSrcW;
+    const float sv1 = ld1(d->srcs, m);
+    const float sv2 = nsub > 1 ? ld1(d->srcs, m + 1) : 0.f;
+    const float sv3 = nsub > 2 ? ld1(d->srcs, m + 2) : 0.f;
+    const float* srcw = d->srcw;
+    float2* traces = d->traces;
+    const int nrec = d->nrec;
+    int recA = -1, recB = -1;
+    if (kb == 0) {
+        recA = ldi(d->recmap, i0);
+        recB = ldi(d->recmap, i0 + 1);
+    }
+    const NodeRow z = NodeRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const float2 z2 = make_float2(0.f, 0.f);
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int j0 = kb >= 2 ? kb - 2 : 0;
+    const int j1 = min(ke + 1, nz - 2);                 // last step-1 row
+    const int s2lo = kb >= 1 ? kb - 1 : 0, s2hi = min(ke, nz - 2);
+
+    auto wts = [&](bool s, int dk, int di, float& wu, float& wv) {
+        wu = 0.f;
+        wv = 0.f;
+        if (s && dk >= 0 && dk < kSrcW) {
+            wu = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
+            wv = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
+        }
+    };
+
+    NodeRow am, bm, ac, bc, an, bn;
+    if (j0 >= 1) {
+        make_rows2(load_raw2(cur, (size_t)(j0 - 1) * pitch, i0, hc, hl), am, bm);
+    } else {
+        am = bm = z;
+    }
+    make_rows2(load_raw2(cur, (size_t)j0 * pitch, i0, hc, hl), ac, bc);
+    Raw2 q1;
+    q1.c = z4;
+    q1.h = z2;
+    if (j0 + 1 <= nz - 1) q1 = load_raw2(cur, (size_t)(j0 + 1) * pitch, i0, hc, hl);
+    float4 p0 = ld4(prev, (size_t)j0 * pitch + i0);
+    NodeRow a1m = z, b1m = z, a1c = z, b1c = z;   // u^{m+1} rows j-2, j-1
+    NodeRow a2m = z, b2m = z, a2c = z, b2c = z;   // u^{m+2} rows j-3, j-2
+    for (int j = j0; j <= ke + 1; ++j) {
+        Raw2 qn;
+        qn.c = z4;
+        qn.h = z2;
+        float4 pn = z4;
+        if (j + 2 <= nz - 1 && j + 1 <= j1) qn = load_raw2(cur, (size_t)(j + 2) * pitch, i0, hc, hl);
+        if (j + 1 <= j1) pn = ld4(prev, (size_t)(j + 1) * pitch + i0);
+        // step 1 at row j
+        NodeRow a1n = z, b1n = z;
+        if (j <= j1) {
+            make_rows2(q1, an, bn);
+            const LayerCoef cj = load_coef(coef, j);
+            float wua, wva, wub, wvb;
+            wts(sA, j - sk0, dA, wua, wva);
+            wts(sB, j - sk0, dB, wub, wvb);
+            const bool r1 = j - sk0 >= 0 && j - sk0 < kSrcW;
+            float2 xa = layered_update(cj, am, ac, an, p0.x, p0.y, sA && r1, cj.c[kFco] * sv1,
+                                       wua, wva);
+            float2 xb = layered_update(cj, bm, bc, bn, p0.z, p0.w, sB && r1, cj.c[kFco] * sv1,
+                                       wub, wvb);
+            if (!updA) xa = z2;
+            if (!updB) xb = z2;
+            if (j == 0) {
+                if (recA >= 0) st2(traces, (size_t)(m + 1) * nrec + recA, xa);
+                if (recB >= 0) st2(traces, (size_t)(m + 1) * nrec + recB, xb);
+            }
+            const float2 xt = side ? ld2(side, (size_t)j * 4 + sofs) : z2;
+            make_rows_x(xa, xb, xt, a1n, b1n);
+        } else {
+            an = bn = z;
+        }
+        // step 2 at row j - 1
+        NodeRow a2n = z, b2n = z;
+        const int k2 = j - 1;
+        if (nsub > 1 && k2 >= s2lo && k2 <= s2hi) {
+            const LayerCoef ck = load_coef(coef, k2);
+            float wua, wva, wub, wvb;
+            wts(sA, k2 - sk0, dA, wua, wva);
+            wts(sB, k2 - sk0, dB, wub, wvb);
+            const bool r2 = k2 - sk0 >= 0 && k2 - sk0 < kSrcW;
+            float2 ya = layered_update(ck, a1m, a1c, a1n, am.u, am.v, sA && r2,
+                                       ck.c[kFco] * sv2, wua, wva);
+            float2 yb = layered_update(ck, b1m, b1c, b1n, bm.u, bm.v, sB && r2,
+                                       ck.c[kFco] * sv2, wub, wvb);
+            if (!updA) ya = z2;
+            if (!updB) yb = z2;
+            if (k2 >= kb && k2 < ke)
+                st4(outA, (size_t)k2 * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
+            if (k2 == 0) {
+                if (recA >= 0) st2(traces, (size_t)(m + 2) * nrec + recA, ya);
+                if (recB >= 0) st2(traces, (size_t)(m + 2) * nrec + recB, yb);
+            }
+            const float2 xt = side ? ld2(side, (size_t)k2 * 4 + 2 + sofs) : z2;
+            make_rows_x(ya, yb, xt, a2n, b2n);
+        }
+        // step 3 at row j - 2
+        const int k3 = j - 2;
+        if (nsub > 2 && k3 >= kb && k3 < ke) {
+            const LayerCoef ck = load_coef(coef, k3);
+            float wua, wva, wub, wvb;
+            wts(sA, k3 - sk0, dA, wua, wva);
+            wts(sB, k3 - sk0, dB, wub, wvb);
+            const bool r3 = k3 - sk0 >= 0 && k3 - sk0 < kSrcW;
+            float2 za = layered_update(ck, a2m, a2c, a2n, a1m.u, a1m.v, sA && r3,
+                                       ck.c[kFco] * sv3, wua, wva);
+            float2 zb = layered_update(ck, b2m, b2c, b2n, b1m.u, b1m.v, sB && r3,
+                                       ck.c[kFco] * sv3, wub, wvb);
+            if (!updA) za = z2;
+            if (!updB) zb = z2;
+            st4(outB, (size_t)k3 * pitch + i0, make_float4(za.x, za.y, zb.x, zb.y));
+            if (k3 == 0) {
+                if (recA >= 0) st2(traces, (size_t)(m + 3) * nrec + recA, za);
+                if (recB >= 0) st2(traces, (size_t)(m + 3) * nrec + recB, zb);
+            }
+        }
+        am = ac;
+        bm = bc;
+        ac = an;
+        bc = bn;
+        a1m = a1c;
+        b1m = b1c;
+        a1c = a1n;
+        b1c = b1n;
+        a2m = a2c;
+        b2m = b2c;
+        a2c = a2n;
+        b2c = b2n;
+        q1 = qn;
+        p0 = pn;
+    }
+}
+
 // Nodal media: coef = three planes (lambda, mu, s = dt^2/(rho h^2)).
 struct RowN {
     float u, v, hu, hv;   // centre and halo-column values of u^m
@@ -1054,6 +1346,13 @@ __global__ void zero_level0_kernel(const SolveDesc* __restrict__ descs) {
 
 }  // namespace
 
+void launch_tb3_halo(const SolveDesc* descs, const int2* htiles, int nhtiles, int pass,
+                     hipStream_t s) {
+    if (nhtiles <= 0) return;
+    const int blocks = (nhtiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    stencil_tb3_halo<<<blocks, 64 * kWavesPerBlock, 0, s>>>(descs, htiles, nhtiles, pass);
+}
+
 void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s) {
     if (n > 0) zero_level0_kernel<<<n, 64, 0, s>>>(descs);
 }
@@ -1086,6 +1385,8 @@ const StencilVariant kVariants[kNumVariants] = {
     {128, 128, EIG_MEDIUM_LAYERED, 2}, // 12: two steps per launch
     {128, 64, EIG_MEDIUM_LAYERED, 2},  // 13: two steps, halo columns up front
     {128, 32, EIG_MEDIUM_LAYERED, 2},  // 14: two steps, halo columns up front
+    {128, 64, EIG_MEDIUM_LAYERED, 3},  // 15: three steps per launch
+    {128, 32, EIG_MEDIUM_LAYERED, 3},  // 16: three steps per launch
 };
 
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
@@ -1108,6 +1409,8 @@ void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int s
         case 12: stencil_layered_tb2<128, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         case 13: stencil_layered_tb2h<64, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         case 14: stencil_layered_tb2h<32, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 15: stencil_layered_tb3<64><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 16: stencil_layered_tb3<32><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
 
         default: stencil_nodal<<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
     }

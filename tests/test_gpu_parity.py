@@ -370,7 +370,7 @@ def test_edge_cases(ctx):
 
 
 @pytest.mark.parametrize("nsteps", [700, 333])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16])
 def test_stencil_variants_bitwise_identical(variant, nsteps, monkeypatch):
     # every layered-medium stencil variant computes the same arithmetic per
     # node, so the traces must agree bit for bit (and with the oracle)
@@ -399,6 +399,42 @@ def test_stencil_variants_bitwise_identical(variant, nsteps, monkeypatch):
         if nsteps % 2:
             assert np.max(np.abs(ref[-1])) > 0
         assert _relerr(outs[variant][s], ref) <= TRACE_TOL
+
+
+def test_three_step_family_with_mixed_lengths_matches_one_step():
+    # temporal_blocking = 3 through the normal (tuned) path: solves of
+    # different lengths in one wave (running prefixes of tiles and halo
+    # tiles), tails of one and two steps; bitwise equal to one step per launch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context
+    from paper_1502_07873_amd.query import grid_tuple
+    rng = np.random.default_rng(33)
+    nx, nz, h = 300, 141, 10.0
+    med = synthetic.random_layers_medium(rng, nz, h, 3)
+    dt = synthetic.cfl_dt(h, med.vp_max())
+    lens = [600, 431, 302, 601]
+    grids = [synthetic.Grid(nx, nz, h, dt, n) for n in lens]
+    lo, hi = synthetic.prior_box(grids[0])
+    th = synthetic.draw_uniform(rng, lo, hi, len(lens))
+    th[:, 2] = 0.08
+    rec = np.array([1, 127, 128, 129, 255, 256, nx - 2], dtype=np.int32)
+    _say("three-step family, mixed lengths")
+    dm = _dev_medium(med)
+    outs = []
+    for tb in (3, 0):
+        with Context(0, 4 << 30) as c:
+            c.set_option("temporal_blocking", tb)
+            tr = [torch.empty((n + 1, len(rec), 2), dtype=torch.float32, device="cuda")
+                  for n in lens]
+            c.forward_solve_batch([grid_tuple(g) for g in grids], [dm] * len(lens), th,
+                                  [rec] * len(lens), tr)
+            torch.cuda.synchronize()
+            outs.append([t.cpu().numpy() for t in tr])
+            assert c.get_option("temporal_blocking") == (3 if tb == 3 else 1)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    assert np.max(np.abs(outs[0][2])) > 0
 
 
 def test_server_alone_equals_mix_and_matches_jacobian_path(ctx):
