@@ -162,3 +162,30 @@ def test_pipeline_dkl_same_from_either_jacobian():
     b = pipeline.query(wl, sigma=0.01, jacobian="sensitivity")
     assert np.max(np.abs(a["dkl"] - b["dkl"])) < 1e-4
     assert np.array_equal(a["nominal"], b["nominal"])
+
+
+def test_hessian_grows_with_receivers_and_recording_time():
+    # the paper's concentration argument: H_1 is O(N), N = N_R x N_t.  In the
+    # closed rigid box the signal persists, and on a dense surface array
+    # doubling the receivers or the record length doubles H_1, so D^_KL
+    # gains N_theta/2 log 2 (log det H_1 grows by 7 log 2) -- here within 15 %
+    import synthetic
+    wl = synthetic.config("c1", nsample=1, grid_override=(64, 64, 1600))[0]
+    rec = np.arange(1, 63, dtype=np.int32)
+    th = wl.theta[0]
+    _, J = elastic.jacobian_sensitivity(wl.grid, wl.medium, th, rec, wl.stf)
+    sig = 1e-3 * np.abs(elastic.forward(wl.grid, wl.medium, th, rec, wl.stf)).max()
+    prior = laplace.uniform_prior(wl.lo, wl.hi)
+    dkl = lambda JJ: laplace.dkl_hat(laplace.hessian_h1(JJ, sig), th, prior)[0]  # noqa: E731
+    # recording time: windows [0, 800] and [0, 1600] steps (H_1 additive in time)
+    gain_t = dkl(J) - dkl(J[:801])
+    assert abs(gain_t / (3.5 * math.log(1601 / 801)) - 1) < 0.15, gain_t
+    # receivers: every second surface node against all of them
+    half = np.arange(0, 62, 2)
+    gain_r = dkl(J) - dkl(J[:, half])
+    assert abs(gain_r / (3.5 * math.log(62 / 31)) - 1) < 0.15, gain_r
+    # and H_1 itself doubles: scaled trace of the sub-array's H_1 is half
+    Hf = laplace.hessian_h1(J, sig)
+    ratio = np.trace(Hf / np.diag(Hf)[None, :]) / np.trace(
+        laplace.hessian_h1(J[:, half], sig) / np.diag(Hf)[None, :])
+    assert abs(ratio / 2 - 1) < 0.15, ratio
