@@ -98,6 +98,45 @@ def _copy_rate(nbytes=4 << 30, reps=5):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def _graph_gain(reps=20):
+    """A launch-bound query (c1: 8 samples x 15 solves of 64^2 x 400 steps)
+    repeated with the time loop replayed from a captured HIP graph and with
+    direct launches; sample-EIG evals/s of each."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_1502_07873_amd import Context
+    from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
+    wl = synthetic.config("c1")[0]
+    med = device_medium(wl.medium.kind, wl.medium.rho, wl.medium.lam, wl.medium.mu)
+    g = grid_tuple(wl.grid)
+    out = {}
+    for graphs in (1, 0):
+        with Context(0, 4 << 30) as ctx:
+            ctx.set_option("graphs", graphs)
+            sig = ctx.noise_sigma_peak(g, med, wl.theta_bar, wl.noise_rel)
+            for _ in range(3):   # tune, capture, replay once
+                run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, wl.theta, wl.weights,
+                          sigma=sig)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, wl.theta, wl.weights,
+                              sigma=sig)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            out["graphs" if graphs else "direct"] = {
+                "sample_eig_evals_per_s": reps * len(wl.theta) / t,
+                "ms_per_query": 1e3 * t / reps,
+                "graph_replays": ctx.get_option("graph_replays"),
+                "eig": float(r["eig"].cpu()[0])}
+    out["speedup"] = (out["graphs"]["sample_eig_evals_per_s"] /
+                      out["direct"]["sample_eig_evals_per_s"])
+    out["workload"] = "c1 query: 8 samples x 15 solves, 64x64 grid, 400 steps (launch-bound)"
+    return out
+
+
 def _copy_calibration(nbytes=4 << 30, reps=4):
     """A plain device-to-device copy of nbytes, reps times: the HBM counters
     of these dispatches should read nbytes fetched and nbytes written."""
@@ -706,6 +745,8 @@ def main():
         "speedup_of_batched": value / (2 / t1),
         "dkl_match": bool(np.allclose(o1["dkl"].cpu().numpy(), dkl[:2], rtol=0, atol=0))}
     ctx1.close()
+    print("[bench] launch-bound query with and without graph replay", flush=True)
+    line["graph_replay"] = _graph_gain()
     # the forward-sensitivity Jacobian (1 + 7 solves per sample) on the same query
     print("[bench] forward-sensitivity Jacobian path (same samples)", flush=True)
     sig = ctx.noise_sigma_peak(g, med, theta_bar, wl.noise_rel)

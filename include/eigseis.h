@@ -157,6 +157,12 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  *                      new grid class and keep the fastest; 0: use
  *                      "default_variant"
  *   "default_variant"  variant used before/without tuning
+ *   "graphs"           1 (default): once a wave's variants are tuned, its time
+ *                      loop is captured as a HIP graph (kernels only) and
+ *                      replayed when the same wave (same descriptors at the
+ *                      same device addresses) comes again; 0: direct launches.
+ *                      get_option also reports "graph_captures" and
+ *                      "graph_replays"
  *   "max_wave_solves"  0 (default): every solve of a wave advances in the same
  *                      launches; n > 0: at most n solves per launch (n = 1 is
  *                      the plain one-solve-at-a-time path)

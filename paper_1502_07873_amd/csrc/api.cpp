@@ -363,6 +363,30 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
             }
         }
     }
+    // graph capture: only without an open tuning window (no events inside)
+    bool any_tuning = false;
+    for (const auto& tn : tune) any_tuning = any_tuning || tn.active;
+    const bool use_graph = c->graphs && !any_tuning && max_steps > 0;
+    std::tuple<uint64_t, uintptr_t, size_t> gkey{0, 0, 0};
+    hipGraphExec_t gexec = nullptr;
+    bool capturing = false;
+    if (use_graph) {
+        uint64_t hsh = 1469598103934665603ull;   // FNV-1a over the blob and the variants
+        for (char ch : blob.data) hsh = (hsh ^ (uint8_t)ch) * 1099511628211ull;
+        for (int u : use) hsh = (hsh ^ (uint64_t)(u + 1)) * 1099511628211ull;
+        gkey = std::make_tuple(hsh, (uintptr_t)bd, blob.data.size());
+        auto it = c->graph_cache.find(gkey);
+        if (it != c->graph_cache.end()) {
+            gexec = it->second;
+        } else {
+            if (!c->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream,
+                                                                      hipStreamNonBlocking));
+            capturing = hipStreamBeginCapture(c->capture_stream,
+                                              hipStreamCaptureModeThreadLocal) == hipSuccess;
+        }
+    }
+    const bool replay = gexec != nullptr;
+    hipStream_t ls = capturing ? c->capture_stream : s;   // where launches go
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (max_steps > 0) {
         HIP_TRY(hipEventCreate(&ev0));
@@ -398,18 +422,20 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
             if (ntile > 0) {
                 c->last_variant = g.cand[vi];
                 if (slot >= 0) HIP_TRY(hipEventRecord(tn.ev[2 * slot], s));
-                if (spl == 3) {
+                if (spl == 3 && !replay) {
                     int nh = 0;
                     for (const auto& hs : g.steps_htiles[vi]) {
                         if (hs.first > step * spl) nh = hs.second;
                         else break;
                     }
-                    launch_tb3_halo(ddesc, (const int2*)(bd + o_htiles[gi][vi]), nh, step, s);
+                    launch_tb3_halo(ddesc, (const int2*)(bd + o_htiles[gi][vi]), nh, step, ls);
                 }
-                launch_stencil(ddesc, (const int2*)(bd + o_tiles[gi][vi]), ntile, step,
-                               g.cand[vi], s);
+                if (!replay)
+                    launch_stencil(ddesc, (const int2*)(bd + o_tiles[gi][vi]), ntile, step,
+                                   g.cand[vi], ls);
                 if (slot >= 0) HIP_TRY(hipEventRecord(tn.ev[2 * slot + 1], s));
-                if (g.bc == EIG_BC_ABSORBING) launch_ce_edges(ddesc + g.first, nrun, step, s);
+                if (g.bc == EIG_BC_ABSORBING && !replay)
+                    launch_ce_edges(ddesc + g.first, nrun, step, ls);
                 c->launches += 1;
                 c->updates += upd;
                 c->bytes += upd * (g.kind == EIG_MEDIUM_NODAL ? 36.0 : 24.0);
@@ -434,6 +460,33 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
             }
         }
     }
+    if (capturing) {
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
+        if (e == hipSuccess && graph) {
+            e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+        }
+        if (e != hipSuccess || !gexec) {
+            (void)hipGetLastError();
+            return set_error(EIG_EHIP, "graph capture of the time loop failed");
+        }
+        if (c->graph_order.size() >= 8) {   // keep the eight most recent graphs
+            auto old_key = c->graph_order.front();
+            c->graph_order.erase(c->graph_order.begin());
+            auto it = c->graph_cache.find(old_key);
+            if (it != c->graph_cache.end()) {
+                (void)hipGraphExecDestroy(it->second);
+                c->graph_cache.erase(it);
+            }
+        }
+        c->graph_cache[gkey] = gexec;
+        c->graph_order.push_back(gkey);
+        c->graph_captures += 1;
+    } else if (replay) {
+        c->graph_replays += 1;
+    }
+    if (gexec) HIP_TRY(hipGraphLaunch(gexec, s));
     if (max_steps > 0) {
         HIP_TRY(hipEventRecord(ev1, s));
         c->timing.push_back({ev0, ev1});
@@ -534,6 +587,8 @@ void eig_ctx_destroy(eig_ctx* c) {
         if (c->stage[r]) (void)hipHostFree(c->stage[r]);
         if (c->stage_ev[r]) (void)hipEventDestroy(c->stage_ev[r]);
     }
+    for (auto& kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;
 }
 
@@ -557,6 +612,8 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
     } else if (n == "max_wave_solves") {
         if (value < 0) return set_error(EIG_EINVAL, "max_wave_solves < 0");
         c->max_wave_solves = value;
+    } else if (n == "graphs") {
+        c->graphs = value != 0;
     } else {
         return set_error(EIG_EINVAL, "unknown option " + n);
     }
@@ -571,6 +628,9 @@ int eig_ctx_get_option(const eig_ctx* c, const char* name, int64_t* value) {
     else if (n == "default_variant") *value = c->default_variant;
     else if (n == "temporal_blocking") *value = c->temporal_blocking;
     else if (n == "max_wave_solves") *value = c->max_wave_solves;
+    else if (n == "graphs") *value = c->graphs;
+    else if (n == "graph_captures") *value = c->graph_captures;
+    else if (n == "graph_replays") *value = c->graph_replays;
     else if (n == "last_variant") *value = c->last_variant;
     else return set_error(EIG_EINVAL, "unknown option " + n);
     return EIG_OK;

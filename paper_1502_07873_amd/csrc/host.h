@@ -64,6 +64,13 @@ struct eig_ctx {
     std::map<std::tuple<int, int, int, int, int>, int> tuned;
     int last_variant = -1;  // variant of the most recent stencil launch
     int64_t max_wave_solves = 0;  // 0: no limit (all solves of a wave per launch)
+    // time loops captured as HIP graphs and replayed when a wave repeats
+    // exactly (same descriptor blob at the same device address, same variants)
+    bool graphs = true;
+    hipStream_t capture_stream = nullptr;  // capture only; never runs work
+    std::map<std::tuple<uint64_t, uintptr_t, size_t>, hipGraphExec_t> graph_cache;
+    std::vector<std::tuple<uint64_t, uintptr_t, size_t>> graph_order;
+    int64_t graph_captures = 0, graph_replays = 0;
 };
 
 namespace {

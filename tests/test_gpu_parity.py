@@ -437,6 +437,49 @@ def test_three_step_family_with_mixed_lengths_matches_one_step():
     assert np.max(np.abs(outs[0][2])) > 0
 
 
+def test_graph_replays_match_direct_launches():
+    # the time loop captured once and replayed: every replay, with eager work
+    # and synchronisations in between, equals the direct-launch result
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context
+    from paper_1502_07873_amd.query import grid_tuple
+    wl = synthetic.config("c1", nsample=4)[0]
+    _say("graph capture and replays")
+    g = grid_tuple(wl.grid)
+    dm = _dev_medium(wl.medium)
+    S = len(wl.theta)
+
+    # the same destinations every time: they are part of the replayed launches
+    tr = [torch.empty((wl.grid.nsteps + 1, len(wl.receivers), 2), dtype=torch.float32,
+                      device="cuda") for _ in range(S)]
+
+    def run(c):
+        for t in tr:
+            t.fill_(-1.0)
+        c.forward_solve_batch([g] * S, [dm] * S, wl.theta, [wl.receivers] * S, tr)
+        return tr
+
+    with Context(0, 2 << 30) as c:
+        c.set_option("graphs", 0)
+        c.set_option("autotune", 0)
+        ref = [t.cpu().numpy() for t in run(c)]
+    with Context(0, 2 << 30) as c:
+        c.set_option("autotune", 0)
+        outs = []
+        for rep in range(4):
+            run(c)
+            junk = torch.randn(1 << 20, device="cuda")   # eager work between replays
+            junk.mul_(2.0).sum()
+            torch.cuda.synchronize()
+            outs.append([t.cpu().numpy() for t in tr])
+        assert c.get_option("graph_captures") == 1
+        assert c.get_option("graph_replays") == 3
+    for o in outs:
+        for a, b in zip(o, ref):
+            assert np.array_equal(a, b)
+
+
 def test_server_alone_equals_mix_and_matches_jacobian_path(ctx):
     from paper_1502_07873_amd import eigseis, make_prior
     from paper_1502_07873_amd.query import grid_tuple, run_query
