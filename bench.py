@@ -34,9 +34,10 @@ ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_layered_c2_traffic.json")
 
 
-def _measured_traffic(samples):
-    """HBM bytes per stencil launch from the committed rocprofv3 counter
-    record, only if it was taken on this exact kernel source and workload."""
+def _measured_traffic(solves_per_launch, wave_cache_bytes):
+    """Bytes per stencil launch past the L2 caches (served by the last-level
+    cache or HBM) from the committed rocprofv3 counter record, only if it was
+    taken on this exact kernel source, workload and wave size."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_RECORD))
@@ -44,7 +45,9 @@ def _measured_traffic(samples):
         return None
     src = os.path.join(ROOT, "paper_1502_07873_amd", "csrc", "stencil.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if sha != rec.get("kernel_source_sha256") or samples != 256:
+    if (sha != rec.get("kernel_source_sha256")
+            or rec.get("solves_per_launch") != solves_per_launch
+            or rec.get("wave_cache_bytes") != wave_cache_bytes):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -664,7 +667,7 @@ def main():
     total_ms = ev[0].elapsed_time(ev[-1])
     st = jac_stats
     variant = ctx.get_option("last_variant")
-    steps_per_launch = 2 if variant in (9, 10, 11, 12) else 1
+    steps_per_launch = 3 if variant in (15, 16) else (2 if 9 <= variant <= 14 else 1)
     S = len(wl.theta)
     value = S * args.steps / (total_ms / 1e3)
     avg_launch_ms = st["ms"] / max(st["launches"], 1)
@@ -673,7 +676,10 @@ def main():
     dkl = out["dkl"].cpu().numpy()
     eig = float(out["eig"].cpu()[0])
     copy_gbs = _copy_rate()
-    traffic = _measured_traffic(S)
+    llc_copy_gbs = _copy_rate(96 << 20, reps=200)
+    solves_per_launch = st["updates"] / max(st["launches"], 1) / (
+        wl.grid.nx * wl.grid.nz * steps_per_launch)
+    traffic = _measured_traffic(round(solves_per_launch), ctx.get_option("wave_cache_bytes"))
     status_ok = int(out["status"].abs().sum()) == 0 and int(out["chol_status"].abs().sum()) == 0
     line = {
         "metric": METRIC,
@@ -703,10 +709,14 @@ def main():
                     "achieved_at_kernel_floor_GBs":
                         achieved * (16 if steps_per_launch == 2 else 24) / 24,
                     "time_frac_of_step": st["ms"] / total_ms,
-                    "note": "launches of the 15*S-solve jacobian_fd wave; bytes_per_launch "
-                            "and roofline.achieved count 24 B per grid-point update (read u^m, "
-                            "u^{m-1}, write u^{m+1}); a two-steps-per-launch kernel needs only "
-                            "16 B per update (achieved_at_kernel_floor_GBs)"},
+                    "solves_per_launch": solves_per_launch,
+                    "note": "launches of the 15*S-solve jacobian_fd wave, run as chunks "
+                            "whose fields (4 buffers per solve) fit wave_cache_bytes, so "
+                            "they stay in the 256 MB last-level cache between launches; "
+                            "bytes_per_launch and roofline.achieved count 24 B per "
+                            "grid-point update (read u^m, u^{m-1}, write u^{m+1}); a "
+                            "two-steps-per-launch kernel needs only 16 B per update "
+                            "(achieved_at_kernel_floor_GBs)"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)),
                        "p99": float(np.percentile(lat, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -715,16 +725,42 @@ def main():
                      "traffic_rate_GBs": (traffic / (avg_launch_ms * 1e-3) / 1e9
                                           if traffic else None),
                      "copy_GBs_measured": copy_gbs,
-                     "note": "achieved counts 24 B per update (algorithmic); traffic is "
-                             "the counters' HBM bytes per launch; copy_GBs_measured is a "
-                             "plain 4 GiB device copy (read + write) timed in this run, the "
-                             "practical ceiling for mixed read/write streams"},
+                     "llc_copy_GBs_measured": llc_copy_gbs,
+                     "wave_cache_bytes": ctx.get_option("wave_cache_bytes"),
+                     "note": "achieved counts 24 B per update (algorithmic) over the "
+                             "launch time; the fields of a launch live in the last-level "
+                             "cache, so achieved can approach or pass the HBM peak. "
+                             "traffic: the counters' bytes per launch past L2 (last-level "
+                             "cache or HBM). copy_GBs_measured: a 4 GiB device copy timed "
+                             "in this run (HBM); llc_copy_GBs_measured: a 96 MiB copy that "
+                             "stays in the last-level cache"},
         "wall_s": wall,
     }
     if args.headline_only:
         print(json.dumps(line), flush=True)
         ctx.close()
         return
+    # the same query as one unsplit wave: every launch streams all fields
+    # through HBM
+    print("[bench] unsplit wave (fields streamed through HBM)", flush=True)
+    ctx.set_option("wave_cache_bytes", 0)
+    one_step()
+    torch.cuda.synchronize()
+    ctx.stencil_stats(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ou = one_step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stu = ctx.stencil_stats(reset=True)
+    tu = e0.elapsed_time(e1) / 1e3
+    ctx.set_option("wave_cache_bytes", 192 << 20)
+    line["unsplit_wave"] = {
+        "value": S / tu, "unit": "sample-EIG evals/s",
+        "avg_launch_ms": stu["ms"] / max(stu["launches"], 1),
+        "achieved_GBs": stu["bytes"] / (stu["ms"] * 1e-3) / 1e9,
+        "speedup_of_chunked": value / (S / tu),
+        "dkl_match": bool(np.array_equal(ou["dkl"].cpu().numpy(), dkl))}
     # the plain GPU path: the same kernels, one solve per launch
     print("[bench] one-solve-per-launch GPU baseline (2 samples)", flush=True)
     ctx1 = Context(0, 8 << 30)

@@ -163,9 +163,16 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  *                      same device addresses) comes again; 0: direct launches.
  *                      get_option also reports "graph_captures" and
  *                      "graph_replays"
- *   "max_wave_solves"  0 (default): every solve of a wave advances in the same
- *                      launches; n > 0: at most n solves per launch (n = 1 is
- *                      the plain one-solve-at-a-time path)
+ *   "wave_cache_bytes" 201326592 (192 MiB, default): when the field buffers a
+ *                      wave keeps live between launches (four per solve for
+ *                      several steps per launch, else two) exceed this, the
+ *                      wave runs as consecutive chunks of about this many
+ *                      bytes, so that each chunk's fields stay in the
+ *                      device's 256 MB last-level cache; waves where fewer
+ *                      than four solves would fit are not split.  0: never
+ *                      split for the cache.  Results do not depend on it.
+ *   "max_wave_solves"  0 (default): no limit; n > 0: at most n solves per
+ *                      launch (n = 1 is the plain one-solve-at-a-time path)
  * EIG_EINVAL for an unknown name or value. */
 int eig_ctx_set_option(eig_ctx* ctx, const char* name, int64_t value);
 /* Reads an option back; "last_variant" gives the stencil variant of the most

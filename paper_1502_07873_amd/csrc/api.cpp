@@ -43,19 +43,67 @@ namespace {
 
 int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
               const std::vector<eig_grid>& grids, const std::vector<MediumKey>& media,
-              const std::vector<RecSet>& recsets, char* base, size_t cap, hipStream_t s);
+              const std::vector<RecSet>& recsets, char* base, size_t cap, hipStream_t s,
+              bool allow_graph);
 
-// All solves of a wave advance together; with max_wave_solves set, they run
-// in consecutive chunks of at most that many solves instead (the chunks
-// reuse the same workspace in stream order).
+// Field bytes one solve keeps live from launch to launch: four buffers when
+// a depth-only medium with rigid edges advances several steps per launch,
+// two otherwise.
+size_t live_field_bytes(const eig_ctx* c, const SolveSpec& sp, const eig_grid& g,
+                        const MediumKey& mk) {
+    const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
+    const bool one_step = g.bc == EIG_BC_ABSORBING || sp.rforce != nullptr;
+    int steps = (mk.kind == EIG_MEDIUM_LAYERED && !one_step) ? c->temporal_blocking : 1;
+    if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == mk.kind &&
+        !(one_step && kVariants[c->forced_variant].steps != 1))
+        steps = kVariants[c->forced_variant].steps;
+    return (steps >= 2 ? 4 : 2) * field;
+}
+
+// A wave's solves advance together, but not necessarily in one set of
+// launches.  When their live fields exceed wave_cache_bytes (sized to the
+// device's last-level cache), the wave runs as consecutive chunks of about
+// that many bytes each, so that every chunk's fields stay in that cache from
+// one launch to the next instead of streaming through HBM; the chunks reuse
+// the same workspace in stream order.  A chunk also holds at most
+// max_wave_solves solves when that is set.  Waves where fewer than four
+// solves would fit are not split for the cache.
 int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
              const std::vector<eig_grid>& grids, const std::vector<MediumKey>& media,
              const std::vector<RecSet>& recsets, char* base, size_t cap, hipStream_t s) {
-    const size_t per = c->max_wave_solves > 0 ? (size_t)c->max_wave_solves : solves.size();
-    for (size_t i0 = 0; i0 < solves.size(); i0 += per) {
-        std::vector<SolveSpec> part(solves.begin() + i0,
-                                    solves.begin() + std::min(solves.size(), i0 + per));
-        const int rc = run_chunk(c, part, grids, media, recsets, base, cap, s);
+    const size_t n = solves.size();
+    if (n == 0) return EIG_OK;
+    std::vector<size_t> live(n);
+    double total = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        live[i] = live_field_bytes(c, solves[i], grids[solves[i].grid], media[solves[i].medium]);
+        total += (double)live[i];
+    }
+    // chunk boundaries: cumulative live bytes cut into nch equal spans
+    std::vector<size_t> cut{0};
+    const double lim = (double)c->wave_cache_bytes;
+    if (lim > 0 && total > lim && 4.0 * total / (double)n <= lim) {
+        const size_t nch = (size_t)std::ceil(total / lim);
+        const double span = total / (double)nch;
+        double acc = 0.0;
+        for (size_t i = 0; i < n; ++i) {
+            if (i > cut.back() && acc + 0.5 * (double)live[i] > span * (double)cut.size())
+                cut.push_back(i);
+            acc += (double)live[i];
+        }
+    }
+    cut.push_back(n);
+    std::vector<std::pair<size_t, size_t>> parts;
+    const size_t per = c->max_wave_solves > 0 ? (size_t)c->max_wave_solves : n;
+    for (size_t k = 0; k + 1 < cut.size(); ++k)
+        for (size_t i0 = cut[k]; i0 < cut[k + 1]; i0 += per)
+            parts.push_back({i0, std::min(cut[k + 1], i0 + per)});
+    // captured time loops are cached eight at a time: a wave of more chunks
+    // could never replay them
+    const bool allow_graph = parts.size() <= 8;
+    for (const auto& pr : parts) {
+        std::vector<SolveSpec> part(solves.begin() + pr.first, solves.begin() + pr.second);
+        const int rc = run_chunk(c, part, grids, media, recsets, base, cap, s, allow_graph);
         if (rc) return rc;
     }
     return EIG_OK;
@@ -95,7 +143,7 @@ void stencil_candidates(const eig_ctx* c, int kind, bool one_step, std::vector<i
 int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
              const std::vector<eig_grid>& grids, const std::vector<MediumKey>& media,
              const std::vector<RecSet>& recsets, char* base, size_t cap,
-             hipStream_t s) {
+             hipStream_t s, bool allow_graph) {
     const int n = (int)solves.size();
     if (n == 0) return EIG_OK;
     Carve cv;
@@ -366,7 +414,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     // graph capture: only without an open tuning window (no events inside)
     bool any_tuning = false;
     for (const auto& tn : tune) any_tuning = any_tuning || tn.active;
-    const bool use_graph = c->graphs && !any_tuning && max_steps > 0;
+    const bool use_graph = c->graphs && allow_graph && !any_tuning && max_steps > 0;
     std::tuple<uint64_t, uintptr_t, size_t> gkey{0, 0, 0};
     hipGraphExec_t gexec = nullptr;
     bool capturing = false;
@@ -614,6 +662,9 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
         c->max_wave_solves = value;
     } else if (n == "graphs") {
         c->graphs = value != 0;
+    } else if (n == "wave_cache_bytes") {
+        if (value < 0) return set_error(EIG_EINVAL, "wave_cache_bytes < 0");
+        c->wave_cache_bytes = (size_t)value;
     } else {
         return set_error(EIG_EINVAL, "unknown option " + n);
     }
@@ -629,6 +680,7 @@ int eig_ctx_get_option(const eig_ctx* c, const char* name, int64_t* value) {
     else if (n == "temporal_blocking") *value = c->temporal_blocking;
     else if (n == "max_wave_solves") *value = c->max_wave_solves;
     else if (n == "graphs") *value = c->graphs;
+    else if (n == "wave_cache_bytes") *value = (int64_t)c->wave_cache_bytes;
     else if (n == "graph_captures") *value = c->graph_captures;
     else if (n == "graph_replays") *value = c->graph_replays;
     else if (n == "last_variant") *value = c->last_variant;

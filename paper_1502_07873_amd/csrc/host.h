@@ -64,6 +64,9 @@ struct eig_ctx {
     std::map<std::tuple<int, int, int, int, int>, int> tuned;
     int last_variant = -1;  // variant of the most recent stencil launch
     int64_t max_wave_solves = 0;  // 0: no limit (all solves of a wave per launch)
+    // live field bytes per wave chunk (0: no limit); 192 MiB leaves room in
+    // the device's 256 MB last-level cache for everything else a launch reads
+    size_t wave_cache_bytes = (size_t)192 << 20;
     // time loops captured as HIP graphs and replayed when a wave repeats
     // exactly (same descriptor blob at the same device address, same variants)
     bool graphs = true;

@@ -247,9 +247,20 @@ class Context:
         return arr
 
     @staticmethod
-    def _media(media):
+    def _media(media, grids):
+        """The library reads nz (layered) or nz*nx (nodal) float64 values from
+        each device array; shorter or non-contiguous arrays are refused here."""
+        import torch
+        if len(media) != len(grids):
+            raise EigError(EIG_EINVAL, "one medium per grid expected")
         arr = (Medium * len(media))()
-        for k, (kind, rho, lam, mu) in enumerate(media):
+        for k, ((kind, rho, lam, mu), g) in enumerate(zip(media, grids)):
+            need = g[1] if kind == MEDIUM_LAYERED else g[0] * g[1]
+            for a in (rho, lam, mu):
+                if (a is None or a.dtype != torch.float64 or not a.is_cuda
+                        or not a.is_contiguous() or a.numel() < need):
+                    raise EigError(EIG_EINVAL, f"medium {k}: expected contiguous float64 "
+                                               f"device arrays of at least {need} values")
             arr[k] = Medium(kind, _ptr(rho), _ptr(lam), _ptr(mu))
         return arr
 
@@ -274,7 +285,7 @@ class Context:
         dp = None if dev_param is None else np.ascontiguousarray(dev_param, dtype=np.int32)
         ds = None if dev_step is None else np.ascontiguousarray(dev_step, dtype=np.float64)
         _check(_lib.forward_solve_batch(
-            self._h, n, self._grids(grids), self._media(media), _np_ptr(th),
+            self._h, n, self._grids(grids), self._media(media, grids), _np_ptr(th),
             None if dp is None else _np_ptr(dp), None if ds is None else _np_ptr(ds),
             STF_KINDS[stf], recs, _ptr_array(traces), _stream(stream)))
         del keep
@@ -288,7 +299,7 @@ class Context:
         sg = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (n,)))
         recs, keep = self._receivers(receivers)
         _check(_lib.jacobian_fd(
-            self._h, n, self._grids(grids), self._media(media), _np_ptr(th),
+            self._h, n, self._grids(grids), self._media(media, grids), _np_ptr(th),
             float(rel_step), STF_KINDS[stf], recs, int(sigma_mode), _np_ptr(sg),
             1 if per_receiver else 0, _ptr_array(nominal), _ptr_array(J), _ptr(H1),
             _ptr(status), _stream(stream)))
@@ -302,7 +313,7 @@ class Context:
         sg = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (n,)))
         recs, keep = self._receivers(receivers)
         _check(_lib.jacobian_sensitivity(
-            self._h, n, self._grids(grids), self._media(media), _np_ptr(th),
+            self._h, n, self._grids(grids), self._media(media, grids), _np_ptr(th),
             STF_KINDS[stf], recs, int(sigma_mode), _np_ptr(sg), 1 if per_receiver else 0,
             _ptr_array(nominal), _ptr_array(J), _ptr(H1), _ptr(status), _stream(stream)))
         del keep
@@ -329,7 +340,7 @@ class Context:
         wa = np.ascontiguousarray(np.broadcast_to(np.asarray(w, dtype=np.float64), (n,)))
         out = np.zeros((n, NTHETA))
         recs, keep = self._receivers(receivers)
-        _check(_lib.theorem3_eig(self._h, n, self._grids(grids), self._media(media), _np_ptr(th),
+        _check(_lib.theorem3_eig(self._h, n, self._grids(grids), self._media(media, grids), _np_ptr(th),
                                  STF_KINDS[stf], recs, _ptr_array(noise), float(sigma),
                                  ctypes.byref(prior), _np_ptr(wa), int(iters), _np_ptr(out),
                                  _ptr(H1), _ptr(H2), _ptr(val), _ptr(eig), _ptr(status),
@@ -369,7 +380,7 @@ class Context:
                          stream=None) -> float:
         out = ctypes.c_double(0.0)
         th = np.ascontiguousarray(theta, dtype=np.float64)
-        _check(_lib.noise_sigma_peak(self._h, self._grids([grid]), self._media([medium]),
+        _check(_lib.noise_sigma_peak(self._h, self._grids([grid]), self._media([medium], [grid]),
                                      _np_ptr(th), STF_KINDS[stf], float(rel),
                                      ctypes.byref(out), _stream(stream)))
         return out.value
@@ -404,7 +415,7 @@ class Server:
         recs, keep = Context._receivers([receivers])
         qid = ctypes.c_int64()
         _check(_lib.eig_server_submit(
-            self._h, Context._grids([grid]), Context._media([medium]), n, _np_ptr(th),
+            self._h, Context._grids([grid]), Context._media([medium], [grid]), n, _np_ptr(th),
             float(rel_step), STF_KINDS[stf], recs, int(sigma_mode), float(sigma),
             ctypes.byref(prior), _np_ptr(wa), _ptr(H1), _ptr(dkl), _ptr(eig), _ptr(status),
             _ptr(chol_status), ctypes.byref(qid)))

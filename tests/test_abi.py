@@ -48,3 +48,16 @@ def test_sparse_grid_rejects_bad_arguments():
         p.sparse_grid_gl(0, 3)
     with pytest.raises(p.EigError):
         p.sparse_grid_gl(3, -1)
+
+
+def test_binding_refuses_media_it_cannot_pass_on():
+    # the library reads nz (layered) or nz*nx (nodal) float64 device values
+    # per medium array; the binding refuses anything else before a launch
+    torch = pytest.importorskip("torch")
+    from paper_1502_07873_amd import eigseis
+    g = (40, 30, 10.0, 1e-3, 10, 0)
+    short = torch.zeros(29, dtype=torch.float64)
+    with pytest.raises(eigseis.EigError):
+        eigseis.Context._media([(eigseis.MEDIUM_LAYERED, short, short, short)], [g])
+    with pytest.raises(eigseis.EigError):
+        eigseis.Context._media([(eigseis.MEDIUM_LAYERED,) + (short,) * 3] * 2, [g])

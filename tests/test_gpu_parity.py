@@ -480,6 +480,60 @@ def test_graph_replays_match_direct_launches():
             assert np.array_equal(a, b)
 
 
+def test_cache_sized_wave_chunks_match_one_wave():
+    # a wave whose live fields exceed wave_cache_bytes runs as consecutive
+    # chunks (more launches); every solve's traces are bitwise those of the
+    # unsplit wave.  Mixed grids, lengths, media kinds and edge conditions.
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context
+    from paper_1502_07873_amd.query import grid_tuple
+    rng = np.random.default_rng(41)
+    cases = []
+    medA = synthetic.random_layers_medium(rng, 141, 10.0, 3)
+    dtA = synthetic.cfl_dt(10.0, medA.vp_max())
+    for n in (400, 352, 400, 290, 401, 400, 333, 400, 398, 400):
+        cases.append((synthetic.Grid(300, 141, 10.0, dtA, n), medA))
+    medB = synthetic.random_layers_medium(rng, 70, 15.0, 2)
+    dtB = synthetic.cfl_dt(15.0, medB.vp_max())
+    for n in (260, 261, 199, 260, 260, 230):
+        cases.append((synthetic.Grid(90, 70, 15.0, dtB, n), medB))
+    medC = synthetic.random_layers_medium(rng, 80, 15.0, 2)
+    dtC = synthetic.cfl_dt(15.0, medC.vp_max())
+    for n in (240, 240, 211, 240):
+        cases.append((synthetic.Grid(120, 80, 15.0, dtC, n, bc="absorbing"), medC))
+    medN = synthetic.nodal_perturbed_medium(rng, 70, 90, 15.0)
+    dtN = synthetic.cfl_dt(15.0, medN.vp_max())
+    for n in (250, 250, 180, 250):
+        cases.append((synthetic.Grid(90, 70, 15.0, dtN, n), medN))
+    th = []
+    for g, _ in cases:
+        lo, hi = synthetic.prior_box(g)
+        th.append(synthetic.draw_uniform(rng, lo, hi, 1)[0])
+    th = np.stack(th)
+    recs = [synthetic.random_receivers(rng, g.nx, 9) for g, _ in cases]
+    dms = {id(m): _dev_medium(m) for _, m in cases}
+    _say("cache-sized wave chunks vs one wave (24 mixed solves)")
+    outs, launches = [], []
+    for lim in (0, 4 << 20):
+        with Context(0, 2 << 30) as c:
+            c.set_option("wave_cache_bytes", lim)
+            assert c.get_option("wave_cache_bytes") == lim
+            tr = [torch.empty((g.nsteps + 1, len(r), 2), dtype=torch.float32, device="cuda")
+                  for (g, _), r in zip(cases, recs)]
+            c.stencil_stats(reset=True)
+            c.forward_solve_batch([grid_tuple(g) for g, _ in cases],
+                                  [dms[id(m)] for _, m in cases], th, recs, tr)
+            torch.cuda.synchronize()
+            launches.append(c.stencil_stats(reset=True)["launches"])
+            outs.append([t.cpu().numpy() for t in tr])
+    assert launches[1] > launches[0]
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+        assert np.isfinite(a).all()
+    assert max(np.max(np.abs(a)) for a in outs[0]) > 0
+
+
 def test_server_alone_equals_mix_and_matches_jacobian_path(ctx):
     from paper_1502_07873_amd import eigseis, make_prior
     from paper_1502_07873_amd.query import grid_tuple, run_query
