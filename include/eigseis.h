@@ -168,9 +168,10 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  *                      several steps per launch, else two) exceed this, the
  *                      wave runs as consecutive chunks of about this many
  *                      bytes, so that each chunk's fields stay in the
- *                      device's 256 MB last-level cache; waves where fewer
- *                      than four solves would fit are not split.  0: never
- *                      split for the cache.  Results do not depend on it.
+ *                      device's 256 MB last-level cache (solves grouped by
+ *                      grid and length); waves where fewer than 16 solves
+ *                      would fit are not split.  0: never split for the
+ *                      cache.  Results do not depend on it.
  *   "max_wave_solves"  0 (default): no limit; n > 0: at most n solves per
  *                      launch (n = 1 is the plain one-solve-at-a-time path)
  * EIG_EINVAL for an unknown name or value. */

@@ -65,44 +65,59 @@ size_t live_field_bytes(const eig_ctx* c, const SolveSpec& sp, const eig_grid& g
 // device's last-level cache), the wave runs as consecutive chunks of about
 // that many bytes each, so that every chunk's fields stay in that cache from
 // one launch to the next instead of streaming through HBM; the chunks reuse
-// the same workspace in stream order.  A chunk also holds at most
-// max_wave_solves solves when that is set.  Waves where fewer than four
-// solves would fit are not split for the cache.
+// the same workspace in stream order.  For the split the solves are ordered
+// by kind, grid and length, so that each chunk is one or two uniform groups
+// of launches.  Waves where fewer than kMinCacheChunk solves would fit are
+// not split for the cache (too few tiles per launch to pay).  A chunk also
+// holds at most max_wave_solves solves when that is set.
+constexpr double kMinCacheChunk = 16.0;
+
 int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
              const std::vector<eig_grid>& grids, const std::vector<MediumKey>& media,
              const std::vector<RecSet>& recsets, char* base, size_t cap, hipStream_t s) {
     const size_t n = solves.size();
     if (n == 0) return EIG_OK;
-    std::vector<size_t> live(n);
+    std::vector<size_t> live(n), order(n);
     double total = 0.0;
     for (size_t i = 0; i < n; ++i) {
         live[i] = live_field_bytes(c, solves[i], grids[solves[i].grid], media[solves[i].medium]);
         total += (double)live[i];
+        order[i] = i;
     }
     // chunk boundaries: cumulative live bytes cut into nch equal spans
     std::vector<size_t> cut{0};
     const double lim = (double)c->wave_cache_bytes;
-    if (lim > 0 && total > lim && 4.0 * total / (double)n <= lim) {
+    if (lim > 0 && total > lim && kMinCacheChunk * total / (double)n <= lim) {
+        auto key = [&](size_t i) {
+            const SolveSpec& sp = solves[i];
+            const eig_grid& g = grids[sp.grid];
+            return std::make_tuple(media[sp.medium].kind, g.bc, sp.rforce != nullptr, g.nx,
+                                   g.nz, -g.nsteps, sp.medium);
+        };
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t b) { return key(a) < key(b); });
         const size_t nch = (size_t)std::ceil(total / lim);
         const double span = total / (double)nch;
         double acc = 0.0;
-        for (size_t i = 0; i < n; ++i) {
-            if (i > cut.back() && acc + 0.5 * (double)live[i] > span * (double)cut.size())
-                cut.push_back(i);
-            acc += (double)live[i];
+        for (size_t q = 0; q < n; ++q) {
+            const double b = (double)live[order[q]];
+            if (q > cut.back() && acc + 0.5 * b > span * (double)cut.size()) cut.push_back(q);
+            acc += b;
         }
     }
     cut.push_back(n);
     std::vector<std::pair<size_t, size_t>> parts;
     const size_t per = c->max_wave_solves > 0 ? (size_t)c->max_wave_solves : n;
     for (size_t k = 0; k + 1 < cut.size(); ++k)
-        for (size_t i0 = cut[k]; i0 < cut[k + 1]; i0 += per)
-            parts.push_back({i0, std::min(cut[k + 1], i0 + per)});
+        for (size_t q0 = cut[k]; q0 < cut[k + 1]; q0 += per)
+            parts.push_back({q0, std::min(cut[k + 1], q0 + per)});
     // captured time loops are cached eight at a time: a wave of more chunks
     // could never replay them
     const bool allow_graph = parts.size() <= 8;
+    std::vector<SolveSpec> part;
     for (const auto& pr : parts) {
-        std::vector<SolveSpec> part(solves.begin() + pr.first, solves.begin() + pr.second);
+        part.clear();
+        for (size_t q = pr.first; q < pr.second; ++q) part.push_back(solves[order[q]]);
         const int rc = run_chunk(c, part, grids, media, recsets, base, cap, s, allow_graph);
         if (rc) return rc;
     }

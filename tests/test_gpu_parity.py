@@ -496,15 +496,15 @@ def test_cache_sized_wave_chunks_match_one_wave():
         cases.append((synthetic.Grid(300, 141, 10.0, dtA, n), medA))
     medB = synthetic.random_layers_medium(rng, 70, 15.0, 2)
     dtB = synthetic.cfl_dt(15.0, medB.vp_max())
-    for n in (260, 261, 199, 260, 260, 230):
+    for n in (260, 261, 199, 260, 260, 230, 260, 260, 261, 199, 260, 260, 230, 260):
         cases.append((synthetic.Grid(90, 70, 15.0, dtB, n), medB))
     medC = synthetic.random_layers_medium(rng, 80, 15.0, 2)
     dtC = synthetic.cfl_dt(15.0, medC.vp_max())
-    for n in (240, 240, 211, 240):
+    for n in (240, 240, 211, 240, 240, 240, 211, 240):
         cases.append((synthetic.Grid(120, 80, 15.0, dtC, n, bc="absorbing"), medC))
     medN = synthetic.nodal_perturbed_medium(rng, 70, 90, 15.0)
     dtN = synthetic.cfl_dt(15.0, medN.vp_max())
-    for n in (250, 250, 180, 250):
+    for n in (250, 250, 180, 250, 250, 250, 180, 250):
         cases.append((synthetic.Grid(90, 70, 15.0, dtN, n), medN))
     th = []
     for g, _ in cases:
@@ -513,9 +513,11 @@ def test_cache_sized_wave_chunks_match_one_wave():
     th = np.stack(th)
     recs = [synthetic.random_receivers(rng, g.nx, 9) for g, _ in cases]
     dms = {id(m): _dev_medium(m) for _, m in cases}
-    _say("cache-sized wave chunks vs one wave (24 mixed solves)")
+    _say("cache-sized wave chunks vs one wave (40 mixed solves)")
     outs, launches = [], []
-    for lim in (0, 4 << 20):
+    # ~24 MB of live fields, mean 0.6 MB: a 10 MiB limit fits 16 solves,
+    # giving three chunks (solves regrouped by kind, grid and length)
+    for lim in (0, 10 << 20):
         with Context(0, 2 << 30) as c:
             c.set_option("wave_cache_bytes", lim)
             assert c.get_option("wave_cache_bytes") == lim
