@@ -1,0 +1,73 @@
+"""Parity at the full size of the c2 Monte Carlo query (256 prior samples x
+15 solves of 512x512 x 2000 steps), through the C ABI in the launch
+configuration the benchmark times: the 3840-solve wave runs as 24-solve
+chunks whose fields stay in the last-level cache.  One sample, whose 15
+solves straddle a chunk boundary, is recomputed by the oracle; every sample
+is checked for the properties that hold at any size.  Tolerances: traces
+relative L2 <= 1e-5, Jacobian columns <= 1e-3, D^_KL <= 1e-3 nats.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import pipeline as opipe
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TRACE_TOL = 1e-5
+JAC_TOL = 1e-3
+NAT_TOL = 1e-3
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+
+
+def test_c2_full_query_sampled_against_oracle():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context
+    from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
+    wl = synthetic.config("c2")[0]
+    S = len(wl.theta)
+    assert S == 256
+    g = grid_tuple(wl.grid)
+    med = device_medium(wl.medium.kind, wl.medium.rho, wl.medium.lam, wl.medium.mu)
+    _say("c2 full query: 3840 solves of 512x512x2000 in 24-solve chunks")
+    with Context(0, 200 << 30) as ctx:
+        sig = ctx.noise_sigma_peak(g, med, 0.5 * (wl.lo + wl.hi), wl.noise_rel)
+        ctx.stencil_stats(reset=True)
+        out = run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, wl.theta, wl.weights,
+                        sigma=sig, keep_nominal=True, keep_J=True)
+        torch.cuda.synchronize()
+        st = ctx.stencil_stats(reset=True)
+        steps = 3 if ctx.get_option("last_variant") in (15, 16) else 2
+        solves_per_launch = st["updates"] / st["launches"] / (512 * 512 * steps)
+        assert solves_per_launch == pytest.approx(24.0)
+        k = 137   # solves 2055..2069: the chunk boundary at solve 2064 cuts this sample
+        gpu = {"nominal": out["nominal"][k].cpu().numpy().astype(np.float64),
+               "J": out["J"][k].cpu().numpy(), "H1": out["H1"].cpu().numpy(),
+               "dkl": out["dkl"].cpu().numpy(), "eig": float(out["eig"].cpu()[0]),
+               "status": out["status"].cpu().numpy(),
+               "chol": out["chol_status"].cpu().numpy()}
+        del out
+    # properties of every sample
+    assert (gpu["status"] == 0).all() and (gpu["chol"] == 0).all()
+    assert np.isfinite(gpu["dkl"]).all()
+    H = gpu["H1"]
+    assert np.allclose(H, np.transpose(H, (0, 2, 1)), rtol=1e-12, atol=0)
+    assert (np.diagonal(H, axis1=1, axis2=2) > 0).all()
+    assert gpu["eig"] == pytest.approx(float(np.dot(wl.weights, gpu["dkl"])), rel=1e-12)
+    # the sampled sample against the oracle (same sigma)
+    _say(f"oracle: sample {k} of the c2 query (15 solves)")
+    ref = opipe.query(wl, theta=wl.theta[k:k + 1], weights=[1.0], sigma=sig, keep_J=True)
+    tr = float(np.linalg.norm(gpu["nominal"] - ref["nominal"][0]) /
+               np.linalg.norm(ref["nominal"][0]))
+    assert tr <= TRACE_TOL
+    Jr, Jg = ref["J"][0], gpu["J"]
+    for j in range(7):
+        assert np.linalg.norm(Jg[..., j] - Jr[..., j]) <= JAC_TOL * np.linalg.norm(Jr[..., j])
+    assert abs(float(gpu["dkl"][k]) - float(ref["dkl"][0])) <= NAT_TOL
+    d = np.sqrt(np.diag(ref["H1"][0]))
+    assert np.max(np.abs((H[k] - ref["H1"][0]) / np.outer(d, d))) <= 1e-3
