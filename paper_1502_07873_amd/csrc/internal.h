@@ -125,7 +125,7 @@ struct StencilVariant {
     int cols, rows, medium_kind;
     int steps;  // leapfrog steps per launch (2, 3: four field buffers per solve)
 };
-constexpr int kNumVariants = 17;
+constexpr int kNumVariants = 19;
 extern const StencilVariant kVariants[kNumVariants];
 // tiles: (solve index, strip << 16 | chunk) per wavefront
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,

@@ -1185,12 +1185,80 @@ stencil_layered_tb3(const SolveDesc* __restrict__ descs, const int2* __restrict_
 }
 
 // Nodal media: coef = three planes (lambda, mu, s = dt^2/(rho h^2)).
+//
+// Operands of the nodal operator at one node (i, k): the node's own values,
+// its x-neighbours on row k, rows k+1 and k-1 (centre values and the
+// x-difference w_{i+1} - w_{i-1}), and the x-neighbours' products
+// p = lambda Dz v and q = mu Dz u (Dz over rows k+1, k-1, or k+1, k on the
+// free surface).  Every nodal variant hands nodal_accel / nodal_new the same
+// operand values, so all of them produce bitwise-identical fields.
+struct NodalView {
+    float u, v, lam, mu;                   // node (i, k)
+    float uL, uR, vL, vR, aL, aR, mL, mR;  // x-neighbours on row k (a = lambda + 2 mu)
+    float un, vn, lamn, mun, dxun, dxvn;   // row k+1
+    float um, vm, lamm, mum, dxum, dxvm;   // row k-1 (unused on the free surface)
+    float pR, pL, qR, qL;                  // the x-neighbours' p and q
+};
+
+// Acceleration terms at one node, before the scaling by s.
+__device__ __forceinline__ float2 nodal_accel(const NodalView& n, bool top) {
+    const float ac = n.lam + 2.f * n.mu;
+    const float an = n.lamn + 2.f * n.mun;
+    float au = 0.5f * ((ac + n.aR) * (n.uR - n.u) - (n.aL + ac) * (n.u - n.uL));
+    float av = 0.5f * ((n.mu + n.mR) * (n.vR - n.v) - (n.mL + n.mu) * (n.v - n.vL));
+    if (top) {
+        const float dxu_c = n.uR - n.uL, dxv_c = n.vR - n.vL;
+        au += (n.mu + n.mun) * (n.un - n.u);
+        av += (ac + an) * (n.vn - n.v);
+        // 1/2 [lam_{i+1,0} (v_{i+1,1}-v_{i+1,0}) - lam_{i-1,0} (...)]
+        au += 0.5f * (n.pR - n.pL) + 0.5f * (n.mu * dxv_c + n.mun * n.dxvn);
+        av += 0.5f * (n.lam * dxu_c + n.lamn * n.dxun) + 0.5f * (n.qR - n.qL);
+    } else {
+        const float am = n.lamm + 2.f * n.mum;
+        au += 0.5f * ((n.mu + n.mun) * (n.un - n.u) - (n.mum + n.mu) * (n.u - n.um));
+        av += 0.5f * ((ac + an) * (n.vn - n.v) - (am + ac) * (n.v - n.vm));
+        // 1/4 [lam_{i+1,k} Dz v_{i+1} - lam_{i-1,k} Dz v_{i-1}], Dz w = w_{k+1} - w_{k-1}
+        au += 0.25f * (n.pR - n.pL) + 0.25f * (n.mun * n.dxvn - n.mum * n.dxvm);
+        av += 0.25f * (n.lamn * n.dxun - n.lamm * n.dxum) + 0.25f * (n.qR - n.qL);
+    }
+    return make_float2(au, av);
+}
+
+// u^{m+1} from the acceleration terms, s, u^m, u^{m-1} and the forcing:
+// inj 1 adds a receiver force density (w0, w1) (dual solves), inj 2 the
+// source window weights (w0, w1) times the series value; dt^2/rho f = s h^2 f.
+__device__ __forceinline__ float2 nodal_new(float2 acc, float sc, float u, float v, float upu,
+                                           float upv, int inj, float h2, float sval,
+                                           float w0, float w1) {
+    float au = acc.x * sc, av = acc.y * sc;
+    if (inj == 1) {
+        au += sc * h2 * w0;
+        av += sc * h2 * w1;
+    } else if (inj == 2) {
+        const float f = sc * h2 * sval;
+        au += f * w0;
+        av += f * w1;
+    }
+    float2 nw;
+    nw.x = u + ((u - upu) + au);
+    nw.y = v + ((v - upv) + av);
+    return nw;
+}
+
+// An opaque copy: the compiler may not fuse the product that made x into a
+// later addition, so x enters every use rounded, as it does after a DPP move.
+__device__ __forceinline__ float pinned(float x) {
+    __asm__ volatile("" : "+v"(x));
+    return x;
+}
+
 struct RowN {
     float u, v, hu, hv;   // centre and halo-column values of u^m
     float lam, mu;        // centre nodal coefficients
     float hlam, hmu;      // halo-column coefficients
 };
 
+// Variant 6: one node per lane (64 columns per wave), 32 rows per wave.
 __global__ void __launch_bounds__(256)
 stencil_nodal(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
               int ntiles, int step) {
@@ -1263,65 +1331,303 @@ stencil_nodal(const SolveDesc* __restrict__ descs, const int2* __restrict__ tile
             upn = ld2(P, (size_t)(k + 1) * pitch + i);
             scn = ld1(SC, (size_t)(k + 1) * pitch + i);
         }
-        // x-direction neighbours of row k
-        const float uL = from_left(rc.u, rc.hu), uR = from_right(rc.u, rc.hu);
-        const float vL = from_left(rc.v, rc.hv), vR = from_right(rc.v, rc.hv);
+        NodalView n;
+        n.u = rc.u;
+        n.v = rc.v;
+        n.lam = rc.lam;
+        n.mu = rc.mu;
+        n.uL = from_left(rc.u, rc.hu);
+        n.uR = from_right(rc.u, rc.hu);
+        n.vL = from_left(rc.v, rc.hv);
+        n.vR = from_right(rc.v, rc.hv);
         const float ac = rc.lam + 2.f * rc.mu;
         const float ah = rc.hlam + 2.f * rc.hmu;
-        const float aL = from_left(ac, ah), aR = from_right(ac, ah);
-        const float mL = from_left(rc.mu, rc.hmu), mR = from_right(rc.mu, rc.hmu);
-        float au = 0.5f * ((ac + aR) * (uR - rc.u) - (aL + ac) * (rc.u - uL));
-        float av = 0.5f * ((rc.mu + mR) * (vR - rc.v) - (mL + rc.mu) * (rc.v - vL));
-        // Dx of rows k+1 (and k-1 or k on the top row)
-        const float dxu_n = from_right(rn.u, rn.hu) - from_left(rn.u, rn.hu);
-        const float dxv_n = from_right(rn.v, rn.hv) - from_left(rn.v, rn.hv);
-        const float an = rn.lam + 2.f * rn.mu;
-        if (k == 0) {
-            const float dxu_c = uR - uL, dxv_c = vR - vL;
-            au += (rc.mu + rn.mu) * (rn.u - rc.u);
-            av += (ac + an) * (rn.v - rc.v);
-            // 1/2 [lam_{i+1,0} (v_{i+1,1}-v_{i+1,0}) - lam_{i-1,0} (...)]
-            const float p = rc.lam * (rn.v - rc.v), ph = rc.hlam * (rn.hv - rc.hv);
-            const float q = rc.mu * (rn.u - rc.u), qh = rc.hmu * (rn.hu - rc.hu);
-            au += 0.5f * (from_right(p, ph) - from_left(p, ph))
-                + 0.5f * (rc.mu * dxv_c + rn.mu * dxv_n);
-            av += 0.5f * (rc.lam * dxu_c + rn.lam * dxu_n)
-                + 0.5f * (from_right(q, qh) - from_left(q, qh));
+        n.aL = from_left(ac, ah);
+        n.aR = from_right(ac, ah);
+        n.mL = from_left(rc.mu, rc.hmu);
+        n.mR = from_right(rc.mu, rc.hmu);
+        n.un = rn.u;
+        n.vn = rn.v;
+        n.lamn = rn.lam;
+        n.mun = rn.mu;
+        n.dxun = from_right(rn.u, rn.hu) - from_left(rn.u, rn.hu);
+        n.dxvn = from_right(rn.v, rn.hv) - from_left(rn.v, rn.hv);
+        const bool top = k == 0;
+        float p, ph, q, qh;
+        if (top) {
+            n.um = n.vm = n.lamm = n.mum = n.dxum = n.dxvm = 0.f;
+            p = rc.lam * (rn.v - rc.v);
+            ph = rc.hlam * (rn.hv - rc.hv);
+            q = rc.mu * (rn.u - rc.u);
+            qh = rc.hmu * (rn.hu - rc.hu);
         } else {
-            const float am = rm.lam + 2.f * rm.mu;
-            au += 0.5f * ((rc.mu + rn.mu) * (rn.u - rc.u) - (rm.mu + rc.mu) * (rc.u - rm.u));
-            av += 0.5f * ((ac + an) * (rn.v - rc.v) - (am + ac) * (rc.v - rm.v));
-            const float dxu_m = from_right(rm.u, rm.hu) - from_left(rm.u, rm.hu);
-            const float dxv_m = from_right(rm.v, rm.hv) - from_left(rm.v, rm.hv);
-            // 1/4 [lam_{i+1,k} Dz v_{i+1} - lam_{i-1,k} Dz v_{i-1}], Dz w = w_{k+1} - w_{k-1}
-            const float p = rc.lam * (rn.v - rm.v), ph = rc.hlam * (rn.hv - rm.hv);
-            const float q = rc.mu * (rn.u - rm.u), qh = rc.hmu * (rn.hu - rm.hu);
-            au += 0.25f * (from_right(p, ph) - from_left(p, ph))
-                + 0.25f * (rn.mu * dxv_n - rm.mu * dxv_m);
-            av += 0.25f * (rn.lam * dxu_n - rm.lam * dxu_m)
-                + 0.25f * (from_right(q, qh) - from_left(q, qh));
+            n.um = rm.u;
+            n.vm = rm.v;
+            n.lamm = rm.lam;
+            n.mum = rm.mu;
+            n.dxum = from_right(rm.u, rm.hu) - from_left(rm.u, rm.hu);
+            n.dxvm = from_right(rm.v, rm.hv) - from_left(rm.v, rm.hv);
+            p = rc.lam * (rn.v - rm.v);
+            ph = rc.hlam * (rn.hv - rm.hv);
+            q = rc.mu * (rn.u - rm.u);
+            qh = rc.hmu * (rn.hu - rm.hu);
         }
-        au *= sc;
-        av *= sc;
+        n.pR = from_right(p, ph);
+        n.pL = from_left(p, ph);
+        n.qR = from_right(q, qh);
+        n.qL = from_left(q, qh);
+        const float2 acc = nodal_accel(n, top);
         const int dk = k - sk0;
         const bool in_win = src_lane && dk >= 0 && dk < kSrcW;
+        int inj = 0;
+        float w0 = 0.f, w1 = 0.f;
         if (rfz && k == 0 && rec >= 0) {  // dual solve: receiver injection
             const float2 rf = ld2(rfz, (size_t)m * nrec + rec);
-            au += sc * h2 * rf.x;
-            av += sc * h2 * rf.y;
+            inj = 1;
+            w0 = rf.x;
+            w1 = rf.y;
         } else if (in_win) {
-            // dt^2/rho f = s h^2 f
-            const float f = sc * h2 * sval;
-            au += f * ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
-            av += f * ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
+            inj = 2;
+            w0 = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
+            w1 = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
         }
-        float2 nw;
-        nw.x = rc.u + ((rc.u - up.x) + au);
-        nw.y = rc.v + ((rc.v - up.y) + av);
+        const float2 nw = nodal_new(acc, sc, rc.u, rc.v, up.x, up.y, inj, h2, sval, w0, w1);
         if (upd) {
             st2(P, (size_t)k * pitch + i, nw);
             if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
             if (wrec && in_win) st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
+        }
+        rm = rc;
+        rc = rn;
+        rn = rnn;
+        up = upn;
+        sc = scn;
+    }
+}
+
+// Nodal media, two nodes per lane (128 columns per wave) with 16- and 8-byte
+// loads, R rows per wave.  Lane l owns columns x0+2l (A) and x0+2l+1 (B);
+// each x-neighbour quantity needs one cross-lane move per node pair instead
+// of one per node, and lanes 0 / 63 load the halo column.
+struct RawN2 {
+    float4 c;                     // (u, v) of A and B
+    float lamA, lamB, muA, muB;   // their coefficients
+    float hu, hv, hlam, hmu;      // halo column (lanes 0 / 63), else 0
+};
+
+__device__ __forceinline__ float2 ld2f(const float* p, size_t i) {  // i even
+    const fv2 v = *(const GAS fv2*)((const GAS float*)p + i);
+    return make_float2(v.x, v.y);
+}
+
+__device__ __forceinline__ RawN2 load_rawn2(const float2* Q, const float* LAM,
+                                            const float* MU, size_t o, int i0, int hc,
+                                            bool hl) {
+    RawN2 r;
+    r.c = ld4(Q, o + i0);
+    const float2 l = ld2f(LAM, o + i0), mu = ld2f(MU, o + i0);
+    r.lamA = l.x;
+    r.lamB = l.y;
+    r.muA = mu.x;
+    r.muB = mu.y;
+    r.hu = r.hv = r.hlam = r.hmu = 0.f;
+    if (hl) {
+        const float2 h = ld2(Q, o + hc);
+        r.hu = h.x;
+        r.hv = h.y;
+        r.hlam = ld1(LAM, o + hc);
+        r.hmu = ld1(MU, o + hc);
+    }
+    return r;
+}
+
+template <int R>
+__global__ void __launch_bounds__(256)
+stencil_nodal_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
+                 int ntiles, int step) {
+    TileInfo t;
+    if (!decode_tile(descs, tiles, ntiles, step, 128, R, t)) return;
+    const SolveDesc* d = t.d;
+    const int lane = threadIdx.x & 63;
+    const int m = t.m, x0 = t.x0, kb = t.kb, ke = t.ke;
+    const int nx = d->nx, nz = d->nz, pitch = d->pitch;
+    const int i0 = x0 + 2 * lane;
+    const float2* Q = (m & 1) ? d->buf1 : d->buf0;
+    float2* P = (m & 1) ? d->buf0 : d->buf1;
+    const size_t plane = (size_t)nz * pitch;
+    const float* LAM = d->coef;
+    const float* MU = LAM + plane;
+    const float* SC = LAM + 2 * plane;
+    const bool upd0 = (i0 >= 1) && (i0 <= nx - 2);
+    const bool upd1 = (i0 + 1 <= nx - 2);
+    const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + 128 < nx);
+    const int hc = (lane == 0) ? x0 - 1 : x0 + 128;
+    const int si0 = d->src_i0, sk0 = d->src_k0;
+    const bool src_cols = (si0 < x0 + 128) && (si0 + kSrcW > x0);
+    const int di0 = i0 - si0, di1 = di0 + 1;
+    const bool s0 = src_cols && di0 >= 0 && di0 < kSrcW;
+    const bool s1 = src_cols && di1 >= 0 && di1 < kSrcW;
+    const float sval = src_cols ? ld1(d->srcs, m) : 0.0f;
+    const float* srcw = d->srcw;
+    float2* traces = d->traces;
+    const int nrec = d->nrec;
+    const float h2 = d->h2;
+    int rec0 = -1, rec1 = -1;
+    if (kb == 0) {
+        rec0 = ldi(d->recmap, i0);
+        rec1 = ldi(d->recmap, i0 + 1);
+    }
+    const float2* rfz = d->rforce;
+    float2* wrec = d->wrec;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const RawN2 zr = RawN2{z4, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+    RawN2 rm = zr, rc, rn;
+    if (kb > 0) rm = load_rawn2(Q, LAM, MU, (size_t)(kb - 1) * pitch, i0, hc, hl);
+    rc = load_rawn2(Q, LAM, MU, (size_t)kb * pitch, i0, hc, hl);
+    rn = load_rawn2(Q, LAM, MU, (size_t)(kb + 1) * pitch, i0, hc, hl);
+    float4 up = ld4(P, (size_t)kb * pitch + i0);
+    float2 sc = ld2f(SC, (size_t)kb * pitch + i0);
+
+    for (int k = kb; k < ke; ++k) {
+        RawN2 rnn = zr;
+        float4 upn = z4;
+        float2 scn = make_float2(0.f, 0.f);
+        if (k + 2 <= nz - 1) rnn = load_rawn2(Q, LAM, MU, (size_t)(k + 2) * pitch, i0, hc, hl);
+        if (k + 1 < ke) {
+            upn = ld4(P, (size_t)(k + 1) * pitch + i0);
+            scn = ld2f(SC, (size_t)(k + 1) * pitch + i0);
+        }
+        NodalView A, B;
+        A.u = rc.c.x;
+        A.v = rc.c.y;
+        A.lam = rc.lamA;
+        A.mu = rc.muA;
+        B.u = rc.c.z;
+        B.v = rc.c.w;
+        B.lam = rc.lamB;
+        B.mu = rc.muB;
+        // the in-lane neighbour values are pinned: A's right flux and B's left
+        // flux are then separate products with one use each, as in the
+        // one-node kernel, so the compiler fuses them into the same FMAs
+        A.uL = from_left(rc.c.z, rc.hu);
+        A.uR = pinned(rc.c.z);
+        A.vL = from_left(rc.c.w, rc.hv);
+        A.vR = pinned(rc.c.w);
+        B.uL = pinned(rc.c.x);
+        B.uR = from_right(rc.c.x, rc.hu);
+        B.vL = pinned(rc.c.y);
+        B.vR = from_right(rc.c.y, rc.hv);
+        const float aA = pinned(rc.lamA + 2.f * rc.muA);
+        const float aB = pinned(rc.lamB + 2.f * rc.muB);
+        const float ah = rc.hlam + 2.f * rc.hmu;
+        A.aL = from_left(aB, ah);
+        A.aR = aB;
+        B.aL = aA;
+        B.aR = from_right(aA, ah);
+        A.mL = from_left(rc.muB, rc.hmu);
+        A.mR = pinned(rc.muB);
+        B.mL = pinned(rc.muA);
+        B.mR = from_right(rc.muA, rc.hmu);
+        A.un = rn.c.x;
+        A.vn = rn.c.y;
+        A.lamn = rn.lamA;
+        A.mun = rn.muA;
+        B.un = rn.c.z;
+        B.vn = rn.c.w;
+        B.lamn = rn.lamB;
+        B.mun = rn.muB;
+        A.dxun = rn.c.z - from_left(rn.c.z, rn.hu);
+        A.dxvn = rn.c.w - from_left(rn.c.w, rn.hv);
+        B.dxun = from_right(rn.c.x, rn.hu) - rn.c.x;
+        B.dxvn = from_right(rn.c.y, rn.hv) - rn.c.y;
+        const bool top = k == 0;
+        float pA, pB, ph, qA, qB, qh;
+        if (top) {
+            A.um = A.vm = A.lamm = A.mum = A.dxum = A.dxvm = 0.f;
+            B.um = B.vm = B.lamm = B.mum = B.dxum = B.dxvm = 0.f;
+            pA = rc.lamA * (rn.c.y - rc.c.y);
+            pB = rc.lamB * (rn.c.w - rc.c.w);
+            ph = rc.hlam * (rn.hv - rc.hv);
+            qA = rc.muA * (rn.c.x - rc.c.x);
+            qB = rc.muB * (rn.c.z - rc.c.z);
+            qh = rc.hmu * (rn.hu - rc.hu);
+        } else {
+            A.um = rm.c.x;
+            A.vm = rm.c.y;
+            A.lamm = rm.lamA;
+            A.mum = rm.muA;
+            B.um = rm.c.z;
+            B.vm = rm.c.w;
+            B.lamm = rm.lamB;
+            B.mum = rm.muB;
+            A.dxum = rm.c.z - from_left(rm.c.z, rm.hu);
+            A.dxvm = rm.c.w - from_left(rm.c.w, rm.hv);
+            B.dxum = from_right(rm.c.x, rm.hu) - rm.c.x;
+            B.dxvm = from_right(rm.c.y, rm.hv) - rm.c.y;
+            pA = rc.lamA * (rn.c.y - rm.c.y);
+            pB = rc.lamB * (rn.c.w - rm.c.w);
+            ph = rc.hlam * (rn.hv - rm.hv);
+            qA = rc.muA * (rn.c.x - rm.c.x);
+            qB = rc.muB * (rn.c.z - rm.c.z);
+            qh = rc.hmu * (rn.hu - rm.hu);
+        }
+        pA = pinned(pA);
+        pB = pinned(pB);
+        qA = pinned(qA);
+        qB = pinned(qB);
+        A.pR = pB;
+        A.pL = from_left(pB, ph);
+        B.pL = pA;
+        B.pR = from_right(pA, ph);
+        A.qR = qB;
+        A.qL = from_left(qB, qh);
+        B.qL = qA;
+        B.qR = from_right(qA, qh);
+        const float2 accA = nodal_accel(A, top), accB = nodal_accel(B, top);
+        const int dk = k - sk0;
+        const bool row_src = dk >= 0 && dk < kSrcW;
+        const bool wa = s0 && row_src, wb = s1 && row_src;
+        int injA = 0, injB = 0;
+        float wa0 = 0.f, wa1 = 0.f, wb0 = 0.f, wb1 = 0.f;
+        if (rfz && k == 0 && rec0 >= 0) {  // dual solve: receiver injection
+            const float2 rf = ld2(rfz, (size_t)m * nrec + rec0);
+            injA = 1;
+            wa0 = rf.x;
+            wa1 = rf.y;
+        } else if (wa) {
+            injA = 2;
+            wa0 = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di0);
+            wa1 = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di0);
+        }
+        if (rfz && k == 0 && rec1 >= 0) {
+            const float2 rf = ld2(rfz, (size_t)m * nrec + rec1);
+            injB = 1;
+            wb0 = rf.x;
+            wb1 = rf.y;
+        } else if (wb) {
+            injB = 2;
+            wb0 = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di1);
+            wb1 = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di1);
+        }
+        const float2 na = nodal_new(accA, sc.x, A.u, A.v, up.x, up.y, injA, h2, sval, wa0, wa1);
+        const float2 nb = nodal_new(accB, sc.y, B.u, B.v, up.z, up.w, injB, h2, sval, wb0, wb1);
+        if (wrec) {
+            const size_t w0 = (size_t)m * (kSrcW * kSrcW) + dk * kSrcW;
+            if (wa && upd0) st2(wrec, w0 + di0, na);
+            if (wb && upd1) st2(wrec, w0 + di1, nb);
+        }
+        // edge and padding columns are never written
+        if (upd0 && upd1) {
+            st4(P, (size_t)k * pitch + i0, make_float4(na.x, na.y, nb.x, nb.y));
+        } else if (upd0) {
+            st2(P, (size_t)k * pitch + i0, na);
+        } else if (upd1) {
+            st2(P, (size_t)k * pitch + i0 + 1, nb);
+        }
+        if (k == 0) {
+            if (rec0 >= 0) st2(traces, (size_t)(m + 1) * nrec + rec0, na);
+            if (rec1 >= 0) st2(traces, (size_t)(m + 1) * nrec + rec1, nb);
         }
         rm = rc;
         rc = rn;
@@ -1387,6 +1693,8 @@ const StencilVariant kVariants[kNumVariants] = {
     {128, 32, EIG_MEDIUM_LAYERED, 2},  // 14: two steps, halo columns up front
     {128, 64, EIG_MEDIUM_LAYERED, 3},  // 15: three steps per launch
     {128, 32, EIG_MEDIUM_LAYERED, 3},  // 16: three steps per launch
+    {128, 16, EIG_MEDIUM_NODAL, 1},    // 17: nodal media, two nodes per lane
+    {128, 32, EIG_MEDIUM_NODAL, 1},    // 18: nodal media, two nodes per lane
 };
 
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
@@ -1411,6 +1719,8 @@ void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int s
         case 14: stencil_layered_tb2h<32, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         case 15: stencil_layered_tb3<64><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         case 16: stencil_layered_tb3<32><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 17: stencil_nodal_w2<16><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
+        case 18: stencil_nodal_w2<32><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
 
         default: stencil_nodal<<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
     }

@@ -94,6 +94,41 @@ def test_absorbing_ragged_and_mixed_with_rigid(ctx, kind):
         assert e <= TRACE_TOL, (kind, s, g.bc, e)
 
 
+@pytest.mark.parametrize("variant", [17, 18])
+def test_absorbing_nodal_variants_bitwise_identical(variant):
+    # nodal media with absorbing edges: the two-nodes-per-lane kernels leave
+    # the edge nodes to the edge kernel exactly as the one-node kernel does
+    from paper_1502_07873_amd import Context
+    from paper_1502_07873_amd.query import grid_tuple
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    rng = np.random.default_rng(29)
+    nx, nz, h = 133, 71, 12.0
+    med = synthetic.nodal_perturbed_medium(rng, nz, nx, h, nlayers=3, corr_len=60.0)
+    grid = synthetic.Grid(nx, nz, h, synthetic.cfl_dt(h, med.vp_max()), 600, bc="absorbing")
+    lo, hi = synthetic.prior_box(grid)
+    th = synthetic.draw_uniform(rng, lo, hi, 2)
+    th[:, 2] = 0.05
+    rec = np.array([1, 2, 64, 127, 128, nx - 2], dtype=np.int32)
+    _say(f"absorbing nodal variant {variant}")
+    dm = _dev_medium(med)
+    outs = []
+    for v in (variant, 6):
+        with Context(0, 4 << 30) as c:
+            c.set_option("stencil_variant", v)
+            tr = [torch.empty((grid.nsteps + 1, len(rec), 2), dtype=torch.float32, device="cuda")
+                  for _ in range(len(th))]
+            c.forward_solve_batch([grid_tuple(grid)] * len(th), [dm] * len(th), th,
+                                  [rec] * len(th), tr)
+            torch.cuda.synchronize()
+            assert c.get_option("last_variant") == v
+            outs.append([t.cpu().numpy() for t in tr])
+    for s in range(len(th)):
+        assert np.array_equal(outs[0][s], outs[1][s]), s
+        ref = elastic.forward(grid, med, th[s], rec)
+        assert _relerr(outs[0][s].astype(np.float64), ref) <= TRACE_TOL
+
+
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 7, 8, 11])
 def test_absorbing_variants_bitwise_identical(variant):
     # every one-step layered kernel gives the same bits; a forced two-step

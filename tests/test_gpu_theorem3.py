@@ -62,10 +62,11 @@ def _run(ctx_opts, grid, med, rec, th, sigma, noise, prior, iters):
 
 
 @pytest.mark.parametrize("kind,opts", [("layered", {}), ("layered", {"stencil_variant": 0}),
-                                       ("nodal", {})])
+                                       ("nodal", {"stencil_variant": 6}),
+                                       ("nodal", {"stencil_variant": 17})])
 def test_h2_from_dual_solve_matches_direct_second_derivatives(kind, opts):
     # iters = 0: theta^ = theta*, so only the dual solve and its contraction
-    # are compared (two-nodes-per-lane, one-node-per-lane and nodal kernels)
+    # are compared (two-nodes-per-lane, one-node-per-lane and both nodal kernels)
     from paper_1502_07873_amd import make_prior
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
