@@ -234,6 +234,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         const eig_grid& g = grids[solves[i].grid];
         for (int v : cand_of(i)) {
             ntiles_total += tiles_of(g, kVariants[v]);
+            if (kVariants[v].edges) ntiles_total += edge_tiles_of(g.nx, g.nz);
             if (kVariants[v].steps == 3)
                 ntiles_total += (size_t)std::max(nbound(g), 0) * ((g.nz - 1 + 63) / 64);
         }
@@ -343,6 +344,9 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
             for (int ch = 0; ch < nchunk; ++ch)
                 for (int st = 0; st < nstrip; ++st)
                     gr.tiles[v].push_back(make_int2(oi, (st << 16) | ch));
+            if (sv.edges && g.bc == EIG_BC_ABSORBING && c->fused_edges)
+                for (int part = 0; part < edge_tiles_of(g.nx, g.nz); ++part)
+                    gr.tiles[v].push_back(make_int2(oi, (kEdgeStrip << 16) | part));
             gr.steps_tiles[v].push_back({g.nsteps, (int)gr.tiles[v].size()});
             if (sv.steps == 3) {
                 const int nhch = (g.nz - 1 + 63) / 64;
@@ -497,7 +501,8 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
                     launch_stencil(ddesc, (const int2*)(bd + o_tiles[gi][vi]), ntile, step,
                                    g.cand[vi], ls);
                 if (slot >= 0) HIP_TRY(hipEventRecord(tn.ev[2 * slot + 1], s));
-                if (g.bc == EIG_BC_ABSORBING && !replay)
+                if (g.bc == EIG_BC_ABSORBING && !replay &&
+                    !(kVariants[g.cand[vi]].edges && c->fused_edges))
                     launch_ce_edges(ddesc + g.first, nrun, step, ls);
                 c->launches += 1;
                 c->updates += upd;
@@ -573,7 +578,8 @@ struct WaveSizer {
     size_t cost(const SolveSpec& sp) const {
         const eig_grid& g = grids[sp.grid];
         size_t b = solve_bytes(g) + sizeof(SolveDesc) + sizeof(SourceJob) + 64;
-        for (int v = 0; v < kNumVariants; ++v) b += tiles_of(g, kVariants[v]) * sizeof(int2);
+        for (int v = 0; v < kNumVariants; ++v)
+            b += (tiles_of(g, kVariants[v]) + edge_tiles_of(g.nx, g.nz)) * sizeof(int2);
         // three-step halo: side buffer and halo tile maps (upper bound)
         const size_t nb = (size_t)(g.nx + 127) / 128;
         b += nb * g.nz * 4 * sizeof(float2) + 2 * nb * ((g.nz + 63) / 64) * sizeof(int2) + kAlign;
@@ -677,6 +683,8 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
         c->max_wave_solves = value;
     } else if (n == "graphs") {
         c->graphs = value != 0;
+    } else if (n == "fused_edges") {
+        c->fused_edges = value != 0;
     } else if (n == "wave_cache_bytes") {
         if (value < 0) return set_error(EIG_EINVAL, "wave_cache_bytes < 0");
         c->wave_cache_bytes = (size_t)value;
@@ -696,6 +704,7 @@ int eig_ctx_get_option(const eig_ctx* c, const char* name, int64_t* value) {
     else if (n == "max_wave_solves") *value = c->max_wave_solves;
     else if (n == "graphs") *value = c->graphs;
     else if (n == "wave_cache_bytes") *value = (int64_t)c->wave_cache_bytes;
+    else if (n == "fused_edges") *value = c->fused_edges;
     else if (n == "graph_captures") *value = c->graph_captures;
     else if (n == "graph_replays") *value = c->graph_replays;
     else if (n == "last_variant") *value = c->last_variant;

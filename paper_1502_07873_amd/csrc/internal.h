@@ -124,7 +124,15 @@ void launch_source_tables(const SourceJob* jobs, int njobs, int max_nsteps,
 struct StencilVariant {
     int cols, rows, medium_kind;
     int steps;  // leapfrog steps per launch (2, 3: four field buffers per solve)
+    int edges;  // 1: runs edge tiles (absorbing edges in the same launch)
 };
+// Tile entries (solve, kEdgeStrip << 16 | part) of a variant with `edges`:
+// absorbing edge nodes part * kEdgeTileNodes .. +kEdgeTileNodes of a solve.
+constexpr int kEdgeStrip = 0x7fff;
+constexpr int kEdgeTileNodes = 128;
+inline int edge_tiles_of(int nx, int nz) {
+    return (2 * nz + nx - 2 + kEdgeTileNodes - 1) / kEdgeTileNodes;
+}
 constexpr int kNumVariants = 19;
 extern const StencilVariant kVariants[kNumVariants];
 // tiles: (solve index, strip << 16 | chunk) per wavefront

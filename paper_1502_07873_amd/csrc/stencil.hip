@@ -23,6 +23,7 @@
 // HBM once per step (tile halos hit L2), u^{m-1} is read once and u^{m+1}
 // written in place of it: 24 bytes of field traffic per grid-point update.
 // Depth-only coefficients are per-row scalars (SGPR loads).
+#include "ce.h"
 #include "internal.h"
 
 namespace eig {
@@ -167,6 +168,16 @@ __device__ __forceinline__ bool decode_tile(const SolveDesc* descs, const int2* 
     return true;
 }
 
+// True if this wave's tile is an edge tile (absorbing edge nodes, ce.h):
+// the wave updates them and the kernel returns.
+__device__ __forceinline__ bool edge_wave(const SolveDesc* descs, const int2* tiles,
+                                          int ntiles, int step) {
+    const int tile = __builtin_amdgcn_readfirstlane(
+        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
+    if (tile >= ntiles) return false;
+    return ce_edge_tile(descs, tiles[tile], step, threadIdx.x & 63);
+}
+
 // Variant 0: one node per lane (64 columns per wave), one row of prefetch.
 __device__ __forceinline__ void load_row(const float2* Q, size_t off, int i,
                                          int hc, bool hl, float2& c, float2& h) {
@@ -288,6 +299,7 @@ template <int R, int D>
 __global__ void __launch_bounds__(256)
 stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
                    int ntiles, int step) {
+    if (edge_wave(descs, tiles, ntiles, step)) return;
     TileInfo t;
     if (!decode_tile(descs, tiles, ntiles, step, 128, R, t)) return;
     const SolveDesc* d = t.d;
@@ -386,8 +398,10 @@ stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__
             if (wa && upd0) st2(wrec, wb0 + di0, na);
             if (wb && upd1) st2(wrec, wb0 + di1, nb);
         }
-        // edge and padding columns are never written (absorbing edges are
-        // updated by their own kernel, rigid ones stay zero)
+        // edge and padding columns are never written: rigid edges stay zero,
+        // absorbing ones belong to the edge waves of this launch (or to the
+        // edge kernel); the u^{m-1} an edge wave may already have replaced
+        // feeds only edge results that are discarded here
         if (upd0 && upd1) {
             st4(P, (size_t)k * pitch + i0, make_float4(na.x, na.y, nb.x, nb.y));
         } else if (upd0) {
@@ -1445,6 +1459,7 @@ template <int R>
 __global__ void __launch_bounds__(256)
 stencil_nodal_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
                  int ntiles, int step) {
+    if (edge_wave(descs, tiles, ntiles, step)) return;
     TileInfo t;
     if (!decode_tile(descs, tiles, ntiles, step, 128, R, t)) return;
     const SolveDesc* d = t.d;
@@ -1677,14 +1692,14 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
 
 const StencilVariant kVariants[kNumVariants] = {
     {64, 32, EIG_MEDIUM_LAYERED, 1},   // 0: one node per lane
-    {128, 32, EIG_MEDIUM_LAYERED, 1},  // 1: two nodes per lane, prefetch 1
-    {128, 32, EIG_MEDIUM_LAYERED, 1},  // 2: two nodes per lane, prefetch 2
-    {128, 64, EIG_MEDIUM_LAYERED, 1},  // 3: prefetch 2
-    {128, 16, EIG_MEDIUM_LAYERED, 1},  // 4: prefetch 2
-    {128, 64, EIG_MEDIUM_LAYERED, 1},  // 5: prefetch 1
+    {128, 32, EIG_MEDIUM_LAYERED, 1, 1},  // 1: two nodes per lane, prefetch 1
+    {128, 32, EIG_MEDIUM_LAYERED, 1, 1},  // 2: two nodes per lane, prefetch 2
+    {128, 64, EIG_MEDIUM_LAYERED, 1, 1},  // 3: prefetch 2
+    {128, 16, EIG_MEDIUM_LAYERED, 1, 1},  // 4: prefetch 2
+    {128, 64, EIG_MEDIUM_LAYERED, 1, 1},  // 5: prefetch 1
     {64, 32, EIG_MEDIUM_NODAL, 1},     // 6: nodal media
-    {128, 8, EIG_MEDIUM_LAYERED, 1},   // 7: prefetch 2
-    {128, 16, EIG_MEDIUM_LAYERED, 1},  // 8: prefetch 1
+    {128, 8, EIG_MEDIUM_LAYERED, 1, 1},   // 7: prefetch 2
+    {128, 16, EIG_MEDIUM_LAYERED, 1, 1},  // 8: prefetch 1
     {128, 16, EIG_MEDIUM_LAYERED, 2},  // 9: two steps per launch
     {128, 32, EIG_MEDIUM_LAYERED, 2},  // 10: two steps per launch
     {128, 64, EIG_MEDIUM_LAYERED, 2},  // 11: two steps per launch
@@ -1693,8 +1708,8 @@ const StencilVariant kVariants[kNumVariants] = {
     {128, 32, EIG_MEDIUM_LAYERED, 2},  // 14: two steps, halo columns up front
     {128, 64, EIG_MEDIUM_LAYERED, 3},  // 15: three steps per launch
     {128, 32, EIG_MEDIUM_LAYERED, 3},  // 16: three steps per launch
-    {128, 16, EIG_MEDIUM_NODAL, 1},    // 17: nodal media, two nodes per lane
-    {128, 32, EIG_MEDIUM_NODAL, 1},    // 18: nodal media, two nodes per lane
+    {128, 16, EIG_MEDIUM_NODAL, 1, 1},    // 17: nodal media, two nodes per lane
+    {128, 32, EIG_MEDIUM_NODAL, 1, 1},    // 18: nodal media, two nodes per lane
 };
 
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
