@@ -172,6 +172,10 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  *                      grid and length); waves where fewer than 16 solves
  *                      would fit are not split.  0: never split for the
  *                      cache.  Results do not depend on it.
+ *   "fused_edges"      1 (default): the two-nodes-per-lane one-step kernels
+ *                      update absorbing edge nodes in extra wavefronts of
+ *                      their own launch; 0: a separate edge kernel after each
+ *                      launch.  Same results either way.
  *   "max_wave_solves"  0 (default): no limit; n > 0: at most n solves per
  *                      launch (n = 1 is the plain one-solve-at-a-time path)
  * EIG_EINVAL for an unknown name or value. */

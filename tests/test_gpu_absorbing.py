@@ -129,20 +129,23 @@ def test_absorbing_nodal_variants_bitwise_identical(variant):
         assert _relerr(outs[0][s].astype(np.float64), ref) <= TRACE_TOL
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 7, 8, 11])
-def test_absorbing_variants_bitwise_identical(variant):
-    # every one-step layered kernel gives the same bits; a forced two-step
-    # variant falls back to one step for absorbing grids
+@pytest.mark.parametrize("variant,fused", [(0, 1), (1, 0), (2, 1), (3, 1), (4, 1), (5, 1),
+                                           (7, 1), (8, 1), (11, 1)])
+def test_absorbing_variants_bitwise_identical(variant, fused):
+    # every one-step layered kernel gives the same bits, with the edges in
+    # the stencil launch (edge waves) or in the separate edge kernel (variant
+    # 0, or fused_edges 0); a forced two-step variant falls back to one step
     from paper_1502_07873_amd import Context
     from paper_1502_07873_amd.query import grid_tuple
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     wl = synthetic.loh_workload(3)
-    _say(f"absorbing variant {variant}")
+    _say(f"absorbing variant {variant}, fused_edges {fused}")
     outs = []
-    for v in (variant, 1):
+    for v, f in ((variant, fused), (1, 1)):
         with Context(0, 4 << 30) as c:
             c.set_option("stencil_variant", v)
+            c.set_option("fused_edges", f)
             tr = [torch.empty((wl.grid.nsteps + 1, len(wl.receivers), 2), dtype=torch.float32,
                               device="cuda") for _ in range(3)]
             c.forward_solve_batch([grid_tuple(wl.grid)] * 3, [_dev_medium(wl.medium)] * 3,
