@@ -122,6 +122,7 @@ struct eig_server {
     int64_t launch = 0;
     int group_samples = 16;
     int variant_layered = 4;
+    int variant_nodal = 18;
     int spl = 1;  // leapfrog steps per launch of the layered variant
     std::deque<SrvQuery*> queue;
     std::map<int64_t, std::unique_ptr<SrvQuery>> queries;
@@ -359,7 +360,7 @@ int srv_rebuild_tiles(eig_server* v, hipStream_t s) {
     v->kind_tiles.clear();
     v->kind_tile_off.clear();
     for (int kind : {EIG_MEDIUM_LAYERED, EIG_MEDIUM_NODAL}) {
-        const int var = kind == EIG_MEDIUM_NODAL ? 6 : v->variant_layered;
+        const int var = kind == EIG_MEDIUM_NODAL ? v->variant_nodal : v->variant_layered;
         const StencilVariant& sv = kVariants[var];
         const size_t begin = all.size();
         for (const auto& gr : v->groups) {
@@ -403,6 +404,9 @@ int eig_server_create(eig_ctx* c, size_t budget, int32_t group_samples, eig_serv
                              ? c->forced_variant
                              : (c->temporal_blocking >= 2 ? c->default_variant_tb : c->default_variant);
     v->spl = kVariants[v->variant_layered].steps;
+    // nodal media: two nodes per lane unless a nodal variant is forced
+    if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_NODAL)
+        v->variant_nodal = c->forced_variant;
     v->nslot_cap = 1 << 17;
     if (hipMalloc((void**)&v->mem, budget) != hipSuccess) {
         (void)hipGetLastError();

@@ -580,6 +580,12 @@ def test_server_alone_equals_mix_and_matches_jacobian_path(ctx):
     thB = synthetic.draw_uniform(rng, loB, hiB, 7)
     recB = synthetic.random_receivers(rng, 90, 11)
     dA, dB = _dev_medium(wlA.medium), _dev_medium(medB)
+    medN = synthetic.nodal_perturbed_medium(rng, 60, 150, 15.0, nlayers=3, corr_len=80.0)
+    gN = synthetic.Grid(150, 60, 15.0, synthetic.cfl_dt(15.0, medN.vp_max()), 240)
+    loN, hiN = synthetic.prior_box(gN)
+    thN = synthetic.draw_uniform(rng, loN, hiN, 3)
+    recN = synthetic.random_receivers(rng, 150, 9)
+    dN = _dev_medium(medN)
 
     def run(queries, stagger):
         srv = eigseis.Server(ctx, 2 << 30, group_samples=2)
@@ -606,8 +612,9 @@ def test_server_alone_equals_mix_and_matches_jacobian_path(ctx):
 
     qA = (wlA.grid, dA, wlA.theta, wlA.receivers, wlA.lo, wlA.hi)
     qB = (gB, dB, thB, recB, loB, hiB)
+    qN = (gN, dN, thN, recN, loN, hiN)
     alone = run([qA], 0)
-    mix = run([qB, qA, qB], 37)
+    mix = run([qB, qA, qB, qN], 37)
     assert torch.equal(alone[0]["H1"], mix[1]["H1"])
     assert torch.equal(alone[0]["dkl"], mix[1]["dkl"])
     assert torch.equal(alone[0]["eig"], mix[1]["eig"])
@@ -617,6 +624,12 @@ def test_server_alone_equals_mix_and_matches_jacobian_path(ctx):
     torch.cuda.synchronize()
     assert torch.equal(ref["H1"], alone[0]["H1"])
     assert torch.equal(ref["dkl"], alone[0]["dkl"])
+    # a nodal-medium query in the mix (the server's two-node nodal kernel)
+    refN = run_query(ctx, grid_tuple(gN), dN, recN, loN, hiN, thN, np.full(3, 1.0 / 3),
+                     sigma=0.9)
+    torch.cuda.synchronize()
+    assert torch.equal(refN["H1"], mix[3]["H1"])
+    assert torch.equal(refN["dkl"], mix[3]["dkl"])
 
 
 def test_sparse_quadrature_greedy_pipeline_c5_shape(ctx):
