@@ -34,7 +34,7 @@ ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_layered_c2_traffic.json")
 
 
-def _measured_traffic(solves_per_launch, wave_cache_bytes):
+def _measured_traffic(solves_per_launch, wave_cache_bytes, variant):
     """Bytes per stencil launch past the L2 caches (served by the last-level
     cache or HBM) from the committed rocprofv3 counter record, only if it was
     taken on this exact kernel source, workload and wave size."""
@@ -47,6 +47,7 @@ def _measured_traffic(solves_per_launch, wave_cache_bytes):
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if (sha != rec.get("kernel_source_sha256")
             or rec.get("solves_per_launch") != solves_per_launch
+            or rec.get("variant") != variant
             or rec.get("wave_cache_bytes") != wave_cache_bytes):
         return None
     return rec["traffic_bytes_per_launch"]
@@ -685,7 +686,8 @@ def main():
     llc_copy_gbs = _copy_rate(96 << 20, reps=200)
     solves_per_launch = st["updates"] / max(st["launches"], 1) / (
         wl.grid.nx * wl.grid.nz * steps_per_launch)
-    traffic = _measured_traffic(round(solves_per_launch), ctx.get_option("wave_cache_bytes"))
+    traffic = _measured_traffic(round(solves_per_launch), ctx.get_option("wave_cache_bytes"),
+                                variant)
     status_ok = int(out["status"].abs().sum()) == 0 and int(out["chol_status"].abs().sum()) == 0
     line = {
         "metric": METRIC,
