@@ -396,7 +396,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     // class has not been tuned yet (the tuning launches are real steps)
     struct Tune {
         bool active = false;
-        int begin = 0, reps = 2;
+        int begin = 0, reps = 4;
         std::vector<hipEvent_t> ev;  // 2 per tuning launch
         std::tuple<int, int, int, int, int> key;
     };
@@ -511,11 +511,13 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
             if (slot == ncand * tn.reps - 1) {
                 // end of the tuning window: pick the fastest variant
                 HIP_TRY(hipEventSynchronize(tn.ev.back()));
-                std::vector<double> tot(ncand, 0.0);
+                // each candidate's fastest launch: robust to a launch slowed
+                // by something else on the device
+                std::vector<double> tot(ncand, 1e30);
                 for (int q = 0; q < ncand * tn.reps; ++q) {
                     float ms = 0.f;
                     HIP_TRY(hipEventElapsedTime(&ms, tn.ev[2 * q], tn.ev[2 * q + 1]));
-                    tot[q % ncand] += ms;
+                    tot[q % ncand] = std::min(tot[q % ncand], (double)ms);
                 }
                 int best = 0;
                 for (int v = 1; v < ncand; ++v)
