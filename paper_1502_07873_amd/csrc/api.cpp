@@ -84,7 +84,10 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
         total += (double)live[i];
         order[i] = i;
     }
-    // chunk boundaries: cumulative live bytes cut into nch equal spans
+    // chunk boundaries: every change of kind, edges, grid or length (so a
+    // chunk is uniform and its tuned variant suits the chunks that share its
+    // tuning key), and within a uniform segment its live bytes cut into
+    // equal spans of at most the limit
     std::vector<size_t> cut{0};
     const double lim = (double)c->wave_cache_bytes;
     if (lim > 0 && total > lim && kMinCacheChunk * total / (double)n <= lim) {
@@ -94,15 +97,33 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
             return std::make_tuple(media[sp.medium].kind, g.bc, sp.rforce != nullptr, g.nx,
                                    g.nz, -g.nsteps, sp.medium);
         };
+        auto uniform = [&](size_t a, size_t b) {
+            const auto ka = key(a), kb = key(b);
+            return std::get<0>(ka) == std::get<0>(kb) && std::get<1>(ka) == std::get<1>(kb) &&
+                   std::get<2>(ka) == std::get<2>(kb) && std::get<3>(ka) == std::get<3>(kb) &&
+                   std::get<4>(ka) == std::get<4>(kb) && std::get<5>(ka) == std::get<5>(kb);
+        };
         std::stable_sort(order.begin(), order.end(),
                          [&](size_t a, size_t b) { return key(a) < key(b); });
-        const size_t nch = (size_t)std::ceil(total / lim);
-        const double span = total / (double)nch;
-        double acc = 0.0;
-        for (size_t q = 0; q < n; ++q) {
-            const double b = (double)live[order[q]];
-            if (q > cut.back() && acc + 0.5 * b > span * (double)cut.size()) cut.push_back(q);
-            acc += b;
+        size_t q0 = 0;
+        while (q0 < n) {
+            size_t q1 = q0 + 1;
+            double seg = (double)live[order[q0]];
+            while (q1 < n && uniform(order[q0], order[q1])) seg += (double)live[order[q1++]];
+            const size_t nch = (size_t)std::ceil(seg / lim);
+            const double span = seg / (double)nch;
+            double acc = 0.0;
+            size_t made = 1;
+            for (size_t q = q0; q < q1; ++q) {
+                const double b = (double)live[order[q]];
+                if (q > cut.back() && acc + 0.5 * b > span * (double)made) {
+                    cut.push_back(q);
+                    ++made;
+                }
+                acc += b;
+            }
+            if (q1 < n) cut.push_back(q1);
+            q0 = q1;
         }
     }
     cut.push_back(n);
