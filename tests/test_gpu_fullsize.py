@@ -3,8 +3,10 @@
 configuration the benchmark times: the 3840-solve wave runs as 24-solve
 chunks whose fields stay in the last-level cache.  One sample, whose 15
 solves straddle a chunk boundary, is recomputed by the oracle; every sample
-is checked for the properties that hold at any size.  Tolerances: traces
-relative L2 <= 1e-5, Jacobian columns <= 1e-3, D^_KL <= 1e-3 nats.
+is checked for the properties that hold at any size, among them that the
+forward-sensitivity Jacobian gives the same D^_KL within 1e-3 nats.
+Tolerances: traces relative L2 <= 1e-5, Jacobian columns <= 1e-3, D^_KL
+<= 1e-3 nats.
 """
 import numpy as np
 import pytest
@@ -52,6 +54,15 @@ def test_c2_full_query_sampled_against_oracle():
                "status": out["status"].cpu().numpy(),
                "chol": out["chol_status"].cpu().numpy()}
         del out
+        # the forward-sensitivity Jacobian (1 + 7 solves per sample, 2048
+        # solves in cache chunks) gives the same D^_KL up to the central
+        # differences' O(d^2) truncation, for every sample
+        _say("c2 full query, forward-sensitivity Jacobian")
+        outs = run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, wl.theta, wl.weights,
+                         sigma=sig, jacobian="sensitivity")
+        torch.cuda.synchronize()
+        assert int(outs["status"].abs().sum()) == 0
+        dkl_sens = outs["dkl"].cpu().numpy()
     # properties of every sample
     assert (gpu["status"] == 0).all() and (gpu["chol"] == 0).all()
     assert np.isfinite(gpu["dkl"]).all()
@@ -59,6 +70,7 @@ def test_c2_full_query_sampled_against_oracle():
     assert np.allclose(H, np.transpose(H, (0, 2, 1)), rtol=1e-12, atol=0)
     assert (np.diagonal(H, axis1=1, axis2=2) > 0).all()
     assert gpu["eig"] == pytest.approx(float(np.dot(wl.weights, gpu["dkl"])), rel=1e-12)
+    assert np.max(np.abs(dkl_sens - gpu["dkl"])) <= NAT_TOL
     # the sampled sample against the oracle (same sigma)
     _say(f"oracle: sample {k} of the c2 query (15 solves)")
     ref = opipe.query(wl, theta=wl.theta[k:k + 1], weights=[1.0], sigma=sig, keep_J=True)
