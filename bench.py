@@ -27,8 +27,9 @@ if ROOT not in sys.path:
 METRIC = ("EIG evals/s and grid-pt updates/s (HBM GB/s % peak) at ≤1e-3 nat err; "
           "p50/p99")
 HBM_PEAK_GBS = 8000.0
-# FP32 vector issue rate without packed-FP32 instructions (which this build
-# never emits): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations/s; the
+# FP32 vector issue rate without packed-FP32 instructions (the library's
+# kernels are compiled not to use them): 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz lane operations/s; the
 # published 157.3 TFLOP/s counts an FMA as two flops on packed pairs.
 ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_layered_c2_traffic.json")
@@ -599,9 +600,9 @@ def main():
         _copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(samples would shard across GPUs with one all-reduce of the "
-              "per-design sums; see the design notes).", file=sys.stderr)
+              "per-design sums).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
