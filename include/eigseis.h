@@ -244,7 +244,7 @@ int jacobian_fd(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
 
 /*
  * jacobian_sensitivity — the forward-sensitivity form of the same quantity
- * (Algorithm 1, steps 1-5; the remark of Section 3.3.2 that H_I needs only
+ * (Algorithm 1, its sensitivity solves; the remark of Section 3.3.2 that H_I needs only
  * N_theta primal solves): for each sample 1 nominal solve plus, for every
  * parameter j, one solve whose forcing is dF/dtheta_j, the exact derivative of
  * the discretised point source f = S(t) M grad(delta):
@@ -295,9 +295,9 @@ int nested_mc_eig(eig_ctx* ctx, int32_t nouter, int32_t ninner, int32_t nobs,
  * (theta*_s, noise e_s): data y_s = g(theta*_s) + sigma e_s; the MAP point
  * theta^_s by Gauss-Newton from theta*_s (Theorem 1 puts it within
  * O(N^-1/2)); at theta^_s
- *   H_1 from the 7 forward-sensitivity solves (Algorithm 1, steps 1-5),
+ *   H_1 from the 7 forward-sensitivity solves (Algorithm 1),
  *   H_2 = -sum_{r,m} grad grad g o C_eps^-1 (y - g(theta^)) (Theorem 2) from one
- *         dual solve (Algorithm 1, steps 6-10): with rigid edges the adjoint of
+ *         dual solve (Algorithm 1): with rigid edges the adjoint of
  *         the leapfrog scheme is the same stencil run backward in time, driven
  *         at the receivers by the residuals divided by the lumped mass
  *         h^2/2 of a surface node; its field on the 7x7 forcing window is

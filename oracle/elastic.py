@@ -238,7 +238,7 @@ def noise_sigma(grid, medium, theta_bar, rel=1e-3, stf_kind="gauss_deriv"):
 
 
 # ---------------------------------------------------------------------------
-# Forward sensitivities (Algorithm 1, steps 1-3): solves driven by the
+# Forward sensitivities (Algorithm 1): solves driven by the
 # derivative of the discretised source with respect to each parameter.
 # ---------------------------------------------------------------------------
 # The regularised delta / delta' weights as polynomials in alpha: per node

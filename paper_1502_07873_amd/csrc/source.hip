@@ -213,7 +213,7 @@ __global__ void source_kernel(const SourceJob* __restrict__ jobs) {
     const bool spatial = (J.param == 0 || J.param == 1 || J.param >= 4);
     const bool temporal = (J.param == 2 || J.param == 3);
     if (J.deriv) {
-        // sensitivity forcing dF/dtheta_param (Algorithm 1, step 2)
+        // sensitivity forcing dF/dtheta_param (Algorithm 1)
         double tu[kNT];
         for (int j = 0; j < kNT; ++j) tu[j] = th[j];
         if (J.param >= 4) {

@@ -136,7 +136,7 @@ SENS_TOL = 1e-4   # one FP32 solve per column, no difference taken
 
 
 def test_sensitivity_jacobian_hessian_eig_c1(ctx):
-    # Algorithm 1 steps 1-5 on the GPU vs the oracle's sensitivity solves
+    # Algorithm 1's sensitivity solves on the GPU vs the oracle's
     from paper_1502_07873_amd.query import grid_tuple, run_query
     wl = synthetic.config("c1")[0]
     _say("sensitivity jacobian/H1/eig c1")

@@ -134,7 +134,7 @@ def test_scaling_moments_adds_four_log_c(small):
 
 
 def test_sensitivity_jacobian_matches_central_differences(small):
-    # Algorithm 1 steps 1-3 (solves driven by dF/dtheta_j) against the
+    # Algorithm 1's sensitivity solves (driven by dF/dtheta_j) against the
     # central differences: equal up to the O(d^2) truncation of the latter
     grid, med, rec, theta = small
     nom_s, Js = elastic.jacobian_sensitivity(grid, med, theta, rec)
