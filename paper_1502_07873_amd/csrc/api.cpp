@@ -706,6 +706,9 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
         c->max_wave_solves = value;
     } else if (n == "graphs") {
         c->graphs = value != 0;
+    } else if (n == "serve_cache_bytes") {
+        if (value < 0) return set_error(EIG_EINVAL, "serve_cache_bytes < 0");
+        c->serve_cache_bytes = (size_t)value;
     } else if (n == "fused_edges") {
         c->fused_edges = value != 0;
     } else if (n == "wave_cache_bytes") {
@@ -728,6 +731,7 @@ int eig_ctx_get_option(const eig_ctx* c, const char* name, int64_t* value) {
     else if (n == "graphs") *value = c->graphs;
     else if (n == "wave_cache_bytes") *value = (int64_t)c->wave_cache_bytes;
     else if (n == "fused_edges") *value = c->fused_edges;
+    else if (n == "serve_cache_bytes") *value = (int64_t)c->serve_cache_bytes;
     else if (n == "graph_captures") *value = c->graph_captures;
     else if (n == "graph_replays") *value = c->graph_replays;
     else if (n == "last_variant") *value = c->last_variant;

@@ -70,6 +70,9 @@ struct eig_ctx {
     // absorbing edges updated inside the one-step kernels that can (else by
     // the separate edge kernel after every step)
     bool fused_edges = true;
+    // serving engines created on this context: live field bytes their
+    // admitted groups may hold (0: no limit)
+    size_t serve_cache_bytes = (size_t)192 << 20;
     // time loops captured as HIP graphs and replayed when a wave repeats
     // exactly (same descriptor blob at the same device address, same variants)
     bool graphs = true;

@@ -87,6 +87,7 @@ struct SrvGroup {
     int s0 = 0, s1 = 0;      // samples [s0, s1) of the query
     size_t slot0 = 0, nslot = 0;
     size_t off = 0, bytes = 0;
+    size_t live = 0;         // field bytes its solves keep live between launches
     int64_t start = 0;       // launch index of step 0
     int nsteps = 0;
     size_t o_sd = 0, o_given = 0, o_sig = 0;
@@ -123,6 +124,11 @@ struct eig_server {
     int group_samples = 16;
     int variant_layered = 4;
     int variant_nodal = 18;
+    // cache-limited admission: the admitted groups' live fields stay within
+    // cache_bytes (the device's last-level cache), so launches read and write
+    // that cache instead of HBM; 0: admit whatever memory and slots allow
+    size_t cache_bytes = 0;
+    size_t live = 0;
     int spl = 1;  // leapfrog steps per launch of the layered variant
     std::deque<SrvQuery*> queue;
     std::map<int64_t, std::unique_ptr<SrvQuery>> queries;
@@ -140,6 +146,13 @@ int srv_admit(eig_server* v, hipStream_t s) {
     while (!v->queue.empty()) {
         SrvQuery& q = *v->queue.front();
         int G = std::min(v->group_samples, q.nsample - q.next_sample);
+        const bool four_buf = q.medium.kind == EIG_MEDIUM_LAYERED && v->spl == 2;
+        const size_t sample_live = (size_t)15 * (four_buf ? 4 : 2) * q.grid.nz *
+                                   pitch_of(q.grid.nx) * sizeof(float2);
+        if (v->cache_bytes) {
+            G = std::min<int>(G, (int)std::max<size_t>(1, v->cache_bytes / sample_live));
+            if (!v->groups.empty() && v->live + (size_t)G * sample_live > v->cache_bytes) break;
+        }
         size_t bytes = group_bytes(q, G);
         size_t off = 0, slot0 = 0;
         if (q.next_sample == 0 && q.tail_bytes == 0) {
@@ -162,6 +175,7 @@ int srv_admit(eig_server* v, hipStream_t s) {
         gr.nslot = (size_t)15 * G;
         gr.off = off;
         gr.bytes = bytes;
+        gr.live = (size_t)G * sample_live;
         gr.start = v->launch;
         gr.nsteps = q.grid.nsteps;
         const bool four = q.medium.kind == EIG_MEDIUM_LAYERED && v->spl == 2;
@@ -287,6 +301,7 @@ int srv_admit(eig_server* v, hipStream_t s) {
         launch_fill_zero(base + fields_begin, fields_end - fields_begin, s);
         launch_zero_level0(v->descs + gr.slot0, (int)gr.nslot, s);
         HIP_TRY(hipGetLastError());
+        v->live += gr.live;
         q.next_sample += G;
         q.groups_running += 1;
         if (q.next_sample >= q.nsample) v->queue.pop_front();
@@ -342,6 +357,7 @@ int srv_retire(eig_server* v, hipStream_t s) {
         HIP_TRY(hipGetLastError());
         v->arena.release(gr.off, gr.bytes);
         v->slots.release(gr.slot0, gr.nslot);
+        v->live -= gr.live;
         v->tiles_dirty = true;
         q.groups_running -= 1;
         if (q.next_sample >= q.nsample && q.groups_running == 0) {
@@ -403,6 +419,10 @@ int eig_server_create(eig_ctx* c, size_t budget, int32_t group_samples, eig_serv
                                  kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_LAYERED
                              ? c->forced_variant
                              : (c->temporal_blocking >= 2 ? c->default_variant_tb : c->default_variant);
+    v->cache_bytes = c->serve_cache_bytes;
+    if (v->cache_bytes && !(c->forced_variant >= 0 &&
+                            kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_LAYERED))
+        v->variant_layered = c->temporal_blocking >= 2 ? 9 : c->default_variant;
     v->spl = kVariants[v->variant_layered].steps;
     // nodal media: two nodes per lane unless a nodal variant is forced
     if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_NODAL)
