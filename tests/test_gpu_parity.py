@@ -568,13 +568,14 @@ def test_cache_sized_wave_chunks_match_one_wave():
     assert max(np.max(np.abs(a)) for a in outs[0]) > 0
 
 
-@pytest.mark.parametrize("cache_bytes", [0, 3 << 20])
+@pytest.mark.parametrize("cache_bytes", [0, 3 << 20, 192 << 20])
 def test_server_alone_equals_mix_and_matches_jacobian_path(ctx, cache_bytes):
     # cache_bytes > 0: admission limited to that many live field bytes
     # (groups shrink to fit, queries wait for room) - the same results
     from paper_1502_07873_amd import eigseis, make_prior
     from paper_1502_07873_amd.query import grid_tuple, run_query
     _say(f"serving engine: alone vs mix (serve_cache_bytes {cache_bytes})")
+    default_cache = ctx.get_option("serve_cache_bytes")
     ctx.set_option("serve_cache_bytes", cache_bytes)
     wlA = synthetic.config("c1", nsample=5)[0]
     rng = np.random.default_rng(3)
@@ -634,7 +635,7 @@ def test_server_alone_equals_mix_and_matches_jacobian_path(ctx, cache_bytes):
     torch.cuda.synchronize()
     assert torch.equal(refN["H1"], mix[3]["H1"])
     assert torch.equal(refN["dkl"], mix[3]["dkl"])
-    ctx.set_option("serve_cache_bytes", 0)
+    ctx.set_option("serve_cache_bytes", default_cache)
 
 
 def test_sparse_quadrature_greedy_pipeline_c5_shape(ctx):
