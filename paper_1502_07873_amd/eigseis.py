@@ -70,6 +70,12 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    # PyTorch ships its own HIP runtime and puts it in the global symbol
+    # scope; importing it first makes the library bind to that same runtime,
+    # so device memory, streams and ordering are shared with torch.  Loaded
+    # the other way round, the library would start the system runtime and a
+    # second one would come up beside it.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     sig = {

@@ -61,3 +61,24 @@ def test_binding_refuses_media_it_cannot_pass_on():
         eigseis.Context._media([(eigseis.MEDIUM_LAYERED, short, short, short)], [g])
     with pytest.raises(eigseis.EigError):
         eigseis.Context._media([(eigseis.MEDIUM_LAYERED,) + (short,) * 3] * 2, [g])
+
+
+def test_library_binds_to_torchs_hip_runtime():
+    # one HIP runtime per process: the binding imports torch before loading
+    # the library, so the library's HIP calls resolve into torch's runtime
+    # whatever the caller imported first (checked in a fresh process)
+    import subprocess
+    import sys
+    pytest.importorskip("torch")
+    code = ("import sys; sys.path.insert(0, %r); "
+            "from paper_1502_07873_amd import eigseis" % ROOT)
+    env = dict(os.environ, LD_DEBUG="bindings")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       env=env, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stderr.splitlines()
+             if "libeigseis.so" in ln and "`hipLaunchKernel'" in ln]
+    assert lines, "no binding of hipLaunchKernel reported"
+    import torch
+    torch_lib = os.path.realpath(os.path.join(os.path.dirname(torch.__file__), "lib"))
+    assert all(torch_lib in ln for ln in lines), lines
