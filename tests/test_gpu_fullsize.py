@@ -83,3 +83,113 @@ def test_c2_full_query_sampled_against_oracle():
     assert abs(float(gpu["dkl"][k]) - float(ref["dkl"][0])) <= NAT_TOL
     d = np.sqrt(np.diag(ref["H1"][0]))
     assert np.max(np.abs((H[k] - ref["H1"][0]) / np.outer(d, d))) <= 1e-3
+
+
+def test_c3_full_batch_sampled_against_oracle():
+    # the whole uneven batch (4096 samples x 15 solves of {256,384,512}^2 x
+    # {1000,1500,2000} steps, per-sample media) in one jacobian_fd call, run
+    # as uniform cache chunks; two samples of different grids recomputed by
+    # the oracle, properties on all
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context
+    from paper_1502_07873_amd.query import device_medium, grid_tuple
+    wls = synthetic.config("c3")
+    S = len(wls)
+    assert S == 4096
+    # candidates for the oracle check: 256^2 x 1000 and 384^2 x 1500 samples
+    cands = [[40, 50, 60], [3, 9, 17]]
+    assert all((wls[k].grid.nx, wls[k].grid.nsteps) == (256, 1000) for k in cands[0])
+    assert all((wls[k].grid.nx, wls[k].grid.nsteps) == (384, 1500) for k in cands[1])
+    grids = [grid_tuple(w.grid) for w in wls]
+    media = [device_medium(w.medium.kind, w.medium.rho, w.medium.lam, w.medium.mu)
+             for w in wls]
+    theta = np.concatenate([w.theta for w in wls])
+    recs = [w.receivers for w in wls]
+    nominal = [None] * S
+    J = [None] * S
+    for k in cands[0] + cands[1]:
+        g = wls[k].grid
+        nominal[k] = torch.empty((g.nsteps + 1, len(recs[k]), 2), dtype=torch.float32,
+                                 device="cuda")
+        J[k] = torch.empty((g.nsteps + 1, len(recs[k]), 2, 7), dtype=torch.float64,
+                           device="cuda")
+    H1 = torch.empty((S, 7, 7), dtype=torch.float64, device="cuda")
+    status = torch.empty(S, dtype=torch.int32, device="cuda")
+    _say("c3 full batch: 61440 solves in one jacobian_fd call")
+    with Context(0, 200 << 30) as ctx:
+        ctx.stencil_stats(reset=True)
+        ctx.jacobian_fd(grids, media, theta, recs, 1.0, H1, nominal=nominal, J=J,
+                        status=status)
+        torch.cuda.synchronize()
+        # unsplit, the batch's waves would take ~1000 launches each
+        assert ctx.stencil_stats()["launches"] > 100000
+    st = status.cpu().numpy()
+    Hg = H1.cpu().numpy()
+    assert (st == 0).all()
+    assert np.isfinite(Hg).all()
+    assert np.allclose(Hg, np.transpose(Hg, (0, 2, 1)), rtol=1e-12, atol=0)
+    diag = np.diagonal(Hg, axis1=1, axis2=2)
+    assert (diag >= 0).all()
+    # a deep source with the shortest record may never reach the surface:
+    # its Jacobian and H_1 are exactly zero; most samples record signal
+    seen = (diag > 0).all(axis=1)
+    assert seen.mean() > 0.5
+    _say(f"c3: {int(seen.sum())} of {S} samples record signal within their duration")
+    picks = [next(k for k in group if seen[k]) for group in cands]
+    for k in picks:
+        _say(f"oracle: c3 sample {k} ({wls[k].grid.nx}^2 x {wls[k].grid.nsteps})")
+        ref = opipe.query(wls[k], sigma=1.0, keep_J=True)
+        nom = nominal[k].cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(nom - ref["nominal"][0]) <= TRACE_TOL * np.linalg.norm(ref["nominal"][0])
+        Jg, Jr = J[k].cpu().numpy(), ref["J"][0]
+        for j in range(7):
+            assert np.linalg.norm(Jg[..., j] - Jr[..., j]) <= JAC_TOL * np.linalg.norm(Jr[..., j])
+        d = np.sqrt(np.diag(ref["H1"][0]))
+        assert np.max(np.abs((Hg[k] - ref["H1"][0]) / np.outer(d, d))) <= 1e-3
+
+
+def test_c5_full_size_properties():
+    # 2048 x 1024 x 4000 on a nodal medium, one sparse-grid node: an oracle
+    # solve takes minutes here, so properties that hold at any size: the
+    # per-candidate H_1 of the 201 receivers sum to the whole-array H_1, the
+    # forward-sensitivity Jacobian gives the same scaled H_1 within the
+    # central differences' truncation, and every nodal kernel gives the same
+    # bits
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context, sparse_grid_gl
+    from paper_1502_07873_amd.query import device_medium, grid_tuple
+    wl = synthetic.config("c5")[0]
+    nodes, _ = sparse_grid_gl(7, 3, wl.lo, wl.hi)
+    th = nodes[:1]
+    g = grid_tuple(wl.grid)
+    med = device_medium(wl.medium.kind, wl.medium.rho, wl.medium.lam, wl.medium.mu)
+    R = len(wl.receivers)
+    _say("c5 full size: per-receiver and whole-array H1, sensitivity path")
+    Hr = torch.empty((1, R, 7, 7), dtype=torch.float64, device="cuda")
+    Ha = torch.empty((1, 7, 7), dtype=torch.float64, device="cuda")
+    Hs = torch.empty((1, 7, 7), dtype=torch.float64, device="cuda")
+    with Context(0, 64 << 30) as ctx:
+        ctx.jacobian_fd([g], [med], th, [wl.receivers], 1.0, Hr, per_receiver=True)
+        ctx.jacobian_fd([g], [med], th, [wl.receivers], 1.0, Ha)
+        ctx.jacobian_sensitivity([g], [med], th, [wl.receivers], 1.0, Hs)
+        torch.cuda.synchronize()
+    Hr, Ha, Hs = Hr.cpu().numpy()[0], Ha.cpu().numpy()[0], Hs.cpu().numpy()[0]
+    d = np.sqrt(np.diag(Ha))
+    sc = np.outer(d, d)
+    assert np.max(np.abs((Hr.sum(axis=0) - Ha) / sc)) <= 1e-12
+    assert np.linalg.eigvalsh(Ha / sc).min() > 0
+    assert np.max(np.abs((Hs - Ha) / sc)) <= 1e-3
+    _say("c5 full size: nodal kernels 6, 17, 18 on one solve")
+    outs = []
+    for v in (6, 17, 18):
+        tr = [torch.empty((wl.grid.nsteps + 1, R, 2), dtype=torch.float32, device="cuda")]
+        with Context(0, 16 << 30) as ctx:
+            ctx.set_option("stencil_variant", v)
+            ctx.forward_solve_batch([g], [med], th, [wl.receivers], tr)
+            torch.cuda.synchronize()
+            assert ctx.get_option("last_variant") == v
+        outs.append(tr[0].cpu().numpy())
+    assert np.abs(outs[0]).max() > 0
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
