@@ -173,12 +173,14 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  *                      would fit are not split.  0: never split for the
  *                      cache.  Results do not depend on it.
  *   "serve_cache_bytes" 201326592 (192 MiB, default): serving engines created
- *                      afterwards admit sample groups only while the live
- *                      field bytes of all admitted groups stay within this
- *                      (groups shrink to fit; at least one group is always
- *                      admitted) and use 16-row tiles, so their launches work
- *                      in the last-level cache; 0: admit whatever memory and
- *                      slots allow.  Results do not depend on it.
+ *                      afterwards admit sample groups of a query one of whose
+ *                      samples fits this only while the live field bytes of
+ *                      all such admitted groups stay within it (groups shrink
+ *                      to fit; at least one group is always admitted), and
+ *                      use 16-row tiles, so their launches work in the
+ *                      last-level cache; queries with larger samples are
+ *                      admitted by memory alone.  0: admit whatever memory
+ *                      and slots allow.  Results do not depend on it.
  *   "fused_edges"      1 (default): the two-nodes-per-lane one-step kernels
  *                      update absorbing edge nodes in extra wavefronts of
  *                      their own launch; 0: a separate edge kernel after each

@@ -149,8 +149,11 @@ int srv_admit(eig_server* v, hipStream_t s) {
         const bool four_buf = q.medium.kind == EIG_MEDIUM_LAYERED && v->spl == 2;
         const size_t sample_live = (size_t)15 * (four_buf ? 4 : 2) * q.grid.nz *
                                    pitch_of(q.grid.nx) * sizeof(float2);
-        if (v->cache_bytes) {
-            G = std::min<int>(G, (int)std::max<size_t>(1, v->cache_bytes / sample_live));
+        // the cache limit applies to queries one of whose samples fits it;
+        // larger ones gain nothing from it and are admitted by memory alone
+        const bool cached = v->cache_bytes && sample_live <= v->cache_bytes;
+        if (cached) {
+            G = std::min<int>(G, (int)(v->cache_bytes / sample_live));
             if (!v->groups.empty() && v->live + (size_t)G * sample_live > v->cache_bytes) break;
         }
         size_t bytes = group_bytes(q, G);
@@ -175,7 +178,7 @@ int srv_admit(eig_server* v, hipStream_t s) {
         gr.nslot = (size_t)15 * G;
         gr.off = off;
         gr.bytes = bytes;
-        gr.live = (size_t)G * sample_live;
+        gr.live = cached ? (size_t)G * sample_live : 0;
         gr.start = v->launch;
         gr.nsteps = q.grid.nsteps;
         const bool four = q.medium.kind == EIG_MEDIUM_LAYERED && v->spl == 2;

@@ -193,3 +193,47 @@ def test_c5_full_size_properties():
         outs.append(tr[0].cpu().numpy())
     assert np.abs(outs[0]).max() > 0
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_c4_largest_query_through_the_server_equals_jacobian_path():
+    # the largest serving query shape (1024^2 grid, 4000 steps, 101 random
+    # receivers, 64 samples = 960 solves): the engine's H_1, D^_KL and EIG
+    # equal the jacobian_fd + laplace_eig path bit for bit (its samples are
+    # larger than the cache limit, so memory alone admits them)
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context, eigseis, make_prior
+    from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
+    rng = np.random.default_rng(44)
+    n, nt, h = 1024, 4000, 10.0
+    med = synthetic.random_layers_medium(rng, n, h, 4)
+    grid = synthetic.Grid(n, n, h, synthetic.cfl_dt(h, med.vp_max()), nt)
+    lo, hi = synthetic.prior_box(grid)
+    th = synthetic.draw_uniform(rng, lo, hi, 64)
+    rec = synthetic.random_receivers(rng, n, 101)
+    g = grid_tuple(grid)
+    dm = device_medium(med.kind, med.rho, med.lam, med.mu)
+    S = len(th)
+    w = np.full(S, 1.0 / S)
+    _say("c4 largest query: 960 solves of 1024^2 x 4000 through the server")
+    with Context(0, 200 << 30) as ctx:
+        srv = eigseis.Server(ctx, 120 << 30, group_samples=16)
+        o = {"H1": torch.empty((S, 7, 7), dtype=torch.float64, device="cuda"),
+             "dkl": torch.empty(S, dtype=torch.float64, device="cuda"),
+             "eig": torch.empty(1, dtype=torch.float64, device="cuda")}
+        qid = srv.submit(g, dm, th, rec, make_prior(lo, hi), w, o["H1"], o["dkl"], o["eig"], 0.5)
+        for _ in range(100000):
+            srv.step(400)
+            torch.cuda.synchronize()
+            if srv.poll(qid):
+                break
+        else:
+            raise AssertionError("query did not complete")
+        srv.close()
+        _say("c4 largest query: jacobian_fd + laplace_eig")
+        ref = run_query(ctx, g, dm, rec, lo, hi, th, w, sigma=0.5)
+        torch.cuda.synchronize()
+        assert torch.equal(ref["H1"], o["H1"])
+        assert torch.equal(ref["dkl"], o["dkl"])
+        assert torch.equal(ref["eig"], o["eig"])
+        assert int(ref["status"].abs().sum()) == 0
