@@ -702,7 +702,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 wavefields / f64 Jacobian-Hessian-logdet",
+        "dtype": "f32/f64",
+        "precision": "f32 wavefields; f64 forcing differences, Jacobian, H_1, scaling, "
+                     "Cholesky, log-det, averages",
         "data": "synthetic",
         "config": {"workload": "c2 Monte Carlo query: 512x512 grid, h=10 m, 2000 steps, "
                                "two-layer medium, 21 receivers, "
