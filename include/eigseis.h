@@ -290,10 +290,15 @@ int jacobian_sensitivity(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
  *   noise:   device float [nouter][nobs], standard normal draws (the caller's)
  *   g_inner: device float [ninner][nobs]
  *   sigma > 0; logratio: device double [nouter]; eig: device double [1] or NULL
- * y_n, distances, sums and log-sum-exp in FP64 (the FP32 inputs are exact in
- * FP64); context workspace: 16 bytes per outer sample per inner-range split
- * (splits only when nouter is small).  Errors: EIG_EINVAL for non-positive sizes or sigma, NULL
- * arrays.
+ * y_n in FP64 (the FP32 inputs are exact in FP64); squared distances in
+ * Gram form |y|^2 + |g|^2 - 2 <y, g> on the FP64 matrix cores, which adds
+ * about K 2^-53 (|y_n|^2 + |g_m|^2) / (2 sigma^2) nats of rounding to a log
+ * ratio; log-sum-exp with its maximum and rescaling in FP64 and the terms
+ * within 40 nats of the maximum as FP32 exponentials (at most ~3e-6 nats),
+ * terms further down dropped.  Context workspace: 16 bytes per outer sample
+ * per inner-range split (splits only when nouter is small) plus 8 bytes per
+ * outer and per inner sample.  Errors: EIG_EINVAL for non-positive sizes or
+ * sigma, NULL arrays.
  */
 int nested_mc_eig(eig_ctx* ctx, int32_t nouter, int32_t ninner, int32_t nobs,
                   const float* g_outer, const float* noise, const float* g_inner,

@@ -144,7 +144,7 @@ void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s);
 void launch_tb3_halo(const SolveDesc* descs, const int2* htiles, int nhtiles, int pass,
                      hipStream_t s);
 // Nested Monte Carlo log ratios (and their mean when eig != NULL); work
-// holds nested_workspace() bytes of per-split partial sums.
+// holds nested_workspace() bytes: per-split partial sums, squared norms.
 int nested_splits(int nouter, int ninner);
 size_t nested_workspace(int nouter, int ninner);
 void launch_nested(const float* gout, const float* noise, const float* gin, int nouter,

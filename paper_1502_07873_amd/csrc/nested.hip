@@ -9,118 +9,228 @@
 // y_n is formed in FP64, where its rounding is ~1e-14 of sigma e_n even when
 // |g_n| is hundreds of sigma (in FP32 it would lose sigma e_n to g_n).
 //
-// Work decomposition: a 256-thread block owns 64 outer rows and a range of
-// inner samples (the range is split over several blocks when the outer rows
-// alone cannot fill the chip), swept in tiles of 64; observations are
-// staged through LDS in chunks of 16 as FP64 (y = g + sigma e of the rows,
-// g of the columns); each thread accumulates a 4 x 4 block of squared
-// distances and keeps an online log-sum-exp per row; the 16 threads sharing
-// a row, then the inner-range splits, are merged in a fixed order.  The log
-// ratios grow with the data's information (hundreds to thousands of nats
-// for few inner samples), so distances are kept in FP64 (full-rate vector
-// FP64 on this chip, the same issue rate as unpacked FP32).  It is bound by
-// vector ALU throughput: 2 FP64 operations (sub, FMA) per (n, m, k).
+// Distances in Gram form, |y_n - g_m|^2 = |y_n|^2 + |g_m|^2 - 2 <y_n, g_m>:
+// the (n, m, k) work becomes one FP64 multiply-add of the dense product
+// Y G^T, which runs on the FP64 matrix cores (16x16x4 MFMA); the squared
+// norms come from a small pass of their own.  The expansion's rounding is
+// about K u (|y_n|^2 + |g_m|^2) in a squared distance (u = 2^-53), i.e.
+// K u (|y_n|^2 + |g_m|^2) / (2 sigma^2) nats in a log ratio: ~1e-9 nats for
+// traces of ~100 sigma over K ~ 200 values, ~1e-5 at ~3000 sigma.
+//
+// Work decomposition: a 512-thread block (8 waves, 4 x 2) owns 128 outer rows
+// and a range of inner samples (the range is split over several blocks when
+// the rows alone cannot fill the chip), swept in tiles of 64 columns; each
+// wave accumulates 2 x 2 MFMA tiles (32 rows x 32 columns).  k is staged
+// through LDS in chunks of 16 (y in FP64, g as FP64 copies of the FP32
+// inputs), double buffered, with the global loads of the chunk after next in
+// flight while the current one is multiplied: one barrier per chunk.  After a
+// tile's last chunk every lane folds its 16 distances into an online
+// log-sum-exp per row: the running maximum and the rescaling of the running
+// sum in FP64, the terms within 40 nats of the maximum as FP32 exponentials
+// (relative error ~3e-6 each, so at most ~3e-6 nats in a log ratio).  Terms
+// further down are dropped: each is below exp(-40) = 4.2e-18 of the maximum
+// term, M of them below M * 4.2e-18 of the sum.  Per-lane partials are
+// merged over the block, then over the inner-range splits, in a fixed order.
 #include "internal.h"
 
 namespace eig {
 
 namespace {
 
-constexpr int kTN = 64, kTM = 64, kKC = 16;
+typedef double dv4 __attribute__((ext_vector_type(4)));
 
-// Partial log-sum-exp of rows [n0, n0+64) over inner samples [mb, me):
-// part_max / part_sum [split][nouter].
+// Tile geometry: 8 waves as kGR x kGC, each kWR x kWC 16x16 MFMA tiles.
+constexpr int kWR = 2, kWC = 2, kGR = 4, kGC = 2, kKC = 16;
+constexpr int kThreads = 64 * kGR * kGC;          // 512
+constexpr int kTN = 16 * kGR * kWR;               // 128 outer rows per block
+constexpr int kTM = 16 * kGC * kWC;               // 64 inner columns per tile
+constexpr int kLY = kTN + 1, kLB = kTM + 1;       // padded LDS rows (conflict-free stores)
+constexpr int kQY = kKC * kTN / kThreads;         // y values staged per thread and chunk
+constexpr int kQB = kKC * kTM / kThreads;         // g values staged per thread and chunk
+constexpr int kNP = 16 * kGC;                     // per-row partials in a block
+constexpr int kBuf = kKC * (kLY + kLB);
+constexpr int kLds = 2 * kBuf > 2 * kNP * kTN ? 2 * kBuf : 2 * kNP * kTN;
+static_assert(kQY * kThreads == kKC * kTN && kQB * kThreads == kKC * kTM, "staging split");
+constexpr double kDrop = -40.0;                   // terms below max - 40 nats are dropped
+
+// Squared norms of y_n = g_n + sigma e_n (noise != NULL) or of g_m, one
+// wave per row, FP64.  The same fma forms y as the staging below.
 __global__ void __launch_bounds__(256)
+nested_sqnorm_kernel(const float* __restrict__ g, const float* __restrict__ noise, int rows,
+                     int nobs, double sigma, double* __restrict__ out) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+    if (row >= rows) return;
+    double s = 0.0;
+    for (int k = l; k < nobs; k += 64) {
+        double y = (double)g[(size_t)row * nobs + k];
+        if (noise) y = fma(sigma, (double)noise[(size_t)row * nobs + k], y);
+        s = fma(y, y, s);
+    }
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (l == 0) out[row] = s;
+}
+
+// Partial log-sum-exp of rows [n0, n0+128) over inner samples [mb, me):
+// part_max / part_sum [split][nouter].
+__global__ void __launch_bounds__(kThreads)
 nested_lse_kernel(const float* __restrict__ gout, const float* __restrict__ noise,
-                  const float* __restrict__ gin, int nouter, int ninner, int nobs,
+                  const float* __restrict__ gin, const double* __restrict__ ynorm,
+                  const double* __restrict__ gnorm, int nouter, int ninner, int nobs,
                   double sigma, double inv2s2, int mchunk, double* __restrict__ part_max,
                   double* __restrict__ part_sum) {
-    __shared__ double sY[kKC][kTN];   // y = g + sigma e of the rows
-    __shared__ double sB[kKC][kTM];   // g of the columns
-    __shared__ double pmx[16][kTN], psum[16][kTN];
-    const int t = threadIdx.x;
-    const int tr = t >> 4, tc = t & 15;
+    __shared__ double smem[kLds];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int wr = w / kGC, wc = w % kGC;
+    // MFMA lane layout: operand lane (li, lk) holds row/column li of k-slice
+    // lk; accumulator register v of lane l holds row lk + 4 v, column li
+    const int li = l & 15, lk = l >> 4;
     const int n0 = blockIdx.x * kTN;
     const int mb = blockIdx.y * mchunk, me = min(ninner, mb + mchunk);
-    double mx[4], sm[4];
+    const int ntile = me > mb ? (me - mb + kTM - 1) / kTM : 0;
+    const int nk = (nobs + kKC - 1) / kKC;
+    const int nchunks = ntile * nk;
+
+    double mx[kWR][4], sm[kWR][4], yn[kWR][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        mx[i] = -INFINITY;
-        sm[i] = 0.0;
-    }
-    for (int m0 = mb; m0 < me; m0 += kTM) {
-        double acc[4][4];
+    for (int x = 0; x < kWR; ++x)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-        for (int k0 = 0; k0 < nobs; k0 += kKC) {
-            // stage 1024 elements of each tile, 4 per thread, k fastest; in
-            // FP64 the sum g + sigma e keeps sigma e to ~1e-14 relative
-            for (int e = t; e < kKC * kTN; e += 256) {
-                const int r = e / kKC, kk = e % kKC;
-                const int n = n0 + r, m = m0 + r, k = k0 + kk;
-                double y = 0.0, b = 0.0;
-                if (k < nobs) {
-                    if (n < nouter)
-                        y = (double)gout[(size_t)n * nobs + k] +
-                            sigma * (double)noise[(size_t)n * nobs + k];
-                    if (m < me) b = gin[(size_t)m * nobs + k];
-                }
-                sY[kk][r] = y;
-                sB[kk][r] = b;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int kk = 0; kk < kKC; ++kk) {
-                double y[4], b[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    y[i] = sY[kk][tr + 16 * i];
-                    b[i] = sB[kk][tc + 16 * i];
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const double d = y[i] - b[j];
-                        acc[i][j] = fma(d, d, acc[i][j]);
-                    }
-            }
-            __syncthreads();
+        for (int v = 0; v < 4; ++v) {
+            const int n = n0 + wr * 16 * kWR + 16 * x + lk + 4 * v;
+            yn[x][v] = n < nouter ? ynorm[n] : 0.0;
+            mx[x][v] = -INFINITY;
+            sm[x][v] = 0.0;
         }
+
+    // chunk c = (column tile c / nk, k chunk c % nk); loads clamp their
+    // indices into the arrays, the LDS stores zero what lies outside
+    float rg[2][kQY], re[2][kQY], rb[2][kQB];
+    auto fetch = [&](int c, float* g, float* e, float* b) {
+        if (c >= nchunks) return;
+        const int m0 = mb + (c / nk) * kTM, k0 = (c % nk) * kKC;
+#pragma unroll
+        for (int q = 0; q < kQY; ++q) {
+            const int i = t + kThreads * q;
+            const int n = min(n0 + i / kKC, nouter - 1), k = min(k0 + i % kKC, nobs - 1);
+            g[q] = gout[(size_t)n * nobs + k];
+            e[q] = noise[(size_t)n * nobs + k];
+        }
+#pragma unroll
+        for (int q = 0; q < kQB; ++q) {
+            const int i = t + kThreads * q;
+            const int m = min(m0 + i / kKC, me - 1), k = min(k0 + i % kKC, nobs - 1);
+            b[q] = gin[(size_t)m * nobs + k];
+        }
+    };
+    auto store = [&](int c, const float* g, const float* e, const float* b) {
+        double* sY = smem + (c & 1) * kBuf;
+        double* sB = sY + kKC * kLY;
+        const int m0 = mb + (c / nk) * kTM, k0 = (c % nk) * kKC;
+#pragma unroll
+        for (int q = 0; q < kQY; ++q) {
+            const int i = t + kThreads * q;
+            const bool in = k0 + i % kKC < nobs && n0 + i / kKC < nouter;
+            sY[(i % kKC) * kLY + i / kKC] = in ? fma(sigma, (double)e[q], (double)g[q]) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kQB; ++q) {
+            const int i = t + kThreads * q;
+            const bool in = k0 + i % kKC < nobs && m0 + i / kKC < me;
+            sB[(i % kKC) * kLB + i / kKC] = in ? (double)b[q] : 0.0;
+        }
+    };
+    dv4 acc[kWR][kWC];
+    auto compute = [&](int c) {
+        const double* sY = smem + (c & 1) * kBuf;
+        const double* sB = sY + kKC * kLY;
+        const int kc = c % nk;
+        if (kc == 0) {
+#pragma unroll
+            for (int x = 0; x < kWR; ++x)
+#pragma unroll
+                for (int y = 0; y < kWC; ++y) acc[x][y] = dv4{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (int ks = 0; ks < kKC / 4; ++ks) {
+            double a[kWR], b[kWC];
+#pragma unroll
+            for (int x = 0; x < kWR; ++x) a[x] = sY[(4 * ks + lk) * kLY + wr * 16 * kWR + 16 * x + li];
+#pragma unroll
+            for (int y = 0; y < kWC; ++y) b[y] = sB[(4 * ks + lk) * kLB + wc * 16 * kWC + 16 * y + li];
+#pragma unroll
+            for (int x = 0; x < kWR; ++x)
+#pragma unroll
+                for (int y = 0; y < kWC; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+        }
+        if (kc != nk - 1) return;
         // online log-sum-exp over this tile's columns
+        const int m0 = mb + (c / nk) * kTM;
+        double gn[kWC];
+        bool ok[kWC];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            double tmax = -INFINITY;
-            double ll[4];
+        for (int y = 0; y < kWC; ++y) {
+            const int m = m0 + wc * 16 * kWC + 16 * y + li;
+            ok[y] = m < me;
+            gn[y] = ok[y] ? gnorm[m] : 0.0;
+        }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int m = m0 + tc + 16 * j;
-                ll[j] = m < me ? -acc[i][j] * inv2s2 : -INFINITY;
-                tmax = fmax(tmax, ll[j]);
+        for (int x = 0; x < kWR; ++x)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double ll[kWC], tmax = -INFINITY;
+#pragma unroll
+                for (int y = 0; y < kWC; ++y) {
+                    const double d2 = fma(-2.0, acc[x][y][v], yn[x][v] + gn[y]);
+                    ll[y] = ok[y] ? -d2 * inv2s2 : -INFINITY;
+                    tmax = fmax(tmax, ll[y]);
+                }
+                if (tmax == -INFINITY) continue;
+                const double nm = fmax(mx[x][v], tmax);
+                double s = sm[x][v];
+                if (mx[x][v] != nm) s = mx[x][v] - nm > kDrop ? s * exp(mx[x][v] - nm) : 0.0;
+                float f = 0.f;
+#pragma unroll
+                for (int y = 0; y < kWC; ++y) {
+                    const double z = ll[y] - nm;
+                    if (z > kDrop) f += __expf((float)z);
+                }
+                mx[x][v] = nm;
+                sm[x][v] = s + (double)f;
             }
-            if (tmax == -INFINITY) continue;
-            const double nm = fmax(mx[i], tmax);
-            double s = sm[i] * exp(mx[i] - nm);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) s += exp(ll[j] - nm);
-            mx[i] = nm;
-            sm[i] = s;
+    };
+
+    fetch(0, rg[0], re[0], rb[0]);
+    fetch(1, rg[1], re[1], rb[1]);
+    for (int c = 0; c < nchunks; c += 2) {
+        store(c, rg[0], re[0], rb[0]);
+        __syncthreads();
+        fetch(c + 2, rg[0], re[0], rb[0]);
+        compute(c);
+        if (c + 1 < nchunks) {
+            store(c + 1, rg[1], re[1], rb[1]);
+            __syncthreads();
+            fetch(c + 3, rg[1], re[1], rb[1]);
+            compute(c + 1);
         }
     }
+    __syncthreads();
+    double* pmx = smem;
+    double* psum = smem + kNP * kTN;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        pmx[tc][tr + 16 * i] = mx[i];
-        psum[tc][tr + 16 * i] = sm[i];
-    }
+    for (int x = 0; x < kWR; ++x)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = wr * 16 * kWR + 16 * x + lk + 4 * v;
+            pmx[(wc * 16 + li) * kTN + r] = mx[x][v];
+            psum[(wc * 16 + li) * kTN + r] = sm[x][v];
+        }
     __syncthreads();
     if (t < kTN && n0 + t < nouter) {
         double M = -INFINITY;
-        for (int c = 0; c < 16; ++c) M = fmax(M, pmx[c][t]);
+        for (int c = 0; c < kNP; ++c) M = fmax(M, pmx[c * kTN + t]);
         double S = 0.0;
-        for (int c = 0; c < 16; ++c)
-            if (pmx[c][t] > -INFINITY) S += psum[c][t] * exp(pmx[c][t] - M);
+        for (int c = 0; c < kNP; ++c)
+            if (pmx[c * kTN + t] > -INFINITY) S += psum[c * kTN + t] * exp(pmx[c * kTN + t] - M);
         part_max[(size_t)blockIdx.y * nouter + n0 + t] = M;
         part_sum[(size_t)blockIdx.y * nouter + n0 + t] = S;
     }
@@ -164,8 +274,11 @@ __global__ void mean_kernel(const double* __restrict__ x, int n, double* __restr
 
 }  // namespace
 
+// Partials (max, sum) per split and outer sample, then the squared norms of
+// the y_n and of the g_m.
 size_t nested_workspace(int nouter, int ninner) {
-    return 2 * (size_t)nested_splits(nouter, ninner) * nouter * sizeof(double);
+    return (2 * (size_t)nested_splits(nouter, ninner) * nouter + nouter + ninner) *
+           sizeof(double);
 }
 
 // Inner-range splits: enough blocks to fill the chip when the outer rows
@@ -185,9 +298,14 @@ void launch_nested(const float* gout, const float* noise, const float* gin, int 
     mchunk = (mchunk + kTM - 1) / kTM * kTM;
     double* pmax = work;
     double* psum = work + (size_t)split * nouter;
+    double* ynorm = psum + (size_t)split * nouter;
+    double* gnorm = ynorm + nouter;
+    nested_sqnorm_kernel<<<(nouter + 3) / 4, 256, 0, s>>>(gout, noise, nouter, nobs, sigma, ynorm);
+    nested_sqnorm_kernel<<<(ninner + 3) / 4, 256, 0, s>>>(gin, nullptr, ninner, nobs, 0.0, gnorm);
     const dim3 grid((nouter + kTN - 1) / kTN, split);
-    nested_lse_kernel<<<grid, 256, 0, s>>>(gout, noise, gin, nouter, ninner, nobs, sigma,
-                                           1.0 / (2.0 * sigma * sigma), mchunk, pmax, psum);
+    nested_lse_kernel<<<grid, kThreads, 0, s>>>(gout, noise, gin, ynorm, gnorm, nouter, ninner,
+                                                nobs, sigma, 1.0 / (2.0 * sigma * sigma), mchunk,
+                                                pmax, psum);
     nested_merge_kernel<<<(nouter + 255) / 256, 256, 0, s>>>(noise, nouter, ninner, nobs,
                                                              split, pmax, psum, logratio);
     if (eig) mean_kernel<<<1, 256, 0, s>>>(logratio, nouter, eig);

@@ -57,6 +57,45 @@ def test_nested_kernel_matches_oracle(ctx, N, M, K):
     assert abs(eig - ref.mean()) <= NAT_TOL
 
 
+def test_nested_inner_splits_with_empty_tail_match_oracle(ctx):
+    # 130 outer rows (a full and a 2-row block), 4100 inner samples over 16
+    # inner-range splits of 320 whose last three hold no columns, 45
+    # observations (two full k chunks and a ragged one)
+    _say("nested kernel N=130 M=4100 K=45 (splits, empty tail)")
+    rng = np.random.default_rng(41)
+    sigma = 0.02
+    A = rng.standard_normal((45, 4)) * 0.2
+    go = (rng.standard_normal((130, 4)) @ A.T).astype(np.float32)
+    gi = (rng.standard_normal((4100, 4)) @ A.T).astype(np.float32)
+    noise = rng.standard_normal((130, 45)).astype(np.float32)
+    lr, eig = _run(ctx, go, noise, gi, sigma)
+    ref = nested.log_ratios(go.astype(np.float64), noise.astype(np.float64),
+                            gi.astype(np.float64), sigma)
+    assert np.max(np.abs(lr - ref)) <= NAT_TOL, np.max(np.abs(lr - ref))
+    assert abs(eig - ref.mean()) <= NAT_TOL
+
+
+def test_nested_large_amplitude_within_gram_rounding(ctx):
+    # traces of up to ~3e4 sigma: the squared distances, formed as |y|^2 +
+    # |g|^2 - 2<y, g>, round to ~K 2^-53 (|y|^2 + |g|^2) / (2 sigma^2), here
+    # ~3e-5 nats at most
+    _say("nested kernel N=257 M=700 K=37 at up to ~3e4 sigma")
+    rng = np.random.default_rng(77)
+    sigma = 0.01
+    A = rng.standard_normal((37, 3)) * 30.0
+    go = (rng.standard_normal((257, 3)) @ A.T).astype(np.float32)
+    gi = (rng.standard_normal((700, 3)) @ A.T).astype(np.float32)
+    noise = rng.standard_normal((257, 37)).astype(np.float32)
+    assert np.abs(go).max() / sigma > 1000
+    lr, _ = _run(ctx, go, noise, gi, sigma)
+    ref = nested.log_ratios(go.astype(np.float64), noise.astype(np.float64),
+                            gi.astype(np.float64), sigma)
+    y = go.astype(np.float64) + sigma * noise.astype(np.float64)
+    bound = 37 * 2.0 ** -53 * (np.sum(y ** 2, axis=1).max() + np.sum(gi.astype(np.float64) ** 2, axis=1).max()) \
+        / (2 * sigma ** 2)
+    assert np.max(np.abs(lr - ref)) <= max(4 * bound, 1e-5), (np.max(np.abs(lr - ref)), bound)
+
+
 def test_nested_reuse_bound_and_single_sample(ctx):
     rng = np.random.default_rng(5)
     g = rng.standard_normal((200, 50)).astype(np.float32)
