@@ -1195,6 +1195,7 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
     std::vector<double> th_cur(theta_star, theta_star + (size_t)nsample * kNT);
     // per-sample device region: truth, nominal and 7 sensitivity traces, the
     // dual's traces, injection and window record, descriptors, H1, grad, H2
+    // (the last three as rows of chunk-wide arrays)
     auto sample_bytes = [&](int i) {
         const size_t tr = align_up((size_t)(grid[i].nsteps + 1) * rec[i].n * sizeof(float2));
         return 10 * tr + align_up((size_t)grid[i].nsteps * rec[i].n * sizeof(float2)) +
@@ -1224,7 +1225,7 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
         const int ns = s1 - s0;
         Carve cv;
         struct Off {
-            size_t ystar, nominal, sens[kNT], dtr, rf, wrec, H1, grad, H2;
+            size_t ystar, nominal, sens[kNT], dtr, rf, wrec;
         };
         std::vector<Off> off(ns);
         for (int q = 0; q < ns; ++q) {
@@ -1236,10 +1237,12 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
             off[q].dtr = cv.take(tr);
             off[q].rf = cv.take((size_t)grid[i].nsteps * rec[i].n * sizeof(float2));
             off[q].wrec = cv.take((size_t)grid[i].nsteps * kSrcW * kSrcW * sizeof(float2));
-            off[q].H1 = cv.take(kNT * kNT * sizeof(double));
-            off[q].grad = cv.take(kNT * sizeof(double));
-            off[q].H2 = cv.take(kNT * kNT * sizeof(double));
         }
+        // H1 [ns][7][7], gradients [ns][7], H2 [ns][7][7]: one Hessian launch
+        // and one copy each per chunk
+        const size_t o_H1 = cv.take((size_t)ns * kNT * kNT * sizeof(double));
+        const size_t o_grad = cv.take((size_t)ns * kNT * sizeof(double));
+        const size_t o_H2 = cv.take((size_t)ns * kNT * kNT * sizeof(double));
         const size_t o_sd = cv.take(ns * sizeof(SampleDesc));
         const size_t o_h2 = cv.take(ns * sizeof(H2Job));
         const size_t o_sig = cv.take(ns * sizeof(double));
@@ -1297,7 +1300,7 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
                 sd.nominal = tp(off[q].nominal);
                 sd.ystar = tp(off[q].ystar);
                 sd.noise = (const float2*)noise[i];
-                sd.grad = (double*)(ws + off[q].grad);
+                sd.grad = (double*)(ws + o_grad) + (size_t)q * kNT;
                 for (int j = 0; j < kNT; ++j) {
                     SolveSpec pj = sp;
                     pj.param = j;
@@ -1314,26 +1317,22 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
             std::vector<char> blob(ns * sizeof(SampleDesc));
             std::memcpy(blob.data(), sds.data(), blob.size());
             if ((rc = upload(c, ws + o_sd, blob, s))) return rc;
-            // H1 of every sample into its own slot: one launch per sample keeps
-            // the output contiguous per sample
-            for (int q = 0; q < ns; ++q)
-                launch_hessian((const SampleDesc*)(ws + o_sd) + q, 1, 0, 1,
-                               (const double*)(ws + o_sig) + q, (double*)(ws + off[q].H1), s);
+            // H1 and the gradient of every sample (row q of the chunk arrays)
+            launch_hessian((const SampleDesc*)(ws + o_sd), ns, 0, 1, (const double*)(ws + o_sig),
+                           (double*)(ws + o_H1), s);
             HIP_TRY(hipGetLastError());
             if (it == iters) break;
-            for (int q = 0; q < ns; ++q) {
-                HIP_TRY(hipMemcpyAsync(&hbuf[(size_t)q * (kNT * kNT + kNT)], ws + off[q].H1,
-                                       kNT * kNT * sizeof(double), hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipMemcpyAsync(&hbuf[(size_t)q * (kNT * kNT + kNT) + kNT * kNT],
-                                       ws + off[q].grad, kNT * sizeof(double),
-                                       hipMemcpyDeviceToHost, s));
-            }
+            HIP_TRY(hipMemcpyAsync(hbuf.data(), ws + o_H1, (size_t)ns * kNT * kNT * sizeof(double),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(hbuf.data() + (size_t)ns * kNT * kNT, ws + o_grad,
+                                   (size_t)ns * kNT * sizeof(double), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             for (int q = 0; q < ns; ++q) {
-                const double* Hq = &hbuf[(size_t)q * (kNT * kNT + kNT)];
+                const double* Hq = &hbuf[(size_t)q * kNT * kNT];
+                const double* gq = &hbuf[(size_t)ns * kNT * kNT + (size_t)q * kNT];
                 double* th = &th_cur[(size_t)(s0 + q) * kNT];
                 double step[kNT];
-                if (!gn_step(Hq, Hq + kNT * kNT, *prior, th, step))
+                if (!gn_step(Hq, gq, *prior, th, step))
                     return set_error(EIG_ENOTPD, "Gauss-Newton system not positive definite");
                 for (int j = 0; j < kNT; ++j) th[j] += step[j];
             }
@@ -1366,7 +1365,7 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
                 J.i0 = J.kx - 2;
                 J.k0 = J.kz - 2;
                 J.wrec = tp(off[q].wrec);
-                J.H2 = (double*)(ws + off[q].H2);
+                J.H2 = (double*)(ws + o_H2) + (size_t)q * kNT * kNT;
             }
             HIP_TRY(hipGetLastError());
             if ((rc = run_wave(c, sol, grids, media, recsets, ws + solve_base,
@@ -1378,12 +1377,10 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
             launch_h2((const H2Job*)(ws + o_h2), ns, s);
         }
         // 5. outputs of the chunk
-        for (int q = 0; q < ns; ++q) {
-            HIP_TRY(hipMemcpyAsync(H1out + (size_t)(s0 + q) * kNT * kNT, ws + off[q].H1,
-                                   kNT * kNT * sizeof(double), hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(H2out + (size_t)(s0 + q) * kNT * kNT, ws + off[q].H2,
-                                   kNT * kNT * sizeof(double), hipMemcpyDeviceToDevice, s));
-        }
+        HIP_TRY(hipMemcpyAsync(H1out + (size_t)s0 * kNT * kNT, ws + o_H1,
+                               (size_t)ns * kNT * kNT * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(H2out + (size_t)s0 * kNT * kNT, ws + o_H2,
+                               (size_t)ns * kNT * kNT * sizeof(double), hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));  // the next chunk reuses the workspace
         s0 = s1;
     }
