@@ -1200,7 +1200,7 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
         const size_t tr = align_up((size_t)(grid[i].nsteps + 1) * rec[i].n * sizeof(float2));
         return 10 * tr + align_up((size_t)grid[i].nsteps * rec[i].n * sizeof(float2)) +
                align_up((size_t)grid[i].nsteps * kSrcW * kSrcW * sizeof(float2)) +
-               align_up(sizeof(SampleDesc)) + align_up(sizeof(H2Job)) +
+               align_up(sizeof(SampleDesc)) + align_up(sizeof(H2Job)) + align_up(sizeof(DualJob)) +
                3 * align_up(kNT * kNT * sizeof(double)) + 4 * kAlign;
     };
     int s0 = 0;
@@ -1245,6 +1245,7 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
         const size_t o_H2 = cv.take((size_t)ns * kNT * kNT * sizeof(double));
         const size_t o_sd = cv.take(ns * sizeof(SampleDesc));
         const size_t o_h2 = cv.take(ns * sizeof(H2Job));
+        const size_t o_dj = cv.take(ns * sizeof(DualJob));
         const size_t o_sig = cv.take(ns * sizeof(double));
         const size_t o_th = cv.take((size_t)ns * kNT * sizeof(double));
         const size_t solve_base = align_up(cv.off);
@@ -1341,11 +1342,14 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
         {
             std::vector<SolveSpec> sol;
             std::vector<H2Job> jobs(ns);
+            std::vector<DualJob> djobs(ns);
+            size_t max_elems = 0;
             for (int q = 0; q < ns; ++q) {
                 const int i = s0 + q;
                 const eig_grid& g = grid[i];
-                launch_dual_force(tp(off[q].ystar), (const float2*)noise[i], tp(off[q].nominal),
-                                  sigma, 2.0 / (g.h * g.h), g.nsteps, rec[i].n, tp(off[q].rf), s);
+                djobs[q] = DualJob{tp(off[q].ystar), (const float2*)noise[i], tp(off[q].nominal),
+                                   tp(off[q].rf), sigma, 2.0 / (g.h * g.h), g.nsteps, rec[i].n};
+                max_elems = std::max(max_elems, (size_t)g.nsteps * rec[i].n);
                 double th0[kNT];
                 std::memcpy(th0, &th_cur[(size_t)i * kNT], sizeof(th0));
                 SolveSpec sp = base_spec(i, th0);
@@ -1366,6 +1370,12 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
                 J.k0 = J.kz - 2;
                 J.wrec = tp(off[q].wrec);
                 J.H2 = (double*)(ws + o_H2) + (size_t)q * kNT * kNT;
+            }
+            {
+                std::vector<char> dblob(ns * sizeof(DualJob));
+                std::memcpy(dblob.data(), djobs.data(), dblob.size());
+                if ((rc = upload(c, ws + o_dj, dblob, s))) return rc;
+                launch_dual_force((const DualJob*)(ws + o_dj), ns, max_elems, s);
             }
             HIP_TRY(hipGetLastError());
             if ((rc = run_wave(c, sol, grids, media, recsets, ws + solve_base,

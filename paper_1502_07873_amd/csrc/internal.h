@@ -109,6 +109,15 @@ struct H2Job {
     double* H2;                  // [7][7] output
 };
 
+struct DualJob {
+    const float2* ystar;         // truth traces g(theta*) [N+1][nrec]
+    const float2* noise;         // standard normal draws [N+1][nrec]
+    const float2* ghat;          // traces at the MAP point [N+1][nrec]
+    float2* rforce;              // [N][nrec] output
+    double sigma, w_inv;
+    int32_t nsteps, nrec;
+};
+
 // launchers (all asynchronous on `s`)
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 void launch_layered_coef(const double* rho, const double* lam, const double* mu,
@@ -171,11 +180,10 @@ void launch_greedy_step(const double* H1r, int nsample, int ncand,
 void launch_surface_peak(const float2* traces, int count, double rel,
                          double* out, hipStream_t s);
 void launch_h2(const H2Job* jobs, int njobs, hipStream_t s);
+// Receiver forcing of the dual solves, one job per solve:
 // rforce[s][r] = w_inv * ((ystar - ghat) + sigma noise)[N - s][r] / sigma^2,
-// s = 0..N-1, for one dual solve (traces [N+1][nrec]).
-void launch_dual_force(const float2* ystar, const float2* noise, const float2* ghat,
-                       double sigma, double w_inv, int nsteps, int nrec, float2* rforce,
-                       hipStream_t s);
+// s = 0..N-1 (traces [N+1][nrec]); max_elems = the largest N * nrec.
+void launch_dual_force(const DualJob* jobs, int njobs, size_t max_elems, hipStream_t s);
 // Theorem 3 integrand per sample and the weighted average.
 void launch_theorem3(const double* H1, const double* H2, int nsample,
                      const eig_prior* prior_dev, const double* theta_hat, const double* w,

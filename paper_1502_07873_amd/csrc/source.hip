@@ -400,20 +400,20 @@ __global__ void __launch_bounds__(128) h2_kernel(const H2Job* __restrict__ jobs)
     }
 }
 
-__global__ void dual_force_kernel(const float2* __restrict__ ystar,
-                                  const float2* __restrict__ noise,
-                                  const float2* __restrict__ ghat, double sigma, double w_inv,
-                                  int nsteps, int nrec, float2* __restrict__ rforce) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)nsteps * nrec) return;
-    const int s = (int)(e / nrec), r = (int)(e % nrec);
-    const size_t src = (size_t)(nsteps - s) * nrec + r;   // level N - s
-    const float2 y = ystar[src], g = ghat[src], z = noise[src];
-    const double sc = w_inv / (sigma * sigma);
-    float2 o;
-    o.x = (float)((((double)y.x - (double)g.x) + sigma * (double)z.x) * sc);
-    o.y = (float)((((double)y.y - (double)g.y) + sigma * (double)z.y) * sc);
-    rforce[e] = o;
+__global__ void dual_force_kernel(const DualJob* __restrict__ jobs, int njobs) {
+    for (int j = blockIdx.y; j < njobs; j += gridDim.y) {
+        const DualJob& J = jobs[j];
+        const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (e >= (size_t)J.nsteps * J.nrec) continue;
+        const int s = (int)(e / J.nrec), r = (int)(e % J.nrec);
+        const size_t src = (size_t)(J.nsteps - s) * J.nrec + r;   // level N - s
+        const float2 y = J.ystar[src], g = J.ghat[src], z = J.noise[src];
+        const double sigma = J.sigma, sc = J.w_inv / (sigma * sigma);
+        float2 o;
+        o.x = (float)((((double)y.x - (double)g.x) + sigma * (double)z.x) * sc);
+        o.y = (float)((((double)y.y - (double)g.y) + sigma * (double)z.y) * sc);
+        J.rforce[e] = o;
+    }
 }
 
 }  // namespace
@@ -443,13 +443,10 @@ void launch_h2(const H2Job* jobs, int njobs, hipStream_t s) {
     if (njobs > 0) h2_kernel<<<njobs, 128, 0, s>>>(jobs);
 }
 
-void launch_dual_force(const float2* ystar, const float2* noise, const float2* ghat,
-                       double sigma, double w_inv, int nsteps, int nrec, float2* rforce,
-                       hipStream_t s) {
-    const size_t n = (size_t)nsteps * nrec;
-    if (n == 0) return;
-    dual_force_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ystar, noise, ghat, sigma,
-                                                                  w_inv, nsteps, nrec, rforce);
+void launch_dual_force(const DualJob* jobs, int njobs, size_t max_elems, hipStream_t s) {
+    if (njobs <= 0 || max_elems == 0) return;
+    const dim3 grid((unsigned)((max_elems + 255) / 256), (unsigned)(njobs < 65535 ? njobs : 65535));
+    dual_force_kernel<<<grid, 256, 0, s>>>(jobs, njobs);
 }
 
 }  // namespace eig
