@@ -19,12 +19,12 @@
 //
 // Work decomposition: a 512-thread block (8 waves, 4 x 2) owns 128 outer rows
 // and a range of inner samples (the range is split over several blocks when
-// the rows alone cannot fill the chip), swept in tiles of 64 columns; each
-// wave accumulates 2 x 2 MFMA tiles (32 rows x 32 columns).  k is staged
+// the rows alone cannot fill the chip), swept in tiles of 128 columns; each
+// wave accumulates 2 x 4 MFMA tiles (32 rows x 64 columns).  k is staged
 // through LDS in chunks of 16 (y in FP64, g as FP64 copies of the FP32
 // inputs), double buffered, with the global loads of the chunk after next in
 // flight while the current one is multiplied: one barrier per chunk.  After a
-// tile's last chunk every lane folds its 16 distances into an online
+// tile's last chunk every lane folds its 32 distances into an online
 // log-sum-exp per row: the running maximum and the rescaling of the running
 // sum in FP64, the terms within 40 nats of the maximum as FP32 exponentials
 // (relative error ~3e-6 each, so at most ~3e-6 nats in a log ratio).  Terms
@@ -40,10 +40,10 @@ namespace {
 typedef double dv4 __attribute__((ext_vector_type(4)));
 
 // Tile geometry: 8 waves as kGR x kGC, each kWR x kWC 16x16 MFMA tiles.
-constexpr int kWR = 2, kWC = 2, kGR = 4, kGC = 2, kKC = 16;
+constexpr int kWR = 2, kWC = 4, kGR = 4, kGC = 2, kKC = 16;
 constexpr int kThreads = 64 * kGR * kGC;          // 512
 constexpr int kTN = 16 * kGR * kWR;               // 128 outer rows per block
-constexpr int kTM = 16 * kGC * kWC;               // 64 inner columns per tile
+constexpr int kTM = 16 * kGC * kWC;               // 128 inner columns per tile
 constexpr int kLY = kTN + 1, kLB = kTM + 1;       // padded LDS rows (conflict-free stores)
 constexpr int kQY = kKC * kTN / kThreads;         // y values staged per thread and chunk
 constexpr int kQB = kKC * kTM / kThreads;         // g values staged per thread and chunk
@@ -282,11 +282,11 @@ size_t nested_workspace(int nouter, int ninner) {
 }
 
 // Inner-range splits: enough blocks to fill the chip when the outer rows
-// are few, each split at least four column tiles long.
+// are few, each split at least two column tiles long.
 int nested_splits(int nouter, int ninner) {
     const int rows = (nouter + kTN - 1) / kTN;
     int split = 1;
-    while (rows * split < 2048 && (ninner + split * 2 - 1) / (split * 2) >= 4 * kTM) split *= 2;
+    while (rows * split < 2048 && (ninner + split * 2 - 1) / (split * 2) >= 2 * kTM) split *= 2;
     return split;
 }
 

@@ -59,7 +59,7 @@ def test_nested_kernel_matches_oracle(ctx, N, M, K):
 
 def test_nested_inner_splits_with_empty_tail_match_oracle(ctx):
     # 130 outer rows (a full and a 2-row block), 4100 inner samples over 16
-    # inner-range splits of 320 whose last three hold no columns, 45
+    # inner-range splits of 384 whose last five hold no columns, 45
     # observations (two full k chunks and a ragged one)
     _say("nested kernel N=130 M=4100 K=45 (splits, empty tail)")
     rng = np.random.default_rng(41)
