@@ -27,11 +27,6 @@ if ROOT not in sys.path:
 METRIC = ("EIG evals/s and grid-pt updates/s (HBM GB/s % peak) at ≤1e-3 nat err; "
           "p50/p99")
 HBM_PEAK_GBS = 8000.0
-# FP32 vector issue rate without packed-FP32 instructions (the library's
-# kernels are compiled not to use them): 256 CUs x 4 SIMDs x 16 lanes x
-# 2.4 GHz lane operations/s; the
-# published 157.3 TFLOP/s counts an FMA as two flops on packed pairs.
-ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 FP64_MFMA_PEAK_FLOPS = 78.6e12   # published dense FP64 matrix rate
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_layered_c2_traffic.json")
 
