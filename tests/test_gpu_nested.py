@@ -174,3 +174,34 @@ def test_active_mask_gaussian_prior_marginal(ctx):
     pr = {"kind": "gaussian", "mean": mean[act], "cov": cov[np.ix_(act, act)]}
     want = [laplace.dkl_hat(H[s][np.ix_(act, act)], th[s][act], pr)[0] for s in range(S)]
     assert np.max(np.abs(dkl.cpu().numpy() - want)) < 1e-9
+
+
+def test_nested_full_size_sampled_rows(ctx):
+    # Section 4.4 size: N = M = 4e5 outer samples reused as the inner ones,
+    # K = 204 observations (51 levels x 2 receivers x 2 components), traces of
+    # up to ~16 sigma, so log ratios of 6-10 nats, below log M: many inner
+    # samples contribute to each evidence.  Every log ratio is at most log M
+    # (reuse); sampled rows, the first and last blocks' edges included,
+    # against the oracle
+    N, K, sigma = 400_000, 204, 0.01
+    _say(f"nested full size N=M={N} K={K}")
+    rng = np.random.default_rng(2024)
+    A = (rng.standard_normal((K, 3)) * 0.03).astype(np.float32)
+    th = rng.uniform(-1.0, 1.0, (N, 3)).astype(np.float32)
+    g = th @ A.T
+    noise = rng.standard_normal((N, K), dtype=np.float32)
+    gd = torch.as_tensor(g, device="cuda")
+    nd = torch.as_tensor(noise, device="cuda")
+    lr = torch.empty(N, dtype=torch.float64, device="cuda")
+    eig = torch.empty(1, dtype=torch.float64, device="cuda")
+    ctx.nested_mc_eig(gd, nd, gd, sigma, lr, eig)
+    torch.cuda.synchronize()
+    lr = lr.cpu().numpy()
+    assert np.all(np.isfinite(lr))
+    assert np.all(lr <= math.log(N) + 1e-6)
+    assert abs(float(eig.cpu()[0]) - lr.mean()) < 1e-9 * max(1.0, abs(lr.mean()))
+    rows = np.unique(np.concatenate([[0, 127, 128, N - 129, N - 1],
+                                     rng.integers(0, N, 11)]))
+    g64 = g.astype(np.float64)
+    ref = nested.log_ratios(g64[rows], noise[rows].astype(np.float64), g64, sigma)
+    assert np.max(np.abs(lr[rows] - ref)) <= NAT_TOL, np.max(np.abs(lr[rows] - ref))
