@@ -137,6 +137,50 @@ def _ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
+def _dev(t, name, dtype, count, optional=False):
+    """A device array the library reads or writes through a raw pointer is
+    refused here, before any launch, unless it is a contiguous GPU tensor of
+    `dtype` holding at least `count` values (None where it is optional)."""
+    import torch
+    if t is None:
+        if optional:
+            return
+        raise EigError(EIG_EINVAL, f"{name}: a device tensor is required")
+    if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype
+            or not t.is_contiguous() or t.numel() < count):
+        raise EigError(EIG_EINVAL, f"{name}: expected a contiguous {dtype} device tensor "
+                                   f"of at least {count} values")
+
+
+def _dev_list(ts, name, dtype, counts, optional=False, entries_optional=False):
+    """One device array per solve or sample (see _dev); with
+    entries_optional, single entries may be None (nothing kept for them)."""
+    if ts is None:
+        if optional:
+            return
+        raise EigError(EIG_EINVAL, f"{name}: a list of device tensors is required")
+    if len(ts) != len(counts):
+        raise EigError(EIG_EINVAL, f"{name}: expected {len(counts)} tensors, got {len(ts)}")
+    for i, (t, c) in enumerate(zip(ts, counts)):
+        _dev(t, f"{name}[{i}]", dtype, c, optional=entries_optional)
+
+
+def _host(a, name, count, dtype=np.float64):
+    """A host array the library reads `count` values of."""
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if arr.size < count:
+        raise EigError(EIG_EINVAL, f"{name}: expected at least {count} values, got {arr.size}")
+    return arr
+
+
+def _theta(a, name, n):
+    """Host [n][7] parameter rows."""
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    if arr.size != n * NTHETA:
+        raise EigError(EIG_EINVAL, f"{name}: expected {n} x {NTHETA} values, got {arr.size}")
+    return arr.reshape(n, NTHETA)
+
+
 def _np_ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -278,6 +322,22 @@ class Context:
             arr[k] = Receivers(r.size, r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         return arr, keep
 
+    @staticmethod
+    def _jacobian_outputs(grids, receivers, per_receiver, H1, nominal, J, status):
+        """Device outputs of jacobian_fd / jacobian_sensitivity (see _dev)."""
+        import torch
+        n = len(grids)
+        if len(receivers) != n:
+            raise EigError(EIG_EINVAL, "one receiver array per grid expected")
+        groups = len(receivers[0]) if (per_receiver and n) else 1
+        _dev(H1, "H1", torch.float64, n * groups * NTHETA * NTHETA)
+        _dev(status, "status", torch.int32, n, optional=True)
+        levels = [(int(g[4]) + 1) * len(r) * 2 for g, r in zip(grids, receivers)]
+        _dev_list(nominal, "nominal", torch.float32, levels, optional=True,
+                  entries_optional=True)
+        _dev_list(J, "J", torch.float64, [c * NTHETA for c in levels], optional=True,
+                  entries_optional=True)
+
     # -- entry points --------------------------------------------------------
     def forward_solve_batch(self, grids, media, theta, receivers, traces,
                             dev_param=None, dev_step=None, stf="gauss_deriv",
@@ -285,11 +345,16 @@ class Context:
         """grids: [(nx, nz, h, dt, nsteps)]; media: [(kind, rho, lam, mu)]
         with device float64 tensors; theta: [n][7]; receivers: [int arrays];
         traces: [float32 device tensors [nsteps+1][nrec][2]]."""
+        import torch
         n = len(grids)
-        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(n, NTHETA)
+        if len(receivers) != n:
+            raise EigError(EIG_EINVAL, "one receiver array per grid expected")
+        _dev_list(traces, "traces", torch.float32,
+                  [(int(g[4]) + 1) * len(r) * 2 for g, r in zip(grids, receivers)])
+        th = _theta(theta, "theta", n)
         recs, keep = self._receivers(receivers)
-        dp = None if dev_param is None else np.ascontiguousarray(dev_param, dtype=np.int32)
-        ds = None if dev_step is None else np.ascontiguousarray(dev_step, dtype=np.float64)
+        dp = None if dev_param is None else _host(dev_param, "dev_param", n, np.int32)
+        ds = None if dev_step is None else _host(dev_step, "dev_step", n)
         _check(_lib.forward_solve_batch(
             self._h, n, self._grids(grids), self._media(media, grids), _np_ptr(th),
             None if dp is None else _np_ptr(dp), None if ds is None else _np_ptr(ds),
@@ -301,7 +366,8 @@ class Context:
                     per_receiver=False, nominal=None, J=None, status=None,
                     stream=None):
         n = len(grids)
-        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(n, NTHETA)
+        self._jacobian_outputs(grids, receivers, per_receiver, H1, nominal, J, status)
+        th = _theta(theta, "theta", n)
         sg = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (n,)))
         recs, keep = self._receivers(receivers)
         _check(_lib.jacobian_fd(
@@ -315,7 +381,8 @@ class Context:
                              stf="gauss_deriv", sigma_mode=SIGMA_GIVEN, per_receiver=False,
                              nominal=None, J=None, status=None, stream=None):
         n = len(grids)
-        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(n, NTHETA)
+        self._jacobian_outputs(grids, receivers, per_receiver, H1, nominal, J, status)
+        th = _theta(theta, "theta", n)
         sg = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (n,)))
         recs, keep = self._receivers(receivers)
         _check(_lib.jacobian_sensitivity(
@@ -325,14 +392,20 @@ class Context:
         del keep
 
     def nested_mc_eig(self, g_outer, noise, g_inner, sigma, logratio, eig=None, stream=None):
-        """g_outer/noise [N][K], g_inner [M][K] device float32 (contiguous)."""
+        """g_outer/noise [N][K], g_inner [M][K] device float32 (contiguous);
+        logratio [N] and eig [1] (or None) device float64."""
+        import torch
+        if g_outer.dim() != 2 or g_inner.dim() != 2:
+            raise EigError(EIG_EINVAL, "nested_mc_eig: g_outer and g_inner are [rows][K]")
         n, k = int(g_outer.shape[0]), int(g_outer.shape[1])
         m = int(g_inner.shape[0])
-        for t in (g_outer, noise, g_inner):
-            if not t.is_contiguous() or str(t.dtype) != "torch.float32":
-                raise ValueError("nested_mc_eig needs contiguous float32 tensors")
         if tuple(noise.shape) != (n, k) or int(g_inner.shape[1]) != k:
-            raise ValueError("nested_mc_eig shape mismatch")
+            raise EigError(EIG_EINVAL, "nested_mc_eig: shape mismatch")
+        _dev(g_outer, "g_outer", torch.float32, n * k)
+        _dev(noise, "noise", torch.float32, n * k)
+        _dev(g_inner, "g_inner", torch.float32, m * k)
+        _dev(logratio, "logratio", torch.float64, n)
+        _dev(eig, "eig", torch.float64, 1, optional=True)
         _check(_lib.nested_mc_eig(self._h, n, m, k, _ptr(g_outer), _ptr(noise), _ptr(g_inner),
                                   float(sigma), _ptr(logratio), _ptr(eig), _stream(stream)))
 
@@ -341,8 +414,18 @@ class Context:
                      stream=None):
         """Returns theta_hat [n][7] (numpy); H1/H2/val/eig/status are device
         tensors filled asynchronously."""
+        import torch
         n = len(grids)
-        th = np.ascontiguousarray(theta_star, dtype=np.float64).reshape(n, NTHETA)
+        if len(receivers) != n:
+            raise EigError(EIG_EINVAL, "one receiver array per grid expected")
+        _dev_list(noise, "noise", torch.float32,
+                  [(int(g[4]) + 1) * len(r) * 2 for g, r in zip(grids, receivers)])
+        _dev(H1, "H1", torch.float64, n * NTHETA * NTHETA)
+        _dev(H2, "H2", torch.float64, n * NTHETA * NTHETA)
+        _dev(val, "val", torch.float64, n)
+        _dev(eig, "eig", torch.float64, 1, optional=True)
+        _dev(status, "status", torch.int32, n, optional=True)
+        th = _theta(theta_star, "theta_star", n)
         wa = np.ascontiguousarray(np.broadcast_to(np.asarray(w, dtype=np.float64), (n,)))
         out = np.zeros((n, NTHETA))
         recs, keep = self._receivers(receivers)
@@ -356,28 +439,42 @@ class Context:
 
     def laplace_eig(self, H1, prior: Prior, w, dkl, eig, theta=None, logdet=None,
                     status=None, stream=None):
+        import torch
         n = int(H1.shape[0])
-        wa = np.ascontiguousarray(w, dtype=np.float64)
-        th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+        _dev(H1, "H1", torch.float64, n * NTHETA * NTHETA)
+        _dev(dkl, "dkl", torch.float64, n)
+        _dev(eig, "eig", torch.float64, 1)
+        _dev(logdet, "logdet", torch.float64, n, optional=True)
+        _dev(status, "status", torch.int32, n, optional=True)
+        wa = _host(w, "w", n)
+        th = None if theta is None else _host(theta, "theta", n * NTHETA)
         _check(_lib.laplace_eig(self._h, n, _ptr(H1), ctypes.byref(prior),
                                 None if th is None else _np_ptr(th), _np_ptr(wa),
                                 _ptr(dkl), _ptr(logdet), _ptr(eig), _ptr(status),
                                 _stream(stream)))
 
     def design_eval(self, H1r, mask, prior: Prior, w, eig, theta=None, stream=None):
+        import torch
         ns, nc = int(H1r.shape[0]), int(H1r.shape[1])
         nd = int(mask.shape[0])
-        wa = np.ascontiguousarray(w, dtype=np.float64)
-        th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+        _dev(H1r, "H1r", torch.float64, ns * nc * NTHETA * NTHETA)
+        _dev(mask, "mask", torch.uint8, nd * nc)
+        _dev(eig, "eig", torch.float64, nd)
+        wa = _host(w, "w", ns)
+        th = None if theta is None else _host(theta, "theta", ns * NTHETA)
         _check(_lib.design_eval(self._h, ns, nc, _ptr(H1r), nd, _ptr(mask),
                                 ctypes.byref(prior), None if th is None else _np_ptr(th),
                                 _np_ptr(wa), _ptr(eig), _stream(stream)))
 
     def design_greedy(self, H1r, prior: Prior, w, kmax, order, curve, theta=None,
                       stream=None):
+        import torch
         ns, nc = int(H1r.shape[0]), int(H1r.shape[1])
-        wa = np.ascontiguousarray(w, dtype=np.float64)
-        th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+        _dev(H1r, "H1r", torch.float64, ns * nc * NTHETA * NTHETA)
+        _dev(order, "order", torch.int32, max(int(kmax), 0))
+        _dev(curve, "curve", torch.float64, max(int(kmax), 0))
+        wa = _host(w, "w", ns)
+        th = None if theta is None else _host(theta, "theta", ns * NTHETA)
         _check(_lib.design_greedy(self._h, ns, nc, _ptr(H1r), ctypes.byref(prior),
                                   None if th is None else _np_ptr(th), _np_ptr(wa),
                                   int(kmax), _ptr(order), _ptr(curve), _stream(stream)))
@@ -385,7 +482,7 @@ class Context:
     def noise_sigma_peak(self, grid, medium, theta, rel=1e-3, stf="gauss_deriv",
                          stream=None) -> float:
         out = ctypes.c_double(0.0)
-        th = np.ascontiguousarray(theta, dtype=np.float64)
+        th = _theta(theta, "theta", 1)
         _check(_lib.noise_sigma_peak(self._h, self._grids([grid]), self._media([medium], [grid]),
                                      _np_ptr(th), STF_KINDS[stf], float(rel),
                                      ctypes.byref(out), _stream(stream)))
@@ -415,9 +512,15 @@ class Server:
     def submit(self, grid, medium, theta, receivers, prior: Prior, w, H1, dkl, eig,
                sigma, sigma_mode=SIGMA_GIVEN, rel_step=1e-4, stf="gauss_deriv",
                status=None, chol_status=None) -> int:
-        th = np.ascontiguousarray(theta, dtype=np.float64)
+        import torch
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1, NTHETA)
         n = th.shape[0]
-        wa = np.ascontiguousarray(w, dtype=np.float64)
+        _dev(H1, "H1", torch.float64, n * NTHETA * NTHETA)
+        _dev(dkl, "dkl", torch.float64, n)
+        _dev(eig, "eig", torch.float64, 1)
+        _dev(status, "status", torch.int32, n, optional=True)
+        _dev(chol_status, "chol_status", torch.int32, n, optional=True)
+        wa = _host(w, "w", n)
         recs, keep = Context._receivers([receivers])
         qid = ctypes.c_int64()
         _check(_lib.eig_server_submit(

@@ -82,3 +82,46 @@ def test_library_binds_to_torchs_hip_runtime():
     import torch
     torch_lib = os.path.realpath(os.path.join(os.path.dirname(torch.__file__), "lib"))
     assert all(torch_lib in ln for ln in lines), lines
+
+
+def test_binding_argument_checks_refuse_before_any_call():
+    # device arrays must be contiguous GPU tensors of the right dtype and at
+    # least the size the library will touch; host rows must match exactly
+    torch = pytest.importorskip("torch")
+    from paper_1502_07873_amd import eigseis
+    cpu = torch.zeros(8, dtype=torch.float64)
+    with pytest.raises(eigseis.EigError, match="dkl"):
+        eigseis._dev(cpu, "dkl", torch.float64, 8)
+    with pytest.raises(eigseis.EigError, match="required"):
+        eigseis._dev(None, "H1", torch.float64, 49)
+    eigseis._dev(None, "status", torch.int32, 8, optional=True)
+    with pytest.raises(eigseis.EigError, match="expected 3 tensors"):
+        eigseis._dev_list([cpu, cpu], "traces", torch.float32, [1, 1, 1])
+    eigseis._dev_list(None, "nominal", torch.float32, [1], optional=True)
+    eigseis._dev_list([None, None], "nominal", torch.float32, [1, 1], entries_optional=True)
+    with pytest.raises(eigseis.EigError, match=r"noise\[0\]"):
+        eigseis._dev_list([None, None], "noise", torch.float32, [1, 1])
+    with pytest.raises(eigseis.EigError, match="at least 5"):
+        eigseis._host([1.0, 2.0], "w", 5)
+    assert eigseis._host([1.0, 2.0, 3.0], "w", 3).dtype == np.float64
+    with pytest.raises(eigseis.EigError, match="2 x 7"):
+        eigseis._theta(np.zeros(13), "theta", 2)
+    assert eigseis._theta(np.zeros(14), "theta", 2).shape == (2, 7)
+    # entry points check their arrays before reaching the library: a context
+    # without a device handle never gets that far
+    ctx = object.__new__(eigseis.Context)
+    f32 = torch.zeros((4, 3), dtype=torch.float32)
+    with pytest.raises(eigseis.EigError, match="g_outer"):
+        ctx.nested_mc_eig(f32, f32, f32, 0.1, torch.zeros(4, dtype=torch.float64))
+    with pytest.raises(eigseis.EigError, match="shape mismatch"):
+        ctx.nested_mc_eig(f32, f32[:3], f32, 0.1, torch.zeros(4, dtype=torch.float64))
+    H = torch.zeros((2, 7, 7), dtype=torch.float64)
+    with pytest.raises(eigseis.EigError, match="H1"):
+        ctx.laplace_eig(H, eigseis.make_prior(-np.ones(7), np.ones(7)), [0.5, 0.5],
+                        torch.zeros(2, dtype=torch.float64), torch.zeros(1, dtype=torch.float64))
+    g = (40, 30, 10.0, 1e-3, 10, 0)
+    with pytest.raises(eigseis.EigError, match="traces"):
+        ctx.forward_solve_batch([g], [None], np.zeros(7), [np.array([3, 5])],
+                                [torch.zeros(10, dtype=torch.float32)])
+    with pytest.raises(eigseis.EigError, match="one receiver array per grid"):
+        ctx.forward_solve_batch([g, g], [None, None], np.zeros(14), [np.array([3])], [None, None])
