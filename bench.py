@@ -152,8 +152,8 @@ def _copy_calibration(nbytes=4 << 30, reps=4):
 
 def _serving(ctx, updates_per_s, nquery=24, load=0.7, seed=3, overlap=True):
     """A c4-shaped query stream served by the continuous-batching engine with
-    Poisson arrivals at `load` x the capacity implied by updates_per_s (the
-    grid-point update rate of one unsplit wave, the engine's regime)."""
+    Poisson arrivals at `load` x the capacity implied by updates_per_s (by
+    default the grid-point update rate of one unsplit wave)."""
     import numpy as np
 
     import synthetic
@@ -823,6 +823,15 @@ def main():
         line["serving_queue_only"] = _serving(ctx, unsplit_updates_per_s, overlap=False)
         line["latency_ms"]["serving_p50"] = line["serving"]["latency_p50_s"] * 1e3
         line["latency_ms"]["serving_p99"] = line["serving"]["latency_p99_s"] * 1e3
+        # the same stream offered at twice the rate the cache-chunked waves
+        # sustain (the headline's update rate): a queue forms and admission
+        # decides who waits
+        print("[bench] serving run at 2x the chunked update rate, both disciplines", flush=True)
+        chunked = line["grid_pt_updates_per_s"]
+        line["serving_overload"] = _serving(ctx, chunked, load=2.0)
+        line["serving_overload_queue_only"] = _serving(ctx, chunked, load=2.0, overlap=False)
+        for k in ("serving_overload", "serving_overload_queue_only"):
+            line[k]["load_basis"] = "cache-chunked update rate of the headline wave"
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, 1 sample)", flush=True)
         sig = ctx.noise_sigma_peak(g, med, theta_bar, wl.noise_rel)
