@@ -279,10 +279,14 @@ struct Raw2 {
     float2 h;  // halo column (edge lanes only)
 };
 
+// live: the lane's first column lies inside the grid.  Lanes past nx hold
+// only padding columns, which stay zero in memory and feed no updated node,
+// so their loads are skipped (zeros) and their stores left out.
 __device__ __forceinline__ Raw2 load_raw2(const float2* Q, size_t off, int i0, int hc,
-                                          bool hl) {
+                                          bool hl, bool live = true) {
     Raw2 r;
-    r.c = ld4(Q, off + i0);
+    r.c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live) r.c = ld4(Q, off + i0);
     r.h = make_float2(0.f, 0.f);
     if (hl) r.h = ld2(Q, off + hc);
     return r;
@@ -312,6 +316,7 @@ stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__
     const float* coef = d->coef;
     const bool upd0 = (i0 >= 1) && (i0 <= nx - 2);
     const bool upd1 = (i0 + 1 <= nx - 2);
+    const bool live = i0 < nx;
     const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + 128 < nx);
     const int hc = (lane == 0) ? x0 - 1 : x0 + 128;
     const int si0 = d->src_i0, sk0 = d->src_k0;
@@ -335,21 +340,22 @@ stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__
     if (kb == 0) {
         am = bm = NodeRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     } else {
-        make_rows2(load_raw2(Q, (size_t)(kb - 1) * pitch, i0, hc, hl), am, bm);
+        make_rows2(load_raw2(Q, (size_t)(kb - 1) * pitch, i0, hc, hl, live), am, bm);
     }
-    make_rows2(load_raw2(Q, (size_t)kb * pitch, i0, hc, hl), ac, bc);
+    make_rows2(load_raw2(Q, (size_t)kb * pitch, i0, hc, hl, live), ac, bc);
     // prefetch ring: raw rows k+1..k+D of u^m, rows k..k+D-1 of u^{m-1}
     Raw2 q1, q2;
     float4 p0, p1;
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    q1 = load_raw2(Q, (size_t)(kb + 1) * pitch, i0, hc, hl);
-    p0 = ld4(P, (size_t)kb * pitch + i0);
+    q1 = load_raw2(Q, (size_t)(kb + 1) * pitch, i0, hc, hl, live);
+    p0 = z4;
+    if (live) p0 = ld4(P, (size_t)kb * pitch + i0);
     if (D == 2) {
         q2.c = z4;
         q2.h = make_float2(0.f, 0.f);
-        if (kb + 2 <= nz - 1) q2 = load_raw2(Q, (size_t)(kb + 2) * pitch, i0, hc, hl);
+        if (kb + 2 <= nz - 1) q2 = load_raw2(Q, (size_t)(kb + 2) * pitch, i0, hc, hl, live);
         p1 = z4;
-        if (kb + 1 < ke) p1 = ld4(P, (size_t)(kb + 1) * pitch + i0);
+        if (live && kb + 1 < ke) p1 = ld4(P, (size_t)(kb + 1) * pitch + i0);
     }
 
     for (int k = kb; k < ke; ++k) {
@@ -357,8 +363,8 @@ stencil_layered_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__
         qn.c = z4;
         qn.h = make_float2(0.f, 0.f);
         float4 pn = z4;
-        if (k + 1 + D <= nz - 1) qn = load_raw2(Q, (size_t)(k + 1 + D) * pitch, i0, hc, hl);
-        if (k + D < ke) pn = ld4(P, (size_t)(k + D) * pitch + i0);
+        if (k + 1 + D <= nz - 1) qn = load_raw2(Q, (size_t)(k + 1 + D) * pitch, i0, hc, hl, live);
+        if (live && k + D < ke) pn = ld4(P, (size_t)(k + D) * pitch + i0);
         make_rows2(q1, an, bn);
         const LayerCoef cf = load_coef(coef, k);
         float fsa = cf.c[kFco] * sval, fsb = fsa;
@@ -444,9 +450,10 @@ struct RawTB {
 };
 
 __device__ __forceinline__ RawTB load_raw_tb(const float2* Q, size_t off, int i0, int hcol,
-                                             bool hl) {
+                                             bool hl, bool live) {
     RawTB r;
-    r.c = ld4(Q, off + i0);
+    r.c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live) r.c = ld4(Q, off + i0);
     r.h = make_float4(0.f, 0.f, 0.f, 0.f);
     if (hl) r.h = ld4(Q, off + hcol);
     return r;
@@ -477,13 +484,11 @@ __device__ __forceinline__ void make_rows_x(float2 xa, float2 xb, float2 xt, Nod
     b = node_row(xb.x, xb.y, xa.x, xa.y, from_right(xa.x, xt.x), from_right(xa.y, xt.y));
 }
 
-template <int R, int D>
-__global__ void __launch_bounds__(256)
-stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
-                    int ntiles, int pass) {
-    const int tile = __builtin_amdgcn_readfirstlane(
-        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
-    if (tile >= ntiles) return;
+// PART: the tile's strip runs past nx (lanes beyond it are not live); full
+// strips compile without the lane predicate.
+template <int R, int D, bool PART>
+__device__ __forceinline__ void tb2_tile(const SolveDesc* __restrict__ descs,
+                                         const int2* __restrict__ tiles, int tile, int pass) {
     const int2 te = tiles[tile];
     const SolveDesc* d = descs + __builtin_amdgcn_readfirstlane(te.x);
     const int sc = __builtin_amdgcn_readfirstlane(te.y);
@@ -505,6 +510,7 @@ stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict_
     const float* coef = d->coef;
     const bool updA = (i0 >= 1) && (i0 <= nx - 2);
     const bool updB = (i0 + 1 <= nx - 2);
+    const bool live = !PART || i0 < nx;
     const int tcol = first ? x0 - 1 : x0 + 128;
     const bool edge = (first && x0 > 0) || (lane == 63 && x0 + 128 < nx);
     const bool updT = edge && tcol >= 1 && tcol <= nx - 2;
@@ -534,11 +540,11 @@ stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict_
     const int j1 = min(ke, nz - 2);
     RowTB um, uc, un;
     if (j0 >= 1) {
-        um = make_row_tb(load_raw_tb(cur, (size_t)(j0 - 1) * pitch, i0, hcol, edge), first);
+        um = make_row_tb(load_raw_tb(cur, (size_t)(j0 - 1) * pitch, i0, hcol, edge, live), first);
     } else {
         um.a = um.b = um.t = z;
     }
-    uc = make_row_tb(load_raw_tb(cur, (size_t)j0 * pitch, i0, hcol, edge), first);
+    uc = make_row_tb(load_raw_tb(cur, (size_t)j0 * pitch, i0, hcol, edge, live), first);
     // prefetch ring: raw u^m rows j+1..j+D, u^{m-1} rows j..j+D-1 (one row
     // measured fastest: deeper rings cost more than the latency they hide)
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -551,8 +557,8 @@ stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict_
         rq[q].h = z4;
         pq[q] = z4;
         tq[q] = z2;
-        if (j0 + 1 + q <= nz - 1) rq[q] = load_raw_tb(cur, (size_t)(j0 + 1 + q) * pitch, i0, hcol, edge);
-        if (j0 + q <= j1) {
+        if (j0 + 1 + q <= nz - 1) rq[q] = load_raw_tb(cur, (size_t)(j0 + 1 + q) * pitch, i0, hcol, edge, live);
+        if (live && j0 + q <= j1) {
             pq[q] = ld4(prev, (size_t)(j0 + q) * pitch + i0);
             if (edge) tq[q] = ld2(prev, (size_t)(j0 + q) * pitch + tcol);
         }
@@ -566,8 +572,8 @@ stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict_
         rnn.h = z4;
         float4 pvn = z4;
         float2 ptn = z2;
-        if (j + 1 + D <= nz - 1) rnn = load_raw_tb(cur, (size_t)(j + 1 + D) * pitch, i0, hcol, edge);
-        if (j + D <= j1) {
+        if (j + 1 + D <= nz - 1) rnn = load_raw_tb(cur, (size_t)(j + 1 + D) * pitch, i0, hcol, edge, live);
+        if (live && j + D <= j1) {
             pvn = ld4(prev, (size_t)(j + D) * pitch + i0);
             if (edge) ptn = ld2(prev, (size_t)(j + D) * pitch + tcol);
         }
@@ -609,7 +615,7 @@ stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict_
         if (!updB) xb = z2;
         if (!updT) xt = z2;
         if (j >= kb && j < ke) {
-            st4(out1, (size_t)j * pitch + i0, make_float4(xa.x, xa.y, xb.x, xb.y));
+            if (live) st4(out1, (size_t)j * pitch + i0, make_float4(xa.x, xa.y, xb.x, xb.y));
             if (j == 0) {
                 if (recA >= 0) st2(traces, (size_t)(m + 1) * nrec + recA, xa);
                 if (recB >= 0) st2(traces, (size_t)(m + 1) * nrec + recB, xb);
@@ -637,7 +643,7 @@ stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict_
             float2 yb = layered_update(ck, b2m, b2c, b2n, um.b.u, um.b.v, sB && row2, f2, qub, qvb);
             if (!updA) ya = z2;
             if (!updB) yb = z2;
-            st4(out2, (size_t)k * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
+            if (live) st4(out2, (size_t)k * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
             if (k == 0) {
                 if (recA >= 0) st2(traces, (size_t)(m + 2) * nrec + recA, ya);
                 if (recB >= 0) st2(traces, (size_t)(m + 2) * nrec + recB, yb);
@@ -670,12 +676,28 @@ stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict_
         float2 yb = layered_update(ck, b2m, b2c, z, um.b.u, um.b.v, sB && row2, f2, qub, qvb);
         if (!updA) ya = z2;
         if (!updB) yb = z2;
-        st4(out2, (size_t)k * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
+        if (live) st4(out2, (size_t)k * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
         if (k == 0) {
             if (recA >= 0) st2(traces, (size_t)(m + 2) * nrec + recA, ya);
             if (recB >= 0) st2(traces, (size_t)(m + 2) * nrec + recB, yb);
         }
     }
+}
+
+template <int R, int D>
+__global__ void __launch_bounds__(256)
+stencil_layered_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
+                    int ntiles, int pass) {
+    const int tile = __builtin_amdgcn_readfirstlane(
+        xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
+    if (tile >= ntiles) return;
+    const int2 te = tiles[tile];
+    const int nx = descs[__builtin_amdgcn_readfirstlane(te.x)].nx;
+    const int x0 = (__builtin_amdgcn_readfirstlane(te.y) >> 16) * 128;
+    if (x0 + 128 <= nx)
+        tb2_tile<R, D, false>(descs, tiles, tile, pass);
+    else
+        tb2_tile<R, D, true>(descs, tiles, tile, pass);
 }
 
 // Two leapfrog steps per launch with the halo columns computed up front.
@@ -717,6 +739,7 @@ stencil_layered_tb2h(const SolveDesc* __restrict__ descs, const int2* __restrict
     const float* coef = d->coef;
     const bool updA = (i0 >= 1) && (i0 <= nx - 2);
     const bool updB = (i0 + 1 <= nx - 2);
+    const bool live = i0 < nx;
     const bool hl = (lane == 0 && x0 > 0) || (lane == 63 && x0 + 128 < nx);
     const int hc = (lane == 0) ? x0 - 1 : x0 + 128;
     const int si0 = d->src_i0, sk0 = d->src_k0;
@@ -779,11 +802,11 @@ stencil_layered_tb2h(const SolveDesc* __restrict__ descs, const int2* __restrict
 
     NodeRow am, bm, ac, bc, an, bn;
     if (j0 >= 1) {
-        make_rows2(load_raw2(cur, (size_t)(j0 - 1) * pitch, i0, hc, hl), am, bm);
+        make_rows2(load_raw2(cur, (size_t)(j0 - 1) * pitch, i0, hc, hl, live), am, bm);
     } else {
         am = bm = z;
     }
-    make_rows2(load_raw2(cur, (size_t)j0 * pitch, i0, hc, hl), ac, bc);
+    make_rows2(load_raw2(cur, (size_t)j0 * pitch, i0, hc, hl, live), ac, bc);
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
     // prefetch ring: raw u^m rows j+1..j+D, u^{m-1} rows j..j+D-1
     Raw2 rq[D];
@@ -793,8 +816,8 @@ stencil_layered_tb2h(const SolveDesc* __restrict__ descs, const int2* __restrict
         rq[q].c = z4;
         rq[q].h = z2;
         pq[q] = z4;
-        if (j0 + 1 + q <= nz - 1) rq[q] = load_raw2(cur, (size_t)(j0 + 1 + q) * pitch, i0, hc, hl);
-        if (j0 + q <= j1) pq[q] = ld4(prev, (size_t)(j0 + q) * pitch + i0);
+        if (j0 + 1 + q <= nz - 1) rq[q] = load_raw2(cur, (size_t)(j0 + 1 + q) * pitch, i0, hc, hl, live);
+        if (live && j0 + q <= j1) pq[q] = ld4(prev, (size_t)(j0 + q) * pitch + i0);
     }
     // u^{m+1} rows k-1 and k for the second step
     NodeRow a2m = z, b2m = z, a2c = z, b2c = z;
@@ -803,8 +826,8 @@ stencil_layered_tb2h(const SolveDesc* __restrict__ descs, const int2* __restrict
         qn.c = z4;
         qn.h = z2;
         float4 pn = z4;
-        if (j + 1 + D <= nz - 1) qn = load_raw2(cur, (size_t)(j + 1 + D) * pitch, i0, hc, hl);
-        if (j + D <= j1) pn = ld4(prev, (size_t)(j + D) * pitch + i0);
+        if (j + 1 + D <= nz - 1) qn = load_raw2(cur, (size_t)(j + 1 + D) * pitch, i0, hc, hl, live);
+        if (live && j + D <= j1) pn = ld4(prev, (size_t)(j + D) * pitch + i0);
         const Raw2 q1 = rq[0];
         const float4 p0 = pq[0];
 #pragma unroll
@@ -834,7 +857,7 @@ stencil_layered_tb2h(const SolveDesc* __restrict__ descs, const int2* __restrict
         if (!updA) xa = z2;
         if (!updB) xb = z2;
         if (j >= kb && j < ke) {
-            st4(out1, (size_t)j * pitch + i0, make_float4(xa.x, xa.y, xb.x, xb.y));
+            if (live) st4(out1, (size_t)j * pitch + i0, make_float4(xa.x, xa.y, xb.x, xb.y));
             if (j == 0) {
                 if (recA >= 0) st2(traces, (size_t)(m + 1) * nrec + recA, xa);
                 if (recB >= 0) st2(traces, (size_t)(m + 1) * nrec + recB, xb);
@@ -863,7 +886,7 @@ stencil_layered_tb2h(const SolveDesc* __restrict__ descs, const int2* __restrict
             float2 yb = layered_update(ck, b2m, b2c, b2n, bm.u, bm.v, sB && row2, f2, qub, qvb);
             if (!updA) ya = z2;
             if (!updB) yb = z2;
-            st4(out2, (size_t)k * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
+            if (live) st4(out2, (size_t)k * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
             if (k == 0) {
                 if (recA >= 0) st2(traces, (size_t)(m + 2) * nrec + recA, ya);
                 if (recB >= 0) st2(traces, (size_t)(m + 2) * nrec + recB, yb);
@@ -898,7 +921,7 @@ stencil_layered_tb2h(const SolveDesc* __restrict__ descs, const int2* __restrict
         float2 yb = layered_update(ck, b2m, b2c, z, bm.u, bm.v, sB && row2, f2, qub, qvb);
         if (!updA) ya = z2;
         if (!updB) yb = z2;
-        st4(out2, (size_t)k * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
+        if (live) st4(out2, (size_t)k * pitch + i0, make_float4(ya.x, ya.y, yb.x, yb.y));
         if (k == 0) {
             if (recA >= 0) st2(traces, (size_t)(m + 2) * nrec + recA, ya);
             if (recB >= 0) st2(traces, (size_t)(m + 2) * nrec + recB, yb);
