@@ -1247,7 +1247,6 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
         const size_t o_h2 = cv.take(ns * sizeof(H2Job));
         const size_t o_dj = cv.take(ns * sizeof(DualJob));
         const size_t o_sig = cv.take(ns * sizeof(double));
-        const size_t o_th = cv.take((size_t)ns * kNT * sizeof(double));
         const size_t solve_base = align_up(cv.off);
         char* ws = c->ws;
         auto tp = [&](size_t o) { return (float2*)(ws + o); };
