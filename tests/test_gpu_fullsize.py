@@ -246,7 +246,8 @@ def test_c5_greedy_design_at_full_size_against_oracle():
     # (SPD, rank 4 plus a small ridge, candidate-dependent scale) and given
     # to both sides.  The oracle's own greedy covers the first three steps
     # (order exact, values within NAT_TOL * sum |w|); every one of the 40
-    # reported values is the oracle's I of the design chosen up to that step
+    # reported values is the oracle's I of the design chosen up to that step,
+    # and design_eval on those 40 designs gives the same I
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     from paper_1502_07873_amd import Context, make_prior
@@ -270,13 +271,20 @@ def test_c5_greedy_design_at_full_size_against_oracle():
         torch.cuda.synchronize()
         order = order.cpu().numpy().astype(np.int64)
         curve = curve.cpu().numpy()
+        # design_eval on the 40 designs the greedy search went through
+        masks = np.zeros((K, C), dtype=np.uint8)
+        for k in range(K):
+            masks[k, order[:k + 1]] = 1
+        ev = torch.empty(K, dtype=torch.float64, device="cuda")
+        ctx.design_eval(Hd, torch.as_tensor(masks, device="cuda"), make_prior(lo, hi), W, ev,
+                        theta=X)
+        torch.cuda.synchronize()
+        ev = ev.cpu().numpy()
     tol = NAT_TOL * np.sum(np.abs(W))
     assert len(set(order.tolist())) == K and order.min() >= 0 and order.max() < C
     order_ref, curve_ref = laplace.greedy(H1r, X, W, prior, 3)
     assert list(order[:3]) == list(order_ref)
     assert np.max(np.abs(curve[:3] - curve_ref)) <= tol
-    masks = np.zeros((K, C), dtype=np.uint8)
-    for k in range(K):
-        masks[k, order[:k + 1]] = 1
     ref = laplace.design_eval(H1r, masks, X, W, prior)
     assert np.max(np.abs(curve - ref)) <= tol, np.max(np.abs(curve - ref))
+    assert np.max(np.abs(ev - ref)) <= tol, np.max(np.abs(ev - ref))
