@@ -135,6 +135,59 @@ hessian_kernel(const SampleDesc* __restrict__ samples, int per_receiver,
     }
 }
 
+// One H_1 per receiver (per_receiver = 1): one block per sample, each thread
+// owns receivers r = threadIdx.x, + blockDim.x, ... and sums that receiver's
+// levels in order, so consecutive threads read consecutive receivers of a
+// level (the traces are [level][receiver][2]) and no cross-thread reduction
+// is needed.  Same Jacobian columns, products and scaling as hessian_kernel.
+__global__ void __launch_bounds__(128)
+hessian_receiver_kernel(const SampleDesc* __restrict__ samples, int ngroup,
+                        const double* __restrict__ sigma, double* __restrict__ H1) {
+    const int s = blockIdx.x;
+    const SampleDesc& sd = samples[s];
+    const int nt = sd.nt, nrec = sd.nrec;
+    double inv2d[kNT];
+    for (int j = 0; j < kNT; ++j) inv2d[j] = sd.inv2d[j];
+    const double sg = sigma[s];
+    for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
+        double acc[kTri];
+        for (int t = 0; t < kTri; ++t) acc[t] = 0.0;
+        for (int q = 0; q < nt; ++q) {
+            const int e = q * nrec + r;
+            double Jx[kNT], Jz[kNT];
+            for (int j = 0; j < kNT; ++j) {
+                const float2 p = sd.dev[2 * j][e];
+                if (sd.dev[2 * j + 1]) {
+                    const float2 n = sd.dev[2 * j + 1][e];
+                    Jx[j] = ((double)p.x - (double)n.x) * inv2d[j];
+                    Jz[j] = ((double)p.y - (double)n.y) * inv2d[j];
+                } else {  // sensitivity solve: the traces are the column itself
+                    Jx[j] = (double)p.x;
+                    Jz[j] = (double)p.y;
+                }
+            }
+            if (sd.J) {
+                double* o = sd.J + (size_t)e * 2 * kNT;
+                for (int j = 0; j < kNT; ++j) {
+                    o[j] = Jx[j];
+                    o[kNT + j] = Jz[j];
+                }
+            }
+            int t = 0;
+            for (int a = 0; a < kNT; ++a)
+                for (int b = a; b < kNT; ++b, ++t) acc[t] += Jx[a] * Jx[b] + Jz[a] * Jz[b];
+        }
+        double* H = H1 + ((size_t)s * ngroup + r) * kNT * kNT;
+        int t = 0;
+        for (int a = 0; a < kNT; ++a)
+            for (int b = a; b < kNT; ++b, ++t) {
+                const double v = acc[t] / (sg * sg);
+                H[a * kNT + b] = v;
+                H[b * kNT + a] = v;
+            }
+    }
+}
+
 __global__ void surface_peak_kernel(const float2* __restrict__ tr, int count,
                                     double rel, double* __restrict__ out) {
     float mx = 0.f;
@@ -167,6 +220,10 @@ void launch_sample_check(const SampleDesc* samples, int nsample, const double* g
 void launch_hessian(const SampleDesc* samples, int nsample, int per_receiver,
                     int ngroup, const double* sigma, double* H1, hipStream_t s) {
     if (nsample <= 0) return;
+    if (per_receiver) {
+        hessian_receiver_kernel<<<nsample, 128, 0, s>>>(samples, ngroup, sigma, H1);
+        return;
+    }
     dim3 grid(nsample, ngroup);
     hessian_kernel<<<grid, 64 * kWavesPerBlock, 0, s>>>(samples, per_receiver, ngroup,
                                                          sigma, H1);
