@@ -584,9 +584,14 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed query: no one-solve baseline, sensitivity path, "
                          "serving or CPU baseline (for counter runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "loh2d", "nested", "estimators"],
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c3", "c5", "loh2d", "nested", "estimators", "serving"],
                     help="c2: the headline query (default); c3/c5/loh2d: extra measurements "
-                         "(loh2d: the paper's model problem and scenarios)")
+                         "(loh2d: the paper's model problem and scenarios); serving: the "
+                         "overloaded serving stream alone")
+    ap.add_argument("--serving-rate", type=float, default=3.34e11,
+                    help="grid-point updates/s that sets the arrival rate of --workload "
+                         "serving (default: the headline wave's chunked rate)")
     ap.add_argument("--wave-cache-mib", type=int, default=192,
                     help="live field MiB per wave chunk (0: whole waves through HBM)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -619,6 +624,9 @@ def main():
             res = _bench_nested(ctx)
         elif args.workload == "estimators":
             res = _bench_estimators(ctx)
+        elif args.workload == "serving":
+            res = {"load_basis_updates_per_s": args.serving_rate,
+                   "serving_overload": _serving(ctx, args.serving_rate, load=2.0)}
         else:
             res = _bench_c5(ctx)
         print(json.dumps({"workload": args.workload, **res}), flush=True)

@@ -929,16 +929,18 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
             sp.recset = rec_of[s1];
             const size_t one = wsz.cost(sp);
             const size_t more = per * one + sample_trace_bytes(s1) + sizeof(SampleDesc) +
-                                3 * kAlign + 2 * sizeof(double);
+                                3 * kAlign + 2 * sizeof(double) + sample_work_bytes(1);
             if (s1 > s0 && wsz.bytes + extra + more > c->budget) break;
             for (int q = 0; q < per; ++q) wsz.add(sp);
-            extra += sample_trace_bytes(s1) + sizeof(SampleDesc) + 3 * kAlign + 2 * sizeof(double);
+            extra += sample_trace_bytes(s1) + sizeof(SampleDesc) + 3 * kAlign + 2 * sizeof(double) +
+                     sample_work_bytes(1);
             need = wsz.bytes + extra;
             ++s1;
         }
         int rc = ensure_ws(c, need);
         if (rc) return rc;
-        // carve: [traces | sample descs | sigma given | sigma | solve region]
+        // carve: [traces | sample descs | sigma given | sigma | per-sample
+        // partials | solve region]
         Carve cv;
         const int ns = s1 - s0;
         std::vector<std::array<size_t, 1 + 2 * kNT>> toff(ns);
@@ -948,6 +950,7 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
         const size_t o_sd = cv.take(ns * sizeof(SampleDesc));
         const size_t o_given = cv.take(ns * sizeof(double));
         const size_t o_sig = cv.take(ns * sizeof(double));
+        const size_t o_work = cv.take(sample_work_bytes(ns));
         const size_t solve_base = align_up(cv.off);
         std::vector<SolveSpec> solves;
         std::vector<SampleDesc> sds(ns);
@@ -1008,10 +1011,11 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
         if (rc) return rc;
         const SampleDesc* dsd = (const SampleDesc*)(c->ws + o_sd);
         double* dsig = (double*)(c->ws + o_sig);
+        double* dwork = (double*)(c->ws + o_work);
         launch_sample_check(dsd, ns, (const double*)(c->ws + o_given), sigma_mode, dsig,
-                            status ? status + s0 : nullptr, s);
+                            status ? status + s0 : nullptr, dwork, s);
         launch_hessian(dsd, ns, per_receiver ? 1 : 0, ngroup, dsig,
-                       H1 + (size_t)s0 * ngroup * kNT * kNT, s);
+                       H1 + (size_t)s0 * ngroup * kNT * kNT, dwork, s);
         HIP_TRY(hipGetLastError());
         s0 = s1;
     }
@@ -1201,6 +1205,7 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
         return 10 * tr + align_up((size_t)grid[i].nsteps * rec[i].n * sizeof(float2)) +
                align_up((size_t)grid[i].nsteps * kSrcW * kSrcW * sizeof(float2)) +
                align_up(sizeof(SampleDesc)) + align_up(sizeof(H2Job)) + align_up(sizeof(DualJob)) +
+               align_up(sample_work_bytes(1)) +
                3 * align_up(kNT * kNT * sizeof(double)) + 4 * kAlign;
     };
     int s0 = 0;
@@ -1247,6 +1252,7 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
         const size_t o_h2 = cv.take(ns * sizeof(H2Job));
         const size_t o_dj = cv.take(ns * sizeof(DualJob));
         const size_t o_sig = cv.take(ns * sizeof(double));
+        const size_t o_work = cv.take(sample_work_bytes(ns));
         const size_t solve_base = align_up(cv.off);
         char* ws = c->ws;
         auto tp = [&](size_t o) { return (float2*)(ws + o); };
@@ -1319,7 +1325,7 @@ int theorem3_eig(eig_ctx* c, int32_t nsample, const eig_grid* grid, const eig_me
             if ((rc = upload(c, ws + o_sd, blob, s))) return rc;
             // H1 and the gradient of every sample (row q of the chunk arrays)
             launch_hessian((const SampleDesc*)(ws + o_sd), ns, 0, 1, (const double*)(ws + o_sig),
-                           (double*)(ws + o_H1), s);
+                           (double*)(ws + o_H1), (double*)(ws + o_work), s);
             HIP_TRY(hipGetLastError());
             if (it == iters) break;
             HIP_TRY(hipMemcpyAsync(hbuf.data(), ws + o_H1, (size_t)ns * kNT * kNT * sizeof(double),

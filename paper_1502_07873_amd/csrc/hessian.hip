@@ -25,21 +25,29 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Per-sample status and noise level.  mode EIG_SIGMA_GIVEN: sigma = given;
 // EIG_SIGMA_NOMINAL_PEAK: sigma = given * max |nominal trace value|.
-__global__ void sample_check_kernel(const SampleDesc* __restrict__ samples,
-                                    const double* __restrict__ given, int mode,
-                                    double* __restrict__ sigma,
-                                    int32_t* __restrict__ status) {
+// Block (s, b) covers range b of sample s and leaves its maximum and
+// non-finite flag in work; the maximum of a set and the flag do not depend on
+// how the set is cut.
+__device__ __forceinline__ void sample_range(int n, int b, int& lo, int& hi) {
+    const int chunk = (n + kSampleSplit - 1) / kSampleSplit;
+    lo = min(n, b * chunk);
+    hi = min(n, lo + chunk);
+}
+
+__global__ void __launch_bounds__(256)
+sample_check_kernel(const SampleDesc* __restrict__ samples, double* __restrict__ work) {
     const SampleDesc& sd = samples[blockIdx.x];
-    const int n = sd.nt * sd.nrec;
+    int lo, hi;
+    sample_range(sd.nt * sd.nrec, blockIdx.y, lo, hi);
     float mx = 0.f;
     int bad = 0;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) {
         const float2 v = sd.nominal[e];
         if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
         mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
     for (int j = 0; j < 2 * kNT && !bad; ++j)
-        for (int e = threadIdx.x; e < n && sd.dev[j]; e += blockDim.x) {
+        for (int e = lo + threadIdx.x; e < hi && sd.dev[j]; e += blockDim.x) {
             const float2 v = sd.dev[j][e];
             if (!isfinite(v.x) || !isfinite(v.y)) { bad = 1; break; }
         }
@@ -56,27 +64,48 @@ __global__ void sample_check_kernel(const SampleDesc* __restrict__ samples,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double g = given[blockIdx.x];
-        sigma[blockIdx.x] = mode == EIG_SIGMA_NOMINAL_PEAK ? g * (double)smx[0] : g;
-        if (status) status[blockIdx.x] = sbad[0] ? EIG_ENONFINITE : EIG_OK;
+        double* w = work + 2 * ((size_t)blockIdx.x * kSampleSplit + blockIdx.y);
+        w[0] = (double)smx[0];
+        w[1] = (double)sbad[0];
     }
 }
 
+__global__ void sample_check_finish_kernel(const double* __restrict__ work, int nsample,
+                                           const double* __restrict__ given, int mode,
+                                           double* __restrict__ sigma,
+                                           int32_t* __restrict__ status) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsample) return;
+    float mx = 0.f;
+    int bad = 0;
+    for (int b = 0; b < kSampleSplit; ++b) {
+        const double* w = work + 2 * ((size_t)s * kSampleSplit + b);
+        mx = fmaxf(mx, (float)w[0]);
+        bad |= w[1] != 0.0;
+    }
+    const double g = given[s];
+    sigma[s] = mode == EIG_SIGMA_NOMINAL_PEAK ? g * (double)mx : g;
+    if (status) status[s] = bad ? EIG_ENONFINITE : EIG_OK;
+}
+
+// Block (s, b) sums J^T J (and J^T r for the gradient) over range b of
+// sample s's (level, receiver) elements and leaves the kTri + kNT sums in
+// work; hessian_finish_kernel adds the ranges in order and scales.
 __global__ void __launch_bounds__(256)
-hessian_kernel(const SampleDesc* __restrict__ samples, int per_receiver,
-               int ngroup, const double* __restrict__ sigma, double* __restrict__ H1) {
-    const int s = blockIdx.x, g = blockIdx.y;
+hessian_kernel(const SampleDesc* __restrict__ samples, const double* __restrict__ sigma,
+               double* __restrict__ work) {
+    const int s = blockIdx.x;
     const SampleDesc& sd = samples[s];
     const int nt = sd.nt, nrec = sd.nrec;
     double acc[kTri + kNT];
     for (int t = 0; t < kTri + kNT; ++t) acc[t] = 0.0;
-    const bool want_grad = sd.grad != nullptr && !per_receiver;
+    const bool want_grad = sd.grad != nullptr;
     const double sgm = sigma[s];
     double inv2d[kNT];
     for (int j = 0; j < kNT; ++j) inv2d[j] = sd.inv2d[j];
-    const int count = per_receiver ? nt : nt * nrec;
-    for (int q = threadIdx.x; q < count; q += blockDim.x) {
-        const int e = per_receiver ? q * nrec + g : q;
+    int lo, hi;
+    sample_range(nt * nrec, blockIdx.y, lo, hi);
+    for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) {
         double Jx[kNT], Jz[kNT];
         for (int j = 0; j < kNT; ++j) {
             const float2 p = sd.dev[2 * j][e];
@@ -113,26 +142,38 @@ hessian_kernel(const SampleDesc* __restrict__ samples, int per_receiver,
         if (lane == 0) part[wave][t] = v;
     }
     __syncthreads();
-    if (want_grad && threadIdx.x >= 64 && threadIdx.x < 64 + kNT) {
-        const int j = threadIdx.x - 64;
-        double v = 0.0;
-        for (int w = 0; w < kWavesPerBlock; ++w) v += part[w][kTri + j];
-        sd.grad[j] = -v / (sgm * sgm);
-    }
-    if (threadIdx.x < kTri) {
+    if (threadIdx.x < kTri + (want_grad ? kNT : 0)) {
         const int t = threadIdx.x;
         double v = 0.0;
         for (int w = 0; w < kWavesPerBlock; ++w) v += part[w][t];
-        const double sg = sigma[s];
-        v /= sg * sg;
-        // map t back to (a, b)
-        int a = 0, base = 0;
-        while (t >= base + (kNT - a)) { base += kNT - a; ++a; }
-        const int b = a + (t - base);
-        double* H = H1 + ((size_t)s * ngroup + g) * kNT * kNT;
-        H[a * kNT + b] = v;
-        H[b * kNT + a] = v;
+        work[((size_t)s * kSampleSplit + blockIdx.y) * (kTri + kNT) + t] = v;
     }
+}
+
+__global__ void hessian_finish_kernel(const SampleDesc* __restrict__ samples,
+                                      const double* __restrict__ sigma,
+                                      const double* __restrict__ work,
+                                      double* __restrict__ H1) {
+    const int s = blockIdx.x, t = threadIdx.x;
+    const SampleDesc& sd = samples[s];
+    const bool want_grad = sd.grad != nullptr;
+    if (t >= kTri + (want_grad ? kNT : 0)) return;
+    double v = 0.0;
+    for (int b = 0; b < kSampleSplit; ++b)
+        v += work[((size_t)s * kSampleSplit + b) * (kTri + kNT) + t];
+    const double sg = sigma[s];
+    if (t >= kTri) {
+        sd.grad[t - kTri] = -v / (sg * sg);
+        return;
+    }
+    v /= sg * sg;
+    // map t back to (a, b)
+    int a = 0, base = 0;
+    while (t >= base + (kNT - a)) { base += kNT - a; ++a; }
+    const int b = a + (t - base);
+    double* H = H1 + (size_t)s * kNT * kNT;
+    H[a * kNT + b] = v;
+    H[b * kNT + a] = v;
 }
 
 // One H_1 per receiver (per_receiver = 1): one block per sample, each thread
@@ -212,21 +253,24 @@ __global__ void surface_peak_kernel(const float2* __restrict__ tr, int count,
 }  // namespace
 
 void launch_sample_check(const SampleDesc* samples, int nsample, const double* given,
-                         int mode, double* sigma, int32_t* status, hipStream_t s) {
+                         int mode, double* sigma, int32_t* status, double* work,
+                         hipStream_t s) {
     if (nsample <= 0) return;
-    sample_check_kernel<<<nsample, 256, 0, s>>>(samples, given, mode, sigma, status);
+    sample_check_kernel<<<dim3(nsample, kSampleSplit), 256, 0, s>>>(samples, work);
+    sample_check_finish_kernel<<<(nsample + 63) / 64, 64, 0, s>>>(work, nsample, given, mode,
+                                                                   sigma, status);
 }
 
 void launch_hessian(const SampleDesc* samples, int nsample, int per_receiver,
-                    int ngroup, const double* sigma, double* H1, hipStream_t s) {
+                    int ngroup, const double* sigma, double* H1, double* work, hipStream_t s) {
     if (nsample <= 0) return;
     if (per_receiver) {
         hessian_receiver_kernel<<<nsample, 128, 0, s>>>(samples, ngroup, sigma, H1);
         return;
     }
-    dim3 grid(nsample, ngroup);
-    hessian_kernel<<<grid, 64 * kWavesPerBlock, 0, s>>>(samples, per_receiver, ngroup,
-                                                         sigma, H1);
+    hessian_kernel<<<dim3(nsample, kSampleSplit), 64 * kWavesPerBlock, 0, s>>>(samples, sigma,
+                                                                             work);
+    hessian_finish_kernel<<<nsample, 64, 0, s>>>(samples, sigma, work, H1);
 }
 
 void launch_surface_peak(const float2* traces, int count, double rel, double* out,

@@ -161,10 +161,20 @@ void launch_nested(const float* gout, const float* noise, const float* gin, int 
                    double* work, hipStream_t s);
 // Absorbing-edge update of level step+1 for descs[0..n) (one-step buffers).
 void launch_ce_edges(const SolveDesc* descs, int n, int step, hipStream_t s);
+// Per-sample checks and H_1: each sample's (level, receiver) elements are cut
+// into kSampleSplit contiguous ranges, one block each, and the block partials
+// are combined in range order by a second kernel, so a sample's result does
+// not depend on the batch it runs in.  work: sample_work_bytes(nsample) of
+// device scratch (the two launches may share it in stream order).
+constexpr int kSampleSplit = 16;
+inline size_t sample_work_bytes(int nsample) {
+    return (size_t)nsample * kSampleSplit * (kNT * (kNT + 1) / 2 + kNT) * sizeof(double);
+}
 void launch_sample_check(const SampleDesc* samples, int nsample, const double* given,
-                         int mode, double* sigma, int32_t* status, hipStream_t s);
+                         int mode, double* sigma, int32_t* status, double* work,
+                         hipStream_t s);
 void launch_hessian(const SampleDesc* samples, int nsample, int per_receiver,
-                    int ngroup, const double* sigma, double* H1, hipStream_t s);
+                    int ngroup, const double* sigma, double* H1, double* work, hipStream_t s);
 void launch_laplace(const double* H1, int nsample, const eig_prior* prior_dev,
                     const double* theta, const double* w, double* dkl,
                     double* logdet, int32_t* status, double* eig, hipStream_t s);

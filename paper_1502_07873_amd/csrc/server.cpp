@@ -90,7 +90,7 @@ struct SrvGroup {
     size_t live = 0;         // field bytes its solves keep live between launches
     int64_t start = 0;       // launch index of step 0
     int nsteps = 0;
-    size_t o_sd = 0, o_given = 0, o_sig = 0;
+    size_t o_sd = 0, o_given = 0, o_sig = 0, o_work = 0;
 };
 
 size_t trace_bytes(const eig_grid& g, int nrec) {
@@ -104,6 +104,7 @@ size_t group_bytes(const SrvQuery& q, int G) {
     size_t b = medium_bytes(mk) + align_up((size_t)pitch_of(g.nx) * sizeof(int32_t));
     b += (size_t)15 * G * (solve_bytes(g) + trace_bytes(g, (int)q.rec.size()));
     b += align_up((size_t)G * sizeof(SampleDesc)) + 2 * align_up((size_t)G * sizeof(double));
+    b += align_up(sample_work_bytes(G));
     b += align_up((size_t)15 * G * sizeof(SourceJob));
     return b + 16 * kAlign;
 }
@@ -212,6 +213,7 @@ int srv_admit(eig_server* v, hipStream_t s) {
         gr.o_sd = cv.take((size_t)G * sizeof(SampleDesc));
         gr.o_given = cv.take((size_t)G * sizeof(double));
         gr.o_sig = cv.take((size_t)G * sizeof(double));
+        gr.o_work = cv.take(sample_work_bytes(G));
         const size_t o_jobs = cv.take(gr.nslot * sizeof(SourceJob));
         if (cv.off > bytes) return set_error(EIG_EBUDGET, "server group carve overflow");
         // descriptors, forcing jobs, sample descriptors
@@ -354,9 +356,10 @@ int srv_retire(eig_server* v, hipStream_t s) {
         const int G = gr.s1 - gr.s0;
         const SampleDesc* dsd = (const SampleDesc*)(base + gr.o_sd);
         double* dsig = (double*)(base + gr.o_sig);
+        double* dwork = (double*)(base + gr.o_work);
         launch_sample_check(dsd, G, (const double*)(base + gr.o_given), q.sigma_mode, dsig,
-                            q.status ? q.status + gr.s0 : nullptr, s);
-        launch_hessian(dsd, G, 0, 1, dsig, q.H1 + (size_t)gr.s0 * kNT * kNT, s);
+                            q.status ? q.status + gr.s0 : nullptr, dwork, s);
+        launch_hessian(dsd, G, 0, 1, dsig, q.H1 + (size_t)gr.s0 * kNT * kNT, dwork, s);
         HIP_TRY(hipGetLastError());
         v->arena.release(gr.off, gr.bytes);
         v->slots.release(gr.slot0, gr.nslot);
