@@ -369,6 +369,48 @@ def test_edge_cases(ctx):
     assert np.isnan(float(eig.cpu()[0]))
 
 
+@pytest.mark.parametrize("nsteps", [1, 2, 400])
+def test_hessian_and_peak_for_any_element_count(ctx, nsteps):
+    """A sample's (level, receiver) elements are summed in 16 ranges: with 10
+    and 15 elements some ranges are empty, with 2005 they are uneven.  H1 in
+    nominal-peak mode must equal sum J^T J / sigma^2 in FP64 over the
+    Jacobian the same call returns, with sigma = rel x the exact maximum of
+    its nominal traces (a source two nodes deep moves the surface in one
+    step)."""
+    from paper_1502_07873_amd import eigseis
+    from paper_1502_07873_amd.query import grid_tuple
+    wl = synthetic.config("c1", nsample=3, grid_override=(40, 40, nsteps))[0]
+    _say(f"H1 reduction, {nsteps} steps")
+    th = wl.theta.copy()
+    th[:, 0] = [400.0, 410.0, 300.0]
+    th[:, 1] = [50.0, 55.0, 90.0]
+    th[:, 2] = [0.01, 0.012, 0.02]
+    S, R = len(th), len(wl.receivers)
+    g = grid_tuple(wl.grid)
+    dm = _dev_medium(wl.medium)
+    H1 = torch.empty((S, 7, 7), dtype=torch.float64, device="cuda")
+    nominal = [torch.empty((nsteps + 1, R, 2), dtype=torch.float32, device="cuda")
+               for _ in range(S)]
+    J = [torch.empty((nsteps + 1, R, 2, 7), dtype=torch.float64, device="cuda")
+         for _ in range(S)]
+    status = torch.empty(S, dtype=torch.int32, device="cuda")
+    rel = 1e-3
+    ctx.jacobian_fd([g] * S, [dm] * S, th, [wl.receivers] * S, rel, H1, nominal=nominal, J=J,
+                    status=status, sigma_mode=eigseis.SIGMA_NOMINAL_PEAK)
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0] * S
+    for s in range(S):
+        peak = float(np.max(np.abs(nominal[s].cpu().numpy())))
+        assert peak > 0.0
+        sig = rel * peak
+        Js = J[s].cpu().numpy().reshape(-1, 7)
+        Href = (Js.T @ Js) / (sig * sig)
+        Hg = H1[s].cpu().numpy()
+        scale = np.sqrt(np.outer(np.diag(Href), np.diag(Href))) + 1e-300
+        assert np.max(np.abs(Hg - Href) / scale) < 1e-12, (s, nsteps)
+        assert np.array_equal(Hg, Hg.T)
+
+
 @pytest.mark.parametrize("nsteps", [700, 333])
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16])
 def test_stencil_variants_bitwise_identical(variant, nsteps, monkeypatch):
