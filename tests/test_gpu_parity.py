@@ -383,7 +383,7 @@ def test_hessian_and_peak_for_any_element_count(ctx, nsteps):
     _say(f"H1 reduction, {nsteps} steps")
     th = wl.theta.copy()
     th[:, 0] = [400.0, 410.0, 300.0]
-    th[:, 1] = [50.0, 55.0, 90.0]
+    th[:, 1] = [41.0, 45.0, 55.0]
     th[:, 2] = [0.01, 0.012, 0.02]
     S, R = len(th), len(wl.receivers)
     g = grid_tuple(wl.grid)
