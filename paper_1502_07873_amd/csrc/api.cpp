@@ -928,11 +928,13 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
             sp.medium = med_of[s1];
             sp.recset = rec_of[s1];
             const size_t one = wsz.cost(sp);
+            // one alignment pad each before sigma given, sigma, the partials
+            // and the solve region
             const size_t more = per * one + sample_trace_bytes(s1) + sizeof(SampleDesc) +
-                                3 * kAlign + 2 * sizeof(double) + sample_work_bytes(1);
+                                4 * kAlign + 2 * sizeof(double) + sample_work_bytes(1);
             if (s1 > s0 && wsz.bytes + extra + more > c->budget) break;
             for (int q = 0; q < per; ++q) wsz.add(sp);
-            extra += sample_trace_bytes(s1) + sizeof(SampleDesc) + 3 * kAlign + 2 * sizeof(double) +
+            extra += sample_trace_bytes(s1) + sizeof(SampleDesc) + 4 * kAlign + 2 * sizeof(double) +
                      sample_work_bytes(1);
             need = wsz.bytes + extra;
             ++s1;
