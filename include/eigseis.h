@@ -213,7 +213,8 @@ int eig_ctx_get_option(const eig_ctx* ctx, const char* name, int64_t* value);
  *              [grid.nsteps+1][rec.n][2]; fully overwritten.
  * EIG_EINVAL if the 6x6 source stencil of theta (or of theta + step e_j)
  * would touch a rigid node, a receiver is off the free surface or repeated,
- * or a size is out of range.
+ * or a size is out of range.  nsolve == 0 does nothing and returns EIG_OK
+ * (the arrays may then be NULL).
  */
 int forward_solve_batch(eig_ctx* ctx, int32_t nsolve, const eig_grid* grid,
                         const eig_medium* medium, const double* theta,
@@ -244,6 +245,7 @@ int forward_solve_batch(eig_ctx* ctx, int32_t nsolve, const eig_grid* grid,
  *   J:         host array [nsample] of device pointers (double
  *              [nsteps+1][nrec][2][7]) or NULL
  *   status:    device [nsample] or NULL: 0, or EIG_ENONFINITE
+ * nsample == 0 does nothing and returns EIG_OK (the arrays may then be NULL).
  */
 int jacobian_fd(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
                 const eig_medium* medium, const double* theta, double rel_step,
@@ -357,6 +359,7 @@ int theorem3_eig(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
  *   dkl:    device [nsample]; logdet: device [nsample] or NULL;
  *   eig:    device [1]; status: device [nsample] or NULL (0 or EIG_ENOTPD).
  *   A failed sample has dkl = NaN, which makes eig NaN.
+ * EIG_EINVAL for nsample <= 0 (an average over no samples) or a NULL array.
  */
 int laplace_eig(eig_ctx* ctx, int32_t nsample, const double* H1,
                 const eig_prior* prior, const double* theta, const double* w,

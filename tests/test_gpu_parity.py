@@ -369,6 +369,28 @@ def test_edge_cases(ctx):
     assert np.isnan(float(eig.cpu()[0]))
 
 
+def test_empty_batches(ctx):
+    """Zero solves or zero samples: forward_solve_batch and jacobian_fd return
+    without work; laplace_eig and the nested estimator, which average over
+    samples, refuse an empty set."""
+    from paper_1502_07873_amd import EigError, make_prior
+    _say("empty batches")
+    ctx.forward_solve_batch([], [], np.zeros((0, 7)), [], [])
+    H1 = torch.empty((0, 7, 7), dtype=torch.float64, device="cuda")
+    ctx.jacobian_fd([], [], np.zeros((0, 7)), [], 1.0, H1)
+    torch.cuda.synchronize()
+    prior = make_prior(-np.ones(7), np.ones(7))
+    eig = torch.empty(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(EigError):
+        ctx.laplace_eig(H1, prior, np.zeros(0), torch.empty(0, dtype=torch.float64,
+                                                             device="cuda"), eig)
+    g0 = torch.empty((0, 6), dtype=torch.float32, device="cuda")
+    g = torch.zeros((5, 6), dtype=torch.float32, device="cuda")
+    with pytest.raises(EigError):
+        ctx.nested_mc_eig(g0, g0, g, 0.1, torch.empty(0, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("nsteps", [1, 2, 400])
 def test_hessian_and_peak_for_any_element_count(ctx, nsteps):
     """A sample's (level, receiver) elements are summed in 16 ranges: with 10
