@@ -28,8 +28,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Block (s, b) covers range b of sample s and leaves its maximum and
 // non-finite flag in work; the maximum of a set and the flag do not depend on
 // how the set is cut.
+// A sample of n elements is cut into sample_ranges(n) ranges: at least
+// kRangeMin elements each (so the block partials stay cheap next to the
+// sums), at most kSampleSplit.  The count depends on n alone.
+__device__ __forceinline__ int sample_ranges(int n) {
+    return min(kSampleSplit, max(1, n / kRangeMin));
+}
+
 __device__ __forceinline__ void sample_range(int n, int b, int& lo, int& hi) {
-    const int chunk = (n + kSampleSplit - 1) / kSampleSplit;
+    const int nr = sample_ranges(n);
+    const int chunk = (n + nr - 1) / nr;
     lo = min(n, b * chunk);
     hi = min(n, lo + chunk);
 }
@@ -37,6 +45,7 @@ __device__ __forceinline__ void sample_range(int n, int b, int& lo, int& hi) {
 __global__ void __launch_bounds__(256)
 sample_check_kernel(const SampleDesc* __restrict__ samples, double* __restrict__ work) {
     const SampleDesc& sd = samples[blockIdx.x];
+    if ((int)blockIdx.y >= sample_ranges(sd.nt * sd.nrec)) return;
     int lo, hi;
     sample_range(sd.nt * sd.nrec, blockIdx.y, lo, hi);
     float mx = 0.f;
@@ -70,7 +79,8 @@ sample_check_kernel(const SampleDesc* __restrict__ samples, double* __restrict__
     }
 }
 
-__global__ void sample_check_finish_kernel(const double* __restrict__ work, int nsample,
+__global__ void sample_check_finish_kernel(const SampleDesc* __restrict__ samples,
+                                           const double* __restrict__ work, int nsample,
                                            const double* __restrict__ given, int mode,
                                            double* __restrict__ sigma,
                                            int32_t* __restrict__ status) {
@@ -78,7 +88,8 @@ __global__ void sample_check_finish_kernel(const double* __restrict__ work, int 
     if (s >= nsample) return;
     float mx = 0.f;
     int bad = 0;
-    for (int b = 0; b < kSampleSplit; ++b) {
+    const int nr = sample_ranges(samples[s].nt * samples[s].nrec);
+    for (int b = 0; b < nr; ++b) {
         const double* w = work + 2 * ((size_t)s * kSampleSplit + b);
         mx = fmaxf(mx, (float)w[0]);
         bad |= w[1] != 0.0;
@@ -97,6 +108,7 @@ hessian_kernel(const SampleDesc* __restrict__ samples, const double* __restrict_
     const int s = blockIdx.x;
     const SampleDesc& sd = samples[s];
     const int nt = sd.nt, nrec = sd.nrec;
+    if ((int)blockIdx.y >= sample_ranges(nt * nrec)) return;
     double acc[kTri + kNT];
     for (int t = 0; t < kTri + kNT; ++t) acc[t] = 0.0;
     const bool want_grad = sd.grad != nullptr;
@@ -159,7 +171,8 @@ __global__ void hessian_finish_kernel(const SampleDesc* __restrict__ samples,
     const bool want_grad = sd.grad != nullptr;
     if (t >= kTri + (want_grad ? kNT : 0)) return;
     double v = 0.0;
-    for (int b = 0; b < kSampleSplit; ++b)
+    const int nr = sample_ranges(sd.nt * sd.nrec);
+    for (int b = 0; b < nr; ++b)
         v += work[((size_t)s * kSampleSplit + b) * (kTri + kNT) + t];
     const double sg = sigma[s];
     if (t >= kTri) {
@@ -257,7 +270,8 @@ void launch_sample_check(const SampleDesc* samples, int nsample, const double* g
                          hipStream_t s) {
     if (nsample <= 0) return;
     sample_check_kernel<<<dim3(nsample, kSampleSplit), 256, 0, s>>>(samples, work);
-    sample_check_finish_kernel<<<(nsample + 63) / 64, 64, 0, s>>>(work, nsample, given, mode,
+    sample_check_finish_kernel<<<(nsample + 63) / 64, 64, 0, s>>>(samples, work, nsample,
+                                                                   given, mode,
                                                                    sigma, status);
 }
 

@@ -162,11 +162,14 @@ void launch_nested(const float* gout, const float* noise, const float* gin, int 
 // Absorbing-edge update of level step+1 for descs[0..n) (one-step buffers).
 void launch_ce_edges(const SolveDesc* descs, int n, int step, hipStream_t s);
 // Per-sample checks and H_1: each sample's (level, receiver) elements are cut
-// into kSampleSplit contiguous ranges, one block each, and the block partials
-// are combined in range order by a second kernel, so a sample's result does
-// not depend on the batch it runs in.  work: sample_work_bytes(nsample) of
-// device scratch (the two launches may share it in stream order).
+// into contiguous ranges of at least kRangeMin elements, at most kSampleSplit
+// of them, one block each, and the block partials are combined in range
+// order by a second kernel.  The cut depends only on the sample's element
+// count, so a sample's result does not depend on the batch it runs in.
+// work: sample_work_bytes(nsample) of device scratch (the two launches may
+// share it in stream order).
 constexpr int kSampleSplit = 16;
+constexpr int kRangeMin = 4096;
 inline size_t sample_work_bytes(int nsample) {
     return (size_t)nsample * kSampleSplit * (kNT * (kNT + 1) / 2 + kNT) * sizeof(double);
 }

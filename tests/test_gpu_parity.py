@@ -391,14 +391,14 @@ def test_empty_batches(ctx):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("nsteps", [1, 2, 400])
+@pytest.mark.parametrize("nsteps", [1, 2, 400, 9000, 13200])
 def test_hessian_and_peak_for_any_element_count(ctx, nsteps):
-    """A sample's (level, receiver) elements are summed in 16 ranges: with 10
-    and 15 elements some ranges are empty, with 2005 they are uneven.  H1 in
-    nominal-peak mode must equal sum J^T J / sigma^2 in FP64 over the
-    Jacobian the same call returns, with sigma = rel x the exact maximum of
-    its nominal traces (a source two nodes deep moves the surface in one
-    step)."""
+    """A sample's (level, receiver) elements are summed in ranges of at least
+    4096, at most 16 ranges: 10, 15 and 2005 elements make one range, 45005
+    ten uneven ones, 66005 sixteen.  H1 in nominal-peak mode must equal
+    sum J^T J / sigma^2 in FP64 over the Jacobian the same call returns, with
+    sigma = rel x the exact maximum of its nominal traces (a source two nodes
+    deep moves the surface in one step)."""
     from paper_1502_07873_amd import eigseis
     from paper_1502_07873_amd.query import grid_tuple
     wl = synthetic.config("c1", nsample=3, grid_override=(40, 40, nsteps))[0]
