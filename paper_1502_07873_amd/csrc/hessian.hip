@@ -23,11 +23,6 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Per-sample status and noise level.  mode EIG_SIGMA_GIVEN: sigma = given;
-// EIG_SIGMA_NOMINAL_PEAK: sigma = given * max |nominal trace value|.
-// Block (s, b) covers range b of sample s and leaves its maximum and
-// non-finite flag in work; the maximum of a set and the flag do not depend on
-// how the set is cut.
 // A sample of n elements is cut into sample_ranges(n) ranges: at least
 // kRangeMin elements each (so the block partials stay cheap next to the
 // sums), at most kSampleSplit.  The count depends on n alone.
@@ -42,6 +37,11 @@ __device__ __forceinline__ void sample_range(int n, int b, int& lo, int& hi) {
     hi = min(n, lo + chunk);
 }
 
+// Per-sample status and noise level.  mode EIG_SIGMA_GIVEN: sigma = given;
+// EIG_SIGMA_NOMINAL_PEAK: sigma = given * max |nominal trace value|.
+// Block (s, b) covers range b of sample s and leaves its maximum and
+// non-finite flag in work (the maximum of a set and the flag do not depend on
+// how the set is cut); sample_check_finish_kernel combines the ranges.
 __global__ void __launch_bounds__(256)
 sample_check_kernel(const SampleDesc* __restrict__ samples, double* __restrict__ work) {
     const SampleDesc& sd = samples[blockIdx.x];
