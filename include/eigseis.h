@@ -212,8 +212,10 @@ int eig_ctx_get_option(const eig_ctx* ctx, const char* name, int64_t* value);
  *   traces:    host array [nsolve] of device pointers, each float
  *              [grid.nsteps+1][rec.n][2]; fully overwritten.
  * EIG_EINVAL if the 6x6 source stencil of theta (or of theta + step e_j)
- * would touch a rigid node, a receiver is off the free surface or repeated,
- * or a size is out of range.  nsolve == 0 does nothing and returns EIG_OK
+ * would touch a rigid node, a deviation step of x_s or z_s moves the source
+ * out of its cell by more than one cell (the forcing window is the 7x7 union
+ * of the two stencils), a receiver is off the free surface or repeated, or a
+ * size is out of range.  nsolve == 0 does nothing and returns EIG_OK
  * (the arrays may then be NULL).
  */
 int forward_solve_batch(eig_ctx* ctx, int32_t nsolve, const eig_grid* grid,
@@ -245,6 +247,10 @@ int forward_solve_batch(eig_ctx* ctx, int32_t nsolve, const eig_grid* grid,
  *   J:         host array [nsample] of device pointers (double
  *              [nsteps+1][nrec][2][7]) or NULL
  *   status:    device [nsample] or NULL: 0, or EIG_ENONFINITE
+ * EIG_EINVAL also when rel_step * |x_s| or rel_step * |z_s| moves the source
+ * out of its cell by more than one cell (the 7x7 forcing window of a
+ * deviation solve covers the nominal and the perturbed stencil only then);
+ * with the paper-sized rel_step = 1e-4 this needs coordinates beyond 1e4 h.
  * nsample == 0 does nothing and returns EIG_OK (the arrays may then be NULL).
  */
 int jacobian_fd(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
@@ -429,13 +435,18 @@ typedef struct eig_server eig_server;
 int eig_server_create(eig_ctx* ctx, size_t budget, int32_t group_samples,
                       eig_server** out);
 void eig_server_destroy(eig_server* srv);
-/* Queue a query (host inputs are copied; device outputs are caller-owned and
- * must stay valid until eig_server_poll reports it done):
+/* Queue a query.  Host inputs are copied.  The medium's device arrays are
+ * read when the query's sample groups are admitted, later, on the stream of
+ * eig_server_step; they and the device outputs are caller-owned and must stay
+ * valid until eig_server_poll reports the query done:
  *   H1 device [nsample][7][7], dkl device [nsample], eig device [1],
  *   status device [nsample] or NULL (0 / EIG_ENONFINITE),
  *   chol_status device [nsample] or NULL (0 / EIG_ENOTPD).
  * sigma_mode/sigma as for jacobian_fd (one value for all samples).
- * EIG_EBUDGET if a single sample cannot fit the arena; *id receives a handle. */
+ * EIG_EBUDGET if one sample's group together with the query's laplace inputs
+ * does not fit the arena (any query accepted here is admitted once the server
+ * is idle: groups shrink to fit); EIG_EINVAL as for jacobian_fd; *id receives
+ * a handle. */
 int eig_server_submit(eig_server* srv, const eig_grid* grid, const eig_medium* medium,
                       int32_t nsample, const double* theta, double rel_step,
                       int32_t stf_kind, const eig_receivers* rec, int32_t sigma_mode,
@@ -444,13 +455,19 @@ int eig_server_submit(eig_server* srv, const eig_grid* grid, const eig_medium* m
                       int64_t* id);
 /* Enqueue up to max_launches stencil launches on `stream`, retiring finished
  * groups (Hessian kernels, then laplace for completed queries) and admitting
- * waiting ones at segment boundaries.  *running = admitted groups left. */
+ * waiting ones at segment boundaries.  *running = admitted groups left.
+ * EIG_EBUDGET (with *running = 0) if queries wait and none can be admitted. */
 int eig_server_step(eig_server* srv, int32_t max_launches, void* stream, int32_t* running);
 /* *done = 1 once query `id`'s outputs are complete on the device (the handle
  * is then released). */
 int eig_server_poll(eig_server* srv, int64_t id, int32_t* done);
 /* Queries still waiting for admission of samples, and admitted groups. */
 int eig_server_pending(eig_server* srv, int32_t* queued, int32_t* running);
+/* Arena accounting: the budget given at creation, the bytes admitted groups
+ * and query inputs hold now, and the most they ever held (never above the
+ * budget).  The slot and tile tables (about 16 MiB plus 8 bytes per
+ * wavefront tile) are allocated beside the arena.  Any pointer may be NULL. */
+int eig_server_memory(eig_server* srv, size_t* budget, size_t* in_use, size_t* peak);
 
 #ifdef __cplusplus
 }

@@ -770,15 +770,13 @@ int forward_solve_batch(eig_ctx* c, int32_t nsolve, const eig_grid* grid,
                         const int32_t* dev_param, const double* dev_step,
                         int32_t stf_kind, const eig_receivers* rec,
                         float* const* traces, void* stream) {
-    if (!c) return set_error(EIG_EINVAL, "ctx is NULL");
+    // host-side argument checks first (they need no device), then the context
     if (nsolve < 0) return set_error(EIG_EINVAL, "nsolve < 0");
-    if (nsolve == 0) return EIG_OK;
+    if (nsolve == 0) return c ? EIG_OK : set_error(EIG_EINVAL, "ctx is NULL");
     if (!grid || !medium || !theta || !rec || !traces)
         return set_error(EIG_EINVAL, "NULL array argument");
     if (stf_kind != EIG_STF_GAUSS && stf_kind != EIG_STF_GAUSS_DERIV)
         return set_error(EIG_EINVAL, "stf_kind");
-    HIP_TRY(hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
     std::vector<eig_grid> grids(grid, grid + nsolve);
     std::vector<MediumKey> media;
     std::map<MediumKey, int> seen;
@@ -812,11 +810,17 @@ int forward_solve_batch(eig_ctx* c, int32_t nsolve, const eig_grid* grid,
             (sp.param == 0 ? x : z) += sp.step;
             if (!source_inside(x, z, g))
                 return set_error(EIG_EINVAL, "perturbed source stencil touches a rigid node");
+            if (!deviation_in_window(sp.theta[sp.param], sp.step, g.h))
+                return set_error(EIG_EINVAL,
+                                 "dev_step moves the source by more than one cell");
         }
         sp.stf = stf_kind;
         sp.traces = (float2*)traces[i];
         solves.push_back(sp);
     }
+    if (!c) return set_error(EIG_EINVAL, "ctx is NULL");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
     // waves within the budget
     size_t i0 = 0;
     while (i0 < solves.size()) {
@@ -848,9 +852,9 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
                          int32_t sigma_mode, const double* sigma, int32_t per_receiver,
                          float* const* nominal, double* const* J, double* H1,
                          int32_t* status, void* stream) {
-    if (!c) return set_error(EIG_EINVAL, "ctx is NULL");
+    // host-side argument checks first (they need no device), then the context
     if (nsample < 0) return set_error(EIG_EINVAL, "nsample < 0");
-    if (nsample == 0) return EIG_OK;
+    if (nsample == 0) return c ? EIG_OK : set_error(EIG_EINVAL, "ctx is NULL");
     if (!grid || !medium || !theta || !rec || !sigma || !H1)
         return set_error(EIG_EINVAL, "NULL array argument");
     if (!sensitivity && (!(rel_step > 0) || !std::isfinite(rel_step) || rel_step > 0.1))
@@ -860,8 +864,6 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
         return set_error(EIG_EINVAL, "stf_kind");
     if (sigma_mode != EIG_SIGMA_GIVEN && sigma_mode != EIG_SIGMA_NOMINAL_PEAK)
         return set_error(EIG_EINVAL, "sigma_mode");
-    HIP_TRY(hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
     const int nrec0 = rec[0].n;
     for (int i = 0; i < nsample; ++i) {
         const eig_grid& g = grid[i];
@@ -889,8 +891,15 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
                 (j == 0 ? x : z) += sg * d;
                 if (!source_inside(x, z, g))
                     return set_error(EIG_EINVAL, "source stencil touches a rigid node");
+                if (!deviation_in_window(th[j], sg * d, g.h))
+                    return set_error(EIG_EINVAL,
+                                     "rel_step * |theta| moves the source by more than one "
+                                     "cell (the forcing window covers one)");
             }
     }
+    if (!c) return set_error(EIG_EINVAL, "ctx is NULL");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
     std::vector<eig_grid> grids(grid, grid + nsample);
     std::vector<MediumKey> media;
     std::map<MediumKey, int> seen;

@@ -170,6 +170,14 @@ inline bool source_inside(double x, double z, const eig_grid& g) {
     return kx - 2 >= 1 && kx + 3 <= g.nx - 2 && kz - 2 >= 0 && kz + 3 <= g.nz - 2;
 }
 
+// A deviation solve is forced on the union of the nominal and the perturbed
+// 6x6 stencils, a window kSrcW = 7 nodes wide: the perturbed coordinate may
+// leave the nominal cell by at most one cell either way.
+inline bool deviation_in_window(double coord, double step, double h) {
+    const int a = floor_cell(coord, h), b = floor_cell(coord + step, h);
+    return std::abs(a - b) <= kSrcW - 6;
+}
+
 inline int pitch_of(int nx) { return (nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign; }
 
 struct SolveSpec {

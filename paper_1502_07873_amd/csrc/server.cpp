@@ -23,10 +23,12 @@ namespace {
 struct Arena {
     std::map<size_t, size_t> free_;  // offset -> length
     size_t size = 0, align = kAlign;
+    size_t used = 0, peak = 0;       // bytes handed out now / at most
     void init(size_t sz, size_t al) {
         size = sz;
         align = al;
         free_.clear();
+        used = peak = 0;
         if (sz) free_[0] = sz;
     }
     size_t round(size_t b) const { return (b + align - 1) / align * align; }
@@ -38,12 +40,15 @@ struct Arena {
             const size_t rest = it->second - bytes, noff = it->first + bytes;
             free_.erase(it);
             if (rest) free_[noff] = rest;
+            used += bytes;
+            peak = std::max(peak, used);
             return true;
         }
         return false;
     }
     void release(size_t off, size_t bytes) {
         bytes = round(std::max<size_t>(bytes, 1));
+        used -= bytes;
         auto it = free_.emplace(off, bytes).first;
         auto nx = std::next(it);
         if (nx != free_.end() && it->first + it->second == nx->first) {
@@ -109,6 +114,13 @@ size_t group_bytes(const SrvQuery& q, int G) {
     return b + 16 * kAlign;
 }
 
+// Arena bytes of a query's laplace inputs (prior, theta, weights), reserved
+// with its first group and released when the query finishes.
+size_t tail_bytes(const SrvQuery& q) {
+    return align_up(sizeof(eig_prior)) + align_up(q.theta.size() * 8) + align_up(q.w.size() * 8) +
+           4 * kAlign;
+}
+
 }  // namespace
 
 struct eig_server {
@@ -147,6 +159,7 @@ int srv_admit(eig_server* v, hipStream_t s) {
     while (!v->queue.empty()) {
         SrvQuery& q = *v->queue.front();
         int G = std::min(v->group_samples, q.nsample - q.next_sample);
+        G = std::min<int>(G, (int)(v->nslot_cap / 15));
         const bool four_buf = q.medium.kind == EIG_MEDIUM_LAYERED && v->spl == 2;
         const size_t sample_live = (size_t)15 * (four_buf ? 4 : 2) * q.grid.nz *
                                    pitch_of(q.grid.nx) * sizeof(float2);
@@ -157,16 +170,24 @@ int srv_admit(eig_server* v, hipStream_t s) {
             G = std::min<int>(G, (int)(v->cache_bytes / sample_live));
             if (!v->groups.empty() && v->live + (size_t)G * sample_live > v->cache_bytes) break;
         }
-        size_t bytes = group_bytes(q, G);
         size_t off = 0, slot0 = 0;
         if (q.next_sample == 0 && q.tail_bytes == 0) {
             // the query's small laplace inputs are reserved with its first group
-            const size_t tb = align_up(sizeof(eig_prior)) + align_up(q.theta.size() * 8) +
-                              align_up(q.w.size() * 8) + 4 * kAlign;
+            const size_t tb = tail_bytes(q);
             if (!v->arena.alloc(tb, &q.tail_off)) break;
             q.tail_bytes = tb;
         }
-        if (!v->arena.alloc(bytes, &off)) break;
+        // a full group when memory allows; with nothing running, halve the
+        // group until it fits (submit guaranteed that one sample does), so
+        // the head of the queue never waits for memory that cannot free up
+        size_t bytes = group_bytes(q, G);
+        bool got = v->arena.alloc(bytes, &off);
+        while (!got && v->groups.empty() && G > 1) {
+            G = (G + 1) / 2;
+            bytes = group_bytes(q, G);
+            got = v->arena.alloc(bytes, &off);
+        }
+        if (!got) break;
         if (!v->slots.alloc((size_t)15 * G, &slot0)) {
             v->arena.release(off, bytes);
             break;
@@ -504,6 +525,10 @@ int eig_server_submit(eig_server* v, const eig_grid* grid, const eig_medium* med
                 (j == 0 ? x : z) += sg * rel_step * std::fabs(th[j]);
                 if (!source_inside(x, z, *grid))
                     return set_error(EIG_EINVAL, "source stencil touches a rigid node");
+                if (!deviation_in_window(th[j], sg * rel_step * std::fabs(th[j]), grid->h))
+                    return set_error(EIG_EINVAL,
+                                     "rel_step * |theta| moves the source by more than one "
+                                     "cell (the forcing window covers one)");
             }
     }
     auto q = std::make_unique<SrvQuery>();
@@ -524,7 +549,10 @@ int eig_server_submit(eig_server* v, const eig_grid* grid, const eig_medium* med
     q->eig = eig;
     q->status = status;
     q->chol_status = chol_status;
-    if (group_bytes(*q, 1) > v->mem_size)
+    // an idle server always admits at least one sample of the query at the
+    // head of the queue: its one-sample group and its laplace inputs must
+    // fit the arena together
+    if (group_bytes(*q, 1) + tail_bytes(*q) > v->mem_size)
         return set_error(EIG_EBUDGET, "one sample of this query exceeds the server budget");
     HIP_TRY(hipEventCreateWithFlags(&q->done_ev, hipEventDisableTiming));
     *id = q->id;
@@ -569,6 +597,8 @@ int eig_server_step(eig_server* v, int32_t max_launches, void* stream, int32_t* 
     }
     HIP_TRY(hipGetLastError());
     if (running) *running = (int32_t)v->groups.size();
+    if (v->groups.empty() && !v->queue.empty())
+        return set_error(EIG_EBUDGET, "the query at the head of the queue cannot be admitted");
     return EIG_OK;
 }
 
@@ -588,6 +618,14 @@ int eig_server_poll(eig_server* v, int64_t id, int32_t* done) {
     }
     if (e == hipErrorNotReady) return EIG_OK;
     return set_error(EIG_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
+}
+
+int eig_server_memory(eig_server* v, size_t* budget, size_t* in_use, size_t* peak) {
+    if (!v) return set_error(EIG_EINVAL, "server is NULL");
+    if (budget) *budget = v->mem_size;
+    if (in_use) *in_use = v->arena.used;
+    if (peak) *peak = v->arena.peak;
+    return EIG_OK;
 }
 
 int eig_server_pending(eig_server* v, int32_t* queued, int32_t* running) {

@@ -107,6 +107,9 @@ def _load():
         "eig_server_step": ([vp, i32, vp, ctypes.POINTER(i32)], ctypes.c_int),
         "eig_server_poll": ([vp, ctypes.c_int64, ctypes.POINTER(i32)], ctypes.c_int),
         "eig_server_pending": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
+        "eig_server_memory": ([vp, ctypes.POINTER(ctypes.c_size_t),
+                               ctypes.POINTER(ctypes.c_size_t),
+                               ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -122,7 +125,7 @@ EXPORTED = ("eig_ctx_create", "eig_ctx_destroy", "eig_last_error", "eig_ctx_work
             "theorem3_eig", "laplace_eig",
             "design_eval", "design_greedy", "noise_sigma_peak", "sparse_grid_gl", "eig_server_create",
             "eig_server_destroy", "eig_server_submit", "eig_server_step", "eig_server_poll",
-            "eig_server_pending")
+            "eig_server_pending", "eig_server_memory")
 
 
 def _check(rc: int):
@@ -497,11 +500,15 @@ class Server:
         _check(_lib.eig_server_create(ctx._h, budget_bytes, group_samples, ctypes.byref(h)))
         self._h = h
         self.ctx = ctx
+        # per query: the device tensors the engine reads (medium) or writes
+        # (outputs) after submit returns, held until poll reports it done
+        self._held = {}
 
     def close(self):
         if getattr(self, "_h", None):
-            _lib.eig_server_destroy(self._h)
+            _lib.eig_server_destroy(self._h)   # waits for the device
             self._h = None
+        self._held = {}
 
     def __del__(self):
         try:
@@ -529,6 +536,7 @@ class Server:
             ctypes.byref(prior), _np_ptr(wa), _ptr(H1), _ptr(dkl), _ptr(eig), _ptr(status),
             _ptr(chol_status), ctypes.byref(qid)))
         del keep
+        self._held[qid.value] = (tuple(medium), H1, dkl, eig, status, chol_status)
         return qid.value
 
     def step(self, max_launches: int, stream=None) -> int:
@@ -540,7 +548,16 @@ class Server:
     def poll(self, qid: int) -> bool:
         done = ctypes.c_int32()
         _check(_lib.eig_server_poll(self._h, int(qid), ctypes.byref(done)))
+        if done.value:
+            self._held.pop(int(qid), None)
         return bool(done.value)
+
+    def memory(self) -> dict:
+        """Arena budget, bytes in use now and the most ever in use."""
+        b, u, p = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.eig_server_memory(self._h, ctypes.byref(b), ctypes.byref(u),
+                                      ctypes.byref(p)))
+        return {"budget": b.value, "in_use": u.value, "peak": p.value}
 
     def pending(self):
         q, r = ctypes.c_int32(), ctypes.c_int32()

@@ -382,6 +382,20 @@ def serving_queries(rng: np.random.Generator, nquery: int,
     return out
 
 
+def c4_largest_query(seed: int = 44, nsample: int = 64) -> Workload:
+    """A design query at the largest serving shape: 1024^2 grid (h = 10 m),
+    4000 steps, random 4-layer medium, 101 random surface receivers,
+    `nsample` prior draws."""
+    rng = np.random.default_rng(seed)
+    n, nt, h = 1024, 4000, 10.0
+    med = random_layers_medium(rng, n, h, 4)
+    grid = Grid(n, n, h, cfl_dt(h, med.vp_max()), nt)
+    lo, hi = prior_box(grid)
+    theta = draw_uniform(rng, lo, hi, nsample)
+    rec = random_receivers(rng, n, 101)
+    return Workload("c4", grid, med, rec, lo, hi, theta, _mc(theta))
+
+
 def serving_stream(rng: np.random.Generator, nquery: int, n_range=(256, 512),
                    steps_range=(500, 2000), rec_range=(5, 101), sample_range=(16, 64),
                    h: float = 10.0, cover_travel: bool = True) -> List[Workload]:

@@ -125,3 +125,52 @@ def test_binding_argument_checks_refuse_before_any_call():
                                 [torch.zeros(10, dtype=torch.float32)])
     with pytest.raises(eigseis.EigError, match="one receiver array per grid"):
         ctx.forward_solve_batch([g, g], [None, None], np.zeros(14), [np.array([3])], [None, None])
+
+
+def _raw_args():
+    """Host structs for raw C-ABI calls whose argument checks fail before
+    the (NULL) context or any device pointer is used."""
+    from paper_1502_07873_amd import eigseis
+    g = eigseis.Grid(2048, 256, 10.0, 1e-3, 10, eigseis.BC_RIGID)
+    med = eigseis.Medium(eigseis.MEDIUM_LAYERED, 256, 256, 256)   # never read
+    rec = np.array([100, 200], dtype=np.int32)
+    R = eigseis.Receivers(2, rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return eigseis, g, med, rec, R
+
+
+@pytest.mark.parametrize("rel_step,moves", [(1e-4, False), (6e-4, False), (0.01, True),
+                                            (0.0015, True)])
+def test_jacobian_refuses_deviation_steps_beyond_the_forcing_window(rel_step, moves):
+    # x_s = 15005 m, h = 10 m: a step of rel_step * x_s leaves the source
+    # cell by more than one cell at rel_step >= 0.0015 (22.5 m); the 7-node
+    # forcing window then no longer holds both 6x6 stencils and the call is
+    # refused; smaller steps pass every argument check and stop at the NULL
+    # context
+    eigseis, g, med, rec, R = _raw_args()
+    theta = np.array([15005.0, 1205.0, 0.2, 7.0, 5e13, 5e13, 5e13])
+    sigma = np.ones(1)
+    rc = eigseis._lib.jacobian_fd(
+        None, 1, ctypes.byref(g), ctypes.byref(med), theta.ctypes.data_as(ctypes.c_void_p),
+        rel_step, eigseis.STF_GAUSS_DERIV, ctypes.byref(R), eigseis.SIGMA_GIVEN,
+        sigma.ctypes.data_as(ctypes.c_void_p), 0, None, None, 256, None, None)
+    msg = eigseis._lib.eig_last_error().decode()
+    assert rc == eigseis.EIG_EINVAL
+    assert ("more than one cell" in msg) == moves, msg
+    assert ("ctx is NULL" in msg) == (not moves), msg
+
+
+def test_forward_solve_refuses_a_deviation_step_of_two_cells():
+    eigseis, g, med, rec, R = _raw_args()
+    theta = np.array([10005.0, 1205.0, 0.2, 7.0, 5e13, 5e13, 5e13])
+    tr = (ctypes.c_void_p * 1)(256)
+    for param, step, moves in ((0, 12.0, False), (0, 20.0, True), (1, -25.0, True),
+                               (1, 9.9, False), (3, 100.0, False)):
+        dp = np.array([param], dtype=np.int32)
+        ds = np.array([step])
+        rc = eigseis._lib.forward_solve_batch(
+            None, 1, ctypes.byref(g), ctypes.byref(med), theta.ctypes.data_as(ctypes.c_void_p),
+            dp.ctypes.data_as(ctypes.c_void_p), ds.ctypes.data_as(ctypes.c_void_p),
+            eigseis.STF_GAUSS_DERIV, ctypes.byref(R), tr, None)
+        msg = eigseis._lib.eig_last_error().decode()
+        assert rc == eigseis.EIG_EINVAL
+        assert ("more than one cell" in msg) == moves, (param, step, msg)
