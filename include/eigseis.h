@@ -400,6 +400,30 @@ int design_greedy(eig_ctx* ctx, int32_t nsample, int32_t ncand,
                   void* stream);
 
 /*
+ * design_greedy_noalloc — design_greedy for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  It calls no hipMalloc, hipFree or other
+ * allocating routine (and no memset: only kernel launches on `stream`), and
+ * gives bitwise the same order and curve as design_greedy.
+ *
+ *   H1r:   device [nsample][ncand][7][7] (as for design_greedy)
+ *   prior: host, copied into device scratch by a kernel launched on `stream`
+ *   theta: DEVICE [nsample][7], needed for EIG_PRIOR_GAUSSIAN, may be NULL
+ *          for EIG_PRIOR_UNIFORM
+ *   w:     DEVICE [nsample] weights
+ *   order, curve: device [kmax], as for design_greedy
+ * Scratch: a 64 MiB static device array per GPU (held until the process
+ * ends), of which a call uses about 8 * nsample * (ncand + 49) + 9 * ncand
+ * bytes plus 1 KiB; EIG_EBUDGET, before any launch, if that exceeds 64 MiB.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or host threads) race and must be serialised by
+ * the caller.  The context's own workspace is not touched.
+ */
+int design_greedy_noalloc(eig_ctx* ctx, int32_t nsample, int32_t ncand, const double* H1r,
+                          const eig_prior* prior, const double* theta, const double* w,
+                          int32_t kmax, int32_t* order, double* curve, void* stream);
+
+/*
  * noise_sigma_peak — sigma = rel * max |u| over all free surface nodes
  * (i = 1..nx-2), both components and all levels, of the nominal solve at
  * theta (usually the prior mean).  Synchronous; writes *sigma_out (host).

@@ -648,6 +648,9 @@ int eig_ctx_create(int device, size_t hbm_budget_bytes, eig_ctx** out) {
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return set_error(EIG_EINVAL, "no such device");
     HIP_TRY(hipSetDevice(device));
+    // device address of this device's no-alloc scratch array; a failure is
+    // reported by the entry point that needs it (it retries the lookup)
+    (void)noalloc_scratch_init(device);
     eig_ctx* c = new eig_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes;

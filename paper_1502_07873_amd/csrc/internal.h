@@ -118,6 +118,10 @@ struct DualJob {
     int32_t nsteps, nrec;
 };
 
+// Looks up (once per device, with that device current) the device address
+// of the file-scope scratch array that design_greedy_noalloc works in.
+int noalloc_scratch_init(int device);
+
 // launchers (all asynchronous on `s`)
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 void launch_layered_coef(const double* rho, const double* lam, const double* mu,

@@ -98,6 +98,8 @@ def _load():
         "laplace_eig": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "design_eval": ([vp, i32, i32, vp, i32, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "design_greedy": ([vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
+        "design_greedy_noalloc": ([vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp],
+                                  ctypes.c_int),
         "noise_sigma_peak": ([vp, vp, vp, vp, i32, dbl, vp, vp], ctypes.c_int),
         "sparse_grid_gl": ([i32, i32, vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "eig_server_create": ([vp, ctypes.c_size_t, i32, ctypes.POINTER(vp)], ctypes.c_int),
@@ -123,7 +125,7 @@ EXPORTED = ("eig_ctx_create", "eig_ctx_destroy", "eig_last_error", "eig_ctx_work
             "eig_ctx_stencil_stats", "eig_ctx_set_option", "eig_ctx_get_option",
             "forward_solve_batch", "jacobian_fd", "jacobian_sensitivity", "nested_mc_eig",
             "theorem3_eig", "laplace_eig",
-            "design_eval", "design_greedy", "noise_sigma_peak", "sparse_grid_gl", "eig_server_create",
+            "design_eval", "design_greedy", "design_greedy_noalloc", "noise_sigma_peak", "sparse_grid_gl", "eig_server_create",
             "eig_server_destroy", "eig_server_submit", "eig_server_step", "eig_server_poll",
             "eig_server_pending", "eig_server_memory")
 
@@ -481,6 +483,22 @@ class Context:
         _check(_lib.design_greedy(self._h, ns, nc, _ptr(H1r), ctypes.byref(prior),
                                   None if th is None else _np_ptr(th), _np_ptr(wa),
                                   int(kmax), _ptr(order), _ptr(curve), _stream(stream)))
+
+    def design_greedy_noalloc(self, H1r, prior: Prior, w, kmax, order, curve, theta=None,
+                              stream=None):
+        """design_greedy without device allocation: w [nsample] and theta
+        [nsample][7] (or None for a uniform prior) are device float64
+        tensors."""
+        import torch
+        ns, nc = int(H1r.shape[0]), int(H1r.shape[1])
+        _dev(H1r, "H1r", torch.float64, ns * nc * NTHETA * NTHETA)
+        _dev(w, "w", torch.float64, ns)
+        _dev(theta, "theta", torch.float64, ns * NTHETA, optional=True)
+        _dev(order, "order", torch.int32, max(int(kmax), 0))
+        _dev(curve, "curve", torch.float64, max(int(kmax), 0))
+        _check(_lib.design_greedy_noalloc(self._h, ns, nc, _ptr(H1r), ctypes.byref(prior),
+                                          _ptr(theta), _ptr(w), int(kmax), _ptr(order),
+                                          _ptr(curve), _stream(stream)))
 
     def noise_sigma_peak(self, grid, medium, theta, rel=1e-3, stf="gauss_deriv",
                          stream=None) -> float:
