@@ -18,8 +18,10 @@
  *    Work is enqueued on `stream` (a hipStream_t; NULL = default stream);
  *    device outputs are valid after the stream has been synchronised.
  *  - Numerical failures found on the device (a non-positive-definite
- *    Hessian, a non-finite wavefield) are reported per sample in `status`
- *    (EIG_ENOTPD / EIG_ENONFINITE) and poison dependent results with NaN.
+ *    Hessian, a non-finite wavefield, a time step the stability bound does
+ *    not cover) are reported per sample in `status` (EIG_ENOTPD /
+ *    EIG_ENONFINITE / EIG_EUNSTABLE) and poison dependent results with NaN;
+ *    the other samples of the call are computed exactly as alone.
  *  - "host" pointers are read before the call returns; "device" pointers are
  *    caller-owned device memory, never freed or kept by the library after
  *    the enqueued work completes.
@@ -56,6 +58,7 @@ extern "C" {
 #define EIG_ENONFINITE (-5)   /* non-finite wavefield (status) */
 #define EIG_EHIP (-6)         /* HIP runtime error */
 #define EIG_EUNSUPPORTED (-7) /* valid but not supported */
+#define EIG_EUNSTABLE (-8)    /* time step beyond the stability bound (status) */
 
 /* source time functions (Section 4.1 and its time derivative) */
 #define EIG_STF_GAUSS 0       /* omega/sqrt(2 pi) exp(-omega^2 (t-t_s)^2 / 2) */
@@ -246,7 +249,16 @@ int forward_solve_batch(eig_ctx* ctx, int32_t nsolve, const eig_grid* grid,
  *              [nsteps+1][nrec][2]) or NULL
  *   J:         host array [nsample] of device pointers (double
  *              [nsteps+1][nrec][2][7]) or NULL
- *   status:    device [nsample] or NULL: 0, or EIG_ENONFINITE
+ *   status:    device [nsample] or NULL: 0; EIG_ENONFINITE if a trace of
+ *              the sample holds a non-finite value; else EIG_EUNSTABLE if the
+ *              step exceeds the sample's stability bound: with B = -dt^2
+ *              rho^-1 A_h (A_h the discrete operator of Section 3.3.1 on the
+ *              sample's medium), some free node's x or depth row has an
+ *              absolute row sum above 4 (Gershgorin: the leapfrog step is
+ *              stable when every eigenvalue of B is at most 4; this bound
+ *              allows v_p dt / h up to 0.816 for v_s = v_p / sqrt 3, the exact
+ *              homogeneous limit being 0.866).  A flagged sample's H_1 is NaN
+ *              (its noise level is set to NaN), whether or not status is given.
  * EIG_EINVAL also when rel_step * |x_s| or rel_step * |z_s| moves the source
  * out of its cell by more than one cell (the 7x7 forcing window of a
  * deviation solve covers the nominal and the perturbed stencil only then);

@@ -976,6 +976,13 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
             sd.nt = grid[i].nsteps + 1;
             sd.nrec = rec[i].n;
             sd.J = J ? J[i] : nullptr;
+            sd.rho = medium[i].rho;
+            sd.lam = medium[i].lam;
+            sd.mu = medium[i].mu;
+            sd.med_kind = medium[i].kind;
+            sd.nx = grid[i].nx;
+            sd.nz = grid[i].nz;
+            sd.dt2_h2 = (grid[i].dt / grid[i].h) * (grid[i].dt / grid[i].h);
             float2* nom = (nominal && nominal[i]) ? (float2*)nominal[i]
                                                   : (float2*)(c->ws + toff[q][0]);
             sd.nominal = nom;

@@ -37,17 +37,70 @@ __device__ __forceinline__ void sample_range(int n, int b, int& lo, int& hi) {
     hi = min(n, lo + chunk);
 }
 
+// Stability of the leapfrog step at free node (i, k): the larger of the two
+// absolute row sums (x and depth components) of B = -dt^2 rho^-1 A_h, the
+// operator the stencil kernels apply (a = lambda + 2 mu; n, m: the rows
+// below and above; R, L: the columns right and left; rigid neighbours are
+// counted too, which only raises the bound).  The step u^{m+1} = (2 - B) u^m
+// - u^{m-1} keeps a positive conserved energy when every eigenvalue of B is
+// at most 4; by Gershgorin's theorem that holds when every row sum is, so a
+// return value <= 1 guarantees stability.
+__device__ double stability_bound(const SampleDesc& sd, int i, int k) {
+    const int nx = sd.nx;
+    const bool nodal = sd.med_kind == EIG_MEDIUM_NODAL;
+    auto at = [&](const double* a, int ii, int kk) {
+        return a[nodal ? (size_t)kk * nx + ii : (size_t)kk];
+    };
+    const double* L = sd.lam;
+    const double* M = sd.mu;
+    const double l = at(L, i, k), m = at(M, i, k), ac = l + 2.0 * m;
+    const double lR = at(L, i + 1, k), mR = at(M, i + 1, k), aR = lR + 2.0 * mR;
+    const double lL = at(L, i - 1, k), mL = at(M, i - 1, k), aL = lL + 2.0 * mL;
+    const double ln = at(L, i, k + 1), mn = at(M, i, k + 1), an = ln + 2.0 * mn;
+    double ru, rv;
+    if (k == 0) {  // traction-free row
+        ru = (ac + aR) + (aL + ac) + 2.0 * (m + mn) +
+             0.5 * (fabs(lR + mn) + fabs(m - lR) + fabs(lL + mn) + fabs(lL - m));
+        rv = (m + mR) + (mL + m) + 2.0 * (ac + an) +
+             0.5 * (fabs(ln + mR) + fabs(l - mR) + fabs(ln + mL) + fabs(l - mL));
+    } else {
+        const double lm = at(L, i, k - 1), mm = at(M, i, k - 1), am = lm + 2.0 * mm;
+        ru = (ac + aR) + (aL + ac) + (m + mn) + (mm + m) +
+             0.25 * (fabs(lR + mn) + fabs(lL + mn) + fabs(lR + mm) + fabs(lL + mm));
+        rv = (m + mR) + (mL + m) + (ac + an) + (am + ac) +
+             0.25 * (fabs(ln + mR) + fabs(ln + mL) + fabs(lm + mR) + fabs(lm + mL));
+    }
+    return sd.dt2_h2 / at(sd.rho, i, k) * fmax(ru, rv) * 0.25;
+}
+
 // Per-sample status and noise level.  mode EIG_SIGMA_GIVEN: sigma = given;
 // EIG_SIGMA_NOMINAL_PEAK: sigma = given * max |nominal trace value|.
-// Block (s, b) covers range b of sample s and leaves its maximum and
-// non-finite flag in work (the maximum of a set and the flag do not depend on
+// Block (s, b) covers range b of sample s's trace elements and of its free
+// nodes and leaves the trace maximum, the non-finite flag and the largest
+// stability bound in work (the maximum of a set and the flag do not depend on
 // how the set is cut); sample_check_finish_kernel combines the ranges.
 __global__ void __launch_bounds__(256)
 sample_check_kernel(const SampleDesc* __restrict__ samples, double* __restrict__ work) {
     const SampleDesc& sd = samples[blockIdx.x];
-    if ((int)blockIdx.y >= sample_ranges(sd.nt * sd.nrec)) return;
+    const int nr = sample_ranges(sd.nt * sd.nrec);
+    if ((int)blockIdx.y >= nr) return;
     int lo, hi;
     sample_range(sd.nt * sd.nrec, blockIdx.y, lo, hi);
+    // free nodes whose bound is checked: the rows of a depth-only medium (its
+    // bound does not vary along x), every free node of a nodal one
+    double gmax = 0.0;
+    if (sd.rho) {
+        const bool nodal = sd.med_kind == EIG_MEDIUM_NODAL;
+        const int ncol = nodal ? sd.nx - 2 : 1;
+        const long long nnode = (long long)ncol * (sd.nz - 1);
+        const long long chunk = (nnode + nr - 1) / nr;
+        const long long n0 = min(nnode, (long long)blockIdx.y * chunk);
+        const long long n1 = min(nnode, n0 + chunk);
+        for (long long q = n0 + threadIdx.x; q < n1; q += blockDim.x) {
+            const int k = (int)(q / ncol), i = 1 + (int)(q % ncol);
+            gmax = fmax(gmax, stability_bound(sd, i, k));
+        }
+    }
     float mx = 0.f;
     int bad = 0;
     for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) {
@@ -62,20 +115,24 @@ sample_check_kernel(const SampleDesc* __restrict__ samples, double* __restrict__
         }
     __shared__ float smx[256];
     __shared__ int sbad[256];
+    __shared__ double sg[256];
     smx[threadIdx.x] = mx;
     sbad[threadIdx.x] = bad;
+    sg[threadIdx.x] = gmax;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
             smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + o]);
             sbad[threadIdx.x] |= sbad[threadIdx.x + o];
+            sg[threadIdx.x] = fmax(sg[threadIdx.x], sg[threadIdx.x + o]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double* w = work + 2 * ((size_t)blockIdx.x * kSampleSplit + blockIdx.y);
+        double* w = work + 3 * ((size_t)blockIdx.x * kSampleSplit + blockIdx.y);
         w[0] = (double)smx[0];
         w[1] = (double)sbad[0];
+        w[2] = sg[0];
     }
 }
 
@@ -88,15 +145,21 @@ __global__ void sample_check_finish_kernel(const SampleDesc* __restrict__ sample
     if (s >= nsample) return;
     float mx = 0.f;
     int bad = 0;
+    double gmax = 0.0;
     const int nr = sample_ranges(samples[s].nt * samples[s].nrec);
     for (int b = 0; b < nr; ++b) {
-        const double* w = work + 2 * ((size_t)s * kSampleSplit + b);
+        const double* w = work + 3 * ((size_t)s * kSampleSplit + b);
         mx = fmaxf(mx, (float)w[0]);
         bad |= w[1] != 0.0;
+        gmax = fmax(gmax, w[2]);
     }
     const double g = given[s];
-    sigma[s] = mode == EIG_SIGMA_NOMINAL_PEAK ? g * (double)mx : g;
-    if (status) status[s] = bad ? EIG_ENONFINITE : EIG_OK;
+    // a step the bound does not vouch for poisons the sample's H_1 (through
+    // a NaN noise level) as a non-finite solve does through its traces
+    const bool unstable = !(gmax <= 1.0);
+    sigma[s] = unstable ? __longlong_as_double(0x7ff8000000000000ULL)
+                        : (mode == EIG_SIGMA_NOMINAL_PEAK ? g * (double)mx : g);
+    if (status) status[s] = bad ? EIG_ENONFINITE : (unstable ? EIG_EUNSTABLE : EIG_OK);
 }
 
 // Block (s, b) sums J^T J (and J^T r for the gradient) over range b of

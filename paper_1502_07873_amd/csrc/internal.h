@@ -96,6 +96,13 @@ struct SampleDesc {
     const float2* ystar;
     const float2* noise;
     double* grad;
+    // stability check of the sample's step (sample_check only; rho NULL:
+    // not checked): its medium's FP64 arrays ([nz] or [nz][nx]) and dt^2/h^2
+    const double* rho;
+    const double* lam;
+    const double* mu;
+    int32_t med_kind, nx, nz;
+    double dt2_h2;
 };
 
 // One H_2 contraction (Theorem 2, through the dual solve of Section 3.3.2):

@@ -248,6 +248,13 @@ int srv_admit(eig_server* v, hipStream_t s) {
             std::memset(&sd, 0, sizeof(sd));
             sd.nt = g.nsteps + 1;
             sd.nrec = nrec;
+            sd.rho = q.medium.rho;
+            sd.lam = q.medium.lam;
+            sd.mu = q.medium.mu;
+            sd.med_kind = q.medium.kind;
+            sd.nx = g.nx;
+            sd.nz = g.nz;
+            sd.dt2_h2 = (g.dt / g.h) * (g.dt / g.h);
             for (int q15 = 0; q15 < 15; ++q15) {
                 const size_t k = (size_t)gs * 15 + q15;
                 const int param = q15 == 0 ? -1 : (q15 - 1) / 2;

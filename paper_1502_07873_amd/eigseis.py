@@ -25,6 +25,7 @@ EIG_ENOTPD = -4
 EIG_ENONFINITE = -5
 EIG_EHIP = -6
 EIG_EUNSUPPORTED = -7
+EIG_EUNSTABLE = -8
 STF_GAUSS = 0
 STF_GAUSS_DERIV = 1
 MEDIUM_LAYERED = 0
