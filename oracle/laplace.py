@@ -73,6 +73,53 @@ def dkl_hat(H1: np.ndarray, theta, prior: dict):
             - log_prior(theta, prior)), True
 
 
+def dkl_hat_stack(H1: np.ndarray, theta: np.ndarray, prior: dict) -> np.ndarray:
+    """dkl_hat over a stack of Hessians H1 [..., N, N] with theta [..., 7]
+    (the same Theorem 4 formula and scaled log-det of Section 3.3.3, with
+    numpy's stacked Cholesky); NaN where a Hessian is not positive definite.
+    Only for the uniform prior, whose h does not depend on theta."""
+    if prior["kind"] != "uniform":
+        raise ValueError("dkl_hat_stack: uniform prior only")
+    n = H1.shape[-1]
+    d = np.diagonal(H1, axis1=-2, axis2=-1)
+    ok = np.all(np.isfinite(H1), axis=(-2, -1)) & np.all(d > 0, axis=-1)
+    s = np.sqrt(np.where(ok[..., None], d, 1.0))
+    Ht = H1 / (s[..., :, None] * s[..., None, :])
+    Ht = np.where(ok[..., None, None], Ht, np.eye(n))
+    ld = np.full(H1.shape[:-2], np.nan)
+    flat_H = Ht.reshape(-1, n, n)
+    flat_ok = ok.reshape(-1)
+    flat_ld = ld.reshape(-1)
+    try:
+        L = np.linalg.cholesky(flat_H)
+        good = flat_ok
+    except np.linalg.LinAlgError:
+        # some scaled Hessian is indefinite: factor one by one
+        L = np.zeros_like(flat_H)
+        good = flat_ok.copy()
+        for q in range(flat_H.shape[0]):
+            try:
+                L[q] = np.linalg.cholesky(flat_H[q])
+            except np.linalg.LinAlgError:
+                good[q] = False
+    diagL = np.diagonal(L, axis1=-2, axis2=-1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = 2.0 * np.sum(np.log(diagL), axis=-1) + \
+            2.0 * np.sum(np.log(s.reshape(-1, n)), axis=-1)
+    flat_ld[good] = v[good]
+    h = log_prior(np.zeros(7), prior)
+    return -0.5 * (n * math.log(2 * math.pi) - ld) - 0.5 * n - h
+
+
+def greedy_step_values(H1r: np.ndarray, base: np.ndarray, theta: np.ndarray,
+                       w: np.ndarray, prior: dict) -> np.ndarray:
+    """I(design + {c}) = sum_s w_s D^_KL(base_s + H_1,c(s)) for every
+    candidate c, where base holds the chosen receivers' summed Hessians
+    [S][7][7] (H_1 additive over receivers, Section 4.5 designs)."""
+    vals = dkl_hat_stack(base[:, None] + H1r, theta[:, None], prior)   # [S][C]
+    return np.sum(np.asarray(w)[:, None] * vals, axis=0)
+
+
 def eig_average(dkl: np.ndarray, w: np.ndarray) -> float:
     """I = sum_i w_i D^_KL(theta_i) (eqs. for the sparse-quadrature and Monte
     Carlo estimates).  Any failed sample (NaN) makes I NaN."""

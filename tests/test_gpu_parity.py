@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import synthetic
+from _compare import check_greedy, check_jacobian, check_receivers, scaled_hessian_err
 from oracle import elastic, laplace, pipeline as opipe
 
 torch = pytest.importorskip("torch")
@@ -37,10 +38,6 @@ def _dev_medium(med):
     return device_medium(med.kind, med.rho, med.lam, med.mu)
 
 
-def _relerr(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-
 def _forward(ctx, grid, medium, thetas, receivers, dev_param=None, dev_step=None,
              stf="gauss_deriv"):
     from paper_1502_07873_amd.query import grid_tuple
@@ -62,7 +59,7 @@ def test_forward_traces_c1(ctx):
     for s, th in enumerate(wl.theta):
         ref = elastic.forward(wl.grid, wl.medium, th, wl.receivers)
         assert np.all(out[s][0] == 0)
-        assert _relerr(out[s], ref) <= TRACE_TOL, (s, _relerr(out[s], ref))
+        check_receivers(out[s], ref, TRACE_TOL, what=f"c1 solve {s}")
 
 
 @pytest.mark.parametrize("case", ["ragged_layered", "ragged_nodal", "gauss_stf"])
@@ -88,7 +85,7 @@ def test_forward_traces_ragged(ctx, case):
     out = _forward(ctx, grid, med, thetas, rec, stf=stf)
     for s, th in enumerate(thetas):
         ref = elastic.forward(grid, med, th, rec, stf)
-        assert _relerr(out[s], ref) <= TRACE_TOL, (case, s, _relerr(out[s], ref))
+        check_receivers(out[s], ref, TRACE_TOL, what=f"{case} solve {s}")
 
 
 def test_deviation_solves_match_literal_differences(ctx):
@@ -105,7 +102,7 @@ def test_deviation_solves_match_literal_differences(ctx):
         tp[j] += steps[q]
         ref = (elastic.forward(wl.grid, wl.medium, tp, wl.receivers)
                - elastic.forward(wl.grid, wl.medium, th, wl.receivers))
-        assert _relerr(out[q], ref) <= 1e-4, (q, _relerr(out[q], ref))
+        check_receivers(out[q], ref, 1e-4, what=f"deviation solve {q}")
 
 
 def test_jacobian_hessian_eig_c1(ctx):
@@ -119,14 +116,11 @@ def test_jacobian_hessian_eig_c1(ctx):
     torch.cuda.synchronize()
     assert int(out["status"].abs().sum()) == 0
     for s in range(len(wl.theta)):
-        Jg = out["J"][s].cpu().numpy()
-        for j in range(7):
-            e = _relerr(Jg[..., j], ref["J"][s][..., j])
-            assert e <= JAC_TOL, (s, j, e)
-    H = out["H1"].cpu().numpy()
-    relH = np.max(np.abs(H - ref["H1"]) / np.sqrt(np.abs(np.einsum("sii,sjj->sij",
-                                                                   ref["H1"], ref["H1"]))))
-    assert relH < 1e-3
+        check_receivers(out["nominal"][s].cpu().numpy(), ref["nominal"][s], TRACE_TOL,
+                        what=f"nominal {s}")
+        check_jacobian(out["J"][s].cpu().numpy(), ref["J"][s], JAC_TOL, what=f"sample {s}")
+    # |dH_ij| <= (2 eps + eps^2) sqrt(H_ii H_jj) for columns within eps
+    assert scaled_hessian_err(out["H1"].cpu().numpy(), ref["H1"]) <= 2 * JAC_TOL
     dkl = out["dkl"].cpu().numpy()
     assert np.max(np.abs(dkl - ref["dkl"])) <= NAT_TOL, np.abs(dkl - ref["dkl"])
     assert abs(float(out["eig"].cpu()[0]) - ref["eig"]) <= NAT_TOL
@@ -148,12 +142,10 @@ def test_sensitivity_jacobian_hessian_eig_c1(ctx):
     assert int(out["status"].abs().sum()) == 0
     worst = 0.0
     for s in range(len(wl.theta)):
-        assert _relerr(out["nominal"][s].cpu().numpy(), ref["nominal"][s]) <= TRACE_TOL
-        Jg = out["J"][s].cpu().numpy()
-        for j in range(7):
-            e = _relerr(Jg[..., j], ref["J"][s][..., j])
-            worst = max(worst, e)
-            assert e <= SENS_TOL, (s, j, e)
+        check_receivers(out["nominal"][s].cpu().numpy(), ref["nominal"][s], TRACE_TOL,
+                        what=f"nominal {s}")
+        worst = max(worst, check_jacobian(out["J"][s].cpu().numpy(), ref["J"][s], SENS_TOL,
+                                          what=f"sample {s}"))
     _say(f"  worst column rel err {worst:.3e}")
     H = out["H1"].cpu().numpy()
     relH = np.max(np.abs(H - ref["H1"]) / np.sqrt(np.abs(np.einsum("sii,sjj->sij",
@@ -206,9 +198,7 @@ def test_sensitivity_ragged(ctx, case):
     for s in range(S):
         _, Jr = elastic.jacobian_sensitivity(grids[s], meds[s], thetas[s], recs[s], stf)
         assert np.max(np.abs(Jr)) > 0
-        Jg = J[s].cpu().numpy()
-        for j in range(7):
-            assert _relerr(Jg[..., j], Jr[..., j]) <= SENS_TOL, (s, j)
+        check_jacobian(J[s].cpu().numpy(), Jr, SENS_TOL, what=f"{case} sample {s}")
         Hr = (laplace.hessian_h1_per_receiver(Jr, sigma) if per
               else laplace.hessian_h1(Jr, sigma))
         Hg = H1[s].cpu().numpy()
@@ -233,9 +223,8 @@ def test_sensitivity_agrees_with_central_differences(ctx):
                   rel_step=1e-4, jacobian="fd", **kw)
     torch.cuda.synchronize()
     for s in range(2):
-        for j in range(7):
-            e = _relerr(b["J"][s].cpu().numpy()[..., j], a["J"][s].cpu().numpy()[..., j])
-            assert e <= JAC_TOL, (s, j, e)
+        check_jacobian(b["J"][s].cpu().numpy(), a["J"][s].cpu().numpy(), JAC_TOL,
+                       what=f"sample {s}")
     assert np.max(np.abs(a["dkl"].cpu().numpy() - b["dkl"].cpu().numpy())) <= NAT_TOL
 
 
@@ -301,17 +290,25 @@ def test_per_receiver_design_eval_and_greedy(ctx):
     ok = ~np.isnan(eig_ref)
     assert np.array_equal(ok, ~np.isnan(eg))
     assert np.max(np.abs(eg[ok] - eig_ref[ok])) <= NAT_TOL
-    order_ref, curve_ref = laplace.greedy(H1r_ref, wl.theta, wl.weights, prior, 5)
-    order = torch.empty(5, dtype=torch.int32, device="cuda")
-    curve = torch.empty(5, dtype=torch.float64, device="cuda")
-    ctx.design_greedy(H1r, make_prior(wl.lo, wl.hi), wl.weights, 5, order, curve,
+    K = 5
+    order = torch.empty(K, dtype=torch.int32, device="cuda")
+    curve = torch.empty(K, dtype=torch.float64, device="cuda")
+    ctx.design_greedy(H1r, make_prior(wl.lo, wl.hi), wl.weights, K, order, curve,
                       theta=wl.theta)
     torch.cuda.synchronize()
     og, cg = order.cpu().numpy(), curve.cpu().numpy()
-    k = len(order_ref)
-    assert np.max(np.abs(cg[:k] - curve_ref)) <= NAT_TOL
-    # the chosen sequence must agree unless two candidates tie within tolerance
-    assert list(og[:k]) == list(order_ref) or np.max(np.abs(np.diff(curve_ref))) < 1e-6
+    # every step: the pick is the argmax of the oracle's I on the same FP64
+    # Hessians and the run's own prefix (ties only within 1e-9 relative), and
+    # the oracle's own argmax on its Hessians wherever its best two
+    # candidates are more than 2 NAT_TOL apart
+    check_greedy(og, cg, Hg, wl.theta, wl.weights, prior, ref_H1r=H1r_ref,
+                 ref_gap=2 * NAT_TOL)
+    # the value of each chosen design on the oracle's Hessians
+    masks = np.zeros((K, len(rec)), dtype=np.uint8)
+    for k in range(K):
+        masks[k, og[:k + 1]] = 1
+    ref_curve = laplace.design_eval(H1r_ref, masks, wl.theta, wl.weights, prior)
+    assert np.max(np.abs(cg - ref_curve)) <= NAT_TOL
     del eigseis
 
 
@@ -462,7 +459,7 @@ def test_stencil_variants_bitwise_identical(variant, nsteps, monkeypatch):
         assert np.max(np.abs(ref)) > 1.0  # the wavefield has reached the receivers
         if nsteps % 2:
             assert np.max(np.abs(ref[-1])) > 0
-        assert _relerr(outs[variant][s], ref) <= TRACE_TOL
+        check_receivers(outs[variant][s], ref, TRACE_TOL, what=f"variant {variant} solve {s}")
 
 
 @pytest.mark.parametrize("variant", [17, 18])
@@ -494,7 +491,7 @@ def test_nodal_variants_bitwise_identical(variant, monkeypatch):
         assert np.array_equal(outs[6][s], outs[variant][s]), s
         ref = elastic.forward(grid, med, thetas[s], rec)
         assert np.max(np.abs(ref)) > 1.0
-        assert _relerr(outs[variant][s], ref) <= TRACE_TOL
+        check_receivers(outs[variant][s], ref, TRACE_TOL, what=f"variant {variant} solve {s}")
 
 
 def test_three_step_family_with_mixed_lengths_matches_one_step():
@@ -727,14 +724,17 @@ def test_sparse_quadrature_greedy_pipeline_c5_shape(ctx):
     scale = np.sqrt(np.abs(np.einsum("scii,scjj->scij", H1r_ref, H1r_ref)))
     assert np.max(np.abs(H1r.cpu().numpy() - H1r_ref) / scale) < 1e-3
     prior = laplace.uniform_prior(wl.lo, wl.hi)
-    k = 6
-    order_ref, curve_ref = laplace.greedy(H1r_ref, X, W, prior, k)
-    order = torch.empty(k, dtype=torch.int32, device="cuda")
-    curve = torch.empty(k, dtype=torch.float64, device="cuda")
-    ctx.design_greedy(H1r, make_prior(wl.lo, wl.hi), w, k, order, curve, theta=nodes)
+    K = 6
+    order = torch.empty(K, dtype=torch.int32, device="cuda")
+    curve = torch.empty(K, dtype=torch.float64, device="cuda")
+    ctx.design_greedy(H1r, make_prior(wl.lo, wl.hi), w, K, order, curve, theta=nodes)
     torch.cuda.synchronize()
-    cg = curve.cpu().numpy()
+    og, cg = order.cpu().numpy(), curve.cpu().numpy()
     # I = sum_s w_s D_s with sparse-grid weights of both signs: a per-sample
     # error bound of NAT_TOL carries over as NAT_TOL * sum |w_s| (= 13 here)
-    assert np.max(np.abs(cg[:len(curve_ref)] - curve_ref)) <= NAT_TOL * np.sum(np.abs(W))
-    assert list(order.cpu().numpy()[:len(order_ref)]) == list(order_ref)
+    wtol = NAT_TOL * np.sum(np.abs(W))
+    check_greedy(og, cg, H1r.cpu().numpy(), X, W, prior, ref_H1r=H1r_ref, ref_gap=2 * wtol)
+    masks = np.zeros((K, len(cand)), dtype=np.uint8)
+    for k in range(K):
+        masks[k, og[:k + 1]] = 1
+    assert np.max(np.abs(cg - laplace.design_eval(H1r_ref, masks, X, W, prior))) <= wtol

@@ -145,6 +145,43 @@ def test_design_eval_and_greedy():
     assert curve[1] <= best_pair + 1e-12
 
 
+def test_stacked_dkl_and_greedy_step_values_equal_the_scalar_forms():
+    # the stacked Theorem 4 formula against dkl_hat one matrix at a time,
+    # including a Hessian with a zero diagonal and an indefinite one (NaN),
+    # and the per-candidate step values against design_eval's sums
+    rng = np.random.default_rng(12)
+    S, C = 6, 9
+    lo, hi = -np.ones(N), 2 * np.ones(N)
+    prior = laplace.uniform_prior(lo, hi)
+    H1r = np.empty((S, C, N, N))
+    for s in range(S):
+        for c in range(C):
+            H1r[s, c] = _spd(rng, np.logspace(-3, 5, N)[rng.permutation(N)])
+    H1r[2, 4] = 0.0
+    H1r[4, 7] = -np.eye(N) + 0.1 * np.ones((N, N))
+    theta = rng.uniform(-1, 2, (S, N))
+    got = laplace.dkl_hat_stack(H1r, np.repeat(theta[:, None], C, axis=1), prior)
+    for s in range(S):
+        for c in range(C):
+            ref, ok = laplace.dkl_hat(H1r[s, c], theta[s], prior)
+            if ok:
+                assert abs(got[s, c] - ref) <= 1e-12 * abs(ref)
+            else:
+                assert np.isnan(got[s, c]) and (s, c) in ((2, 4), (4, 7))
+    w = rng.uniform(-0.5, 1.5, S)
+    base = H1r[:, 1] + H1r[:, 3]
+    vals = laplace.greedy_step_values(H1r, base, theta, w, prior)
+    masks = np.zeros((C, C), np.uint8)
+    masks[:, [1, 3]] = 1
+    masks[np.arange(C), np.arange(C)] = 1
+    ref = laplace.design_eval(H1r, masks, theta, w, prior)
+    rest = np.array([c for c in range(C) if c not in (1, 3)])   # not yet chosen
+    vals, ref = vals[rest], ref[rest]
+    fin = ~np.isnan(ref)
+    assert np.array_equal(fin, ~np.isnan(vals)) and not fin.all()
+    assert np.max(np.abs(vals[fin] - ref[fin])) <= 1e-12 * np.max(np.abs(ref[fin]))
+
+
 def _golden_sizes():
     path = os.path.join(os.path.dirname(__file__), "golden", "sparse_grid_sizes.txt")
     rows = []
