@@ -3,15 +3,23 @@
 // A query is the per-sample Jacobian/H_1 work of jacobian_fd followed by
 // laplace_eig.  Its samples are admitted in groups of `group_samples` as
 // device memory frees up (first-fit arena inside the server's HBM budget)
-// and as descriptor slots allow.  Every launch advances all admitted solves
-// of all queries by one leapfrog step: a solve admitted at launch L takes
-// its step m at launch L + m (SolveDesc::start = L), so queries that arrive
-// while others run join the very next segment.  Segment boundaries fall
-// where the earliest admitted group finishes (or where the caller's launch
-// budget ends); there finished groups get their Hessian kernels and free
-// their memory, waiting groups are admitted and the tile map is rebuilt.
-// Per-sample arithmetic does not depend on the batch, so each query's result
-// is the same alone and in the mix.
+// and as descriptor slots allow, so queries that arrive while others run
+// join at the next segment boundary.  Work is scheduled by segments: at each
+// boundary the admitted groups are ranked by their query's remaining
+// grid-point updates (shortest first, then arrival order); all groups of
+// the first query run, and those of the next queries are added while a
+// launch stays within max(the first query's points, kFillPoints), the size
+// at which a launch already keeps the device busy.  A short query that
+// arrives behind a long one therefore runs at once, alone or beside other
+// short ones, and the long one resumes when it is done.  Every launch
+// advances each scheduled solve by one leapfrog step (two for the two-step
+// kernel): a solve with `done` launches behind it that is scheduled at
+// launch L has SolveDesc::start = L - done, rewritten when a paused group
+// resumes.  Segment boundaries also fall where a scheduled group finishes;
+// there finished groups get their Hessian kernels and free their memory and
+// waiting groups are admitted.  Per-sample arithmetic does not depend on the
+// batch or the schedule, so each query's result is the same alone and in the
+// mix.
 #include <deque>
 #include <memory>
 
@@ -82,6 +90,8 @@ struct SrvQuery {
     int32_t *status = nullptr, *chol_status = nullptr;
     int next_sample = 0;
     int groups_running = 0;
+    double waited = 0.0;     // updates others did while its groups sat paused
+    double queued_at = 0.0;  // the server's update count when it was submitted
     bool finished = false;
     hipEvent_t done_ev = nullptr;
     size_t tail_off = 0, tail_bytes = 0;  // prior, theta, weights for laplace
@@ -93,10 +103,17 @@ struct SrvGroup {
     size_t slot0 = 0, nslot = 0;
     size_t off = 0, bytes = 0;
     size_t live = 0;         // field bytes its solves keep live between launches
-    int64_t start = 0;       // launch index of step 0
+    int64_t start = 0;       // launch index of step 0 in the descriptors on the device
+    int64_t done = 0;        // launches this group has taken
+    bool on = false;         // in the current tile map
     int nsteps = 0;
     size_t o_sd = 0, o_given = 0, o_sig = 0, o_work = 0;
+    std::vector<SolveDesc> desc;  // host copy of its descriptors (start rewritten)
 };
+
+// Grid points per launch at which one launch already keeps the device busy
+// (the two-step kernel's cache-sized chunks hold 6.3 million).
+constexpr double kFillPoints = 16.0 * (1 << 20);
 
 size_t trace_bytes(const eig_grid& g, int nrec) {
     return align_up((size_t)(g.nsteps + 1) * nrec * sizeof(float2));
@@ -150,14 +167,17 @@ struct eig_server {
     std::vector<size_t> kind_tile_off;
     bool tiles_dirty = true;
     int64_t next_id = 1;
+    double work_done = 0.0;  // grid-point updates of all launches so far
 };
 
 namespace {
 
-int srv_admit(eig_server* v, hipStream_t s) {
+// Admits one sample group of queued query q if memory, slots and the cache
+// limit allow (*ok), else leaves everything as it was.
+int srv_admit_group(eig_server* v, SrvQuery& q, hipStream_t s, bool* ok) {
     eig_ctx* c = v->ctx;
-    while (!v->queue.empty()) {
-        SrvQuery& q = *v->queue.front();
+    *ok = false;
+    {
         int G = std::min(v->group_samples, q.nsample - q.next_sample);
         G = std::min<int>(G, (int)(v->nslot_cap / 15));
         const bool four_buf = q.medium.kind == EIG_MEDIUM_LAYERED && v->spl == 2;
@@ -168,13 +188,14 @@ int srv_admit(eig_server* v, hipStream_t s) {
         const bool cached = v->cache_bytes && sample_live <= v->cache_bytes;
         if (cached) {
             G = std::min<int>(G, (int)(v->cache_bytes / sample_live));
-            if (!v->groups.empty() && v->live + (size_t)G * sample_live > v->cache_bytes) break;
+            if (!v->groups.empty() && v->live + (size_t)G * sample_live > v->cache_bytes)
+                return EIG_OK;
         }
         size_t off = 0, slot0 = 0;
         if (q.next_sample == 0 && q.tail_bytes == 0) {
             // the query's small laplace inputs are reserved with its first group
             const size_t tb = tail_bytes(q);
-            if (!v->arena.alloc(tb, &q.tail_off)) break;
+            if (!v->arena.alloc(tb, &q.tail_off)) return EIG_OK;
             q.tail_bytes = tb;
         }
         // a full group when memory allows; with nothing running, halve the
@@ -187,10 +208,10 @@ int srv_admit(eig_server* v, hipStream_t s) {
             bytes = group_bytes(q, G);
             got = v->arena.alloc(bytes, &off);
         }
-        if (!got) break;
+        if (!got) return EIG_OK;
         if (!v->slots.alloc((size_t)15 * G, &slot0)) {
             v->arena.release(off, bytes);
-            break;
+            return EIG_OK;
         }
         SrvGroup gr;
         gr.q = &q;
@@ -324,6 +345,7 @@ int srv_admit(eig_server* v, hipStream_t s) {
             std::memcpy(b.data(), desc.data(), b.size());
             if ((rc = upload(c, v->descs + gr.slot0, b, s))) return rc;
         }
+        gr.desc = std::move(desc);
         if (q.medium.kind == EIG_MEDIUM_NODAL)
             launch_nodal_coef(q.medium.rho, q.medium.lam, q.medium.mu, g.nx, g.nz,
                               pitch_of(g.nx), g.h, g.dt, (float*)(base + o_coef), s);
@@ -337,12 +359,52 @@ int srv_admit(eig_server* v, hipStream_t s) {
         v->live += gr.live;
         q.next_sample += G;
         q.groups_running += 1;
-        if (q.next_sample >= q.nsample) v->queue.pop_front();
-        v->groups.push_back(gr);
+        if (q.next_sample >= q.nsample)
+            v->queue.erase(std::find(v->queue.begin(), v->queue.end(), &q));
+        v->groups.push_back(std::move(gr));
         v->tiles_dirty = true;
     }
+    *ok = true;
     return EIG_OK;
 }
+
+double query_work_left(const eig_server* v, const SrvQuery& q);
+int64_t group_launches(const eig_server* v, const SrvGroup& gr);
+
+// Admission in the scheduler's order: queued queries by remaining work
+// (shortest first, then arrival), each taking as many groups as fit; a query
+// that cannot take a group now is skipped, unless others have done more than
+// twice its remaining work since it arrived, in which case it is admitted
+// first and nothing queued behind it is (so large queries are not starved).
+int srv_admit(eig_server* v, hipStream_t s) {
+    for (;;) {
+        std::vector<SrvQuery*> order(v->queue.begin(), v->queue.end());
+        auto overdue = [&](const SrvQuery* q) {
+            return v->work_done - q->queued_at > 2.0 * query_work_left(v, *q);
+        };
+        std::stable_sort(order.begin(), order.end(), [&](SrvQuery* a, SrvQuery* b) {
+            const bool oa = overdue(a), ob = overdue(b);
+            if (oa != ob) return oa;
+            if (oa) return a->id < b->id;
+            const double wa = query_work_left(v, *a), wb = query_work_left(v, *b);
+            return wa != wb ? wa < wb : a->id < b->id;
+        });
+        bool any = false;
+        for (SrvQuery* q : order) {
+            bool ok = false;
+            const int rc = srv_admit_group(v, *q, s, &ok);
+            if (rc) return rc;
+            if (ok) {
+                any = true;
+                break;   // priorities may change: rank again
+            }
+            if (overdue(q)) break;
+        }
+        if (!any) return EIG_OK;
+    }
+}
+
+
 
 int srv_finish_query(eig_server* v, SrvQuery& q, hipStream_t s) {
     eig_ctx* c = v->ctx;
@@ -375,8 +437,8 @@ int64_t group_launches(const eig_server* v, const SrvGroup& gr) {
 int srv_retire(eig_server* v, hipStream_t s) {
     std::vector<SrvGroup> keep;
     for (auto& gr : v->groups) {
-        if (gr.start + group_launches(v, gr) > v->launch) {
-            keep.push_back(gr);
+        if (gr.done < group_launches(v, gr)) {
+            keep.push_back(std::move(gr));
             continue;
         }
         SrvQuery& q = *gr.q;
@@ -403,6 +465,66 @@ int srv_retire(eig_server* v, hipStream_t s) {
     return EIG_OK;
 }
 
+// Grid-point updates a query still needs (admitted and waiting samples).
+double query_work_left(const eig_server* v, const SrvQuery& q) {
+    const double pts = (double)q.grid.nx * q.grid.nz;
+    double w = 15.0 * (q.nsample - q.next_sample) * pts * q.grid.nsteps;
+    for (const auto& gr : v->groups) {
+        if (gr.q != &q) continue;
+        const int spl = q.medium.kind == EIG_MEDIUM_LAYERED ? v->spl : 1;
+        w += (double)gr.nslot * pts * std::max<int64_t>(0, gr.nsteps - spl * gr.done);
+    }
+    return w;
+}
+
+// Chooses the groups of the next segment (see the file comment) and brings
+// the device descriptors of resumed groups up to date.
+int srv_schedule(eig_server* v, hipStream_t s) {
+    std::vector<std::pair<double, SrvQuery*>> qs;
+    for (const auto& gr : v->groups) {
+        bool seen = false;
+        for (const auto& e : qs) seen = seen || e.second == gr.q;
+        if (!seen) qs.push_back({query_work_left(v, *gr.q), gr.q});
+    }
+    std::stable_sort(qs.begin(), qs.end(), [](const auto& a, const auto& b) {
+        return a.first != b.first ? a.first < b.first : a.second->id < b.second->id;
+    });
+    auto points = [](const SrvGroup& gr) {
+        return (double)gr.nslot * gr.q->grid.nx * gr.q->grid.nz;
+    };
+    std::map<const SrvQuery*, bool> run;
+    double acc = 0.0, cap = 0.0;
+    for (size_t k = 0; k < qs.size(); ++k) {
+        const SrvQuery* q = qs[k].second;
+        double pts = 0.0;
+        for (const auto& gr : v->groups)
+            if (gr.q == q) pts += points(gr);
+        if (k == 0) cap = std::max(pts, kFillPoints);
+        // no starvation: a query while paused for which the others have done
+        // as much work as it still needs runs whatever its rank (its
+        // slowdown stays below about 2x)
+        if (k > 0 && acc + pts > cap && q->waited < qs[k].first) continue;
+        run[q] = true;
+        acc += pts;
+    }
+    for (const auto& e : qs)
+        if (run.count(e.second)) e.second->waited = 0.0;
+    for (auto& gr : v->groups) {
+        const bool on = run.count(gr.q) != 0;
+        if (on != gr.on) v->tiles_dirty = true;
+        gr.on = on;
+        if (!on || gr.start == v->launch - gr.done) continue;
+        // resumed (or first scheduled): step done at launch L = start + done
+        gr.start = v->launch - gr.done;
+        for (auto& d : gr.desc) d.start = (int32_t)gr.start;
+        std::vector<char> b(gr.desc.size() * sizeof(SolveDesc));
+        std::memcpy(b.data(), gr.desc.data(), b.size());
+        const int rc = upload(v->ctx, v->descs + gr.slot0, b, s);
+        if (rc) return rc;
+    }
+    return EIG_OK;
+}
+
 int srv_rebuild_tiles(eig_server* v, hipStream_t s) {
     if (!v->tiles_dirty) return EIG_OK;
     v->tiles_dirty = false;
@@ -414,7 +536,7 @@ int srv_rebuild_tiles(eig_server* v, hipStream_t s) {
         const StencilVariant& sv = kVariants[var];
         const size_t begin = all.size();
         for (const auto& gr : v->groups) {
-            if (gr.q->medium.kind != kind) continue;
+            if (gr.q->medium.kind != kind || !gr.on) continue;
             const eig_grid& g = gr.q->grid;
             const int nstrip = (g.nx + sv.cols - 1) / sv.cols;
             const int nchunk = (g.nz - 1 + sv.rows - 1) / sv.rows;
@@ -563,6 +685,7 @@ int eig_server_submit(eig_server* v, const eig_grid* grid, const eig_medium* med
         return set_error(EIG_EBUDGET, "one sample of this query exceeds the server budget");
     HIP_TRY(hipEventCreateWithFlags(&q->done_ev, hipEventDisableTiming));
     *id = q->id;
+    q->queued_at = v->work_done;
     v->queue.push_back(q.get());
     v->queries[q->id] = std::move(q);
     return EIG_OK;
@@ -578,17 +701,32 @@ int eig_server_step(eig_server* v, int32_t max_launches, void* stream, int32_t* 
     if ((rc = srv_admit(v, s))) return rc;
     int done = 0;
     while (done < max_launches && !v->groups.empty()) {
+        if ((rc = srv_schedule(v, s))) return rc;
         if ((rc = srv_rebuild_tiles(v, s))) return rc;
         int64_t seg = max_launches - done;
         for (const auto& gr : v->groups)
-            seg = std::min(seg, gr.start + group_launches(v, gr) - v->launch);
+            if (gr.on) seg = std::min(seg, group_launches(v, gr) - gr.done);
+        // queries none of whose admitted groups run in this segment
+        std::vector<SrvQuery*> paused;
+        for (const auto& gr : v->groups) {
+            bool any_on = false;
+            for (const auto& g2 : v->groups) any_on = any_on || (g2.q == gr.q && g2.on);
+            if (!any_on && std::find(paused.begin(), paused.end(), gr.q) == paused.end())
+                paused.push_back(gr.q);
+        }
         for (int64_t l = 0; l < seg; ++l) {
-            for (const auto& gr : v->groups) {
+            double upd = 0.0;
+            for (auto& gr : v->groups) {
+                if (!gr.on) continue;
                 const int spl = gr.q->medium.kind == EIG_MEDIUM_LAYERED ? v->spl : 1;
-                const int64_t left = gr.nsteps - spl * (v->launch - gr.start);
-                c->updates += (double)gr.q->grid.nx * gr.q->grid.nz * gr.nslot *
-                              (double)std::min<int64_t>(spl, left);
+                const int64_t left = gr.nsteps - spl * gr.done;
+                upd += (double)gr.q->grid.nx * gr.q->grid.nz * gr.nslot *
+                       (double)std::min<int64_t>(spl, left);
+                gr.done += 1;
             }
+            c->updates += upd;
+            v->work_done += upd;
+            for (SrvQuery* q : paused) q->waited += upd;
             for (size_t kk = 0; kk < v->kind_tiles.size(); ++kk) {
                 const size_t nt = v->kind_tiles[kk].second;
                 if (nt == 0) continue;

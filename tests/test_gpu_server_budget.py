@@ -80,6 +80,56 @@ def test_small_budget_admits_shrunk_groups_within_the_arena(ctx):
     assert torch.equal(ref["eig"], o["eig"])
 
 
+def test_short_query_behind_a_long_one_runs_first(ctx):
+    # a long query (8 samples of 512^2 x 3000 steps: 31 million grid points
+    # per launch, above the size at which one launch fills the device) is
+    # running when a short one (4 samples of 128^2 x 400) arrives: the short
+    # one runs at once and alone, finishing within its own launch count plus
+    # one segment while the long one waits; both equal their runs alone
+    from paper_1502_07873_amd import eigseis, make_prior
+    from paper_1502_07873_amd.query import grid_tuple, run_query
+    gL, mL, thL, rL, loL, hiL = _query(seed=21, n=512, nsteps=3000, nsample=8)
+    gS, mS, thS, rS, loS, hiS = _query(seed=22, n=128, nsteps=400, nsample=4)
+    dL, dS = _dev_medium(mL), _dev_medium(mS)
+
+    def outputs(S):
+        return {"H1": torch.empty((S, 7, 7), dtype=torch.float64, device="cuda"),
+                "dkl": torch.empty(S, dtype=torch.float64, device="cuda"),
+                "eig": torch.empty(1, dtype=torch.float64, device="cuda")}
+
+    srv = eigseis.Server(ctx, 8 << 30, group_samples=8)
+    oL, oS = outputs(8), outputs(4)
+    _say("serving: a short query arriving behind a long one")
+    qL = srv.submit(grid_tuple(gL), dL, thL, rL, make_prior(loL, hiL), np.full(8, 1 / 8),
+                    oL["H1"], oL["dkl"], oL["eig"], 0.7)
+    srv.step(100)
+    qS = srv.submit(grid_tuple(gS), dS, thS, rS, make_prior(loS, hiS), np.full(4, 1 / 4),
+                    oS["H1"], oS["dkl"], oS["eig"], 0.7)
+    short_launches = (gS.nsteps + 1) // 2     # two steps per launch (depth-only media)
+    used = 0
+    while not srv.poll(qS):
+        srv.step(20)
+        torch.cuda.synchronize()
+        used += 20
+        assert used <= short_launches + 40, "the short query waited behind the long one"
+    assert not srv.poll(qL)
+    for _ in range(1000):
+        srv.step(200)
+        torch.cuda.synchronize()
+        if srv.poll(qL):
+            break
+    else:
+        raise AssertionError("long query never completed")
+    srv.close()
+    for g, dm, th, rec, lo, hi, o in ((gL, dL, thL, rL, loL, hiL, oL),
+                                      (gS, dS, thS, rS, loS, hiS, oS)):
+        ref = run_query(ctx, grid_tuple(g), dm, rec, lo, hi, th, np.full(len(th), 1 / len(th)),
+                        sigma=0.7)
+        torch.cuda.synchronize()
+        assert torch.equal(ref["H1"], o["H1"])
+        assert torch.equal(ref["dkl"], o["dkl"])
+
+
 def test_submit_refuses_what_cannot_fit_or_leaves_the_window(ctx):
     from paper_1502_07873_amd import eigseis, make_prior
     from paper_1502_07873_amd.query import grid_tuple
