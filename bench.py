@@ -50,36 +50,58 @@ def _measured_traffic(solves_per_launch, wave_cache_bytes, variant):
     return rec["traffic_bytes_per_launch"]
 
 
+CPU_SHARE = 16   # host cores a one-GPU machine grants a process
+
+
 def _cpu_baseline(wl, theta_s, gpu):
-    """The oracle, untuned, on one prior sample: its own sigma solve, then
-    the 15 solves spread over the host cores (each single-threaded), H_1 and
-    D^_KL.  Also the error set against the GPU's outputs for that sample
-    (gpu: nominal traces, J, H1, dkl of the same sample and sigma)."""
+    """The oracle, untuned, on one prior sample: its noise solve at the
+    prior mean and its 15 Jacobian solves, 16 single-threaded solves spread
+    over the host's CPU share (16 cores per GPU), then H_1 and D^_KL.  Also
+    the error set against the GPU's outputs for that sample (gpu: nominal
+    traces, J, H1, dkl of the same sample and sigma)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
-    from oracle import pipeline as opipe
-    threads = min(16, os.cpu_count() or 1)
+    from oracle import elastic, laplace
+    nproc = os.cpu_count() or 1
+    threads = min(CPU_SHARE, nproc)
     t0 = time.perf_counter()
-    ref = opipe.query(wl, theta=theta_s[None, :], weights=[1.0], threads=threads, keep_J=True)
+    with ThreadPoolExecutor(threads) as pool:
+        fut = pool.submit(elastic.noise_sigma, wl.grid, wl.medium, wl.theta_bar, wl.noise_rel,
+                          wl.stf)
+        nominal, J = elastic.jacobian_literal(wl.grid, wl.medium, theta_s, wl.receivers,
+                                              wl.rel_step, wl.stf, pool=pool)
+        sigma = fut.result()
+    H1 = laplace.hessian_h1(J, sigma)
+    dkl, _ = laplace.dkl_hat(H1, theta_s, laplace.uniform_prior(wl.lo, wl.hi))
     t = time.perf_counter() - t0
-    cores = min(threads, 15)
     upd = 16.0 * wl.grid.nx * wl.grid.nz * wl.grid.nsteps
-    Jr, Jg = ref["J"][0], gpu["J"]
-    Hr, Hg = ref["H1"][0], gpu["H1"]
-    d = np.sqrt(np.abs(np.diag(Hr)))
+    Jg = gpu["J"]
+    d = np.sqrt(np.abs(np.diag(H1)))
+
+    def per_rec(a, b):
+        ax = tuple(k for k in range(b.ndim) if k != 1)
+        return float(np.max(np.sqrt(np.sum((a - b) ** 2, axis=ax)) /
+                            np.sqrt(np.sum(b * b, axis=ax))))
     errors = {
-        "trace_rel_l2": float(np.linalg.norm(gpu["nominal"] - ref["nominal"][0]) /
-                              np.linalg.norm(ref["nominal"][0])),
-        "jacobian_col_rel_l2_max": float(max(np.linalg.norm(Jg[..., j] - Jr[..., j]) /
-                                             np.linalg.norm(Jr[..., j]) for j in range(7))),
-        "scaled_hessian_max_abs": float(np.max(np.abs((Hg - Hr) / np.outer(d, d)))),
-        "dkl_abs": abs(float(ref["dkl"][0]) - float(gpu["dkl"])),
-        "eig_abs": abs(float(ref["eig"]) - float(gpu["dkl"])),
-        "sigma_rel": abs(gpu["sigma"] - ref["sigma"]) / ref["sigma"],
+        "trace_rel_l2": float(np.linalg.norm(gpu["nominal"] - nominal) / np.linalg.norm(nominal)),
+        "trace_rel_l2_worst_receiver": per_rec(gpu["nominal"], nominal),
+        "jacobian_col_rel_l2_max": float(max(np.linalg.norm(Jg[..., j] - J[..., j]) /
+                                             np.linalg.norm(J[..., j]) for j in range(7))),
+        "jacobian_col_rel_l2_worst_receiver": max(per_rec(Jg[..., j], J[..., j])
+                                                  for j in range(7)),
+        "scaled_hessian_max_abs": float(np.max(np.abs((gpu["H1"] - H1) / np.outer(d, d)))),
+        "dkl_abs": abs(float(dkl) - float(gpu["dkl"])),
+        "eig_abs": abs(float(dkl) - float(gpu["dkl"])),
+        "sigma_rel": abs(gpu["sigma"] - sigma) / sigma,
         "sample": "prior sample 0 of the timed query (the oracle with its own sigma)"}
-    return ({"value": 1.0 / t, "unit": "sample-EIG evals/s", "cores": cores,
-             "kind": "oracle", "updates_per_s": upd / t, "updates_per_s_per_core": upd / t / cores,
-             "sample": "1 prior sample of the timed workload (1 sigma solve, then 15 solves "
-                       f"on {cores} threads, 512x512x2000, FP64), {t:.1f} s wall"}, errors)
+    return ({"value": 1.0 / t, "unit": "sample-EIG evals/s", "cores": threads,
+             "host_nproc": nproc, "kind": "oracle", "updates_per_s": upd / t,
+             "updates_per_s_per_core": upd / t / threads,
+             "sample": f"1 prior sample of the timed workload: its noise solve and 15 Jacobian "
+                       f"solves (512x512x2000, FP64), one thread each on {threads} threads "
+                       f"(the box's CPU share of {CPU_SHARE} cores per GPU; the host shows "
+                       f"{nproc}), then H_1 and D^_KL; {t:.1f} s wall"}, errors)
 
 
 def _copy_rate(nbytes=4 << 30, reps=5):
@@ -96,6 +118,7 @@ def _copy_rate(nbytes=4 << 30, reps=5):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     del src, dst
+    torch.cuda.empty_cache()   # later legs need the HBM back
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
@@ -150,128 +173,282 @@ def _copy_calibration(nbytes=4 << 30, reps=4):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def _serving(ctx, updates_per_s, nquery=24, load=0.7, seed=3, overlap=True):
-    """A c4-shaped query stream served by the continuous-batching engine with
-    Poisson arrivals at `load` x the capacity implied by updates_per_s (by
-    default the grid-point update rate of one unsplit wave)."""
-    import numpy as np
+SERVE_BUDGET = 250 << 30   # the serving workload's HBM budget
 
-    import synthetic
+
+def _run_stream(ctx, wls, arrivals, overlap, budget=SERVE_BUDGET, group_samples=16):
+    """Serves design queries (synthetic workloads) arriving at the given
+    offsets; sigma = 1e-3 x each sample's nominal peak.  Returns the queries
+    with their times."""
     from paper_1502_07873_amd import eigseis
     from paper_1502_07873_amd.query import device_medium, grid_tuple
-    from paper_1502_07873_amd.serve import Query, latency_stats, serve
-    rng = np.random.Generator(np.random.PCG64(seed))
-    wls = synthetic.serving_stream(rng, nquery, n_range=(256, 384), sample_range=(8, 32))
-    work = np.array([15 * len(w.theta) * w.grid.nx * w.grid.nz * w.grid.nsteps for w in wls])
-    rate = load * updates_per_s / work.mean()
-    arrivals = synthetic.poisson_arrivals(rng, nquery, rate)
+    from paper_1502_07873_amd.serve import Query, serve
     qs = []
     for w, t in zip(wls, arrivals):
         med = device_medium(w.medium.kind, w.medium.rho, w.medium.lam, w.medium.mu)
         qs.append(Query(grid_tuple(w.grid), med, w.theta, w.receivers, w.lo, w.hi, w.weights,
                         w.noise_rel, eigseis.SIGMA_NOMINAL_PEAK, arrival=float(t)))
-    srv = eigseis.Server(ctx, 120 << 30, group_samples=16)
+    srv = eigseis.Server(ctx, budget, group_samples=group_samples)
     serve(srv, qs, launches_per_step=20, overlap=overlap)
+    mem = srv.memory()
     srv.close()
+    return qs, mem
+
+
+def _stream_stats(qs, mem, work):
+    import numpy as np
+
+    from paper_1502_07873_amd.serve import latency_stats
     st = latency_stats(qs)
     span = max(q.t_done for q in qs) - min(q.t_submit for q in qs)
     nsamp = sum(len(q.theta) for q in qs)
     flagged = sum(int((q.status != 0).sum()) + int((q.chol_status != 0).sum()) for q in qs)
-    return {"discipline": "continuous batching" if overlap else "queue only (one query at a time)",
-            "queries": nquery, "offered_load": load, "arrival_rate_per_s": rate,
-            "latency_p50_s": st["p50_s"], "latency_p99_s": st["p99_s"],
+    return {"queries": len(qs), "latency_p50_s": st["p50_s"], "latency_p99_s": st["p99_s"],
             "latency_mean_s": st["mean_s"], "span_s": span,
-            "design_eig_evals_per_s": nquery / span, "sample_eig_evals_per_s": nsamp / span,
-            "grid_pt_updates": float(work.sum()), "flagged_samples": flagged,
-            "samples": nsamp,
-            "workload": "c4-shaped stream: N in {256..384 step 64}^2, 500..2000 steps "
-                        "(raised to cover 1.5x the P travel time from the deepest source), "
-                        "5..101 random surface receivers, 8..32 samples, random 4-layer "
-                        "media; sigma = 1e-3 x each sample's nominal peak"}
+            "design_eig_evals_per_s": len(qs) / span, "sample_eig_evals_per_s": nsamp / span,
+            "grid_pt_updates": float(np.sum(work)),
+            "grid_pt_updates_per_s": float(np.sum(work)) / span, "samples": nsamp,
+            "flagged_samples": flagged, "arena_budget_GB": mem["budget"] / 1e9,
+            "arena_peak_GB": mem["peak"] / 1e9}
 
 
-def _bench_c3(ctx, nsample):
+def _serving_head_of_line(ctx):
+    """One long query (1024^2 x 4000, 64 samples: 4.0e12 updates) arriving
+    first and eight short ones (256^2, ~1000-2000 steps, 64 samples) arriving
+    every 0.5 s behind it, under both disciplines: continuous batching admits
+    the short queries beside the long one; queue-only makes them wait."""
+    import numpy as np
+
+    import synthetic
+    from paper_1502_07873_amd.serve import latency_stats
+    wls, arr = synthetic.serving_head_of_line()
+    work = np.array([15 * len(w.theta) * w.grid.nx * w.grid.nz * w.grid.nsteps for w in wls])
+    out = {"workload": "head-of-line: 1 query of 1024^2 x 4000 steps, 101 receivers, 64 "
+                       "samples at t=0, then 8 queries of 256^2 x 1249..1952 steps, 7..91 "
+                       "receivers, 64 samples, every 0.5 s; 250 GB arena"}
+    for overlap in (True, False):
+        print(f"[bench] serving head-of-line ({'continuous' if overlap else 'queue-only'})",
+              flush=True)
+        qs, mem = _run_stream(ctx, wls, arr, overlap)
+        d = _stream_stats(qs, mem, work)
+        short = latency_stats(qs[1:])
+        d.update({"short_latency_p50_s": short["p50_s"], "short_latency_p99_s": short["p99_s"],
+                  "long_latency_s": qs[0].t_done - qs[0].arrival})
+        out["continuous_batching" if overlap else "queue_only"] = d
+    cb, qo = out["continuous_batching"], out["queue_only"]
+    out["short_p50_speedup"] = qo["short_latency_p50_s"] / cb["short_latency_p50_s"]
+    out["short_p99_speedup"] = qo["short_latency_p99_s"] / cb["short_latency_p99_s"]
+    return out
+
+
+def _serving_c4(ctx, updates_per_s, max_updates=1.2e13, load=0.8, seed=3, overlap=True,
+                nquery=None):
+    """Design queries drawn from the serving workload's full ranges (grids
+    256..1024^2, 500..4000 steps, 5..101 random receivers, 64..512 samples,
+    random 4-layer media, 250 GB arena), Poisson arrivals at `load` x the
+    capacity implied by updates_per_s; the first queries of the stream up to
+    max_updates grid-point updates (or nquery of them)."""
+    import numpy as np
+
+    import synthetic
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pool = synthetic.serving_queries(rng, 128)
+    work = np.array([15 * len(w.theta) * w.grid.nx * w.grid.nz * w.grid.nsteps for w in pool])
+    n = nquery or max(2, int(np.searchsorted(np.cumsum(work), max_updates, side="right")))
+    wls, work = pool[:n], work[:n]
+    rate = load * updates_per_s / work.mean()
+    arr = synthetic.poisson_arrivals(rng, n, rate)
+    print(f"[bench] serving stream at the serving workload's ranges: {n} queries, "
+          f"{work.sum():.3g} updates ({'continuous' if overlap else 'queue-only'})", flush=True)
+    qs, mem = _run_stream(ctx, wls, arr, overlap)
+    d = _stream_stats(qs, mem, work)
+    d.update({"discipline": "continuous batching" if overlap else "queue only",
+              "offered_load": load, "arrival_rate_per_s": rate,
+              "workload": "serving ranges: N ~ U{256..1024 step 64}^2, steps ~ U{500..4000}, "
+                          "N_R ~ U{5..101} random surface receivers, samples ~ U{64..512}, "
+                          "random 4-layer media, 250 GB arena; sigma = 1e-3 x each sample's "
+                          "nominal peak (samples whose wave never reaches the surface within "
+                          "the record are flagged)",
+              "grids": [int(w.grid.nx) for w in wls], "steps": [int(w.grid.nsteps) for w in wls],
+              "samples_per_query": [len(w.theta) for w in wls]})
+    return d
+
+
+def _leg_roofline(st, bytes_note):
+    """Stencil figures of one leg from the library's timing (eig_ctx_stencil_stats)."""
+    ms = max(st["ms"], 1e-9)
+    achieved = st["bytes"] / (ms * 1e-3) / 1e9
+    return {"stencil_ms": st["ms"], "launches": st["launches"],
+            "avg_launch_ms": st["ms"] / max(st["launches"], 1),
+            "grid_pt_updates_per_s_stencil": st["updates"] / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "note": bytes_note}}
+
+
+def _bench_c3(nsample=4096, oracle_check=True):
     """Uneven batching: nsample single-sample queries with grids from
     {256,384,512}^2 and 1000/1500/2000 steps, each with its own 4-layer
-    medium, all 15*nsample solves in one jacobian_fd call."""
+    medium, all 15*nsample solves in one jacobian_fd call, in its own
+    context (the batch's workspace is ~214 GB).  One 256^2 x 1000 sample is
+    recomputed by the oracle for the error fields."""
     import numpy as np
     import torch
 
     import synthetic
-    from paper_1502_07873_amd import eigseis
+    from paper_1502_07873_amd import Context, eigseis
     from paper_1502_07873_amd.query import device_medium, grid_tuple
     wls = synthetic.config("c3", nsample=nsample)
     grids = [grid_tuple(w.grid) for w in wls]
     media = [device_medium(w.medium.kind, w.medium.rho, w.medium.lam, w.medium.mu) for w in wls]
     theta = np.concatenate([w.theta for w in wls])
     recs = [w.receivers for w in wls]
+    # the sample the oracle checks: the first 256^2 x 1000 one whose wave
+    # reaches the surface (the first of 40, 50, 60)
+    picks = [k for k in (40, 50, 60) if k < nsample]
+    nominal, J = [None] * nsample, [None] * nsample
+    for k in picks:
+        g = wls[k].grid
+        nominal[k] = torch.empty((g.nsteps + 1, len(recs[k]), 2), dtype=torch.float32,
+                                 device="cuda")
+        J[k] = torch.empty((g.nsteps + 1, len(recs[k]), 2, 7), dtype=torch.float64,
+                           device="cuda")
     H1 = torch.empty((nsample, 7, 7), dtype=torch.float64, device="cuda")
     status = torch.empty(nsample, dtype=torch.int32, device="cuda")
     updates = float(sum(15 * g[0] * g[1] * g[4] for g in grids))
-    ctx.stencil_stats(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.jacobian_fd(grids, media, theta, recs, 1e-3, H1, sigma_mode=eigseis.SIGMA_NOMINAL_PEAK,
-                    status=status)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    st = ctx.stencil_stats(reset=True)
-    return {"workload": f"c3 uneven batch: {nsample} samples x 15 solves, grids "
-                        "{256,384,512}^2, 1000/1500/2000 steps, per-sample 4-layer media",
-            "solves": 15 * nsample, "seconds": t, "sample_eig_evals_per_s": nsample / t,
-            "grid_pt_updates_per_s": updates / t, "stencil_ms": st["ms"],
-            "stencil_GBs_24B": st["bytes"] / st["ms"] * 1e-6,
-            "launches": st["launches"], "variant": ctx.get_option("last_variant"),
-            "workspace_GB": ctx.workspace_bytes / 1e9,
-            "flagged": int((status != 0).sum())}
+    with Context(0, 230 << 30) as ctx:
+        ctx.stencil_stats(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.jacobian_fd(grids, media, theta, recs, 1.0, H1, nominal=nominal, J=J,
+                        status=status)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st = ctx.stencil_stats(reset=True)
+        ws = ctx.workspace_bytes
+        variant = ctx.get_option("last_variant")
+    out = {"workload": f"uneven batch: {nsample} samples x 15 solves, grids "
+                       "{256,384,512}^2, 1000/1500/2000 steps, per-sample 4-layer media",
+           "solves": 15 * nsample, "seconds": t, "sample_eig_evals_per_s": nsample / t,
+           "grid_pt_updates_per_s": updates / t, "variant_last": variant,
+           "workspace_GB": ws / 1e9, "flagged": int((status != 0).sum())}
+    out.update(_leg_roofline(st, "24 B per grid-point update (read u^m, u^{m-1}, write "
+                                 "u^{m+1}) over the stencil launch time; waves run as "
+                                 "cache-sized chunks, so most launches read and write the "
+                                 "last-level cache"))
+    Hg = H1.cpu().numpy()
+    seen = [k for k in picks if (np.diag(Hg[k]) > 0).all()]
+    if oracle_check and seen:
+        from oracle import pipeline as opipe
+        k = seen[0]
+        print(f"[bench] c3: oracle on sample {k} ({wls[k].grid.nx}^2 x {wls[k].grid.nsteps})",
+              flush=True)
+        ref = opipe.query(wls[k], sigma=1.0, keep_J=True, threads=CPU_SHARE)
+        Jg, Jr = J[k].cpu().numpy(), ref["J"][0]
+        d = np.sqrt(np.diag(ref["H1"][0]))
+        out["errors"] = {
+            "sample": k,
+            "trace_rel_l2": float(np.linalg.norm(nominal[k].cpu().numpy() - ref["nominal"][0]) /
+                                  np.linalg.norm(ref["nominal"][0])),
+            "jacobian_col_rel_l2_max": float(max(np.linalg.norm(Jg[..., j] - Jr[..., j]) /
+                                                 np.linalg.norm(Jr[..., j]) for j in range(7))),
+            "scaled_hessian_max_abs": float(np.max(np.abs((Hg[k] - ref["H1"][0]) /
+                                                          np.outer(d, d)))),
+            "dkl_abs": None}
+        dk_ref = float(ref["dkl"][0])
+        # the GPU's own D^_KL of that sample through laplace_eig
+        with Context(0, 1 << 30) as c2:
+            dk = torch.empty(1, dtype=torch.float64, device="cuda")
+            eg = torch.empty(1, dtype=torch.float64, device="cuda")
+            c2.laplace_eig(H1[k:k + 1].contiguous(), eigseis.make_prior(wls[k].lo, wls[k].hi),
+                           [1.0], dk, eg, theta=wls[k].theta)
+            torch.cuda.synchronize()
+            out["errors"]["dkl_abs"] = abs(float(dk.cpu()[0]) - dk_ref)
+    del nominal, J, H1
+    torch.cuda.empty_cache()
+    return out
 
 
-def _bench_c5(ctx, reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40):
+def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40):
     """Sparse quadrature + greedy design: (a) the full 2048x1024x4000 nodal
-    problem on `full_nodes` sparse-grid nodes (throughput); (b) the whole
-    pipeline (589 level-3 nodes, 201 candidates, greedy to kmax) on a
-    reduced grid, with the EIG-vs-count curve."""
+    problem on `full_nodes` sparse-grid nodes, the first being the centre
+    node whose oracle values are stored with the tests (throughput, roofline,
+    errors); (b) the whole pipeline (589 level-3 nodes, 201 candidates,
+    greedy to kmax) on a reduced grid, with the EIG-vs-count curve."""
     import numpy as np
     import torch
 
     import synthetic
-    from paper_1502_07873_amd import make_prior, sparse_grid_gl
+    from paper_1502_07873_amd import Context, make_prior, sparse_grid_gl
     from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
     out = {}
     wl = synthetic.config("c5")[0]
     nodes, w = sparse_grid_gl(7, 3, wl.lo, wl.hi)
+    centre = 0.5 * (wl.lo + wl.hi)
+    k0 = int(np.argmin(np.max(np.abs(nodes - centre) / (wl.hi - wl.lo), axis=1)))
+    order = [k0] + [k for k in range(len(w)) if k != k0][:full_nodes - 1]
     med = device_medium(wl.medium.kind, wl.medium.rho, wl.medium.lam, wl.medium.mu)
     g = grid_tuple(wl.grid)
-    ctx.stencil_stats(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, nodes[:full_nodes],
-                  w[:full_nodes], sigma=1.0, per_receiver=True)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    st = ctx.stencil_stats(reset=True)
+    gold_path = os.path.join(ROOT, "tests", "golden", "c5_node_fullsize.npz")
+    gold = np.load(gold_path) if os.path.exists(gold_path) else None
+    sigma = float(gold["sigma"]) if gold is not None else 1.0
+    with Context(0, 64 << 30) as ctx:
+        # warm: tune and grow the workspace on one node
+        run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, nodes[order[:1]], [1.0],
+                  sigma=sigma, per_receiver=True)
+        torch.cuda.synchronize()
+        ctx.stencil_stats(reset=True)
+        t0 = time.perf_counter()
+        r = run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, nodes[order],
+                      w[order], sigma=sigma, per_receiver=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st = ctx.stencil_stats(reset=True)
+        variant = ctx.get_option("last_variant")
+        Hr = r["H1"].cpu().numpy()
     upd = 15 * full_nodes * wl.grid.nx * wl.grid.nz * wl.grid.nsteps
-    out["full_size"] = {"grid": [wl.grid.nx, wl.grid.nz, wl.grid.nsteps],
-                        "sparse_grid_nodes_total": len(w), "nodes_run": full_nodes,
-                        "candidates": len(wl.receivers), "seconds": t,
-                        "grid_pt_updates_per_s": upd / t,
-                        "stencil_GBs_36B": st["bytes"] / max(st["ms"], 1e-9) * 1e-6,
-                        "sample_eig_evals_per_s": full_nodes / t,
-                        "projected_full_query_hours": len(w) * t / full_nodes / 3600}
+    pts = wl.grid.nx * wl.grid.nz
+    shared = (24.0 * st["updates"] + 12.0 * pts * st["launches"]) / max(st["ms"], 1e-9) * 1e-6
+    fs = {"grid": [wl.grid.nx, wl.grid.nz, wl.grid.nsteps],
+          "sparse_grid_nodes_total": len(w), "nodes_run": full_nodes,
+          "candidates": len(wl.receivers), "seconds": t, "variant_last": variant,
+          "grid_pt_updates_per_s": upd / t, "sample_eig_evals_per_s": full_nodes / t,
+          "projected_full_query_minutes": len(w) * t / full_nodes / 60}
+    fs.update(_leg_roofline(st, "36 B per grid-point update (24 B of fields + 12 B of nodal "
+                                "lambda, mu, dt^2/(rho h^2)); the coefficients are shared by "
+                                "all solves of a launch, so this overcounts them"))
+    fs["achieved_shared_coef_GBs"] = shared
+    fs["shared_coef_note"] = ("24 B per update + 12 B per grid point per launch (the "
+                              f"{15 * full_nodes} solves of a launch share one medium)")
+    if gold is not None:
+        from oracle import laplace
+        H = Hr[0].sum(axis=0)
+        Hgold = gold["H1"]
+        d = np.sqrt(np.diag(Hgold))
+        dk, _ = laplace.dkl_hat(H, nodes[k0], laplace.uniform_prior(wl.lo, wl.hi))
+        dr = np.sqrt(np.abs(np.einsum("rii->ri", gold["H1r"])))
+        fs["errors"] = {
+            "node": "centre of the level-3 sparse grid (all parameters at their prior mean)",
+            "scaled_hessian_max_abs": float(np.max(np.abs((H - Hgold) / np.outer(d, d)))),
+            "per_candidate_scaled_hessian_max_abs": float(np.max(
+                np.abs(Hr[0] - gold["H1r"]) / (dr[:, :, None] * dr[:, None, :]))),
+            "dkl_abs": abs(dk - float(gold["dkl"])),
+            "reference": "oracle values stored by tests/golden/make_fullsize_golden.py"}
+    out["full_size"] = fs
     wr = synthetic.config("c5", grid_override=reduced_grid)[0]
     nodes, w = sparse_grid_gl(7, 3, wr.lo, wr.hi)
     medr = device_medium(wr.medium.kind, wr.medium.rho, wr.medium.lam, wr.medium.mu)
     gr = grid_tuple(wr.grid)
-    sigma = ctx.noise_sigma_peak(gr, medr, wr.theta_bar, wr.noise_rel)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = run_query(ctx, gr, medr, wr.receivers, wr.lo, wr.hi, nodes, w, sigma=sigma,
-                  per_receiver=True)
-    order = torch.empty(kmax, dtype=torch.int32, device="cuda")
-    curve = torch.empty(kmax, dtype=torch.float64, device="cuda")
-    ctx.design_greedy(r["H1"], make_prior(wr.lo, wr.hi), w, kmax, order, curve, theta=nodes)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
+    with Context(0, 64 << 30) as ctx:
+        sigma = ctx.noise_sigma_peak(gr, medr, wr.theta_bar, wr.noise_rel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = run_query(ctx, gr, medr, wr.receivers, wr.lo, wr.hi, nodes, w, sigma=sigma,
+                      per_receiver=True)
+        order = torch.empty(kmax, dtype=torch.int32, device="cuda")
+        curve = torch.empty(kmax, dtype=torch.float64, device="cuda")
+        ctx.design_greedy(r["H1"], make_prior(wr.lo, wr.hi), w, kmax, order, curve, theta=nodes)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
     cv = curve.cpu().numpy()
     ks = np.arange(1, kmax + 1)
     ok = np.isfinite(cv)
@@ -581,17 +758,21 @@ def main():
     ap.add_argument("--samples", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="leave out the uneven-batch leg")
+    ap.add_argument("--no-c5", action="store_true", help="leave out the design-sweep leg")
     ap.add_argument("--headline-only", action="store_true",
-                    help="only the timed query: no one-solve baseline, sensitivity path, "
-                         "serving or CPU baseline (for counter runs)")
+                    help="only the timed query: no other leg (for counter runs)")
     ap.add_argument("--workload", default="c2",
                     choices=["c2", "c3", "c5", "loh2d", "nested", "estimators", "serving"],
-                    help="c2: the headline query (default); c3/c5/loh2d: extra measurements "
-                         "(loh2d: the paper's model problem and scenarios); serving: the "
-                         "overloaded serving stream alone")
-    ap.add_argument("--serving-rate", type=float, default=3.34e11,
+                    help="c2: the headline query and every leg (default); c3/c5: those legs "
+                         "alone; loh2d: the paper's model problem and scenarios; serving: "
+                         "the serving streams with both disciplines")
+    ap.add_argument("--serving-rate", type=float, default=3.2e11,
                     help="grid-point updates/s that sets the arrival rate of --workload "
-                         "serving (default: the headline wave's chunked rate)")
+                         "serving (default: about the headline's update rate)")
+    ap.add_argument("--serving-queries", type=int, default=0,
+                    help="--workload serving: queries of the full-range stream (0: up to "
+                         "1.2e13 updates)")
     ap.add_argument("--wave-cache-mib", type=int, default=192,
                     help="live field MiB per wave chunk (0: whole waves through HBM)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -613,22 +794,27 @@ def main():
     from paper_1502_07873_amd import Context
     from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
 
+    if args.workload in ("c3", "c5"):
+        res = (_bench_c3(args.samples if args.samples != 256 else 4096)
+               if args.workload == "c3" else _bench_c5())
+        print(json.dumps({"workload": args.workload, **res}), flush=True)
+        return
     if args.workload != "c2":
         ctx = Context(0, 200 << 30)
         ctx.set_option("wave_cache_bytes", args.wave_cache_mib << 20)
-        if args.workload == "c3":
-            res = _bench_c3(ctx, args.samples if args.samples != 256 else 4096)
-        elif args.workload == "loh2d":
+        if args.workload == "loh2d":
             res = _bench_loh2d(ctx, args.samples if args.samples != 256 else 10000)
         elif args.workload == "nested":
             res = _bench_nested(ctx)
         elif args.workload == "estimators":
             res = _bench_estimators(ctx)
-        elif args.workload == "serving":
-            res = {"load_basis_updates_per_s": args.serving_rate,
-                   "serving_overload": _serving(ctx, args.serving_rate, load=2.0)}
         else:
-            res = _bench_c5(ctx)
+            res = {"load_basis_updates_per_s": args.serving_rate,
+                   "serving_head_of_line": _serving_head_of_line(ctx)}
+            for overlap in (True, False):
+                key = "serving_c4" + ("" if overlap else "_queue_only")
+                res[key] = _serving_c4(ctx, args.serving_rate, overlap=overlap,
+                                       nquery=args.serving_queries or None)
         print(json.dumps({"workload": args.workload, **res}), flush=True)
         ctx.close()
         return
@@ -694,6 +880,7 @@ def main():
         wl.grid.nx * wl.grid.nz * steps_per_launch)
     traffic = _measured_traffic(round(solves_per_launch), ctx.get_option("wave_cache_bytes"),
                                 variant)
+    traffic_rate = traffic / (avg_launch_ms * 1e-3) / 1e9 if traffic else None
     status_ok = int(out["status"].abs().sum()) == 0 and int(out["chol_status"].abs().sum()) == 0
     line = {
         "metric": METRIC,
@@ -735,21 +922,24 @@ def main():
                             "(achieved_at_kernel_floor_GBs)"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)),
                        "p99": float(np.percentile(lat, 99))},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "llc", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "traffic_rate_GBs": (traffic / (avg_launch_ms * 1e-3) / 1e9
-                                          if traffic else None),
-                     "copy_GBs_measured": copy_gbs,
+                     "traffic": traffic, "traffic_rate_GBs": traffic_rate,
                      "llc_copy_GBs_measured": llc_copy_gbs,
+                     "frac_of_llc_copy": (traffic_rate / llc_copy_gbs if traffic_rate
+                                          else None),
+                     "copy_GBs_measured": copy_gbs,
                      "wave_cache_bytes": ctx.get_option("wave_cache_bytes"),
-                     "note": "achieved counts 24 B per update (algorithmic) over the "
-                             "launch time; the fields of a launch live in the last-level "
-                             "cache, so achieved can approach or pass the HBM peak. "
-                             "traffic: the counters' bytes per launch past L2 (last-level "
-                             "cache or HBM). copy_GBs_measured: a 4 GiB device copy timed "
-                             "in this run (HBM); llc_copy_GBs_measured: a 96 MiB copy that "
-                             "stays in the last-level cache"},
+                     "note": "the headline launches work in the 256 MB last-level cache "
+                             "(cache-sized chunks), so the bound is that cache, not HBM. "
+                             "achieved: 24 B per update (algorithmic) over the launch time; "
+                             "frac: achieved / the 8 TB/s HBM peak (the only published "
+                             "figure; achieved can pass it since the cache serves the "
+                             "fields). traffic: bytes per launch past L2 from the counter "
+                             "record; frac_of_llc_copy: that traffic rate over a plain "
+                             "96 MiB copy measured in this run (llc_copy_GBs_measured). "
+                             "hbm_streamed: the same query as one unsplit wave, whose "
+                             "launches stream every field through HBM"},
         "wall_s": wall,
     }
     if args.headline_only:
@@ -771,15 +961,18 @@ def main():
     stu = ctx.stencil_stats(reset=True)
     tu = e0.elapsed_time(e1) / 1e3
     ctx.set_option("wave_cache_bytes", args.wave_cache_mib << 20)
+    hbm_ach = stu["bytes"] / (stu["ms"] * 1e-3) / 1e9
     line["unsplit_wave"] = {
         "value": S / tu, "unit": "sample-EIG evals/s",
         "avg_launch_ms": stu["ms"] / max(stu["launches"], 1),
-        "achieved_GBs": stu["bytes"] / (stu["ms"] * 1e-3) / 1e9,
+        "achieved_GBs": hbm_ach,
         "speedup_of_chunked": value / (S / tu),
         "dkl_match": bool(np.array_equal(ou["dkl"].cpu().numpy(), dkl))}
-    # the serving engine advances all admitted solves together (no cache
-    # chunks): its capacity is the unsplit rate
-    unsplit_updates_per_s = stu["updates"] / (stu["ms"] * 1e-3)
+    line["roofline"]["hbm_streamed"] = {
+        "bound": "hbm", "achieved": hbm_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": hbm_ach / HBM_PEAK_GBS, "frac_of_copy": hbm_ach / copy_gbs,
+        "note": "24 B per update over the launch time of the unsplit 3840-solve wave (two "
+                "steps per launch: the kernel itself moves 16 B per update)"}
     # the plain GPU path: the same kernels, one solve per launch
     print("[bench] one-solve-per-launch GPU baseline (2 samples)", flush=True)
     ctx1 = Context(0, 8 << 30)
@@ -824,24 +1017,9 @@ def main():
         "max_abs_dkl_diff_vs_central_differences":
             float(np.max(np.abs(os_["dkl"].cpu().numpy() - dkl))),
         "status_ok": int(os_["status"].abs().sum()) == 0}
-    if not args.no_serving:
-        print("[bench] serving run (continuous batching, Poisson arrivals)", flush=True)
-        line["serving"] = _serving(ctx, unsplit_updates_per_s)
-        print("[bench] serving run, queue-only discipline", flush=True)
-        line["serving_queue_only"] = _serving(ctx, unsplit_updates_per_s, overlap=False)
-        line["latency_ms"]["serving_p50"] = line["serving"]["latency_p50_s"] * 1e3
-        line["latency_ms"]["serving_p99"] = line["serving"]["latency_p99_s"] * 1e3
-        # the same stream offered at twice the rate the cache-chunked waves
-        # sustain (the headline's update rate): a queue forms and admission
-        # decides who waits
-        print("[bench] serving run at 2x the chunked update rate, both disciplines", flush=True)
-        chunked = line["grid_pt_updates_per_s"]
-        line["serving_overload"] = _serving(ctx, chunked, load=2.0)
-        line["serving_overload_queue_only"] = _serving(ctx, chunked, load=2.0, overlap=False)
-        for k in ("serving_overload", "serving_overload_queue_only"):
-            line[k]["load_basis"] = "cache-chunked update rate of the headline wave"
+    # the CPU baseline's GPU side of the sample (before the other legs)
+    gpu0 = None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle, 1 sample)", flush=True)
         sig = ctx.noise_sigma_peak(g, med, theta_bar, wl.noise_rel)
         o0 = run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, wl.theta[:1], [1.0], sigma=sig,
                        keep_nominal=True, keep_J=True)
@@ -849,12 +1027,37 @@ def main():
         gpu0 = {"nominal": o0["nominal"][0].cpu().numpy().astype(np.float64),
                 "J": o0["J"][0].cpu().numpy(), "H1": o0["H1"][0].cpu().numpy(),
                 "dkl": float(o0["dkl"].cpu()[0]), "sigma": sig}
+        del o0
+    # the remaining legs bring their own contexts: the headline's workspace
+    # goes back to the device first (c3 needs ~214 GB, serving a 250 GB arena)
+    ctx.close()
+    del out, ou, o1, os_
+    torch.cuda.empty_cache()
+    if not args.no_c5:
+        print("[bench] c5: full-size sparse-grid nodes and the reduced design pipeline",
+              flush=True)
+        line["c5"] = _bench_c5()
+    if not args.no_c3:
+        print("[bench] c3: the 61440-solve uneven batch", flush=True)
+        line["c3"] = _bench_c3()
+    if not args.no_serving:
+        rate = line["grid_pt_updates_per_s"]
+        sctx = Context(0, 2 << 30)
+        line["serving_head_of_line"] = _serving_head_of_line(sctx)
+        line["serving_c4"] = _serving_c4(sctx, rate)
+        sctx.close()
+        hol = line["serving_head_of_line"]["continuous_batching"]
+        line["latency_ms"]["serving_p50"] = line["serving_c4"]["latency_p50_s"] * 1e3
+        line["latency_ms"]["serving_p99"] = line["serving_c4"]["latency_p99_s"] * 1e3
+        line["latency_ms"]["serving_hol_short_p50"] = hol["short_latency_p50_s"] * 1e3
+        line["latency_ms"]["serving_hol_short_p99"] = hol["short_latency_p99_s"] * 1e3
+    if gpu0 is not None:
+        print("[bench] cpu baseline (oracle, 1 sample)", flush=True)
         cb, errs = _cpu_baseline(wl, wl.theta[0], gpu0)
         line["cpu_baseline"] = cb
         line["errors"] = errs
         line["sampled_err_nats"] = errs["dkl_abs"]
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

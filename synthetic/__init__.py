@@ -12,5 +12,6 @@ from .workloads import (  # noqa: F401
     random_layers_medium, nodal_perturbed_medium, cfl_dt, config, CONFIG_NAMES,
     PARAM_NAMES, serving_stream, poisson_arrivals, loh_medium, loh_prior, loh_prior_mean_paper,
     loh_receivers, loh_scenarios, loh_candidates, loh_workload, loh_nested_setup,
-    loh_nested_draws, LOH_NESTED_ACTIVE, c4_largest_query,
+    loh_nested_draws, LOH_NESTED_ACTIVE, c4_largest_query, serving_head_of_line,
+    serving_queries,
 )

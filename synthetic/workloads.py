@@ -427,6 +427,22 @@ def serving_stream(rng: np.random.Generator, nquery: int, n_range=(256, 512),
     return out
 
 
+def serving_head_of_line(seed: int = 9, nshort: int = 8, gap: float = 0.5):
+    """A head-of-line stream at the serving workload's sizes: one long query
+    (1024^2 grid, 4000 steps, 101 random receivers, 64 samples) arriving at
+    t = 0 and `nshort` short ones (256^2 grid, 500..1000 steps raised where
+    needed to cover the P travel time, 5..101 receivers, 64 samples)
+    arriving `gap` seconds apart from t = gap.  Returns (workloads, arrival
+    times)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lng = serving_stream(rng, 1, n_range=(1024, 1024), steps_range=(4000, 4000),
+                         rec_range=(101, 101), sample_range=(64, 64), cover_travel=False)
+    short = serving_stream(rng, nshort, n_range=(256, 256), steps_range=(500, 1000),
+                           sample_range=(64, 64))
+    arrivals = np.concatenate([[0.0], gap * (1 + np.arange(nshort))])
+    return lng + short, arrivals
+
+
 def poisson_arrivals(rng: np.random.Generator, n: int, rate: float) -> np.ndarray:
     """Arrival times (s) of a Poisson process with the given rate."""
     return np.cumsum(rng.exponential(1.0 / rate, n))
