@@ -866,7 +866,8 @@ def main():
     total_ms = ev[0].elapsed_time(ev[-1])
     st = jac_stats
     variant = ctx.get_option("last_variant")
-    steps_per_launch = 3 if variant in (15, 16) else (2 if 9 <= variant <= 14 else 1)
+    steps_per_launch = 3 if variant in (15, 16) else (2 if (9 <= variant <= 14 or
+                                                             variant in (19, 20)) else 1)
     S = len(wl.theta)
     value = S * args.steps / (total_ms / 1e3)
     avg_launch_ms = st["ms"] / max(st["launches"], 1)

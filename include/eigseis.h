@@ -172,9 +172,11 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  *                      wave runs as consecutive chunks of about this many
  *                      bytes, so that each chunk's fields stay in the
  *                      device's 256 MB last-level cache (solves grouped by
- *                      grid and length); waves where fewer than 16 solves
- *                      would fit are not split.  0: never split for the
- *                      cache.  Results do not depend on it.
+ *                      grid and length); waves where fewer than
+ *                      "cache_chunk_min_solves" solves would fit are not
+ *                      split.  0: never split for the cache.  Results do not
+ *                      depend on it.
+ *   "cache_chunk_min_solves" 16 (default): see "wave_cache_bytes"; >= 1
  *   "serve_cache_bytes" 201326592 (192 MiB, default): serving engines created
  *                      afterwards admit sample groups of a query one of whose
  *                      samples fits this only while the live field bytes of
@@ -193,10 +195,11 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  * EIG_EINVAL for an unknown name or value. */
 int eig_ctx_set_option(eig_ctx* ctx, const char* name, int64_t value);
 /* Reads an option back; "last_variant" gives the stencil variant of the most
- * recent launch.  "temporal_blocking": leapfrog steps per launch for
- * depth-only media with rigid edges, 2 (default; 1 also selects 2), 3, or 0
- * for one step; two and three steps per launch keep four field buffers per
- * solve.  The serving engine uses at most two. */
+ * recent launch.  "temporal_blocking": leapfrog steps per launch for media
+ * with rigid edges, 2 (default; 1 also selects 2), 3 (depth-only media; nodal
+ * media then take two), or 0 for one step; two and three steps per launch
+ * keep four field buffers per solve.  The serving engine takes two steps per
+ * launch for depth-only media and one for nodal media. */
 int eig_ctx_get_option(const eig_ctx* ctx, const char* name, int64_t* value);
 
 /*

@@ -46,14 +46,23 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
               const std::vector<RecSet>& recsets, char* base, size_t cap, hipStream_t s,
               bool allow_graph);
 
+// Leapfrog steps per launch of the kernels a solve class runs: absorbing
+// edges and dual solves one; depth-only media temporal_blocking (1, 2 or 3);
+// nodal media two unless temporal_blocking is 1.
+int family_steps_of(const eig_ctx* c, int kind, bool one_step) {
+    if (one_step) return 1;
+    if (kind == EIG_MEDIUM_LAYERED) return c->temporal_blocking;
+    return std::min(c->temporal_blocking, 2);
+}
+
 // Field bytes one solve keeps live from launch to launch: four buffers when
-// a depth-only medium with rigid edges advances several steps per launch,
-// two otherwise.
+// a solve with rigid edges advances several steps per launch, two
+// otherwise.
 size_t live_field_bytes(const eig_ctx* c, const SolveSpec& sp, const eig_grid& g,
                         const MediumKey& mk) {
     const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
     const bool one_step = g.bc == EIG_BC_ABSORBING || sp.rforce != nullptr;
-    int steps = (mk.kind == EIG_MEDIUM_LAYERED && !one_step) ? c->temporal_blocking : 1;
+    int steps = family_steps_of(c, mk.kind, one_step);
     if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == mk.kind &&
         !(one_step && kVariants[c->forced_variant].steps != 1))
         steps = kVariants[c->forced_variant].steps;
@@ -67,10 +76,9 @@ size_t live_field_bytes(const eig_ctx* c, const SolveSpec& sp, const eig_grid& g
 // one launch to the next instead of streaming through HBM; the chunks reuse
 // the same workspace in stream order.  For the split the solves are ordered
 // by kind, grid and length, so that each chunk is one or two uniform groups
-// of launches.  Waves where fewer than kMinCacheChunk solves would fit are
-// not split for the cache (too few tiles per launch to pay).  A chunk also
-// holds at most max_wave_solves solves when that is set.
-constexpr double kMinCacheChunk = 16.0;
+// of launches.  Waves where fewer than cache_chunk_min_solves solves would
+// fit are not split for the cache (too few tiles per launch to pay).  A
+// chunk also holds at most max_wave_solves solves when that is set.
 
 int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
              const std::vector<eig_grid>& grids, const std::vector<MediumKey>& media,
@@ -90,7 +98,7 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
     // equal spans of at most the limit
     std::vector<size_t> cut{0};
     const double lim = (double)c->wave_cache_bytes;
-    if (lim > 0 && total > lim && kMinCacheChunk * total / (double)n <= lim) {
+    if (lim > 0 && total > lim && (double)c->cache_chunk_min_solves * total / (double)n <= lim) {
         auto key = [&](size_t i) {
             const SolveSpec& sp = solves[i];
             const eig_grid& g = grids[sp.grid];
@@ -161,7 +169,7 @@ void stencil_candidates(const eig_ctx* c, int kind, bool one_step, std::vector<i
     }
     // one family per wave: two or three steps per launch (four field
     // buffers) or one
-    const int steps = (kind == EIG_MEDIUM_LAYERED && !one_step) ? c->temporal_blocking : 1;
+    const int steps = family_steps_of(c, kind, one_step);
     for (int v = 1; v < kNumVariants; ++v)
         if (kVariants[v].medium_kind == kind && kVariants[v].steps == steps) out.push_back(v);
     if (out.empty()) out.push_back(kind == EIG_MEDIUM_NODAL ? 6 : 0);
@@ -717,6 +725,9 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
     } else if (n == "wave_cache_bytes") {
         if (value < 0) return set_error(EIG_EINVAL, "wave_cache_bytes < 0");
         c->wave_cache_bytes = (size_t)value;
+    } else if (n == "cache_chunk_min_solves") {
+        if (value < 1) return set_error(EIG_EINVAL, "cache_chunk_min_solves < 1");
+        c->cache_chunk_min_solves = (int)value;
     } else {
         return set_error(EIG_EINVAL, "unknown option " + n);
     }
@@ -733,6 +744,7 @@ int eig_ctx_get_option(const eig_ctx* c, const char* name, int64_t* value) {
     else if (n == "max_wave_solves") *value = c->max_wave_solves;
     else if (n == "graphs") *value = c->graphs;
     else if (n == "wave_cache_bytes") *value = (int64_t)c->wave_cache_bytes;
+    else if (n == "cache_chunk_min_solves") *value = c->cache_chunk_min_solves;
     else if (n == "fused_edges") *value = c->fused_edges;
     else if (n == "serve_cache_bytes") *value = (int64_t)c->serve_cache_bytes;
     else if (n == "graph_captures") *value = c->graph_captures;

@@ -67,6 +67,9 @@ struct eig_ctx {
     // live field bytes per wave chunk (0: no limit); 192 MiB leaves room in
     // the device's 256 MB last-level cache for everything else a launch reads
     size_t wave_cache_bytes = (size_t)192 << 20;
+    // waves are split for the cache only if at least this many solves fit a
+    // chunk (fewer leave too few tiles per launch)
+    int cache_chunk_min_solves = 16;
     // absorbing edges updated inside the one-step kernels that can (else by
     // the separate edge kernel after every step)
     bool fused_edges = true;

@@ -153,7 +153,7 @@ constexpr int kEdgeTileNodes = 128;
 inline int edge_tiles_of(int nx, int nz) {
     return (2 * nz + nx - 2 + kEdgeTileNodes - 1) / kEdgeTileNodes;
 }
-constexpr int kNumVariants = 19;
+constexpr int kNumVariants = 21;
 extern const StencilVariant kVariants[kNumVariants];
 // tiles: (solve index, strip << 16 | chunk) per wavefront
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,

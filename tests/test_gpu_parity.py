@@ -462,24 +462,26 @@ def test_stencil_variants_bitwise_identical(variant, nsteps, monkeypatch):
         check_receivers(outs[variant][s], ref, TRACE_TOL, what=f"variant {variant} solve {s}")
 
 
-@pytest.mark.parametrize("variant", [17, 18])
-def test_nodal_variants_bitwise_identical(variant, monkeypatch):
-    # the two-nodes-per-lane nodal kernels hand the per-node update the same
-    # operands as the one-node kernel (variant 6): bit-for-bit equal traces,
-    # across strip boundaries and a ragged last strip, and the oracle's
+@pytest.mark.parametrize("variant,nsteps", [(17, 333), (18, 333), (19, 333), (19, 334),
+                                            (20, 333), (20, 334)])
+def test_nodal_variants_bitwise_identical(variant, nsteps, monkeypatch):
+    # the two-nodes-per-lane nodal kernels (one step per launch: 17, 18; two
+    # steps: 19, 20, with odd and even step counts) hand the per-node update
+    # the same operands as the one-node kernel (variant 6): bit-for-bit equal
+    # traces, across strip boundaries and a ragged last strip, and the oracle's
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     from paper_1502_07873_amd import Context
     rng = np.random.default_rng(23)
     nx, nz, h = 300, 97, 10.0
     med = synthetic.nodal_perturbed_medium(rng, nz, nx, h, nlayers=4, corr_len=80.0)
-    grid = synthetic.Grid(nx, nz, h, synthetic.cfl_dt(h, med.vp_max()), 333)
+    grid = synthetic.Grid(nx, nz, h, synthetic.cfl_dt(h, med.vp_max()), nsteps)
     lo, hi = synthetic.prior_box(grid)
     thetas = synthetic.draw_uniform(rng, lo, hi, 3)
     thetas[:, 2] = 0.1
     thetas[0, 0] = 126.5 * h    # source window across the first strip boundary
     rec = np.array([1, 2, 63, 64, 127, 128, 129, 255, 256, nx - 2], dtype=np.int32)
-    _say(f"nodal stencil variant {variant}")
+    _say(f"nodal stencil variant {variant}, {nsteps} steps")
     outs = {}
     for v in (6, variant):
         monkeypatch.setenv("EIG_STENCIL_VARIANT", str(v))
