@@ -368,7 +368,7 @@ def _bench_c3(nsample=4096, oracle_check=True):
     return out
 
 
-def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40):
+def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40, pipeline=True):
     """Sparse quadrature + greedy design: (a) the full 2048x1024x4000 nodal
     problem on `full_nodes` sparse-grid nodes, the first being the centre
     node whose oracle values are stored with the tests (throughput, roofline,
@@ -434,6 +434,8 @@ def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40):
             "dkl_abs": abs(dk - float(gold["dkl"])),
             "reference": "oracle values stored by tests/golden/make_fullsize_golden.py"}
     out["full_size"] = fs
+    if not pipeline:
+        return out
     wr = synthetic.config("c5", grid_override=reduced_grid)[0]
     nodes, w = sparse_grid_gl(7, 3, wr.lo, wr.hi)
     medr = device_medium(wr.medium.kind, wr.medium.rho, wr.medium.lam, wr.medium.mu)
@@ -760,6 +762,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="leave out the uneven-batch leg")
     ap.add_argument("--no-c5", action="store_true", help="leave out the design-sweep leg")
+    ap.add_argument("--c5-full-only", action="store_true",
+                    help="--workload c5: only the full-size nodes (for counter runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed query: no other leg (for counter runs)")
     ap.add_argument("--workload", default="c2",
@@ -796,7 +800,7 @@ def main():
 
     if args.workload in ("c3", "c5"):
         res = (_bench_c3(args.samples if args.samples != 256 else 4096)
-               if args.workload == "c3" else _bench_c5())
+               if args.workload == "c3" else _bench_c5(pipeline=not args.c5_full_only))
         print(json.dumps({"workload": args.workload, **res}), flush=True)
         return
     if args.workload != "c2":

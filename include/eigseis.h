@@ -177,6 +177,13 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  *                      split.  0: never split for the cache.  Results do not
  *                      depend on it.
  *   "cache_chunk_min_solves" 16 (default): see "wave_cache_bytes"; >= 1
+ *   "coef_interleave"  8 (default): in nodal media, up to this many
+ *                      consecutive solves of a wave on one medium and grid
+ *                      (same length) have their tiles ordered by position
+ *                      first, so that the solves' tiles at one position run
+ *                      together and read the medium's coefficients from L2
+ *                      once; 1 keeps each solve's tiles together.  1..4096.
+ *                      Results do not depend on it.
  *   "serve_cache_bytes" 201326592 (192 MiB, default): serving engines created
  *                      afterwards admit sample groups of a query one of whose
  *                      samples fits this only while the live field bytes of

@@ -386,6 +386,43 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
             }
         }
     }
+    // Nodal media: the kernels read 12 B of coefficients per node for every
+    // solve.  Within a set of up to coef_interleave consecutive solves on one
+    // medium and grid, order the tiles by position first and solve second,
+    // so that the solves' tiles at one position run together and share the
+    // coefficient rows in L2.  Tiles of one launch are independent, so the
+    // order changes no result; members of a set share nsteps, so running
+    // solves still form a prefix of whole sets.
+    if (c->coef_interleave > 1)
+        for (Group& gr : groups) {
+            if (gr.kind != EIG_MEDIUM_NODAL) continue;
+            for (size_t v = 0; v < gr.cand.size(); ++v) {
+                auto& tv = gr.tiles[v];
+                auto& stv = gr.steps_tiles[v];
+                std::vector<int2> out;
+                out.reserve(tv.size());
+                int q = 0;
+                const int nq = (int)stv.size();
+                while (q < nq) {
+                    const SolveDesc& a = desc[gr.first + q];
+                    int e = q + 1;
+                    while (e < nq && e - q < c->coef_interleave) {
+                        const SolveDesc& b = desc[gr.first + e];
+                        if (b.coef != a.coef || b.nx != a.nx || b.nz != a.nz ||
+                            b.nsteps != a.nsteps)
+                            break;
+                        ++e;
+                    }
+                    const int lo = q ? stv[q - 1].second : 0;
+                    const int per = stv[q].second - lo;  // equal for all members
+                    for (int t = 0; t < per; ++t)
+                        for (int r = q; r < e; ++r) out.push_back(tv[lo + (r - q) * per + t]);
+                    for (int r = q; r < e; ++r) stv[r].second = (int)out.size();
+                    q = e;
+                }
+                tv.swap(out);
+            }
+        }
     const size_t o_desc = blob.put(desc.data(), desc.size() * sizeof(SolveDesc));
     std::vector<std::vector<size_t>> o_tiles(groups.size()), o_htiles(groups.size());
     for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -728,6 +765,9 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
     } else if (n == "cache_chunk_min_solves") {
         if (value < 1) return set_error(EIG_EINVAL, "cache_chunk_min_solves < 1");
         c->cache_chunk_min_solves = (int)value;
+    } else if (n == "coef_interleave") {
+        if (value < 1 || value > 4096) return set_error(EIG_EINVAL, "coef_interleave outside 1..4096");
+        c->coef_interleave = (int)value;
     } else {
         return set_error(EIG_EINVAL, "unknown option " + n);
     }
@@ -745,6 +785,7 @@ int eig_ctx_get_option(const eig_ctx* c, const char* name, int64_t* value) {
     else if (n == "graphs") *value = c->graphs;
     else if (n == "wave_cache_bytes") *value = (int64_t)c->wave_cache_bytes;
     else if (n == "cache_chunk_min_solves") *value = c->cache_chunk_min_solves;
+    else if (n == "coef_interleave") *value = c->coef_interleave;
     else if (n == "fused_edges") *value = c->fused_edges;
     else if (n == "serve_cache_bytes") *value = (int64_t)c->serve_cache_bytes;
     else if (n == "graph_captures") *value = c->graph_captures;

@@ -70,6 +70,9 @@ struct eig_ctx {
     // waves are split for the cache only if at least this many solves fit a
     // chunk (fewer leave too few tiles per launch)
     int cache_chunk_min_solves = 16;
+    // nodal media: solves on one medium whose tiles are interleaved by
+    // position (coefficient reuse in L2); 1 keeps solve-major order
+    int coef_interleave = 8;
     // absorbing edges updated inside the one-step kernels that can (else by
     // the separate edge kernel after every step)
     bool fused_edges = true;

@@ -540,10 +540,18 @@ int srv_rebuild_tiles(eig_server* v, hipStream_t s) {
             const eig_grid& g = gr.q->grid;
             const int nstrip = (g.nx + sv.cols - 1) / sv.cols;
             const int nchunk = (g.nz - 1 + sv.rows - 1) / sv.rows;
-            for (size_t k = 0; k < gr.nslot; ++k)
+            // a group's solves share one medium: on nodal media, sets of
+            // coef_interleave solves run position-major (coefficients read
+            // from L2 once per set; the order changes no result)
+            const size_t set = kind == EIG_MEDIUM_NODAL
+                                   ? (size_t)std::max(v->ctx->coef_interleave, 1) : 1;
+            for (size_t k0 = 0; k0 < gr.nslot; k0 += set) {
+                const size_t k1 = std::min(gr.nslot, k0 + set);
                 for (int ch = 0; ch < nchunk; ++ch)
                     for (int st = 0; st < nstrip; ++st)
-                        all.push_back(make_int2((int)(gr.slot0 + k), (st << 16) | ch));
+                        for (size_t k = k0; k < k1; ++k)
+                            all.push_back(make_int2((int)(gr.slot0 + k), (st << 16) | ch));
+            }
         }
         v->kind_tiles.push_back({var, all.size() - begin});
         v->kind_tile_off.push_back(begin);

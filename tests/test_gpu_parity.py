@@ -496,6 +496,56 @@ def test_nodal_variants_bitwise_identical(variant, nsteps, monkeypatch):
         check_receivers(outs[variant][s], ref, TRACE_TOL, what=f"variant {variant} solve {s}")
 
 
+@pytest.mark.parametrize("variant", [20, 18])
+def test_nodal_tile_interleave_is_bitwise_neutral(variant, monkeypatch):
+    # tiles of consecutive solves on one nodal medium run position-major in
+    # sets of coef_interleave; the sets here are ragged (5 solves of one
+    # length split 3 + 2, then 2 shorter ones, then 3 on a second medium and
+    # grid), and every solve's traces equal the solve-major order's bit for
+    # bit, and the oracle's
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context
+    from paper_1502_07873_amd.query import grid_tuple
+    rng = np.random.default_rng(29)
+    h = 10.0
+    mA = synthetic.nodal_perturbed_medium(rng, 97, 300, h, nlayers=4, corr_len=80.0)
+    mB = synthetic.nodal_perturbed_medium(rng, 70, 200, h, nlayers=3, corr_len=60.0)
+    dt = synthetic.cfl_dt(h, max(mA.vp_max(), mB.vp_max()))
+    gA1 = synthetic.Grid(300, 97, h, dt, 301)
+    gA2 = synthetic.Grid(300, 97, h, dt, 250)
+    gB = synthetic.Grid(200, 70, h, dt, 288)
+    spec = [(gA1, mA)] * 5 + [(gA2, mA)] * 2 + [(gB, mB)] * 3
+    thetas = np.concatenate([synthetic.draw_uniform(rng, *synthetic.prior_box(g), 1)
+                             for g, _ in spec])
+    thetas[:, 2] = 0.1
+    rec = {id(gA1): np.array([1, 64, 128, 200, 298], dtype=np.int32),
+           id(gB): np.array([1, 63, 64, 128, 198], dtype=np.int32)}
+    rec[id(gA2)] = rec[id(gA1)]
+    dmA, dmB = _dev_medium(mA), _dev_medium(mB)
+    dms = [dmA if m is mA else dmB for _, m in spec]
+    _say(f"nodal tile interleave, variant {variant}, 10 solves on two media")
+    outs = {}
+    monkeypatch.setenv("EIG_STENCIL_VARIANT", str(variant))
+    for G in (1, 3):
+        c = Context(0, 4 << 30)
+        c.set_option("coef_interleave", G)
+        tr = [torch.empty((g.nsteps + 1, len(rec[id(g)]), 2), dtype=torch.float32,
+                          device="cuda") for g, _ in spec]
+        c.forward_solve_batch([grid_tuple(g) for g, _ in spec], dms, thetas,
+                              [rec[id(g)] for g, _ in spec], tr)
+        torch.cuda.synchronize()
+        assert c.get_option("last_variant") == variant
+        c.close()
+        outs[G] = [t.cpu().numpy().astype(np.float64) for t in tr]
+    for s, (g, m) in enumerate(spec):
+        assert np.array_equal(outs[1][s], outs[3][s]), s
+    for s in (0, 4, 6, 9):
+        g, m = spec[s]
+        ref = elastic.forward(g, m, thetas[s], rec[id(g)])
+        check_receivers(outs[3][s], ref, TRACE_TOL, what=f"interleaved solve {s}")
+
+
 def test_three_step_family_with_mixed_lengths_matches_one_step():
     # temporal_blocking = 3 through the normal (tuned) path: solves of
     # different lengths in one wave (running prefixes of tiles and halo
