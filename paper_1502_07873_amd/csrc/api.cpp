@@ -46,6 +46,18 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
               const std::vector<RecSet>& recsets, char* base, size_t cap, hipStream_t s,
               bool allow_graph);
 
+// A solve whose two field levels fit one workgroup's LDS runs resident
+// (variants 21, 22: its whole time loop in one launch, fields never in HBM),
+// unless that is switched off or a tiled variant is forced.
+bool resident_ok(const eig_ctx* c, const eig_grid& g) {
+    if (!c->resident) return false;
+    if (c->forced_variant >= 0 && !kVariants[c->forced_variant].resident) return false;
+    return (size_t)g.nx * g.nz * 2 * sizeof(float2) <= kResidentLdsBytes;
+}
+// Steps a resident launch stands for in the launch-count arithmetic: above
+// any grid's nsteps (valid grids have nsteps < 2^28).
+constexpr int kResidentSpan = 1 << 28;
+
 // Leapfrog steps per launch of the kernels a solve class runs: absorbing
 // edges and dual solves one; depth-only media temporal_blocking (1, 2 or 3);
 // nodal media two unless temporal_blocking is 1.
@@ -60,10 +72,12 @@ int family_steps_of(const eig_ctx* c, int kind, bool one_step) {
 // otherwise.
 size_t live_field_bytes(const eig_ctx* c, const SolveSpec& sp, const eig_grid& g,
                         const MediumKey& mk) {
+    if (resident_ok(c, g)) return 0;  // fields in LDS
     const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
     const bool one_step = g.bc == EIG_BC_ABSORBING || sp.rforce != nullptr;
     int steps = family_steps_of(c, mk.kind, one_step);
     if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == mk.kind &&
+        !kVariants[c->forced_variant].resident &&
         !(one_step && kVariants[c->forced_variant].steps != 1))
         steps = kVariants[c->forced_variant].steps;
     return (steps >= 2 ? 4 : 2) * field;
@@ -154,6 +168,7 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
 }
 
 size_t tiles_of(const eig_grid& g, const StencilVariant& v) {
+    if (v.resident) return 1;  // one workgroup per solve
     return (size_t)((g.nx + v.cols - 1) / v.cols) * ((g.nz - 1 + v.rows - 1) / v.rows);
 }
 
@@ -163,6 +178,7 @@ size_t tiles_of(const eig_grid& g, const StencilVariant& v) {
 void stencil_candidates(const eig_ctx* c, int kind, bool one_step, std::vector<int>& out) {
     out.clear();
     if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == kind &&
+        !kVariants[c->forced_variant].resident &&
         !(one_step && kVariants[c->forced_variant].steps != 1)) {
         out.push_back(c->forced_variant);
         return;
@@ -171,7 +187,9 @@ void stencil_candidates(const eig_ctx* c, int kind, bool one_step, std::vector<i
     // buffers) or one
     const int steps = family_steps_of(c, kind, one_step);
     for (int v = 1; v < kNumVariants; ++v)
-        if (kVariants[v].medium_kind == kind && kVariants[v].steps == steps) out.push_back(v);
+        if (kVariants[v].medium_kind == kind && kVariants[v].steps == steps &&
+            !kVariants[v].resident)
+            out.push_back(v);
     if (out.empty()) out.push_back(kind == EIG_MEDIUM_NODAL ? 6 : 0);
     if (!c->autotune) {
         const int want = steps == 3 ? c->default_variant_tb3
@@ -211,7 +229,12 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     auto one_step = [&](int i) {
         return grids[solves[i].grid].bc == EIG_BC_ABSORBING || solves[i].rforce != nullptr;
     };
+    // grids that fit one workgroup's LDS run resident (variants 21, 22)
+    static const std::vector<int> res_cand[2] = {{21}, {22}};
+    std::vector<char> res(n);
+    for (int i = 0; i < n; ++i) res[i] = resident_ok(c, grids[solves[i].grid]);
     auto cand_of = [&](int i) -> const std::vector<int>& {
+        if (res[i]) return res_cand[media[solves[i].medium].kind];
         return cands[media[solves[i].medium].kind][one_step(i) ? 1 : 0];
     };
     auto family_steps = [&](int i) { return kVariants[cand_of(i)[0]].steps; };
@@ -221,6 +244,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     const size_t fields_begin = align_up(cv.off);
     cv.off = fields_begin;
     for (int i = 0; i < n; ++i) {
+        if (res[i]) continue;  // fields in LDS only
         const eig_grid& g = grids[solves[i].grid];
         const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
         f0[i] = cv.take(field);
@@ -248,8 +272,8 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     std::vector<int> ord(n);
     for (int i = 0; i < n; ++i) ord[i] = i;
     auto class_of = [&](int i) {
-        return 4 * media[solves[i].medium].kind + 2 * (solves[i].rforce != nullptr) +
-               grids[solves[i].grid].bc;
+        return 8 * res[i] + 4 * media[solves[i].medium].kind +
+               2 * (solves[i].rforce != nullptr) + grids[solves[i].grid].bc;
     };
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
         const int ka = class_of(a), kb = class_of(b);
@@ -292,6 +316,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     struct Group {
         int kind, bc, cls;
         int first, last;               // solve range in launch order
+        size_t lds = 0;                // resident groups: dynamic LDS bytes
         std::vector<int> cand;         // candidate variants
         std::vector<std::vector<int2>> tiles;                     // per candidate
         std::vector<std::vector<std::pair<int, int>>> steps_tiles;  // per candidate
@@ -305,8 +330,8 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         const eig_grid& g = grids[sp.grid];
         const MediumKey& mk = media[sp.medium];
         SolveDesc& d = desc[oi];
-        d.buf0 = (float2*)(base + f0[i]);
-        d.buf1 = (float2*)(base + f1[i]);
+        d.buf0 = res[i] ? nullptr : (float2*)(base + f0[i]);
+        d.buf1 = res[i] ? nullptr : (float2*)(base + f1[i]);
         d.buf2 = f2[i] ? (float2*)(base + f2[i]) : nullptr;
         d.buf3 = f3[i] ? (float2*)(base + f3[i]) : nullptr;
         d.coef = (const float*)(base + med_off[sp.medium]);
@@ -368,6 +393,12 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
         gr.last = oi + 1;
         for (size_t v = 0; v < gr.cand.size(); ++v) {
             const StencilVariant& sv = kVariants[gr.cand[v]];
+            if (sv.resident) {
+                gr.tiles[v].push_back(make_int2(oi, g.bc == EIG_BC_ABSORBING ? 1 : 0));
+                gr.steps_tiles[v].push_back({g.nsteps, (int)gr.tiles[v].size()});
+                gr.lds = std::max(gr.lds, (size_t)g.nx * g.nz * 2 * sizeof(float2));
+                continue;
+            }
             const int nstrip = (g.nx + sv.cols - 1) / sv.cols;
             const int nchunk = (g.nz - 1 + sv.rows - 1) / sv.rows;
             for (int ch = 0; ch < nchunk; ++ch)
@@ -454,7 +485,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     // launches: ceil(steps / steps-per-launch) per group
     int max_steps = 0;
     for (const auto& g : groups) {
-        const int spl = kVariants[g.cand[0]].steps;
+        const int spl = kVariants[g.cand[0]].resident ? kResidentSpan : kVariants[g.cand[0]].steps;
         for (const auto& st : g.steps_tiles[0])
             max_steps = std::max(max_steps, (st.first + spl - 1) / spl);
     }
@@ -537,8 +568,11 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
                 slot = step - tn.begin;
                 vi = slot % ncand;
             }
-            // running solves form a prefix (steps descending within a group)
-            const int spl = kVariants[g.cand[vi]].steps;
+            // running solves form a prefix (steps descending within a group);
+            // a resident group takes all its steps in the first launch
+            const bool resident = kVariants[g.cand[vi]].resident != 0;
+            if (resident && step > 0) continue;
+            const int spl = resident ? kResidentSpan : kVariants[g.cand[vi]].steps;
             int ntile = 0, nrun = 0;
             double upd = 0.0;
             const auto& stv = g.steps_tiles[vi];
@@ -563,11 +597,14 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
                     }
                     launch_tb3_halo(ddesc, (const int2*)(bd + o_htiles[gi][vi]), nh, step, ls);
                 }
-                if (!replay)
+                if (!replay && resident)
+                    launch_resident(ddesc, (const int2*)(bd + o_tiles[gi][vi]), ntile, g.kind,
+                                    g.lds, ls);
+                else if (!replay)
                     launch_stencil(ddesc, (const int2*)(bd + o_tiles[gi][vi]), ntile, step,
                                    g.cand[vi], ls);
                 if (slot >= 0) HIP_TRY(hipEventRecord(tn.ev[2 * slot + 1], s));
-                if (g.bc == EIG_BC_ABSORBING && !replay &&
+                if (g.bc == EIG_BC_ABSORBING && !replay && !resident &&
                     !(kVariants[g.cand[vi]].edges && c->fused_edges))
                     launch_ce_edges(ddesc + g.first, nrun, step, ls);
                 c->launches += 1;
@@ -744,7 +781,8 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
         c->autotune = value != 0;
         if (!c->autotune) c->tuned.clear();
     } else if (n == "default_variant") {
-        if (value < 0 || value >= kNumVariants) return set_error(EIG_EINVAL, "variant");
+        if (value < 0 || value >= kNumVariants || kVariants[value].resident)
+            return set_error(EIG_EINVAL, "variant");
         c->default_variant = (int)value;
     } else if (n == "temporal_blocking") {
         if (value < 0 || value > 3) return set_error(EIG_EINVAL, "temporal_blocking: 0..3");
@@ -768,6 +806,8 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
     } else if (n == "coef_interleave") {
         if (value < 1 || value > 4096) return set_error(EIG_EINVAL, "coef_interleave outside 1..4096");
         c->coef_interleave = (int)value;
+    } else if (n == "resident") {
+        c->resident = value != 0;
     } else {
         return set_error(EIG_EINVAL, "unknown option " + n);
     }
@@ -786,6 +826,7 @@ int eig_ctx_get_option(const eig_ctx* c, const char* name, int64_t* value) {
     else if (n == "wave_cache_bytes") *value = (int64_t)c->wave_cache_bytes;
     else if (n == "cache_chunk_min_solves") *value = c->cache_chunk_min_solves;
     else if (n == "coef_interleave") *value = c->coef_interleave;
+    else if (n == "resident") *value = c->resident ? 1 : 0;
     else if (n == "fused_edges") *value = c->fused_edges;
     else if (n == "serve_cache_bytes") *value = (int64_t)c->serve_cache_bytes;
     else if (n == "graph_captures") *value = c->graph_captures;

@@ -69,13 +69,13 @@ __device__ __forceinline__ CeCoef ce_coef(const SolveDesc& d, int i, int k) {
     return c;
 }
 
-// Edge node e of solve d at its step m (u^m read, u^{m-1} overwritten with
-// u^{m+1}).  Nodes 0..nz-1: left column, nz..2nz-1: right column (corners
-// included), then the bottom row's inner nodes i = 1..nx-2.
-__device__ __forceinline__ void ce_edge_node(const SolveDesc& d, int m, int e) {
-    const int nx = d.nx, nz = d.nz, pitch = d.pitch;
-    const float2* Q = (m & 1) ? d.buf1 : d.buf0;  // u^m
-    float2* P = (m & 1) ? d.buf0 : d.buf1;        // u^{m-1} -> u^{m+1}
+// Edge node e of solve d with u^m in Q and u^{m-1} in P (overwritten with
+// u^{m+1}), rows `pitch` nodes apart (device memory or LDS).  Nodes
+// 0..nz-1: left column, nz..2nz-1: right column (corners included), then
+// the bottom row's inner nodes i = 1..nx-2.
+__device__ __forceinline__ void ce_edge_node_at(const SolveDesc& d, const float2* Q, float2* P,
+                                                int pitch, int e) {
+    const int nx = d.nx, nz = d.nz;
     if (e < 2 * nz) {
         const bool left = e < nz;
         const int k = left ? e : e - nz;
@@ -96,6 +96,13 @@ __device__ __forceinline__ void ce_edge_node(const SolveDesc& d, int m, int e) {
         const CeCoef c = ce_coef(d, i, k);
         P[(size_t)k * pitch + i] = ce_bottom(c.ap, c.as, c.l, r.x - l.x, r.y - l.y, in, old);
     }
+}
+
+// Edge node e of solve d at its step m, fields in the solve's buffers.
+__device__ __forceinline__ void ce_edge_node(const SolveDesc& d, int m, int e) {
+    const float2* Q = (m & 1) ? d.buf1 : d.buf0;  // u^m
+    float2* P = (m & 1) ? d.buf0 : d.buf1;        // u^{m-1} -> u^{m+1}
+    ce_edge_node_at(d, Q, P, d.pitch, e);
 }
 
 // Absorbing edges as extra wavefronts of a stencil launch: tile entries

@@ -73,6 +73,9 @@ struct eig_ctx {
     // nodal media: solves on one medium whose tiles are interleaved by
     // position (coefficient reuse in L2); 1 keeps solve-major order
     int coef_interleave = 8;
+    // grids whose two field levels fit one workgroup's LDS run resident
+    // (their whole time loop in one launch)
+    bool resident = true;
     // absorbing edges updated inside the one-step kernels that can (else by
     // the separate edge kernel after every step)
     bool fused_edges = true;

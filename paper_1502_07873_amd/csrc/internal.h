@@ -145,6 +145,7 @@ struct StencilVariant {
     int cols, rows, medium_kind;
     int steps;  // leapfrog steps per launch (2, 3: four field buffers per solve)
     int edges;  // 1: runs edge tiles (absorbing edges in the same launch)
+    int resident;  // 1: one workgroup per solve, fields in LDS, all steps in one launch
 };
 // Tile entries (solve, kEdgeStrip << 16 | part) of a variant with `edges`:
 // absorbing edge nodes part * kEdgeTileNodes .. +kEdgeTileNodes of a solve.
@@ -153,12 +154,18 @@ constexpr int kEdgeTileNodes = 128;
 inline int edge_tiles_of(int nx, int nz) {
     return (2 * nz + nx - 2 + kEdgeTileNodes - 1) / kEdgeTileNodes;
 }
-constexpr int kNumVariants = 21;
+constexpr int kNumVariants = 23;
 extern const StencilVariant kVariants[kNumVariants];
 // tiles: (solve index, strip << 16 | chunk) per wavefront
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                     int variant, hipStream_t s);
 void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s);
+// Resident solves: both field levels of a solve in one workgroup's LDS
+// (2 nx nz float2 at most kResidentLdsBytes); tiles are (solve, absorbing)
+// pairs, one workgroup each, and one launch takes every time step.
+constexpr size_t kResidentLdsBytes = (size_t)160 << 10;
+void launch_resident(const SolveDesc* descs, const int2* tiles, int ntiles, int kind,
+                     size_t lds_bytes, hipStream_t s);
 // Halo values of the three-steps-per-launch kernels; htiles: (solve,
 // boundary << 16 | 64-row chunk).
 void launch_tb3_halo(const SolveDesc* descs, const int2* htiles, int nhtiles, int pass,

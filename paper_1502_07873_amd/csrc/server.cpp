@@ -579,17 +579,20 @@ int eig_server_create(eig_ctx* c, size_t budget, int32_t group_samples, eig_serv
     auto v = std::make_unique<eig_server>();
     v->ctx = c;
     v->group_samples = group_samples > 0 ? group_samples : 16;
-    v->variant_layered = c->forced_variant >= 0 &&
+    // the server advances groups launch by launch: resident variants (a
+    // whole time loop per launch) are not used here
+    const bool forced = c->forced_variant >= 0 && !kVariants[c->forced_variant].resident;
+    v->variant_layered = forced &&
                                  kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_LAYERED
                              ? c->forced_variant
                              : (c->temporal_blocking >= 2 ? c->default_variant_tb : c->default_variant);
     v->cache_bytes = c->serve_cache_bytes;
-    if (v->cache_bytes && !(c->forced_variant >= 0 &&
+    if (v->cache_bytes && !(forced &&
                             kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_LAYERED))
         v->variant_layered = c->temporal_blocking >= 2 ? 9 : c->default_variant;
     v->spl = kVariants[v->variant_layered].steps;
     // nodal media: two nodes per lane unless a nodal variant is forced
-    if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_NODAL)
+    if (forced && kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_NODAL)
         v->variant_nodal = c->forced_variant;
     v->nslot_cap = 1 << 17;
     if (hipMalloc((void**)&v->mem, budget) != hipSuccess) {

@@ -1700,10 +1700,13 @@ stencil_nodal_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__ t
 // the one-node kernel forms them in the neighbouring lanes, and the products
 // among them are pinned, as a cross-lane move leaves them rounded, so the
 // result is bitwise that of every nodal variant.
-__device__ float2 nodal_node(const float2* Q, const float2* P, const float* LAM,
-                             const float* MU, const float* SC, int pitch, int i, int k,
-                             int inj, float h2, float sval, float w0, float w1) {
-    auto U = [&](int ii, int kk) { return ld2(Q, (size_t)kk * pitch + ii); };
+// U(i, k) gives u^m (from device memory or LDS); up is u^{m-1} at the node;
+// the coefficient planes have row pitch `pitch`.
+template <class UF>
+__device__ __forceinline__ float2 nodal_node_at(UF U, float2 up, const float* LAM,
+                                                const float* MU, const float* SC, int pitch,
+                                                int i, int k, int inj, float h2, float sval,
+                                                float w0, float w1) {
     auto L = [&](int ii, int kk) { return ld1(LAM, (size_t)kk * pitch + ii); };
     auto M = [&](int ii, int kk) { return ld1(MU, (size_t)kk * pitch + ii); };
     const bool top = k == 0;
@@ -1754,9 +1757,16 @@ __device__ float2 nodal_node(const float2* Q, const float2* P, const float* LAM,
     n.qR = pinned(qR);
     n.qL = pinned(qL);
     const float2 acc = nodal_accel(n, top);
-    const float2 up = ld2(P, (size_t)k * pitch + i);
     return nodal_new(acc, ld1(SC, (size_t)k * pitch + i), n.u, n.v, up.x, up.y, inj, h2, sval,
                      w0, w1);
+}
+
+__device__ float2 nodal_node(const float2* Q, const float2* P, const float* LAM,
+                             const float* MU, const float* SC, int pitch, int i, int k,
+                             int inj, float h2, float sval, float w0, float w1) {
+    auto U = [&](int ii, int kk) { return ld2(Q, (size_t)kk * pitch + ii); };
+    return nodal_node_at(U, ld2(P, (size_t)k * pitch + i), LAM, MU, SC, pitch, i, k, inj, h2,
+                         sval, w0, w1);
 }
 
 // Two leapfrog steps per launch for nodal media (rigid edges, no receiver
@@ -1972,6 +1982,144 @@ stencil_nodal_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict__ 
     }
 }
 
+// Resident solves (variants 21, 22): a grid whose two field levels fit one
+// workgroup's LDS (2 nx nz float2, rows nx nodes apart) is advanced through
+// its whole time loop by one workgroup of 16 waves, so the fields never
+// leave the CU; one barrier per step separates the levels.  Level m sits in
+// LDS half m & 1 and u^{m+1} overwrites u^{m-1} in place (every node is
+// read at the old level and written only by its owner).  The free interior
+// (columns 1..nx-2, rows 0..nz-2) is cut into 64-column segments and, per
+// segment, into row bands, so that 16 waves share the work; a wave streams
+// down its band keeping rows k-1, k, k+1 as in the one-node kernels, with
+// the row index wave-uniform (depth-only coefficients are scalar loads).
+// Absorbing edge nodes follow in the same phase: their relation reads only
+// u^m and the node's own u^{m-1}.  The per-node arithmetic is that of the
+// one-node kernels (layered_update, nodal_node_at, ce_edge_node_at), so
+// the fields are bitwise those of every variant.
+constexpr int kResWaves = 16;
+
+template <int KIND>
+__global__ void __launch_bounds__(64 * kResWaves)
+stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
+                 int ntiles) {
+    extern __shared__ float2 res_lds[];
+    if ((int)blockIdx.x >= ntiles) return;
+    const int2 te = tiles[blockIdx.x];
+    const SolveDesc* d = descs + __builtin_amdgcn_readfirstlane(te.x);
+    const bool absorbing = __builtin_amdgcn_readfirstlane(te.y) != 0;
+    const int nx = d->nx, nz = d->nz, nsteps = d->nsteps;
+    const int plane = nx * nz;
+    for (int j = threadIdx.x; j < 2 * plane; j += 64 * kResWaves)
+        res_lds[j] = make_float2(0.f, 0.f);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nseg = (nx - 2 + 63) >> 6;
+    const int nband = max(1, kResWaves / nseg);
+    const int nitem = nseg * nband;
+    const int nrow = nz - 1;  // free rows 0..nz-2
+    const int nedge = 2 * nz + nx - 2;
+    const int si0 = d->src_i0, sk0 = d->src_k0;
+    const float* srcw = d->srcw;
+    const float* srcs = d->srcs;
+    float2* traces = d->traces;
+    const int nrec = d->nrec;
+    const float2* rfz = d->rforce;
+    float2* wrec = d->wrec;
+    const float* coef = d->coef;
+    const int cpitch = d->pitch;
+    const size_t cplane = (size_t)nz * cpitch;
+    const float h2 = d->h2;
+    for (int m = 0; m < nsteps; ++m) {
+        const float2* Q = res_lds + ((m & 1) ? plane : 0);  // u^m
+        float2* P = res_lds + ((m & 1) ? 0 : plane);        // u^{m-1} -> u^{m+1}
+        const float sval = ld1(srcs, m);
+        for (int it = wave; it < nitem; it += kResWaves) {
+            const int seg = it % nseg, band = it / nseg;
+            const int kb = band * nrow / nband, ke = (band + 1) * nrow / nband;
+            const int i = 1 + 64 * seg + lane;
+            const bool upd = i <= nx - 2;
+            const int ic = upd ? i : nx - 2;  // lanes past the interior read a real column
+            const int di = ic - si0;
+            const bool src_lane = di >= 0 && di < kSrcW;
+            int rec = -1;
+            if (kb == 0) rec = ldi(d->recmap, ic);
+            if constexpr (KIND == EIG_MEDIUM_LAYERED) {
+                auto row = [&](int k) {
+                    const float2* r = Q + k * nx + ic;
+                    const float2 l = r[-1], c = r[0], rr = r[1];
+                    return node_row(c.x, c.y, l.x, l.y, rr.x, rr.y);
+                };
+                NodeRow rm = NodeRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if (kb > 0) rm = row(kb - 1);
+                NodeRow rc = row(kb);
+                for (int k = kb; k < ke; ++k) {
+                    const NodeRow rn = row(k + 1);
+                    const LayerCoef cf = load_coef(coef, k);
+                    const int dk = k - sk0;
+                    const bool in_win = src_lane && dk >= 0 && dk < kSrcW;
+                    bool src = in_win;
+                    float wu = 0.f, wv = 0.f, fsv = cf.c[kFco] * sval;
+                    if (src) {
+                        wu = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
+                        wv = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
+                    }
+                    if (rfz && k == 0 && rec >= 0) {  // dual solve: receiver injection
+                        const float2 rf = ld2(rfz, (size_t)m * nrec + rec);
+                        src = true;
+                        fsv = cf.c[kFco];
+                        wu = rf.x;
+                        wv = rf.y;
+                    }
+                    const float2 up = P[k * nx + ic];
+                    const float2 nw = layered_update(cf, rm, rc, rn, up.x, up.y, src, fsv, wu, wv);
+                    if (upd) {
+                        P[k * nx + i] = nw;
+                        if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
+                        if (wrec && in_win)
+                            st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
+                    }
+                    rm = rc;
+                    rc = rn;
+                }
+            } else {
+                const float* LAM = coef;
+                const float* MU = coef + cplane;
+                const float* SC = coef + 2 * cplane;
+                auto U = [&](int ii, int kk) { return Q[kk * nx + ii]; };
+                for (int k = kb; k < ke; ++k) {
+                    const int dk = k - sk0;
+                    const bool in_win = src_lane && dk >= 0 && dk < kSrcW;
+                    int inj = 0;
+                    float w0 = 0.f, w1 = 0.f;
+                    if (rfz && k == 0 && rec >= 0) {  // dual solve: receiver injection
+                        const float2 rf = ld2(rfz, (size_t)m * nrec + rec);
+                        inj = 1;
+                        w0 = rf.x;
+                        w1 = rf.y;
+                    } else if (in_win) {
+                        inj = 2;
+                        w0 = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
+                        w1 = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
+                    }
+                    const float2 nw = nodal_node_at(U, P[k * nx + ic], LAM, MU, SC, cpitch, ic,
+                                                    k, inj, h2, sval, w0, w1);
+                    if (upd) {
+                        P[k * nx + i] = nw;
+                        if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
+                        if (wrec && in_win)
+                            st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
+                    }
+                }
+            }
+        }
+        if (absorbing)
+            for (int e = threadIdx.x; e < nedge; e += 64 * kResWaves)
+                ce_edge_node_at(*d, Q, P, nx, e);
+        __syncthreads();
+    }
+}
+
 __global__ void fill_zero_kernel(uint4* p, size_t n16, uint8_t* tail, size_t ntail) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n16; j += stride)
@@ -2032,7 +2180,27 @@ const StencilVariant kVariants[kNumVariants] = {
     {128, 32, EIG_MEDIUM_NODAL, 1, 1},    // 18: nodal media, two nodes per lane
     {128, 16, EIG_MEDIUM_NODAL, 2},    // 19: nodal media, two steps per launch
     {128, 32, EIG_MEDIUM_NODAL, 2},    // 20: nodal media, two steps per launch
+    {0, 0, EIG_MEDIUM_LAYERED, 1, 1, 1},  // 21: resident in LDS, every step in one launch
+    {0, 0, EIG_MEDIUM_NODAL, 1, 1, 1},    // 22: resident in LDS, every step in one launch
 };
+
+void launch_resident(const SolveDesc* descs, const int2* tiles, int ntiles, int kind,
+                     size_t lds_bytes, hipStream_t s) {
+    if (ntiles <= 0) return;
+    // allow dynamic LDS up to the whole 160 KiB of a CU for this kernel (on
+    // the current device; idempotent, once per wave)
+    const void* fn = kind == EIG_MEDIUM_NODAL ? (const void*)stencil_resident<EIG_MEDIUM_NODAL>
+                                              : (const void*)stencil_resident<EIG_MEDIUM_LAYERED>;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kResidentLdsBytes);
+    (void)hipGetLastError();
+    if (kind == EIG_MEDIUM_NODAL)
+        stencil_resident<EIG_MEDIUM_NODAL><<<ntiles, 64 * kResWaves, lds_bytes, s>>>(
+            descs, tiles, ntiles);
+    else
+        stencil_resident<EIG_MEDIUM_LAYERED><<<ntiles, 64 * kResWaves, lds_bytes, s>>>(
+            descs, tiles, ntiles);
+}
 
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                     int variant, hipStream_t s) {
