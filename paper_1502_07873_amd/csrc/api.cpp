@@ -49,10 +49,11 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
 // A solve whose two field levels fit one workgroup's LDS runs resident
 // (variants 21, 22: its whole time loop in one launch, fields never in HBM),
 // unless that is switched off or a tiled variant is forced.
-bool resident_ok(const eig_ctx* c, const eig_grid& g) {
+bool resident_ok(const eig_ctx* c, const eig_grid& g, int kind) {
     if (!c->resident) return false;
     if (c->forced_variant >= 0 && !kVariants[c->forced_variant].resident) return false;
-    return (size_t)g.nx * g.nz * 2 * sizeof(float2) <= kResidentLdsBytes;
+    return resident_lds_bytes(kind, g.nx, g.nz) <= kResidentLdsBytes &&
+           2 * g.nz + g.nx - 2 <= kResidentMaxEdge;
 }
 // Steps a resident launch stands for in the launch-count arithmetic: above
 // any grid's nsteps (valid grids have nsteps < 2^28).
@@ -72,7 +73,7 @@ int family_steps_of(const eig_ctx* c, int kind, bool one_step) {
 // otherwise.
 size_t live_field_bytes(const eig_ctx* c, const SolveSpec& sp, const eig_grid& g,
                         const MediumKey& mk) {
-    if (resident_ok(c, g)) return 0;  // fields in LDS
+    if (resident_ok(c, g, mk.kind)) return 0;  // fields in LDS
     const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
     const bool one_step = g.bc == EIG_BC_ABSORBING || sp.rforce != nullptr;
     int steps = family_steps_of(c, mk.kind, one_step);
@@ -232,7 +233,8 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
     // grids that fit one workgroup's LDS run resident (variants 21, 22)
     static const std::vector<int> res_cand[2] = {{21}, {22}};
     std::vector<char> res(n);
-    for (int i = 0; i < n; ++i) res[i] = resident_ok(c, grids[solves[i].grid]);
+    for (int i = 0; i < n; ++i)
+        res[i] = resident_ok(c, grids[solves[i].grid], media[solves[i].medium].kind);
     auto cand_of = [&](int i) -> const std::vector<int>& {
         if (res[i]) return res_cand[media[solves[i].medium].kind];
         return cands[media[solves[i].medium].kind][one_step(i) ? 1 : 0];
@@ -396,7 +398,7 @@ int run_chunk(eig_ctx* c, const std::vector<SolveSpec>& solves,
             if (sv.resident) {
                 gr.tiles[v].push_back(make_int2(oi, g.bc == EIG_BC_ABSORBING ? 1 : 0));
                 gr.steps_tiles[v].push_back({g.nsteps, (int)gr.tiles[v].size()});
-                gr.lds = std::max(gr.lds, (size_t)g.nx * g.nz * 2 * sizeof(float2));
+                gr.lds = std::max(gr.lds, resident_lds_bytes(mk.kind, g.nx, g.nz));
                 continue;
             }
             const int nstrip = (g.nx + sv.cols - 1) / sv.cols;

@@ -69,12 +69,19 @@ __device__ __forceinline__ CeCoef ce_coef(const SolveDesc& d, int i, int k) {
     return c;
 }
 
-// Edge node e of solve d with u^m in Q and u^{m-1} in P (overwritten with
-// u^{m+1}), rows `pitch` nodes apart (device memory or LDS).  Nodes
-// 0..nz-1: left column, nz..2nz-1: right column (corners included), then
-// the bottom row's inner nodes i = 1..nx-2.
-__device__ __forceinline__ void ce_edge_node_at(const SolveDesc& d, const float2* Q, float2* P,
-                                                int pitch, int e) {
+// Grid node (i, k) of edge node e: nodes 0..nz-1 are the left column,
+// nz..2nz-1 the right column (corners included), then the bottom row's inner
+// nodes i = 1..nx-2.
+__device__ __forceinline__ int2 ce_edge_pos(int nx, int nz, int e) {
+    if (e < 2 * nz) return make_int2(e < nz ? 0 : nx - 1, e < nz ? e : e - nz);
+    return make_int2(e - 2 * nz + 1, nz - 1);
+}
+
+// Edge node e of solve d with coefficients c, u^m in Q and u^{m-1} in P
+// (overwritten with u^{m+1}), rows `pitch` nodes apart (device memory or
+// LDS).
+__device__ __forceinline__ void ce_edge_update(const SolveDesc& d, const float2* Q, float2* P,
+                                               int pitch, int e, const CeCoef& c) {
     const int nx = d.nx, nz = d.nz;
     if (e < 2 * nz) {
         const bool left = e < nz;
@@ -85,7 +92,6 @@ __device__ __forceinline__ void ce_edge_node_at(const SolveDesc& d, const float2
         const float2 up = Q[(size_t)kb * pitch + i], dn = Q[(size_t)ka * pitch + i];
         const float2 in = Q[(size_t)k * pitch + ii];
         const float2 old = P[(size_t)k * pitch + i];
-        const CeCoef c = ce_coef(d, i, k);
         P[(size_t)k * pitch + i] =
             ce_side(c.ap, c.as, c.l, left ? 1.f : -1.f, half, up, dn, in, old);
     } else {
@@ -93,9 +99,14 @@ __device__ __forceinline__ void ce_edge_node_at(const SolveDesc& d, const float2
         const float2 r = Q[(size_t)k * pitch + i + 1], l = Q[(size_t)k * pitch + i - 1];
         const float2 in = Q[(size_t)(k - 1) * pitch + i];
         const float2 old = P[(size_t)k * pitch + i];
-        const CeCoef c = ce_coef(d, i, k);
         P[(size_t)k * pitch + i] = ce_bottom(c.ap, c.as, c.l, r.x - l.x, r.y - l.y, in, old);
     }
+}
+
+__device__ __forceinline__ void ce_edge_node_at(const SolveDesc& d, const float2* Q, float2* P,
+                                                int pitch, int e) {
+    const int2 ik = ce_edge_pos(d.nx, d.nz, e);
+    ce_edge_update(d, Q, P, pitch, e, ce_coef(d, ik.x, ik.y));
 }
 
 // Edge node e of solve d at its step m, fields in the solve's buffers.

@@ -161,9 +161,17 @@ void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int s
                     int variant, hipStream_t s);
 void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s);
 // Resident solves: both field levels of a solve in one workgroup's LDS
-// (2 nx nz float2 at most kResidentLdsBytes); tiles are (solve, absorbing)
-// pairs, one workgroup each, and one launch takes every time step.
+// (2 nx nz float2, the forcing window weights and for depth-only media the
+// nz x kCoefStride float coefficient table, at most kResidentLdsBytes);
+// tiles are (solve, absorbing) pairs, one workgroup each, and one launch
+// takes every step.
 constexpr size_t kResidentLdsBytes = (size_t)160 << 10;
+constexpr int kResSrcwFloats = 128;  // forcing window weights (2 x 7 x 7, padded)
+constexpr int kResidentMaxEdge = 3 * 1024;  // edge nodes: three per thread at most
+inline size_t resident_lds_bytes(int kind, int nx, int nz) {
+    return (size_t)nx * nz * 2 * sizeof(float2) + kResSrcwFloats * sizeof(float) +
+           (kind == EIG_MEDIUM_LAYERED ? (size_t)nz * kCoefStride * sizeof(float) : 0);
+}
 void launch_resident(const SolveDesc* descs, const int2* tiles, int ntiles, int kind,
                      size_t lds_bytes, hipStream_t s);
 // Halo values of the three-steps-per-launch kernels; htiles: (solve,

@@ -25,6 +25,7 @@
 // Depth-only coefficients are per-row scalars (SGPR loads).
 #include "ce.h"
 #include "internal.h"
+#include "node_update.h"
 
 namespace eig {
 
@@ -48,100 +49,6 @@ __device__ __forceinline__ float from_left(float x, float edge) {
 __device__ __forceinline__ float from_right(float x, float edge) {
     return __int_as_float(__builtin_amdgcn_update_dpp(
         __float_as_int(edge), __float_as_int(x), 0x130 /* wave_shl:1 */, 0xf, 0xf, false));
-}
-
-// Pointers read out of a descriptor are generic; loads through them would be
-// FLAT instructions.  These accessors address global memory explicitly.
-#if defined(__HIP_DEVICE_COMPILE__)
-#define GAS __attribute__((address_space(1)))
-#else
-#define GAS
-#endif
-typedef float fv2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ float2 ld2(const float2* p, size_t i) {
-    const fv2 v = ((const GAS fv2*)p)[i];
-    return make_float2(v.x, v.y);
-}
-__device__ __forceinline__ void st2(float2* p, size_t i, float2 v) {
-    fv2 w;
-    w.x = v.x;
-    w.y = v.y;
-    ((GAS fv2*)p)[i] = w;
-}
-typedef float fv4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float4 ld4(const float2* p, size_t i) {  // i even
-    const fv4 v = *(const GAS fv4*)((const GAS fv2*)p + i);
-    return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ void st4(float2* p, size_t i, float4 v) {  // i even
-    fv4 w;
-    w.x = v.x;
-    w.y = v.y;
-    w.z = v.z;
-    w.w = v.w;
-    *(GAS fv4*)((GAS fv2*)p + i) = w;
-}
-__device__ __forceinline__ float ld1(const float* p, size_t i) {
-    return ((const GAS float*)p)[i];
-}
-__device__ __forceinline__ int ldi(const int32_t* p, size_t i) {
-    return ((const GAS int32_t*)p)[i];
-}
-
-// One row of u^m seen from one node: centre values and the sum and
-// difference of the x-neighbours.
-struct NodeRow {
-    float u, v;      // centre
-    float dxu, dxv;  // w_{i+1} - w_{i-1}
-    float sxu, sxv;  // w_{i+1} + w_{i-1}
-};
-
-__device__ __forceinline__ NodeRow node_row(float u, float v, float lu, float lv,
-                                            float ru, float rv) {
-    NodeRow r;
-    r.u = u;
-    r.v = v;
-    r.dxu = ru - lu;
-    r.dxv = rv - lv;
-    r.sxu = ru + lu;
-    r.sxv = rv + lv;
-    return r;
-}
-
-struct LayerCoef {
-    float c[kFco + 1];
-};
-
-// Row k of a depth-only coefficient table (wave-uniform: scalar loads).
-__device__ __forceinline__ LayerCoef load_coef(const float* coef, int k) {
-    LayerCoef r;
-    const size_t cb = (size_t)k * kCoefStride;
-#pragma unroll
-    for (int j = 0; j <= kFco; ++j) r.c[j] = ld1(coef, cb + j);
-    return r;
-}
-
-// u^{m+1} at one node of a depth-only medium.  Every stencil variant calls
-// this, so all of them produce bitwise-identical fields.
-__device__ __forceinline__ float2 layered_update(const LayerCoef& c, const NodeRow& rm,
-                                                 const NodeRow& rc, const NodeRow& rn,
-                                                 float upu, float upv, bool src, float fsv,
-                                                 float wu, float wv) {
-    float au = c.c[kCxxU] * (rc.sxu - 2.f * rc.u) + c.c[kCzpU] * (rn.u - rc.u)
-             - c.c[kCzmU] * (rc.u - rm.u) + c.c[kCmpU] * rn.dxv
-             - c.c[kCmmU] * rm.dxv + c.c[kCm0U] * rc.dxv;
-    float av = c.c[kCxxV] * (rc.sxv - 2.f * rc.v) + c.c[kCzpV] * (rn.v - rc.v)
-             - c.c[kCzmV] * (rc.v - rm.v) + c.c[kCmpV] * rn.dxu
-             - c.c[kCmmV] * rm.dxu + c.c[kCm0V] * rc.dxu;
-    if (src) {
-        au += fsv * wu;
-        av += fsv * wv;
-    }
-    float2 nw;
-    nw.x = rc.u + ((rc.u - upu) + au);
-    nw.y = rc.v + ((rc.v - upv) + av);
-    return nw;
 }
 
 // Wave-uniform tile decode: tile entry = (solve, strip << 16 | chunk).
@@ -1221,74 +1128,6 @@ stencil_layered_tb3(const SolveDesc* __restrict__ descs, const int2* __restrict_
     }
 }
 
-// Nodal media: coef = three planes (lambda, mu, s = dt^2/(rho h^2)).
-//
-// Operands of the nodal operator at one node (i, k): the node's own values,
-// its x-neighbours on row k, rows k+1 and k-1 (centre values and the
-// x-difference w_{i+1} - w_{i-1}), and the x-neighbours' products
-// p = lambda Dz v and q = mu Dz u (Dz over rows k+1, k-1, or k+1, k on the
-// free surface).  Every nodal variant hands nodal_accel / nodal_new the same
-// operand values, so all of them produce bitwise-identical fields.
-struct NodalView {
-    float u, v, lam, mu;                   // node (i, k)
-    float uL, uR, vL, vR, aL, aR, mL, mR;  // x-neighbours on row k (a = lambda + 2 mu)
-    float un, vn, lamn, mun, dxun, dxvn;   // row k+1
-    float um, vm, lamm, mum, dxum, dxvm;   // row k-1 (unused on the free surface)
-    float pR, pL, qR, qL;                  // the x-neighbours' p and q
-};
-
-// Acceleration terms at one node, before the scaling by s.
-__device__ __forceinline__ float2 nodal_accel(const NodalView& n, bool top) {
-    const float ac = n.lam + 2.f * n.mu;
-    const float an = n.lamn + 2.f * n.mun;
-    float au = 0.5f * ((ac + n.aR) * (n.uR - n.u) - (n.aL + ac) * (n.u - n.uL));
-    float av = 0.5f * ((n.mu + n.mR) * (n.vR - n.v) - (n.mL + n.mu) * (n.v - n.vL));
-    if (top) {
-        const float dxu_c = n.uR - n.uL, dxv_c = n.vR - n.vL;
-        au += (n.mu + n.mun) * (n.un - n.u);
-        av += (ac + an) * (n.vn - n.v);
-        // 1/2 [lam_{i+1,0} (v_{i+1,1}-v_{i+1,0}) - lam_{i-1,0} (...)]
-        au += 0.5f * (n.pR - n.pL) + 0.5f * (n.mu * dxv_c + n.mun * n.dxvn);
-        av += 0.5f * (n.lam * dxu_c + n.lamn * n.dxun) + 0.5f * (n.qR - n.qL);
-    } else {
-        const float am = n.lamm + 2.f * n.mum;
-        au += 0.5f * ((n.mu + n.mun) * (n.un - n.u) - (n.mum + n.mu) * (n.u - n.um));
-        av += 0.5f * ((ac + an) * (n.vn - n.v) - (am + ac) * (n.v - n.vm));
-        // 1/4 [lam_{i+1,k} Dz v_{i+1} - lam_{i-1,k} Dz v_{i-1}], Dz w = w_{k+1} - w_{k-1}
-        au += 0.25f * (n.pR - n.pL) + 0.25f * (n.mun * n.dxvn - n.mum * n.dxvm);
-        av += 0.25f * (n.lamn * n.dxun - n.lamm * n.dxum) + 0.25f * (n.qR - n.qL);
-    }
-    return make_float2(au, av);
-}
-
-// u^{m+1} from the acceleration terms, s, u^m, u^{m-1} and the forcing:
-// inj 1 adds a receiver force density (w0, w1) (dual solves), inj 2 the
-// source window weights (w0, w1) times the series value; dt^2/rho f = s h^2 f.
-__device__ __forceinline__ float2 nodal_new(float2 acc, float sc, float u, float v, float upu,
-                                           float upv, int inj, float h2, float sval,
-                                           float w0, float w1) {
-    float au = acc.x * sc, av = acc.y * sc;
-    if (inj == 1) {
-        au += sc * h2 * w0;
-        av += sc * h2 * w1;
-    } else if (inj == 2) {
-        const float f = sc * h2 * sval;
-        au += f * w0;
-        av += f * w1;
-    }
-    float2 nw;
-    nw.x = u + ((u - upu) + au);
-    nw.y = v + ((v - upv) + av);
-    return nw;
-}
-
-// An opaque copy: the compiler may not fuse the product that made x into a
-// later addition, so x enters every use rounded, as it does after a DPP move.
-__device__ __forceinline__ float pinned(float x) {
-    __asm__ volatile("" : "+v"(x));
-    return x;
-}
-
 struct RowN {
     float u, v, hu, hv;   // centre and halo-column values of u^m
     float lam, mu;        // centre nodal coefficients
@@ -1700,67 +1539,6 @@ stencil_nodal_w2(const SolveDesc* __restrict__ descs, const int2* __restrict__ t
 // the one-node kernel forms them in the neighbouring lanes, and the products
 // among them are pinned, as a cross-lane move leaves them rounded, so the
 // result is bitwise that of every nodal variant.
-// U(i, k) gives u^m (from device memory or LDS); up is u^{m-1} at the node;
-// the coefficient planes have row pitch `pitch`.
-template <class UF>
-__device__ __forceinline__ float2 nodal_node_at(UF U, float2 up, const float* LAM,
-                                                const float* MU, const float* SC, int pitch,
-                                                int i, int k, int inj, float h2, float sval,
-                                                float w0, float w1) {
-    auto L = [&](int ii, int kk) { return ld1(LAM, (size_t)kk * pitch + ii); };
-    auto M = [&](int ii, int kk) { return ld1(MU, (size_t)kk * pitch + ii); };
-    const bool top = k == 0;
-    NodalView n;
-    const float2 c = U(i, k), l = U(i - 1, k), r = U(i + 1, k);
-    n.u = c.x;
-    n.v = c.y;
-    n.lam = L(i, k);
-    n.mu = M(i, k);
-    n.uL = l.x;
-    n.uR = r.x;
-    n.vL = l.y;
-    n.vR = r.y;
-    const float lL = L(i - 1, k), mL = M(i - 1, k), lR = L(i + 1, k), mR = M(i + 1, k);
-    n.aL = pinned(lL + 2.f * mL);
-    n.aR = pinned(lR + 2.f * mR);
-    n.mL = mL;
-    n.mR = mR;
-    const float2 cn = U(i, k + 1), ln = U(i - 1, k + 1), rn = U(i + 1, k + 1);
-    n.un = cn.x;
-    n.vn = cn.y;
-    n.lamn = L(i, k + 1);
-    n.mun = M(i, k + 1);
-    n.dxun = rn.x - ln.x;
-    n.dxvn = rn.y - ln.y;
-    float pR, pL, qR, qL;
-    if (top) {
-        n.um = n.vm = n.lamm = n.mum = n.dxum = n.dxvm = 0.f;
-        pR = lR * (rn.y - r.y);
-        pL = lL * (ln.y - l.y);
-        qR = mR * (rn.x - r.x);
-        qL = mL * (ln.x - l.x);
-    } else {
-        const float2 cm = U(i, k - 1), lm = U(i - 1, k - 1), rm = U(i + 1, k - 1);
-        n.um = cm.x;
-        n.vm = cm.y;
-        n.lamm = L(i, k - 1);
-        n.mum = M(i, k - 1);
-        n.dxum = rm.x - lm.x;
-        n.dxvm = rm.y - lm.y;
-        pR = lR * (rn.y - rm.y);
-        pL = lL * (ln.y - lm.y);
-        qR = mR * (rn.x - rm.x);
-        qL = mL * (ln.x - lm.x);
-    }
-    n.pR = pinned(pR);
-    n.pL = pinned(pL);
-    n.qR = pinned(qR);
-    n.qL = pinned(qL);
-    const float2 acc = nodal_accel(n, top);
-    return nodal_new(acc, ld1(SC, (size_t)k * pitch + i), n.u, n.v, up.x, up.y, inj, h2, sval,
-                     w0, w1);
-}
-
 __device__ float2 nodal_node(const float2* Q, const float2* P, const float* LAM,
                              const float* MU, const float* SC, int pitch, int i, int k,
                              int inj, float h2, float sval, float w0, float w1) {
@@ -1982,144 +1760,6 @@ stencil_nodal_tb2(const SolveDesc* __restrict__ descs, const int2* __restrict__ 
     }
 }
 
-// Resident solves (variants 21, 22): a grid whose two field levels fit one
-// workgroup's LDS (2 nx nz float2, rows nx nodes apart) is advanced through
-// its whole time loop by one workgroup of 16 waves, so the fields never
-// leave the CU; one barrier per step separates the levels.  Level m sits in
-// LDS half m & 1 and u^{m+1} overwrites u^{m-1} in place (every node is
-// read at the old level and written only by its owner).  The free interior
-// (columns 1..nx-2, rows 0..nz-2) is cut into 64-column segments and, per
-// segment, into row bands, so that 16 waves share the work; a wave streams
-// down its band keeping rows k-1, k, k+1 as in the one-node kernels, with
-// the row index wave-uniform (depth-only coefficients are scalar loads).
-// Absorbing edge nodes follow in the same phase: their relation reads only
-// u^m and the node's own u^{m-1}.  The per-node arithmetic is that of the
-// one-node kernels (layered_update, nodal_node_at, ce_edge_node_at), so
-// the fields are bitwise those of every variant.
-constexpr int kResWaves = 16;
-
-template <int KIND>
-__global__ void __launch_bounds__(64 * kResWaves)
-stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
-                 int ntiles) {
-    extern __shared__ float2 res_lds[];
-    if ((int)blockIdx.x >= ntiles) return;
-    const int2 te = tiles[blockIdx.x];
-    const SolveDesc* d = descs + __builtin_amdgcn_readfirstlane(te.x);
-    const bool absorbing = __builtin_amdgcn_readfirstlane(te.y) != 0;
-    const int nx = d->nx, nz = d->nz, nsteps = d->nsteps;
-    const int plane = nx * nz;
-    for (int j = threadIdx.x; j < 2 * plane; j += 64 * kResWaves)
-        res_lds[j] = make_float2(0.f, 0.f);
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nseg = (nx - 2 + 63) >> 6;
-    const int nband = max(1, kResWaves / nseg);
-    const int nitem = nseg * nband;
-    const int nrow = nz - 1;  // free rows 0..nz-2
-    const int nedge = 2 * nz + nx - 2;
-    const int si0 = d->src_i0, sk0 = d->src_k0;
-    const float* srcw = d->srcw;
-    const float* srcs = d->srcs;
-    float2* traces = d->traces;
-    const int nrec = d->nrec;
-    const float2* rfz = d->rforce;
-    float2* wrec = d->wrec;
-    const float* coef = d->coef;
-    const int cpitch = d->pitch;
-    const size_t cplane = (size_t)nz * cpitch;
-    const float h2 = d->h2;
-    for (int m = 0; m < nsteps; ++m) {
-        const float2* Q = res_lds + ((m & 1) ? plane : 0);  // u^m
-        float2* P = res_lds + ((m & 1) ? 0 : plane);        // u^{m-1} -> u^{m+1}
-        const float sval = ld1(srcs, m);
-        for (int it = wave; it < nitem; it += kResWaves) {
-            const int seg = it % nseg, band = it / nseg;
-            const int kb = band * nrow / nband, ke = (band + 1) * nrow / nband;
-            const int i = 1 + 64 * seg + lane;
-            const bool upd = i <= nx - 2;
-            const int ic = upd ? i : nx - 2;  // lanes past the interior read a real column
-            const int di = ic - si0;
-            const bool src_lane = di >= 0 && di < kSrcW;
-            int rec = -1;
-            if (kb == 0) rec = ldi(d->recmap, ic);
-            if constexpr (KIND == EIG_MEDIUM_LAYERED) {
-                auto row = [&](int k) {
-                    const float2* r = Q + k * nx + ic;
-                    const float2 l = r[-1], c = r[0], rr = r[1];
-                    return node_row(c.x, c.y, l.x, l.y, rr.x, rr.y);
-                };
-                NodeRow rm = NodeRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                if (kb > 0) rm = row(kb - 1);
-                NodeRow rc = row(kb);
-                for (int k = kb; k < ke; ++k) {
-                    const NodeRow rn = row(k + 1);
-                    const LayerCoef cf = load_coef(coef, k);
-                    const int dk = k - sk0;
-                    const bool in_win = src_lane && dk >= 0 && dk < kSrcW;
-                    bool src = in_win;
-                    float wu = 0.f, wv = 0.f, fsv = cf.c[kFco] * sval;
-                    if (src) {
-                        wu = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
-                        wv = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
-                    }
-                    if (rfz && k == 0 && rec >= 0) {  // dual solve: receiver injection
-                        const float2 rf = ld2(rfz, (size_t)m * nrec + rec);
-                        src = true;
-                        fsv = cf.c[kFco];
-                        wu = rf.x;
-                        wv = rf.y;
-                    }
-                    const float2 up = P[k * nx + ic];
-                    const float2 nw = layered_update(cf, rm, rc, rn, up.x, up.y, src, fsv, wu, wv);
-                    if (upd) {
-                        P[k * nx + i] = nw;
-                        if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
-                        if (wrec && in_win)
-                            st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
-                    }
-                    rm = rc;
-                    rc = rn;
-                }
-            } else {
-                const float* LAM = coef;
-                const float* MU = coef + cplane;
-                const float* SC = coef + 2 * cplane;
-                auto U = [&](int ii, int kk) { return Q[kk * nx + ii]; };
-                for (int k = kb; k < ke; ++k) {
-                    const int dk = k - sk0;
-                    const bool in_win = src_lane && dk >= 0 && dk < kSrcW;
-                    int inj = 0;
-                    float w0 = 0.f, w1 = 0.f;
-                    if (rfz && k == 0 && rec >= 0) {  // dual solve: receiver injection
-                        const float2 rf = ld2(rfz, (size_t)m * nrec + rec);
-                        inj = 1;
-                        w0 = rf.x;
-                        w1 = rf.y;
-                    } else if (in_win) {
-                        inj = 2;
-                        w0 = ld1(srcw, (0 * kSrcW + dk) * kSrcW + di);
-                        w1 = ld1(srcw, (1 * kSrcW + dk) * kSrcW + di);
-                    }
-                    const float2 nw = nodal_node_at(U, P[k * nx + ic], LAM, MU, SC, cpitch, ic,
-                                                    k, inj, h2, sval, w0, w1);
-                    if (upd) {
-                        P[k * nx + i] = nw;
-                        if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
-                        if (wrec && in_win)
-                            st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
-                    }
-                }
-            }
-        }
-        if (absorbing)
-            for (int e = threadIdx.x; e < nedge; e += 64 * kResWaves)
-                ce_edge_node_at(*d, Q, P, nx, e);
-        __syncthreads();
-    }
-}
-
 __global__ void fill_zero_kernel(uint4* p, size_t n16, uint8_t* tail, size_t ntail) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n16; j += stride)
@@ -2183,24 +1823,6 @@ const StencilVariant kVariants[kNumVariants] = {
     {0, 0, EIG_MEDIUM_LAYERED, 1, 1, 1},  // 21: resident in LDS, every step in one launch
     {0, 0, EIG_MEDIUM_NODAL, 1, 1, 1},    // 22: resident in LDS, every step in one launch
 };
-
-void launch_resident(const SolveDesc* descs, const int2* tiles, int ntiles, int kind,
-                     size_t lds_bytes, hipStream_t s) {
-    if (ntiles <= 0) return;
-    // allow dynamic LDS up to the whole 160 KiB of a CU for this kernel (on
-    // the current device; idempotent, once per wave)
-    const void* fn = kind == EIG_MEDIUM_NODAL ? (const void*)stencil_resident<EIG_MEDIUM_NODAL>
-                                              : (const void*)stencil_resident<EIG_MEDIUM_LAYERED>;
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)kResidentLdsBytes);
-    (void)hipGetLastError();
-    if (kind == EIG_MEDIUM_NODAL)
-        stencil_resident<EIG_MEDIUM_NODAL><<<ntiles, 64 * kResWaves, lds_bytes, s>>>(
-            descs, tiles, ntiles);
-    else
-        stencil_resident<EIG_MEDIUM_LAYERED><<<ntiles, 64 * kResWaves, lds_bytes, s>>>(
-            descs, tiles, ntiles);
-}
 
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                     int variant, hipStream_t s) {
