@@ -13,24 +13,30 @@ namespace {
 // its whole time loop by one workgroup of 16 waves, so the fields never
 // leave the CU; one barrier per step separates the levels.  Level m sits in
 // LDS half m & 1 and u^{m+1} overwrites u^{m-1} in place (every node is
-// read at the old level and written only by its owner).  The free interior
-// (columns 1..nx-2, rows 0..nz-2) is cut into 64-column segments and, per
-// segment, into row bands, so that 16 waves share the work; a wave streams
-// down its band keeping rows k-1, k, k+1 as in the one-node kernels, with
-// the row index wave-uniform.  Nothing inside a step waits on device
-// memory: the forcing window weights and, for depth-only media, the
-// coefficient table (nz rows of kCoefStride floats) are staged in LDS after
-// the fields, the edge nodes' coefficients are held in registers, the
-// receiver map is read once and the series value one step ahead.
-// Absorbing edge nodes follow in the same phase: their relation reads only
-// u^m and the node's own u^{m-1}.  The per-node arithmetic is that of the
-// one-node kernels (layered_update, nodal_node_at, ce_edge_node_at), so
-// the fields are bitwise those of every variant.
+// read at the old level and written only by its owner).
+//
+// Work split: the W = nx-2 free columns times the nz-1 free rows are cut
+// into nb = floor(1024 / W) row bands, and thread t takes column t mod W of
+// band t div W (threads past nb W rest; a grid wider than 1024 columns takes
+// several passes of one band).  Lanes are thus packed across band
+// boundaries instead of rounding each band up to whole waves: 99 columns
+// leave 34 of 1024 lanes idle rather than 29 of every 128.  A thread
+// streams down its band keeping rows k-1, k, k+1 as in the one-node
+// kernels.  Nothing inside a step waits on device memory: the forcing
+// window weights and, for depth-only media, the coefficient table (nz rows
+// of kCoefStride floats, read per lane) are staged in LDS after the
+// fields, the edge nodes' coefficients are held in registers, the receiver
+// map is read once and the series value one step ahead.  Absorbing edge
+// nodes follow in the same phase: their relation reads only u^m and the
+// node's own u^{m-1}.  The per-node arithmetic is that of the one-node
+// kernels (layered_update, nodal_node_at, ce_edge_update), so the fields
+// are bitwise those of every variant.
 constexpr int kResWaves = 16;
-constexpr int kResEdgePerThread = kResidentMaxEdge / (64 * kResWaves);
+constexpr int kResThreads = 64 * kResWaves;
+constexpr int kResEdgePerThread = kResidentMaxEdge / kResThreads;
 
 template <int KIND>
-__global__ void __launch_bounds__(64 * kResWaves)
+__global__ void __launch_bounds__(kResThreads)
 stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
                  int ntiles) {
     extern __shared__ float2 res_lds[];
@@ -40,21 +46,19 @@ stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ t
     const bool absorbing = __builtin_amdgcn_readfirstlane(te.y) != 0;
     const int nx = d->nx, nz = d->nz, nsteps = d->nsteps;
     const int plane = nx * nz;
-    for (int j = threadIdx.x; j < 2 * plane; j += 64 * kResWaves)
+    for (int j = threadIdx.x; j < 2 * plane; j += kResThreads)
         res_lds[j] = make_float2(0.f, 0.f);
     float* const srcw_lds = (float*)(res_lds + 2 * plane);     // 2 kSrcW^2 floats
     float* const coef_lds = srcw_lds + kResSrcwFloats;         // depth-only media
-    for (int j = threadIdx.x; j < 2 * kSrcW * kSrcW; j += 64 * kResWaves)
+    for (int j = threadIdx.x; j < 2 * kSrcW * kSrcW; j += kResThreads)
         srcw_lds[j] = ld1(d->srcw, j);
     if constexpr (KIND == EIG_MEDIUM_LAYERED)
-        for (int j = threadIdx.x; j < nz * kCoefStride; j += 64 * kResWaves)
+        for (int j = threadIdx.x; j < nz * kCoefStride; j += kResThreads)
             coef_lds[j] = ld1(d->coef, j);
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nseg = (nx - 2 + 63) >> 6;
-    const int nband = max(1, kResWaves / nseg);
-    const int nitem = nseg * nband;
-    const int nrow = nz - 1;  // free rows 0..nz-2
+    const int W = nx - 2;           // free columns 1..nx-2
+    const int nrow = nz - 1;        // free rows 0..nz-2
+    const int nb = max(1, kResThreads / W);
+    const int npair = nb * W;       // (band, column) pairs
     const int nedge = 2 * nz + nx - 2;
     const int si0 = d->src_i0, sk0 = d->src_k0;
     const float* srcs = d->srcs;
@@ -69,20 +73,16 @@ stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ t
     CeCoef ecoef[kResEdgePerThread];
 #pragma unroll
     for (int q = 0; q < kResEdgePerThread; ++q) {
-        const int e = threadIdx.x + q * 64 * kResWaves;
+        const int e = threadIdx.x + q * kResThreads;
         ecoef[q] = CeCoef{0.f, 0.f, 0.f};
         if (absorbing && e < nedge) {
             const int2 ik = ce_edge_pos(nx, nz, e);
             ecoef[q] = ce_coef(*d, ik.x, ik.y);
         }
     }
-    // receiver of the surface column of this wave's first item
+    // receiver of the thread's surface node on its first pass
     int rec_first = -1;
-    if (wave < nitem) {
-        const int seg = wave % nseg, band = wave / nseg;
-        const int i = 1 + 64 * seg + lane;
-        if (band * nrow / nband == 0) rec_first = ldi(d->recmap, i <= nx - 2 ? i : nx - 2);
-    }
+    if ((int)threadIdx.x < min(npair, W)) rec_first = ldi(d->recmap, (int)threadIdx.x + 1);
     __syncthreads();
     float sval_next = nsteps > 0 ? ld1(srcs, 0) : 0.f;
     for (int m = 0; m < nsteps; ++m) {
@@ -90,37 +90,33 @@ stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ t
         float2* P = res_lds + ((m & 1) ? 0 : plane);        // u^{m-1} -> u^{m+1}
         const float sval = sval_next;
         if (m + 1 < nsteps) sval_next = ld1(srcs, m + 1);
-        for (int it = wave; it < nitem; it += kResWaves) {
-            const int seg = it % nseg, band = it / nseg;
-            const int kb = band * nrow / nband, ke = (band + 1) * nrow / nband;
-            const int i = 1 + 64 * seg + lane;
-            const bool upd = i <= nx - 2;
-            const int ic = upd ? i : nx - 2;  // lanes past the interior read a real column
-            const int di = ic - si0;
+        for (int v = threadIdx.x; v < npair; v += kResThreads) {
+            const int b = v / W;
+            const int i = v - b * W + 1;
+            const int kb = b * nrow / nb, ke = (b + 1) * nrow / nb;
+            const int di = i - si0;
             const bool src_lane = di >= 0 && di < kSrcW;
             int rec = -1;
-            if (kb == 0) rec = it == wave ? rec_first : ldi(d->recmap, ic);
+            if (kb == 0) rec = v == (int)threadIdx.x ? rec_first : ldi(d->recmap, i);
             if constexpr (KIND == EIG_MEDIUM_LAYERED) {
                 auto row = [&](int k) {
-                    const float2* r = Q + k * nx + ic;
+                    const float2* r = Q + k * nx + i;
                     const float2 l = r[-1], c = r[0], rr = r[1];
                     return node_row(c.x, c.y, l.x, l.y, rr.x, rr.y);
                 };
                 // rows of the source window and the surface row take the
-                // forcing and receiver paths (wave-uniform branches); the
-                // other rows are the plain update.  Lanes past the interior
-                // compute column nx-2 from the same operands as its owner
-                // and store the same value, so the LDS store needs no mask.
+                // forcing and receiver paths; the other rows are the plain
+                // update
                 auto update = [&](int k, const NodeRow& rm, const NodeRow& rc,
                                   const NodeRow& rn) {
                     LayerCoef cf;
 #pragma unroll
                     for (int j = 0; j <= kFco; ++j) cf.c[j] = coef_lds[k * kCoefStride + j];
-                    const float2 up = P[k * nx + ic];
+                    const float2 up = P[k * nx + i];
                     const int dk = k - sk0;
                     if (k != 0 && (unsigned)dk >= (unsigned)kSrcW) {
-                        P[k * nx + ic] = layered_update(cf, rm, rc, rn, up.x, up.y, false, 0.f,
-                                                        0.f, 0.f);
+                        P[k * nx + i] = layered_update(cf, rm, rc, rn, up.x, up.y, false, 0.f,
+                                                       0.f, 0.f);
                         return;
                     }
                     const bool in_win = src_lane && dk >= 0 && dk < kSrcW;
@@ -138,12 +134,10 @@ stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ t
                         wv = rf.y;
                     }
                     const float2 nw = layered_update(cf, rm, rc, rn, up.x, up.y, src, fsv, wu, wv);
-                    P[k * nx + ic] = nw;
-                    if (upd) {
-                        if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
-                        if (wrec && in_win)
-                            st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
-                    }
+                    P[k * nx + i] = nw;
+                    if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
+                    if (wrec && in_win)
+                        st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
                 };
                 NodeRow r0 = NodeRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 if (kb > 0) r0 = row(kb - 1);
@@ -186,21 +180,19 @@ stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ t
                         w0 = srcw_lds[(0 * kSrcW + dk) * kSrcW + di];
                         w1 = srcw_lds[(1 * kSrcW + dk) * kSrcW + di];
                     }
-                    const float2 nw = nodal_node_at(U, P[k * nx + ic], LAM, MU, SC, cpitch, ic,
-                                                    k, inj, h2, sval, w0, w1);
-                    if (upd) {
-                        P[k * nx + i] = nw;
-                        if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
-                        if (wrec && in_win)
-                            st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
-                    }
+                    const float2 nw = nodal_node_at(U, P[k * nx + i], LAM, MU, SC, cpitch, i, k,
+                                                    inj, h2, sval, w0, w1);
+                    P[k * nx + i] = nw;
+                    if (k == 0 && rec >= 0) st2(traces, (size_t)(m + 1) * nrec + rec, nw);
+                    if (wrec && in_win)
+                        st2(wrec, (size_t)m * (kSrcW * kSrcW) + dk * kSrcW + di, nw);
                 }
             }
         }
         if (absorbing) {
 #pragma unroll
             for (int q = 0; q < kResEdgePerThread; ++q) {
-                const int e = threadIdx.x + q * 64 * kResWaves;
+                const int e = threadIdx.x + q * kResThreads;
                 if (e < nedge) ce_edge_update(*d, Q, P, nx, e, ecoef[q]);
             }
         }
@@ -221,10 +213,10 @@ void launch_resident(const SolveDesc* descs, const int2* tiles, int ntiles, int 
                               (int)kResidentLdsBytes);
     (void)hipGetLastError();
     if (kind == EIG_MEDIUM_NODAL)
-        stencil_resident<EIG_MEDIUM_NODAL><<<ntiles, 64 * kResWaves, lds_bytes, s>>>(
+        stencil_resident<EIG_MEDIUM_NODAL><<<ntiles, kResThreads, lds_bytes, s>>>(
             descs, tiles, ntiles);
     else
-        stencil_resident<EIG_MEDIUM_LAYERED><<<ntiles, 64 * kResWaves, lds_bytes, s>>>(
+        stencil_resident<EIG_MEDIUM_LAYERED><<<ntiles, kResThreads, lds_bytes, s>>>(
             descs, tiles, ntiles);
 }
 
