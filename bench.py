@@ -28,7 +28,42 @@ METRIC = ("EIG evals/s and grid-pt updates/s (HBM GB/s % peak) at ≤1e-3 nat er
           "p50/p99")
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_FLOPS = 78.6e12   # published dense FP64 matrix rate
+FP32_VECTOR_PEAK_FLOPS = 157.3e12  # published FP32 vector rate (packed FMA)
+# vector issue: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz (a wave64
+# instruction occupies a SIMD for 4 clocks), in lane-instructions per second
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
+# FP32 operations of one depth-only grid-point update: the row sums and
+# differences (4), 15 per component for the operator, 3 per component for
+# the leapfrog combination
+LAYERED_FLOPS_PER_UPDATE = 40
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_layered_c2_traffic.json")
+NODAL_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_nodal_c5_traffic.json")
+RESIDENT_RECORD = os.path.join(ROOT, "profiles", "stencil_resident_model_problem.json")
+CSRC = os.path.join(ROOT, "paper_1502_07873_amd", "csrc")
+
+
+def _sources_sha(*names):
+    """sha256 over the named kernel sources, in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        h.update(open(os.path.join(CSRC, n), "rb").read())
+    return h.hexdigest()
+
+
+def _counter_record(path, sources, **want):
+    """A committed rocprofv3 counter record, only if it was taken on these
+    kernel sources and matches every `want` field."""
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != _sources_sha(*sources):
+        return None
+    for k, v in want.items():
+        if rec.get(k) != v:
+            return None
+    return rec
 
 
 def _measured_traffic(solves_per_launch, wave_cache_bytes, variant):
@@ -404,6 +439,7 @@ def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40, pipeline=Tru
         t = time.perf_counter() - t0
         st = ctx.stencil_stats(reset=True)
         variant = ctx.get_option("last_variant")
+        coef_interleave = ctx.get_option("coef_interleave")
         Hr = r["H1"].cpu().numpy()
     upd = 15 * full_nodes * wl.grid.nx * wl.grid.nz * wl.grid.nsteps
     pts = wl.grid.nx * wl.grid.nz
@@ -413,12 +449,29 @@ def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40, pipeline=Tru
           "candidates": len(wl.receivers), "seconds": t, "variant_last": variant,
           "grid_pt_updates_per_s": upd / t, "sample_eig_evals_per_s": full_nodes / t,
           "projected_full_query_minutes": len(w) * t / full_nodes / 60}
-    fs.update(_leg_roofline(st, "36 B per grid-point update (24 B of fields + 12 B of nodal "
-                                "lambda, mu, dt^2/(rho h^2)); the coefficients are shared by "
-                                "all solves of a launch, so this overcounts them"))
-    fs["achieved_shared_coef_GBs"] = shared
-    fs["shared_coef_note"] = ("24 B per update + 12 B per grid point per launch (the "
-                              f"{15 * full_nodes} solves of a launch share one medium)")
+    leg = _leg_roofline(st, "")
+    avg_ms = leg["avg_launch_ms"]
+    solves_per_launch = round(st["updates"] / max(st["launches"], 1) / (pts * 2))
+    rec = _counter_record(NODAL_TRAFFIC_RECORD, ("stencil.hip", "node_update.h"),
+                          variant=variant, solves_per_launch=solves_per_launch,
+                          coef_interleave=coef_interleave)
+    traffic = rec["traffic_bytes_per_launch"] if rec else None
+    trate = traffic / (avg_ms * 1e-3) / 1e9 if traffic else None
+    copy_gbs = _copy_rate()
+    leg["roofline"] = {
+        "bound": "hbm", "achieved": shared, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": shared / HBM_PEAK_GBS, "traffic": traffic, "traffic_rate_GBs": trate,
+        "copy_GBs_measured": copy_gbs,
+        "frac_of_copy": trate / copy_gbs if trate else None,
+        "achieved_36B_per_update_GBs": 36.0 * st["updates"] / (max(st["ms"], 1e-9) * 1e-3) / 1e9,
+        "note": "achieved: 24 B of fields per grid-point update plus the medium's 12 B of "
+                "nodal lambda, mu, dt^2/(rho h^2) per grid point once per launch (the "
+                f"{solves_per_launch} solves of a launch share one medium); the 36 B-per-"
+                "update unit (achieved_36B_per_update_GBs) counts those coefficients once "
+                "per solve and so overstates the bytes.  traffic: bytes per launch past L2 "
+                "(FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the counter record; "
+                "frac_of_copy: that rate over a plain 4 GiB copy measured here"}
+    fs.update(leg)
     if gold is not None:
         from oracle import laplace
         H = Hr[0].sum(axis=0)
@@ -463,6 +516,114 @@ def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40, pipeline=Tru
                                "slope_d_eig_d_log_k": slope,
                                "note": "Laplace EIG grows ~ (N_theta/2) log k for large "
                                        "k when H1 grows in proportion to receiver count"}
+    return out
+
+
+def _bench_model(nmc=10000, ncheck=2):
+    """The paper's model problem (Section 4.1, absorbing edges, 91 candidate
+    receivers): per-receiver H_1 for nmc Monte Carlo samples by central
+    differences (15 solves each) and by forward sensitivities (8 solves),
+    every Section 4.5 scenario design's EIG from them, and the oracle's
+    per-receiver H_1 and D_KL on ncheck samples.  The 101 x 76 grid fits one
+    workgroup's LDS, so each solve runs resident (fields never in HBM): the
+    roofline is the FP32 vector rate."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from oracle import laplace
+    from oracle import pipeline as opipe
+    from paper_1502_07873_amd import Context, make_prior
+    from paper_1502_07873_amd.query import device_medium, grid_tuple
+    wl = synthetic.loh_workload(nmc)
+    g = grid_tuple(wl.grid)
+    R = len(wl.receivers)
+    pos = {int(ix): c for c, ix in enumerate(wl.receivers)}
+    designs = [(scen, lab, idx) for scen, ds in synthetic.loh_scenarios().items()
+               for lab, idx in ds]
+    masks = np.zeros((len(designs), R), dtype=np.uint8)
+    for q, (_, _, idx) in enumerate(designs):
+        masks[q, [pos[int(i)] for i in idx]] = 1
+    prior = make_prior(wl.lo, wl.hi)
+    out = {"grid": [wl.grid.nx, wl.grid.nz, wl.grid.nsteps],
+           "edges": "absorbing (first-order Clayton-Engquist)", "samples": nmc,
+           "candidates": R, "designs": len(designs)}
+    with Context(0, 64 << 30) as ctx:
+        med = device_medium(wl.medium.kind, wl.medium.rho, wl.medium.lam, wl.medium.mu)
+        dmask = torch.as_tensor(masks, device="cuda")
+        H = torch.empty((nmc, R, 7, 7), dtype=torch.float64, device="cuda")
+        st_ = torch.empty(nmc, dtype=torch.int32, device="cuda")
+        e = torch.empty(len(designs), dtype=torch.float64, device="cuda")
+        for jac in ("fd", "sensitivity"):
+            fn = ctx.jacobian_fd if jac == "fd" else ctx.jacobian_sensitivity
+            fn([g] * 64, [med] * 64, wl.theta[:64], [wl.receivers] * 64, wl.sigma, H[:64],
+               stf="gauss", per_receiver=True, status=st_[:64])
+            torch.cuda.synchronize()
+            ctx.stencil_stats(reset=True)
+            t0 = time.perf_counter()
+            fn([g] * nmc, [med] * nmc, wl.theta, [wl.receivers] * nmc, wl.sigma, H,
+               stf="gauss", per_receiver=True, status=st_)
+            ctx.design_eval(H, dmask, prior, wl.weights, e, theta=wl.theta)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            st = ctx.stencil_stats(reset=True)
+            variant = ctx.get_option("last_variant")
+            nsol = 15 if jac == "fd" else 8
+            upd_s = st["updates"] / (max(st["ms"], 1e-9) * 1e-3)
+            r = {"seconds": t, "sample_eig_evals_per_s": nmc / t, "solves": nsol * nmc,
+                 "grid_pt_updates_per_s": nsol * nmc * wl.grid.nx * wl.grid.nz *
+                 wl.grid.nsteps / t,
+                 "grid_pt_updates_per_s_stencil": upd_s, "stencil_ms": st["ms"],
+                 "launches": st["launches"], "variant": variant,
+                 "flagged_samples": int(st_.ne(0).sum())}
+            ev = e.cpu().numpy()
+            qb = int(np.argmax(ev))
+            r["best_design"] = {"scenario": designs[qb][0], "design": designs[qb][1],
+                                "eig_nats": float(ev[qb])}
+            if jac == "fd":
+                rec = _counter_record(RESIDENT_RECORD, ("resident.hip", "node_update.h", "ce.h"),
+                                      variant=variant)
+                issue = (upd_s * rec["valu_lane_instr_per_update"] / VALU_ISSUE_PEAK
+                         if rec else None)
+                r["roofline"] = {
+                    "bound": "alu", "achieved": upd_s * LAYERED_FLOPS_PER_UPDATE / 1e12,
+                    "peak": FP32_VECTOR_PEAK_FLOPS / 1e12, "unit": "TFLOP/s",
+                    "frac": upd_s * LAYERED_FLOPS_PER_UPDATE / FP32_VECTOR_PEAK_FLOPS,
+                    "traffic": (rec["traffic_bytes_per_update"] * st["updates"] /
+                                max(st["launches"], 1)) if rec else None,
+                    "valu_issue_frac": issue,
+                    "valu_lane_instr_per_update":
+                        rec["valu_lane_instr_per_update"] if rec else None,
+                    "update_equivalent_GBs_24B": upd_s * 24 / 1e9,
+                    "note": f"{LAYERED_FLOPS_PER_UPDATE} FP32 operations per grid-point "
+                            "update over the kernel time, against the published 157.3 "
+                            "TFLOP/s (packed FP32 FMA, which this build does not emit: "
+                            "adds and multiplies each take a full issue slot); "
+                            "valu_issue_frac: vector lane-instructions per update "
+                            "(SQ_INSTS_VALU x 64 from the counter record) times the "
+                            "update rate over the 3.93e13/s issue limit.  The fields stay "
+                            "in LDS: traffic is the whole launch's bytes past L2"}
+            out[jac] = r
+        # oracle on ncheck samples
+        idx = [0, nmc // 2][:ncheck]
+        Hc = torch.empty((len(idx), R, 7, 7), dtype=torch.float64, device="cuda")
+        ctx.jacobian_fd([g] * len(idx), [med] * len(idx), wl.theta[idx], [wl.receivers] * len(idx),
+           wl.sigma, Hc, stf="gauss", per_receiver=True)
+        torch.cuda.synchronize()
+        Hg = Hc.cpu().numpy()
+    ref = opipe.query(wl, theta=wl.theta[idx], weights=np.full(len(idx), 1 / len(idx)),
+                      per_receiver=True)
+    Hr = ref["H1"]
+    d = np.sqrt(np.abs(np.einsum("srii->sri", Hr)))
+    pr = laplace.uniform_prior(wl.lo, wl.hi)
+    dk = np.array([laplace.dkl_hat(Hg[s].sum(axis=0), wl.theta[idx][s], pr)[0]
+                   for s in range(len(idx))])
+    out["errors"] = {
+        "samples": idx,
+        "per_receiver_scaled_hessian_max_abs": float(np.max(
+            np.abs(Hg - Hr) / (d[..., :, None] * d[..., None, :] + 1e-300))),
+        "dkl_all_receivers_abs": float(np.max(np.abs(dk - ref["dkl"]))),
+        "reference": "oracle (oracle/pipeline.py) on the same samples"}
     return out
 
 
@@ -767,9 +928,11 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed query: no other leg (for counter runs)")
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "c5", "loh2d", "nested", "estimators", "serving"],
+                    choices=["c2", "c3", "c5", "model", "loh2d", "nested", "estimators",
+                             "serving"],
                     help="c2: the headline query and every leg (default); c3/c5: those legs "
-                         "alone; loh2d: the paper's model problem and scenarios; serving: "
+                         "alone; model: the model-problem leg alone; loh2d: the paper's "
+                         "model problem with sparse quadrature and scenarios; serving: "
                          "the serving streams with both disciplines")
     ap.add_argument("--serving-rate", type=float, default=3.2e11,
                     help="grid-point updates/s that sets the arrival rate of --workload "
@@ -798,9 +961,13 @@ def main():
     from paper_1502_07873_amd import Context
     from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
 
-    if args.workload in ("c3", "c5"):
-        res = (_bench_c3(args.samples if args.samples != 256 else 4096)
-               if args.workload == "c3" else _bench_c5(pipeline=not args.c5_full_only))
+    if args.workload in ("c3", "c5", "model"):
+        if args.workload == "c3":
+            res = _bench_c3(args.samples if args.samples != 256 else 4096)
+        elif args.workload == "c5":
+            res = _bench_c5(pipeline=not args.c5_full_only)
+        else:
+            res = _bench_model(args.samples if args.samples != 256 else 10000)
         print(json.dumps({"workload": args.workload, **res}), flush=True)
         return
     if args.workload != "c2":
@@ -1042,6 +1209,8 @@ def main():
         print("[bench] c5: full-size sparse-grid nodes and the reduced design pipeline",
               flush=True)
         line["c5"] = _bench_c5()
+    print("[bench] the paper's model problem (absorbing edges, resident solves)", flush=True)
+    line["model_problem"] = _bench_model()
     if not args.no_c3:
         print("[bench] c3: the 61440-solve uneven batch", flush=True)
         line["c3"] = _bench_c3()

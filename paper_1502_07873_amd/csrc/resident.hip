@@ -80,9 +80,13 @@ stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ t
             ecoef[q] = ce_coef(*d, ik.x, ik.y);
         }
     }
-    // receiver of the thread's surface node on its first pass
+    // the thread's (band, column) pair of its first pass and its receiver,
+    // fixed over the time loop
+    const int b_first = (int)threadIdx.x / W;
+    const int i_first = (int)threadIdx.x - b_first * W + 1;
+    const int kb_first = b_first * nrow / nb, ke_first = (b_first + 1) * nrow / nb;
     int rec_first = -1;
-    if ((int)threadIdx.x < min(npair, W)) rec_first = ldi(d->recmap, (int)threadIdx.x + 1);
+    if ((int)threadIdx.x < min(npair, W)) rec_first = ldi(d->recmap, i_first);
     __syncthreads();
     float sval_next = nsteps > 0 ? ld1(srcs, 0) : 0.f;
     for (int m = 0; m < nsteps; ++m) {
@@ -91,13 +95,18 @@ stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ t
         const float sval = sval_next;
         if (m + 1 < nsteps) sval_next = ld1(srcs, m + 1);
         for (int v = threadIdx.x; v < npair; v += kResThreads) {
-            const int b = v / W;
-            const int i = v - b * W + 1;
-            const int kb = b * nrow / nb, ke = (b + 1) * nrow / nb;
+            const bool first = v == (int)threadIdx.x;
+            int i = i_first, kb = kb_first, ke = ke_first;
+            if (!first) {  // grids wider than one pass
+                const int b = v / W;
+                i = v - b * W + 1;
+                kb = b * nrow / nb;
+                ke = (b + 1) * nrow / nb;
+            }
             const int di = i - si0;
             const bool src_lane = di >= 0 && di < kSrcW;
             int rec = -1;
-            if (kb == 0) rec = v == (int)threadIdx.x ? rec_first : ldi(d->recmap, i);
+            if (kb == 0) rec = first ? rec_first : ldi(d->recmap, i);
             if constexpr (KIND == EIG_MEDIUM_LAYERED) {
                 auto row = [&](int k) {
                     const float2* r = Q + k * nx + i;
