@@ -40,6 +40,10 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_layered_c2_traffic.json
 NODAL_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "stencil_nodal_c5_traffic.json")
 RESIDENT_RECORD = os.path.join(ROOT, "profiles", "stencil_resident_model_problem.json")
 CSRC = os.path.join(ROOT, "paper_1502_07873_amd", "csrc")
+# the kernel sources each counter record was taken on
+LAYERED_SOURCES = ("stencil.hip", "node_update.h", "tile.h")
+NODAL_SOURCES = ("nodal.hip", "node_update.h", "tile.h")
+RESIDENT_SOURCES = ("resident.hip", "node_update.h", "ce.h")
 
 
 def _sources_sha(*names):
@@ -69,20 +73,10 @@ def _counter_record(path, sources, **want):
 def _measured_traffic(solves_per_launch, wave_cache_bytes, variant):
     """Bytes per stencil launch past the L2 caches (served by the last-level
     cache or HBM) from the committed rocprofv3 counter record, only if it was
-    taken on this exact kernel source, workload and wave size."""
-    import hashlib
-    try:
-        rec = json.load(open(TRAFFIC_RECORD))
-    except (OSError, ValueError):
-        return None
-    src = os.path.join(ROOT, "paper_1502_07873_amd", "csrc", "stencil.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if (sha != rec.get("kernel_source_sha256")
-            or rec.get("solves_per_launch") != solves_per_launch
-            or rec.get("variant") != variant
-            or rec.get("wave_cache_bytes") != wave_cache_bytes):
-        return None
-    return rec["traffic_bytes_per_launch"]
+    taken on these kernel sources, workload and wave size."""
+    rec = _counter_record(TRAFFIC_RECORD, LAYERED_SOURCES, solves_per_launch=solves_per_launch,
+                          variant=variant, wave_cache_bytes=wave_cache_bytes)
+    return rec["traffic_bytes_per_launch"] if rec else None
 
 
 CPU_SHARE = 16   # host cores a one-GPU box grants a process
@@ -452,7 +446,7 @@ def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40, pipeline=Tru
     leg = _leg_roofline(st, "")
     avg_ms = leg["avg_launch_ms"]
     solves_per_launch = round(st["updates"] / max(st["launches"], 1) / (pts * 2))
-    rec = _counter_record(NODAL_TRAFFIC_RECORD, ("stencil.hip", "node_update.h"),
+    rec = _counter_record(NODAL_TRAFFIC_RECORD, NODAL_SOURCES,
                           variant=variant, solves_per_launch=solves_per_launch,
                           coef_interleave=coef_interleave)
     traffic = rec["traffic_bytes_per_launch"] if rec else None
@@ -581,8 +575,7 @@ def _bench_model(nmc=10000, ncheck=2):
             r["best_design"] = {"scenario": designs[qb][0], "design": designs[qb][1],
                                 "eig_nats": float(ev[qb])}
             if jac == "fd":
-                rec = _counter_record(RESIDENT_RECORD, ("resident.hip", "node_update.h", "ce.h"),
-                                      variant=variant)
+                rec = _counter_record(RESIDENT_RECORD, RESIDENT_SOURCES, variant=variant)
                 issue = (upd_s * rec["valu_lane_instr_per_update"] / VALU_ISSUE_PEAK
                          if rec else None)
                 r["roofline"] = {

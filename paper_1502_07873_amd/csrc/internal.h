@@ -159,6 +159,9 @@ extern const StencilVariant kVariants[kNumVariants];
 // tiles: (solve index, strip << 16 | chunk) per wavefront
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                     int variant, hipStream_t s);
+// Nodal-media variants (6, 17..20) of launch_stencil.
+void launch_nodal_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
+                          int variant, hipStream_t s);
 void launch_zero_level0(const SolveDesc* descs, int n, hipStream_t s);
 // Resident solves: both field levels of a solve in one workgroup's LDS
 // (2 nx nz float2, the forcing window weights and for depth-only media the

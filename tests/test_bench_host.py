@@ -28,8 +28,7 @@ def test_more_than_one_gpu_is_refused_with_a_reason():
 
 def test_traffic_reported_only_for_the_recorded_kernel_and_launch(tmp_path):
     bench = _bench_module()
-    src = os.path.join(ROOT, "paper_1502_07873_amd", "csrc", "stencil.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = bench._sources_sha(*bench.LAYERED_SOURCES)
     rec = {"kernel_source_sha256": sha, "solves_per_launch": 24, "variant": 9,
            "wave_cache_bytes": 192 << 20, "traffic_bytes_per_launch": 1.5e8}
     path = tmp_path / "traffic.json"
@@ -46,12 +45,18 @@ def test_traffic_reported_only_for_the_recorded_kernel_and_launch(tmp_path):
     assert bench._measured_traffic(24, 192 << 20, 9) is None
 
 
-def test_committed_traffic_record_matches_the_kernel_source():
-    # the record under profiles/ must describe the stencil source as it is
-    rec = json.load(open(os.path.join(ROOT, "profiles", "stencil_layered_c2_traffic.json")))
-    src = os.path.join(ROOT, "paper_1502_07873_amd", "csrc", "stencil.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec["kernel_source_sha256"] != sha:
-        pytest.xfail("stencil.hip changed since the counters were taken: bench reports "
-                     "traffic null until they are taken again")
-    assert rec["traffic_bytes_per_launch"] >= rec["kernel_floor_bytes_per_launch_16B_per_update"]
+@pytest.mark.parametrize("record,sources", [("stencil_layered_c2_traffic.json", "LAYERED_SOURCES"),
+                                            ("stencil_nodal_c5_traffic.json", "NODAL_SOURCES"),
+                                            ("stencil_resident_model_problem.json",
+                                             "RESIDENT_SOURCES")])
+def test_committed_counter_records_match_the_kernel_sources(record, sources):
+    # each record under profiles/ must describe its kernel's sources as they
+    # are (else the bench reports its traffic as null)
+    bench = _bench_module()
+    rec = json.load(open(os.path.join(ROOT, "profiles", record)))
+    if rec["kernel_source_sha256"] != bench._sources_sha(*getattr(bench, sources)):
+        pytest.xfail(f"{sources} changed since the counters of {record} were taken: bench "
+                     "reports their figures as null until they are taken again")
+    traffic = rec.get("traffic_bytes_per_launch", rec.get("traffic_bytes_per_update"))
+    assert traffic > 0
+    assert traffic >= rec.get("kernel_floor_bytes_per_launch", 0)
