@@ -397,7 +397,8 @@ def _bench_c3(nsample=4096, oracle_check=True):
     return out
 
 
-def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40, pipeline=True):
+def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40, pipeline=True,
+              coef_interleave=None):
     """Sparse quadrature + greedy design: (a) the full 2048x1024x4000 nodal
     problem on `full_nodes` sparse-grid nodes, the first being the centre
     node whose oracle values are stored with the tests (throughput, roofline,
@@ -421,6 +422,8 @@ def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40, pipeline=Tru
     gold = np.load(gold_path) if os.path.exists(gold_path) else None
     sigma = float(gold["sigma"]) if gold is not None else 1.0
     with Context(0, 64 << 30) as ctx:
+        if coef_interleave:
+            ctx.set_option("coef_interleave", coef_interleave)
         # warm: tune and grow the workspace on one node
         run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, nodes[order[:1]], [1.0],
                   sigma=sigma, per_receiver=True)
@@ -935,6 +938,9 @@ def main():
                          "1.2e13 updates)")
     ap.add_argument("--wave-cache-mib", type=int, default=192,
                     help="live field MiB per wave chunk (0: whole waves through HBM)")
+    ap.add_argument("--coef-interleave", type=int, default=None,
+                    help="c5 leg: solves of one nodal medium whose tiles run interleaved "
+                         "by position (library default 8; 1: solve-major)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
     args = ap.parse_args()
@@ -958,7 +964,8 @@ def main():
         if args.workload == "c3":
             res = _bench_c3(args.samples if args.samples != 256 else 4096)
         elif args.workload == "c5":
-            res = _bench_c5(pipeline=not args.c5_full_only)
+            res = _bench_c5(pipeline=not args.c5_full_only,
+                            coef_interleave=args.coef_interleave)
         else:
             res = _bench_model(args.samples if args.samples != 256 else 10000)
         print(json.dumps({"workload": args.workload, **res}), flush=True)
