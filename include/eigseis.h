@@ -155,7 +155,19 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
 /* Context options (take effect for later calls):
  *   "stencil_variant"  -1: choose automatically (default), else force one of
  *                      the stencil kernel variants (all give bitwise-identical
- *                      fields; they differ in tile shape and speed)
+ *                      fields; they differ in tile shape and speed).  Forcing
+ *                      a tiled variant also turns the resident kernels off;
+ *                      forcing 21 or 22 leaves the choice among tiled kernels
+ *                      automatic for grids that do not fit LDS
+ *   "resident"         1 (default): a solve whose two field levels (16 nx nz
+ *                      bytes), forcing window (512 B) and, for depth-only
+ *                      media, coefficient table (64 nz bytes) fit the 160 KiB
+ *                      of LDS one workgroup may hold, and whose edge nodes
+ *                      number at most 3072, runs resident: one workgroup per
+ *                      solve takes every time step in one launch (variants 21
+ *                      depth-only, 22 nodal), with no field buffers in device
+ *                      memory; 0: tiled kernels for every grid.  Results do
+ *                      not depend on it
  *   "autotune"         1 (default): time the variants on the first steps of a
  *                      new grid class and keep the fastest; 0: use
  *                      "default_variant"
