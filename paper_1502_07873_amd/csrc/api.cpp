@@ -1030,21 +1030,28 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
         size_t need = 0;
         WaveSizer wsz(grids, media, recsets);
         size_t extra = 4 * kAlign;
+        size_t rstride = 0;  // per-receiver partials: doubles per sample (largest)
         while (s1 < nsample) {
             SolveSpec sp{};
             sp.grid = s1;
             sp.medium = med_of[s1];
             sp.recset = rec_of[s1];
             const size_t one = wsz.cost(sp);
+            const size_t rs = per_receiver
+                                  ? std::max(rstride, receiver_work_doubles(grid[s1].nsteps + 1,
+                                                                            rec[s1].n))
+                                  : 0;
+            const size_t rwork = (size_t)(s1 - s0 + 1) * rs * sizeof(double);
             // one alignment pad each before sigma given, sigma, the partials
             // and the solve region
             const size_t more = per * one + sample_trace_bytes(s1) + sizeof(SampleDesc) +
                                 4 * kAlign + 2 * sizeof(double) + sample_work_bytes(1);
-            if (s1 > s0 && wsz.bytes + extra + more > c->budget) break;
+            if (s1 > s0 && wsz.bytes + extra + more + rwork > c->budget) break;
             for (int q = 0; q < per; ++q) wsz.add(sp);
             extra += sample_trace_bytes(s1) + sizeof(SampleDesc) + 4 * kAlign + 2 * sizeof(double) +
                      sample_work_bytes(1);
-            need = wsz.bytes + extra;
+            rstride = rs;
+            need = wsz.bytes + extra + rwork;
             ++s1;
         }
         int rc = ensure_ws(c, need);
@@ -1060,7 +1067,8 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
         const size_t o_sd = cv.take(ns * sizeof(SampleDesc));
         const size_t o_given = cv.take(ns * sizeof(double));
         const size_t o_sig = cv.take(ns * sizeof(double));
-        const size_t o_work = cv.take(sample_work_bytes(ns));
+        const size_t o_work =
+            cv.take(std::max(sample_work_bytes(ns), (size_t)ns * rstride * sizeof(double)));
         const size_t solve_base = align_up(cv.off);
         std::vector<SolveSpec> solves;
         std::vector<SampleDesc> sds(ns);
@@ -1132,7 +1140,7 @@ static int jacobian_core(eig_ctx* c, int32_t nsample, const eig_grid* grid,
         launch_sample_check(dsd, ns, (const double*)(c->ws + o_given), sigma_mode, dsig,
                             status ? status + s0 : nullptr, dwork, s);
         launch_hessian(dsd, ns, per_receiver ? 1 : 0, ngroup, dsig,
-                       H1 + (size_t)s0 * ngroup * kNT * kNT, dwork, s);
+                       H1 + (size_t)s0 * ngroup * kNT * kNT, dwork, s, rstride);
         HIP_TRY(hipGetLastError());
         s0 = s1;
     }

@@ -252,24 +252,37 @@ __global__ void hessian_finish_kernel(const SampleDesc* __restrict__ samples,
     H[b * kNT + a] = v;
 }
 
-// One H_1 per receiver (per_receiver = 1): one block per sample, each thread
-// owns receivers r = threadIdx.x, + blockDim.x, ... and sums that receiver's
-// levels in order, so consecutive threads read consecutive receivers of a
-// level (the traces are [level][receiver][2]) and no cross-thread reduction
-// is needed.  Same Jacobian columns, products and scaling as hessian_kernel.
-__global__ void __launch_bounds__(128)
-hessian_receiver_kernel(const SampleDesc* __restrict__ samples, int ngroup,
-                        const double* __restrict__ sigma, double* __restrict__ H1) {
+// Per-receiver H_1 (design evaluation needs one H_1 per candidate): a
+// sample's levels are cut into receiver_splits(nt) contiguous ranges of at
+// least kRecvLevelsMin levels, at most kRecvSplit of them, one block each;
+// in a block a thread owns receivers r = threadIdx.x, + blockDim.x, ... and
+// sums that receiver's levels of the range in order, so consecutive threads
+// read consecutive receivers of a level (the traces are
+// [level][receiver][2]).  The partial sums go to work as [range][entry]
+// [receiver] (coalesced) and the finishing kernel adds the ranges in order.
+// The cut depends on nt alone, so a sample's result does not depend on the
+// batch.  Same Jacobian columns, products and scaling as hessian_kernel.
+__device__ __forceinline__ int receiver_splits(int nt) {
+    return min(kRecvSplit, max(1, nt / kRecvLevelsMin));
+}
+
+__global__ void __launch_bounds__(256)
+hessian_receiver_kernel(const SampleDesc* __restrict__ samples, size_t stride,
+                        double* __restrict__ work) {
     const int s = blockIdx.x;
     const SampleDesc& sd = samples[s];
     const int nt = sd.nt, nrec = sd.nrec;
+    const int nb = receiver_splits(nt);
+    if ((int)blockIdx.y >= nb) return;
+    const int lo = (int)((long long)nt * blockIdx.y / nb);
+    const int hi = (int)((long long)nt * (blockIdx.y + 1) / nb);
     double inv2d[kNT];
     for (int j = 0; j < kNT; ++j) inv2d[j] = sd.inv2d[j];
-    const double sg = sigma[s];
+    double* w = work + (size_t)s * stride + (size_t)blockIdx.y * kTri * nrec;
     for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
         double acc[kTri];
         for (int t = 0; t < kTri; ++t) acc[t] = 0.0;
-        for (int q = 0; q < nt; ++q) {
+        for (int q = lo; q < hi; ++q) {
             const int e = q * nrec + r;
             double Jx[kNT], Jz[kNT];
             for (int j = 0; j < kNT; ++j) {
@@ -294,11 +307,28 @@ hessian_receiver_kernel(const SampleDesc* __restrict__ samples, int ngroup,
             for (int a = 0; a < kNT; ++a)
                 for (int b = a; b < kNT; ++b, ++t) acc[t] += Jx[a] * Jx[b] + Jz[a] * Jz[b];
         }
+        for (int t = 0; t < kTri; ++t) w[(size_t)t * nrec + r] = acc[t];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+hessian_receiver_finish_kernel(const SampleDesc* __restrict__ samples, int ngroup,
+                               const double* __restrict__ sigma, size_t stride,
+                               const double* __restrict__ work, double* __restrict__ H1) {
+    const int s = blockIdx.x;
+    const SampleDesc& sd = samples[s];
+    const int nrec = sd.nrec;
+    const int nb = receiver_splits(sd.nt);
+    const double sg = sigma[s];
+    const double* w = work + (size_t)s * stride;
+    for (int r = threadIdx.x; r < nrec; r += blockDim.x) {
         double* H = H1 + ((size_t)s * ngroup + r) * kNT * kNT;
         int t = 0;
         for (int a = 0; a < kNT; ++a)
             for (int b = a; b < kNT; ++b, ++t) {
-                const double v = acc[t] / (sg * sg);
+                double v = 0.0;
+                for (int k = 0; k < nb; ++k) v += w[((size_t)k * kTri + t) * nrec + r];
+                v = v / (sg * sg);
                 H[a * kNT + b] = v;
                 H[b * kNT + a] = v;
             }
@@ -339,10 +369,14 @@ void launch_sample_check(const SampleDesc* samples, int nsample, const double* g
 }
 
 void launch_hessian(const SampleDesc* samples, int nsample, int per_receiver,
-                    int ngroup, const double* sigma, double* H1, double* work, hipStream_t s) {
+                    int ngroup, const double* sigma, double* H1, double* work, hipStream_t s,
+                    size_t receiver_stride) {
     if (nsample <= 0) return;
     if (per_receiver) {
-        hessian_receiver_kernel<<<nsample, 128, 0, s>>>(samples, ngroup, sigma, H1);
+        hessian_receiver_kernel<<<dim3(nsample, kRecvSplit), 256, 0, s>>>(
+            samples, receiver_stride, work);
+        hessian_receiver_finish_kernel<<<nsample, 256, 0, s>>>(samples, ngroup, sigma,
+                                                               receiver_stride, work, H1);
         return;
     }
     hessian_kernel<<<dim3(nsample, kSampleSplit), 64 * kWavesPerBlock, 0, s>>>(samples, sigma,

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 
@@ -205,8 +206,18 @@ inline size_t sample_work_bytes(int nsample) {
 void launch_sample_check(const SampleDesc* samples, int nsample, const double* given,
                          int mode, double* sigma, int32_t* status, double* work,
                          hipStream_t s);
+// Per-receiver H_1 (per_receiver != 0): each sample's levels are cut into
+// at most kRecvSplit ranges of at least kRecvLevelsMin levels; work holds
+// receiver_stride doubles per sample (receiver_work_doubles of the largest).
+constexpr int kRecvSplit = 32;
+constexpr int kRecvLevelsMin = 125;
+inline size_t receiver_work_doubles(int nt, int nrec) {
+    const int nb = std::min(kRecvSplit, std::max(1, nt / kRecvLevelsMin));
+    return (size_t)nb * (kNT * (kNT + 1) / 2) * (size_t)nrec;
+}
 void launch_hessian(const SampleDesc* samples, int nsample, int per_receiver,
-                    int ngroup, const double* sigma, double* H1, double* work, hipStream_t s);
+                    int ngroup, const double* sigma, double* H1, double* work, hipStream_t s,
+                    size_t receiver_stride = 0);
 void launch_laplace(const double* H1, int nsample, const eig_prior* prior_dev,
                     const double* theta, const double* w, double* dkl,
                     double* logdet, int32_t* status, double* eig, hipStream_t s);

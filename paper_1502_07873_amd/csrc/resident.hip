@@ -85,8 +85,8 @@ stencil_resident(const SolveDesc* __restrict__ descs, const int2* __restrict__ t
     const int b_first = (int)threadIdx.x / W;
     const int i_first = (int)threadIdx.x - b_first * W + 1;
     const int kb_first = b_first * nrow / nb, ke_first = (b_first + 1) * nrow / nb;
-    int rec_first = -1;
-    if ((int)threadIdx.x < min(npair, W)) rec_first = ldi(d->recmap, i_first);
+    int rec_first = -1;   // only read where the band starts at the surface
+    if ((int)threadIdx.x < npair && kb_first == 0) rec_first = ldi(d->recmap, i_first);
     __syncthreads();
     float sval_next = nsteps > 0 ? ld1(srcs, 0) : 0.f;
     for (int m = 0; m < nsteps; ++m) {

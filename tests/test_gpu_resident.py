@@ -42,13 +42,18 @@ def _mixed_wave(seed=31):
     L1 = synthetic.random_layers_medium(rng, 64, h, 3)
     L2 = synthetic.random_layers_medium(rng, 76, h, 4)
     L3 = synthetic.random_layers_medium(rng, 97, h, 4)
+    L4 = synthetic.random_layers_medium(rng, 25, h, 2)
     N1 = synthetic.nodal_perturbed_medium(rng, 50, 100, h, nlayers=3, corr_len=60.0)
     N2 = synthetic.nodal_perturbed_medium(rng, 60, 90, h, nlayers=3, corr_len=60.0)
-    vmax = max(m.vp_max() for m in (L1, L2, L3, N1, N2))
+    N3 = synthetic.nodal_perturbed_medium(rng, 20, 34, h, nlayers=2, corr_len=40.0)
+    vmax = max(m.vp_max() for m in (L1, L2, L3, L4, N1, N2, N3))
     dt = synthetic.cfl_dt(h, vmax)
     out = []
+    # 40 x 25 and 34 x 20: more row bands (1024 // (nx - 2)) than free rows,
+    # so some bands are empty and the surface row is not in the first band
     for nx, nz, med, n, bc in ((64, 64, L1, 333, 0), (101, 76, L2, 320, 1), (300, 97, L3, 301, 0),
-                               (100, 50, N1, 290, 0), (90, 60, N2, 311, 1)):
+                               (100, 50, N1, 290, 0), (90, 60, N2, 311, 1), (40, 25, L4, 342, 1),
+                               (34, 20, N3, 287, 0)):
         g = synthetic.Grid(nx, nz, h, dt, n, bc="absorbing" if bc else "rigid")
         rec = np.unique(np.r_[1, 2, 63, 64, 65, nx // 2, nx - 2])
         rec = rec[rec <= nx - 2].astype(np.int32)
@@ -71,7 +76,9 @@ def _thetas(spec, seed):
     rng = np.random.default_rng(seed)
     th = np.concatenate([synthetic.draw_uniform(rng, *synthetic.prior_box(g), 1)
                          for g, _, _ in spec])
-    th[:, 1] = 20 * spec[0][0].h   # 20 rows deep: the wave reaches the surface in time
+    # at most 20 rows deep (within each prior box): the wave reaches the
+    # surface in time
+    th[:, 1] = [min(20 * g.h, synthetic.prior_box(g)[1][1]) for g, _, _ in spec]
     th[:, 2] = 0.1
     return th
 
@@ -81,7 +88,7 @@ def test_forward_resident_equals_tiled_in_a_mixed_wave():
         pytest.skip("no HIP device")
     spec = _mixed_wave()
     th = _thetas(spec, 5)
-    _say("resident vs tiled: mixed wave of 5 grids (4 resident-sized)")
+    _say("resident vs tiled: mixed wave of 7 grids (6 resident-sized)")
     outs = {}
     launches = {}
     for res in (True, False):
