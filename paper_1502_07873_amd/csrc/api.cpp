@@ -787,7 +787,7 @@ int eig_ctx_set_option(eig_ctx* c, const char* name, int64_t value) {
             return set_error(EIG_EINVAL, "variant");
         c->default_variant = (int)value;
     } else if (n == "temporal_blocking") {
-        if (value < 0 || value > 3) return set_error(EIG_EINVAL, "temporal_blocking: 0..3");
+        if (value < 0 || value > 4) return set_error(EIG_EINVAL, "temporal_blocking: 0..4");
         c->temporal_blocking = value == 0 ? 1 : (value == 1 ? 2 : (int)value);
     } else if (n == "max_wave_solves") {
         if (value < 0) return set_error(EIG_EINVAL, "max_wave_solves < 0");

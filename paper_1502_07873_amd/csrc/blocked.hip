@@ -1,0 +1,256 @@
+// Depth-only media, K leapfrog steps per launch with the tile kept in LDS
+// (variant 23: 64 x 56 tiles, K = 4; the temporal_blocking 4 family).
+//
+// A workgroup of 512 threads owns a TW x TH tile of one solve (two share a
+// CU).  It loads u^{m-1} and u^m on the tile and a K-node halo around it
+// (clipped to the grid) into LDS, then takes K steps there: step j forms
+// u^{m+j} on the tile grown by K - j nodes, so the region shrinks by one
+// node per step as the halo's values go stale from the outside in, and
+// writes it over u^{m+j-2} in place (a node is read at the old level and
+// written only by its owner).  Last it stores u^{m+K-1} and u^{m+K} of the
+// tile.  Passes alternate between the two buffer pairs of a solve: pass L
+// reads levels m-1 and m (m = K L) from pair L & 1 and writes its two last
+// levels to the other pair, slot = level & 1, so no workgroup overwrites a
+// value another one still loads.
+//
+// Per update a launch moves (tile + halo) x 2 levels in and the tile x 2
+// levels out: (72 x 64 + 64 x 56) x 16 B / (64 x 56 x 4) = 9.1 B, against
+// 16 for the two-step kernels; the halo costs 10 % more updates (the region
+// of step j is (64 + 2(K-j)) x (56 + 2(K-j))).  Measured on the 512^2 Monte
+// Carlo query: 3.31-3.36e11 updates/s in cache-sized chunks, the same as the
+// two-step kernel (3.34e11), and 3.26e11 as one unsplit wave, where the
+// two-step kernel streams HBM at 2.85e11.  Its vector issue runs at 0.59
+// (68.7 lane-instructions per update); smaller tiles with four workgroups
+// per CU (64 x 24, 32 x 40) and a persistent form that prefetches the next
+// tile into registers (two 8-wave or one 16-wave workgroup per CU, 64 x 56
+// or 64 x 120) were slower (2.5-3.3e11), so the tile's loads are not what
+// holds it back.  Opt-in (temporal_blocking 4), not the default.
+//
+// Work split: threads are packed over (band, column) pairs of the first
+// step's region as in the resident kernel (thread t: column t mod W of band
+// t div W, W the region's free columns), fixed for a tile; at step j a
+// thread clips its column and band to that step's region.  A thread streams
+// down its rows keeping rows k-1, k, k+1 in registers.  Coefficient rows,
+// forcing weights and the forcing series values sit in LDS.  Receivers are
+// recorded by the tile that owns their column; forcing is added at every
+// computed node of the window, halo included, so every tile that computes a
+// node computes it alike.  The per-node arithmetic is layered_update, so the
+// fields are bitwise those of every variant.  Rigid edges only, no receiver
+// injection (dual solves run one step per launch).
+#include "internal.h"
+#include "node_update.h"
+#include "tile.h"
+
+namespace eig {
+
+namespace {
+
+// Where one tile of one pass sits.
+struct BlkTile {
+    const SolveDesc* d;
+    int m, nst;                  // first level of the pass, steps taken
+    int x0, z0, x1, z1;          // tile [x0, x1) x [z0, z1)
+    int rx0, rz0, rw, rh;        // region (tile + halo, clipped)
+    int pin, pout;               // buffer pairs read / written
+};
+
+template <int TW, int TH, int K>
+__device__ __forceinline__ bool blk_setup(const SolveDesc* __restrict__ descs, int2 te, int pass,
+                                          BlkTile& t) {
+    t.d = descs + __builtin_amdgcn_readfirstlane(te.x);
+    const int sc = __builtin_amdgcn_readfirstlane(te.y);
+    const int L = pass - t.d->start;
+    t.m = K * L;
+    if (L < 0 || t.m >= t.d->nsteps) return false;
+    t.nst = min(K, t.d->nsteps - t.m);
+    const int nx = t.d->nx, nz = t.d->nz;
+    t.x0 = (sc >> 16) * TW;
+    t.z0 = (sc & 0xffff) * TH;
+    t.x1 = min(t.x0 + TW, nx);
+    t.z1 = min(t.z0 + TH, nz - 1);  // free rows < nz-1
+    t.rx0 = max(t.x0 - K, 0);
+    t.rz0 = max(t.z0 - K, 0);
+    t.rw = min(t.x1 + K, nx) - t.rx0;
+    t.rh = min(t.z1 + K, nz) - t.rz0;
+    t.pin = 2 * (L & 1);
+    t.pout = 2 - t.pin;
+    return true;
+}
+
+__device__ __forceinline__ const float2* blk_buf(const SolveDesc* d, int i) {
+    return i == 0 ? d->buf0 : (i == 1 ? d->buf1 : (i == 2 ? d->buf2 : d->buf3));
+}
+
+// The thread's (band, column) of a tile's first-step region.
+struct BlkLane {
+    int col, kb, ke;
+    bool active;
+};
+
+template <int K, int NT>
+__device__ __forceinline__ BlkLane blk_lane(const BlkTile& tl) {
+    const int nx = tl.d->nx, nz = tl.d->nz;
+    const int c0 = max(tl.x0 - (K - 1), 1), c1 = min(tl.x1 + (K - 1), nx - 1);
+    const int r0 = max(tl.z0 - (K - 1), 0), r1 = min(tl.z1 + (K - 1), nz - 1);
+    const int W = c1 - c0, nrow = r1 - r0;
+    const int nb = max(1, NT / W);
+    const int band = (int)threadIdx.x / W;
+    BlkLane ln;
+    ln.active = band < nb;
+    ln.col = c0 + ((int)threadIdx.x - band * W);
+    ln.kb = r0 + band * nrow / nb;
+    ln.ke = r0 + (band + 1) * nrow / nb;
+    return ln;
+}
+
+// Receiver recorded by this thread (its column on the tile's surface row),
+// or -1.  Read before a prefetch is issued: vector loads retire in order.
+__device__ __forceinline__ int blk_rec(const BlkTile& tl, const BlkLane& ln) {
+    if (ln.active && ln.kb == 0 && ln.col >= tl.x0 && ln.col < tl.x1)
+        return ldi(tl.d->recmap, ln.col);
+    return -1;
+}
+
+// The K steps of one tile whose region, coefficient rows, forcing weights and
+// series values are in LDS (barrier before the first step is the caller's).
+template <int TW, int TH, int K, int NT, int RW>
+__device__ __forceinline__ void blk_steps(const BlkTile& tl, const BlkLane& ln, int rec,
+                                          float2 (*fld)[RW * (TH + 2 * K)],
+                                          const float* cf_lds, const float* sw_lds,
+                                          const float* sv_lds) {
+    const SolveDesc* d = tl.d;
+    const int nx = d->nx, nz = d->nz;
+    const int m = tl.m, x0 = tl.x0, x1 = tl.x1, z0 = tl.z0, z1 = tl.z1;
+    const int rz0 = tl.rz0;
+    const bool active = ln.active;
+    const int col = ln.col, kb = ln.kb, ke = ln.ke;
+    const int si0 = d->src_i0, sk0 = d->src_k0;
+    const int di = col - si0;
+    const bool src_lane = di >= 0 && di < kSrcW;
+    float2* traces = d->traces;
+    const int nrec = d->nrec;
+    const int lc = col - tl.rx0;  // LDS column
+    for (int j = 1; j <= tl.nst; ++j) {
+        const int lvl = m + j;
+        const float2* Q = fld[(lvl - 1) & 1];
+        float2* P = fld[lvl & 1];
+        const int g = K - j;  // this step's region: the tile grown by g
+        const int cj0 = max(x0 - g, 1), cj1 = min(x1 + g, nx - 1);
+        const int rj0 = max(z0 - g, 0), rj1 = min(z1 + g, nz - 1);
+        const int ka = max(kb, rj0), kz = min(ke, rj1);
+        if (active && col >= cj0 && col < cj1 && ka < kz) {
+            const float sval = sv_lds[j - 1];
+            auto row = [&](int k) {
+                const float2* rr = Q + (k - rz0) * RW + lc;
+                const float2 l = rr[-1], c = rr[0], r = rr[1];
+                return node_row(c.x, c.y, l.x, l.y, r.x, r.y);
+            };
+            auto update = [&](int k, const NodeRow& rm, const NodeRow& rc, const NodeRow& rn) {
+                LayerCoef cf;
+#pragma unroll
+                for (int q = 0; q <= kFco; ++q) cf.c[q] = cf_lds[(k - rz0) * kCoefStride + q];
+                float2* pp = P + (k - rz0) * RW + lc;
+                const float2 up = *pp;
+                const int dk = k - sk0;
+                if (k != 0 && (unsigned)dk >= (unsigned)kSrcW) {
+                    *pp = layered_update(cf, rm, rc, rn, up.x, up.y, false, 0.f, 0.f, 0.f);
+                    return;
+                }
+                const bool in_win = src_lane && dk >= 0 && dk < kSrcW;
+                float wu = 0.f, wv = 0.f;
+                const float fsv = cf.c[kFco] * sval;
+                if (in_win) {
+                    wu = sw_lds[(0 * kSrcW + dk) * kSrcW + di];
+                    wv = sw_lds[(1 * kSrcW + dk) * kSrcW + di];
+                }
+                const float2 nw = layered_update(cf, rm, rc, rn, up.x, up.y, in_win, fsv, wu, wv);
+                *pp = nw;
+                if (k == 0 && rec >= 0) st2(traces, (size_t)lvl * nrec + rec, nw);
+            };
+            NodeRow ra = NodeRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (ka > 0) ra = row(ka - 1);
+            NodeRow rb = row(ka);
+            int k = ka;
+            for (; k + 3 <= kz; k += 3) {
+                const NodeRow r2 = row(k + 1);
+                update(k, ra, rb, r2);
+                const NodeRow r3 = row(k + 2);
+                update(k + 1, rb, r2, r3);
+                const NodeRow r4 = row(k + 3);
+                update(k + 2, r2, r3, r4);
+                ra = r3;
+                rb = r4;
+            }
+            for (; k < kz; ++k) {
+                const NodeRow r2 = row(k + 1);
+                update(k, ra, rb, r2);
+                ra = rb;
+                rb = r2;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Store the tile's last two levels to the other pair.
+template <int TH, int K, int NT, int RW>
+__device__ __forceinline__ void blk_store(const BlkTile& tl, float2 (*fld)[RW * (TH + 2 * K)]) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int pitch = tl.d->pitch;
+    for (int q = 0; q < 2; ++q) {
+        const int lvl = tl.m + tl.nst - 1 + q;
+        float2* out = const_cast<float2*>(blk_buf(tl.d, tl.pout + (lvl & 1)));
+        const float2* F = fld[lvl & 1];
+        for (int r = tl.z0 + wave; r < tl.z1; r += NT / 64)
+            for (int c = tl.x0 + lane; c < tl.x1; c += 64)
+                st2(out, (size_t)r * pitch + c, F[(r - tl.rz0) * RW + (c - tl.rx0)]);
+    }
+}
+
+template <int TW, int TH, int K, int NT, int WPC>
+__global__ void __launch_bounds__(NT, NT / 256 * WPC)  // waves per SIMD for WPC per CU
+stencil_layered_lds(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
+                    int ntiles, int pass) {
+    constexpr int RW = TW + 2 * K, RH = TH + 2 * K;  // largest region
+    __shared__ float2 fld[2][RH * RW];
+    __shared__ float cf_lds[RH * kCoefStride];
+    __shared__ float sw_lds[2 * kSrcW * kSrcW];
+    __shared__ float sv_lds[K];
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (b >= ntiles) return;
+    BlkTile tl;
+    if (!blk_setup<TW, TH, K>(descs, tiles[b], pass, tl)) return;  // uniform
+    const SolveDesc* d = tl.d;
+    const int pitch = d->pitch, m = tl.m;
+    const float2* prev = blk_buf(d, tl.pin + ((m - 1) & 1));  // u^{m-1}
+    const float2* cur = blk_buf(d, tl.pin + (m & 1));         // u^m
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int r = wave; r < tl.rh; r += NT / 64) {
+        const size_t g = (size_t)(tl.rz0 + r) * pitch + tl.rx0;
+        for (int c = lane; c < tl.rw; c += 64) {
+            fld[(m - 1) & 1][r * RW + c] = ld2(prev, g + c);
+            fld[m & 1][r * RW + c] = ld2(cur, g + c);
+        }
+    }
+    for (int j = threadIdx.x; j < tl.rh * kCoefStride; j += NT)
+        cf_lds[j] = ld1(d->coef, (size_t)tl.rz0 * kCoefStride + j);
+    for (int j = threadIdx.x; j < 2 * kSrcW * kSrcW; j += NT) sw_lds[j] = ld1(d->srcw, j);
+    if ((int)threadIdx.x < tl.nst) sv_lds[threadIdx.x] = ld1(d->srcs, m + threadIdx.x);
+    const BlkLane ln = blk_lane<K, NT>(tl);
+    const int rec = blk_rec(tl, ln);
+    __syncthreads();
+    blk_steps<TW, TH, K, NT, RW>(tl, ln, rec, fld, cf_lds, sw_lds, sv_lds);
+    blk_store<TH, K, NT, RW>(tl, fld);
+}
+
+}  // namespace
+
+void launch_blocked_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int pass,
+                            int variant, hipStream_t s) {
+    (void)variant;
+    stencil_layered_lds<64, 56, 4, 512, 2><<<ntiles, 512, 0, s>>>(descs, tiles, ntiles, pass);
+}
+
+}  // namespace eig

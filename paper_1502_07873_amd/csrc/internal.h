@@ -155,11 +155,18 @@ constexpr int kEdgeTileNodes = 128;
 inline int edge_tiles_of(int nx, int nz) {
     return (2 * nz + nx - 2 + kEdgeTileNodes - 1) / kEdgeTileNodes;
 }
-constexpr int kNumVariants = 23;
+constexpr int kNumVariants = 24;
 extern const StencilVariant kVariants[kNumVariants];
 // tiles: (solve index, strip << 16 | chunk) per wavefront
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                     int variant, hipStream_t s);
+// Tiled depth-only variants (0..5, 7..16) of launch_stencil.
+void launch_layered_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
+                            int variant, hipStream_t s);
+// Depth-only variant 23 (K steps per launch, tile in LDS) of launch_stencil:
+// one workgroup per tile.
+void launch_blocked_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int pass,
+                            int variant, hipStream_t s);
 // Nodal-media variants (6, 17..20) of launch_stencil.
 void launch_nodal_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                           int variant, hipStream_t s);

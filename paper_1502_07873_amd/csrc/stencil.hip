@@ -1113,35 +1113,8 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
         (uint4*)p, n16, (uint8_t*)p + n16 * 16, ntail);
 }
 
-const StencilVariant kVariants[kNumVariants] = {
-    {64, 32, EIG_MEDIUM_LAYERED, 1},   // 0: one node per lane
-    {128, 32, EIG_MEDIUM_LAYERED, 1, 1},  // 1: two nodes per lane, prefetch 1
-    {128, 32, EIG_MEDIUM_LAYERED, 1, 1},  // 2: two nodes per lane, prefetch 2
-    {128, 64, EIG_MEDIUM_LAYERED, 1, 1},  // 3: prefetch 2
-    {128, 16, EIG_MEDIUM_LAYERED, 1, 1},  // 4: prefetch 2
-    {128, 64, EIG_MEDIUM_LAYERED, 1, 1},  // 5: prefetch 1
-    {64, 32, EIG_MEDIUM_NODAL, 1},     // 6: nodal media
-    {128, 8, EIG_MEDIUM_LAYERED, 1, 1},   // 7: prefetch 2
-    {128, 16, EIG_MEDIUM_LAYERED, 1, 1},  // 8: prefetch 1
-    {128, 16, EIG_MEDIUM_LAYERED, 2},  // 9: two steps per launch
-    {128, 32, EIG_MEDIUM_LAYERED, 2},  // 10: two steps per launch
-    {128, 64, EIG_MEDIUM_LAYERED, 2},  // 11: two steps per launch
-    {128, 128, EIG_MEDIUM_LAYERED, 2}, // 12: two steps per launch
-    {128, 64, EIG_MEDIUM_LAYERED, 2},  // 13: two steps, halo columns up front
-    {128, 32, EIG_MEDIUM_LAYERED, 2},  // 14: two steps, halo columns up front
-    {128, 64, EIG_MEDIUM_LAYERED, 3},  // 15: three steps per launch
-    {128, 32, EIG_MEDIUM_LAYERED, 3},  // 16: three steps per launch
-    {128, 16, EIG_MEDIUM_NODAL, 1, 1},    // 17: nodal media, two nodes per lane
-    {128, 32, EIG_MEDIUM_NODAL, 1, 1},    // 18: nodal media, two nodes per lane
-    {128, 16, EIG_MEDIUM_NODAL, 2},    // 19: nodal media, two steps per launch
-    {128, 32, EIG_MEDIUM_NODAL, 2},    // 20: nodal media, two steps per launch
-    {0, 0, EIG_MEDIUM_LAYERED, 1, 1, 1},  // 21: resident in LDS, every step in one launch
-    {0, 0, EIG_MEDIUM_NODAL, 1, 1, 1},    // 22: resident in LDS, every step in one launch
-};
-
-void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
-                    int variant, hipStream_t s) {
-    if (ntiles <= 0) return;
+void launch_layered_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
+                            int variant, hipStream_t s) {
     const int blocks = (ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int threads = 64 * kWavesPerBlock;
     switch (variant) {
@@ -1161,7 +1134,7 @@ void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int s
         case 14: stencil_layered_tb2h<32, 1><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         case 15: stencil_layered_tb3<64><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
         case 16: stencil_layered_tb3<32><<<blocks, threads, 0, s>>>(descs, tiles, ntiles, step); break;
-        default: launch_nodal_stencil(descs, tiles, ntiles, step, variant, s); break;
+        default: break;
     }
 }
 

@@ -431,7 +431,7 @@ def test_hessian_and_peak_for_any_element_count(ctx, nsteps):
 
 
 @pytest.mark.parametrize("nsteps", [700, 333])
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 23])
 def test_stencil_variants_bitwise_identical(variant, nsteps, monkeypatch):
     # every layered-medium stencil variant computes the same arithmetic per
     # node, so the traces must agree bit for bit (and with the oracle)
@@ -546,10 +546,12 @@ def test_nodal_tile_interleave_is_bitwise_neutral(variant, monkeypatch):
         check_receivers(outs[3][s], ref, TRACE_TOL, what=f"interleaved solve {s}")
 
 
-def test_three_step_family_with_mixed_lengths_matches_one_step():
-    # temporal_blocking = 3 through the normal (tuned) path: solves of
+@pytest.mark.parametrize("tb", [3, 4])
+def test_multi_step_family_with_mixed_lengths_matches_one_step(tb):
+    # temporal_blocking = 3 or 4 through the normal (tuned) path: solves of
     # different lengths in one wave (running prefixes of tiles and halo
-    # tiles), tails of one and two steps; bitwise equal to one step per launch
+    # tiles), tails of every shorter length; bitwise equal to one step per
+    # launch
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     from paper_1502_07873_amd import Context
@@ -564,19 +566,19 @@ def test_three_step_family_with_mixed_lengths_matches_one_step():
     th = synthetic.draw_uniform(rng, lo, hi, len(lens))
     th[:, 2] = 0.08
     rec = np.array([1, 127, 128, 129, 255, 256, nx - 2], dtype=np.int32)
-    _say("three-step family, mixed lengths")
+    _say(f"{tb}-step family, mixed lengths")
     dm = _dev_medium(med)
     outs = []
-    for tb in (3, 0):
+    for t in (tb, 0):
         with Context(0, 4 << 30) as c:
-            c.set_option("temporal_blocking", tb)
+            c.set_option("temporal_blocking", t)
             tr = [torch.empty((n + 1, len(rec), 2), dtype=torch.float32, device="cuda")
                   for n in lens]
             c.forward_solve_batch([grid_tuple(g) for g in grids], [dm] * len(lens), th,
                                   [rec] * len(lens), tr)
             torch.cuda.synchronize()
             outs.append([t.cpu().numpy() for t in tr])
-            assert c.get_option("temporal_blocking") == (3 if tb == 3 else 1)
+            assert c.get_option("temporal_blocking") == (tb if t == tb else 1)
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
     assert np.max(np.abs(outs[0][2])) > 0
