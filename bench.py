@@ -541,6 +541,56 @@ def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40, pipeline=Tru
     return out
 
 
+def _bench_c5_full_query(batch=30, kmax=40):
+    """The whole c5 query at full size: per-candidate H_1 on all 589 level-3
+    sparse-grid nodes of the 2048 x 1024 x 4000 nodal problem (8835 solves,
+    in batches of `batch` nodes, progress printed per batch), then greedy
+    design over the 201 candidates to kmax receivers."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_1502_07873_amd import Context, make_prior, sparse_grid_gl
+    from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
+    wl = synthetic.config("c5")[0]
+    nodes, w = sparse_grid_gl(7, 3, wl.lo, wl.hi)
+    med = device_medium(wl.medium.kind, wl.medium.rho, wl.medium.lam, wl.medium.mu)
+    g = grid_tuple(wl.grid)
+    R, S = len(wl.receivers), len(w)
+    H = torch.empty((S, R, 7, 7), dtype=torch.float64, device="cuda")
+    flagged = 0
+    with Context(0, 64 << 30) as ctx:
+        t0 = time.perf_counter()
+        sigma = ctx.noise_sigma_peak(g, med, wl.theta_bar, wl.noise_rel)
+        for a in range(0, S, batch):
+            b = min(S, a + batch)
+            r = run_query(ctx, g, med, wl.receivers, wl.lo, wl.hi, nodes[a:b], w[a:b],
+                          sigma=sigma, per_receiver=True)
+            H[a:b] = r["H1"]
+            flagged += int(r["status"].ne(0).sum())
+            torch.cuda.synchronize()
+            print(f"[bench] c5 full query: nodes {b}/{S}, {time.perf_counter() - t0:.1f} s",
+                  flush=True)
+        t_solve = time.perf_counter() - t0
+        order = torch.empty(kmax, dtype=torch.int32, device="cuda")
+        curve = torch.empty(kmax, dtype=torch.float64, device="cuda")
+        t1 = time.perf_counter()
+        ctx.design_greedy(H, make_prior(wl.lo, wl.hi), w, kmax, order, curve, theta=nodes)
+        torch.cuda.synchronize()
+        t_greedy = time.perf_counter() - t1
+        st = ctx.stencil_stats(reset=True)
+    upd = 15.0 * S * wl.grid.nx * wl.grid.nz * wl.grid.nsteps
+    cv = curve.cpu().numpy()
+    return {"workload": "c5 at full size: 2048x1024x4000 nodal medium, level-3 sparse grid "
+                        "(589 nodes, 8835 solves), per-candidate H_1 over 201 receivers, "
+                        f"greedy to {kmax}",
+            "seconds_solves_and_h1": t_solve, "seconds_greedy": t_greedy,
+            "grid_pt_updates_per_s": upd / t_solve, "sigma": sigma,
+            "flagged_nodes": flagged, "stencil_launches": st["launches"],
+            "order": order.cpu().numpy().tolist(), "eig_curve": [float(x) for x in cv],
+            "eig_first_last": [float(cv[0]), float(cv[-1])]}
+
+
 def _bench_model(nmc=10000, ncheck=2):
     """The paper's model problem (Section 4.1, absorbing edges, 91 candidate
     receivers): per-receiver H_1 for nmc Monte Carlo samples by central
@@ -949,10 +999,11 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed query: no other leg (for counter runs)")
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "c5", "model", "loh2d", "nested", "estimators",
-                             "serving"],
+                    choices=["c2", "c3", "c5", "c5-full", "model", "loh2d", "nested",
+                             "estimators", "serving"],
                     help="c2: the headline query and every leg (default); c3/c5: those legs "
-                         "alone; model: the model-problem leg alone; loh2d: the paper's "
+                         "alone; c5-full: the whole 589-node c5 query at full size and its "
+                         "greedy design; model: the model-problem leg alone; loh2d: the paper's "
                          "model problem with sparse quadrature and scenarios; serving: "
                          "the serving streams with both disciplines")
     ap.add_argument("--serving-rate", type=float, default=3.2e11,
@@ -985,8 +1036,10 @@ def main():
     from paper_1502_07873_amd import Context
     from paper_1502_07873_amd.query import device_medium, grid_tuple, run_query
 
-    if args.workload in ("c3", "c5", "model"):
-        if args.workload == "c3":
+    if args.workload in ("c3", "c5", "model", "c5-full"):
+        if args.workload == "c5-full":
+            res = _bench_c5_full_query()
+        elif args.workload == "c3":
             res = _bench_c3(args.samples if args.samples != 256 else 4096)
         elif args.workload == "c5":
             res = _bench_c5(pipeline=not args.c5_full_only,
