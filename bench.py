@@ -205,10 +205,12 @@ def _copy_calibration(nbytes=4 << 30, reps=4):
 SERVE_BUDGET = 250 << 30   # the serving workload's HBM budget
 
 
-def _run_stream(ctx, wls, arrivals, overlap, budget=SERVE_BUDGET, group_samples=16):
+def _run_stream(ctx, wls, arrivals, overlap, budget=SERVE_BUDGET, group_samples=16,
+                progress=False):
     """Serves design queries (synthetic workloads) arriving at the given
     offsets; sigma = 1e-3 x each sample's nominal peak.  Returns the queries
-    with their times."""
+    with their times; progress prints a line as each query is submitted and
+    done."""
     from paper_1502_07873_amd import eigseis
     from paper_1502_07873_amd.query import device_medium, grid_tuple
     from paper_1502_07873_amd.serve import Query, serve
@@ -218,7 +220,14 @@ def _run_stream(ctx, wls, arrivals, overlap, budget=SERVE_BUDGET, group_samples=
         qs.append(Query(grid_tuple(w.grid), med, w.theta, w.receivers, w.lo, w.hi, w.weights,
                         w.noise_rel, eigseis.SIGMA_NOMINAL_PEAK, arrival=float(t)))
     srv = eigseis.Server(ctx, budget, group_samples=group_samples)
-    serve(srv, qs, launches_per_step=20, overlap=overlap)
+    index = {id(q): k for k, q in enumerate(qs)}
+
+    def report(kind, q, t):
+        print(f"[bench] serving: query {index[id(q)]} ({q.grid[0]}^2 x {q.grid[4]}, "
+              f"{len(q.theta)} samples) {kind} at {t:.1f} s", flush=True)
+
+    serve(srv, qs, launches_per_step=20, overlap=overlap,
+          on_event=report if progress else None)
     mem = srv.memory()
     srv.close()
     return qs, mem
@@ -289,7 +298,7 @@ def _serving_c4(ctx, updates_per_s, max_updates=1.2e13, load=0.8, seed=3, overla
     arr = synthetic.poisson_arrivals(rng, n, rate)
     print(f"[bench] serving stream at the serving workload's ranges: {n} queries, "
           f"{work.sum():.3g} updates ({'continuous' if overlap else 'queue-only'})", flush=True)
-    qs, mem = _run_stream(ctx, wls, arr, overlap)
+    qs, mem = _run_stream(ctx, wls, arr, overlap, progress=True)
     d = _stream_stats(qs, mem, work)
     d.update({"discipline": "continuous batching" if overlap else "queue only",
               "offered_load": load, "arrival_rate_per_s": rate,

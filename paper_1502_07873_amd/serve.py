@@ -40,11 +40,13 @@ class Query:
 
 
 def serve(server: eigseis.Server, queries, launches_per_step: int = 40,
-          max_inflight_steps: int = 2, overlap: bool = True):
+          max_inflight_steps: int = 2, overlap: bool = True, on_event=None):
     """Runs the arrival process in real time.  Returns the queries with
     t_submit / t_done filled in (seconds from the start).  overlap=False is
     the queue-only discipline: a query is submitted only once the previous
-    one has completed (no continuous batching)."""
+    one has completed (no continuous batching).  on_event(kind, query, t),
+    if given, is called as each query is submitted ("submit") and done
+    ("done")."""
     pending = sorted(queries, key=lambda q: q.arrival)
     active = []
     inflight = collections.deque()
@@ -58,6 +60,8 @@ def serve(server: eigseis.Server, queries, launches_per_step: int = 40,
             q.t_submit = now
             active.append(q)
             i += 1
+            if on_event:
+                on_event("submit", q, now)
         queued, running = server.pending()
         if queued or running:
             server.step(launches_per_step)
@@ -74,6 +78,8 @@ def serve(server: eigseis.Server, queries, launches_per_step: int = 40,
             if server.poll(q.qid):
                 q.t_done = time.perf_counter() - t0
                 active.remove(q)
+                if on_event:
+                    on_event("done", q, q.t_done)
     torch.cuda.synchronize()
     return queries
 
