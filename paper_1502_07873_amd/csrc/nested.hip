@@ -281,12 +281,23 @@ size_t nested_workspace(int nouter, int ninner) {
            sizeof(double);
 }
 
-// Inner-range splits: enough blocks to fill the chip when the outer rows
-// are few, each split at least two column tiles long.
+// Inner-range splits, each at least two column tiles long: enough blocks to
+// fill the chip when the outer rows are few, and a block count whose last
+// round of the chip's block slots is nearly full.  Every block of a launch
+// does the same work, so with b blocks on kSlots slots the launch takes
+// ceil(b / kSlots) rounds: 3125 blocks at N = 4e5 take 13 rounds for 12.2
+// rounds of work (6 % idle), 12500 take 49 for 48.8.
+constexpr int kSlots = 256;   // one block per CU: 8 waves of ~214 VGPRs fill its 4 SIMDs
 int nested_splits(int nouter, int ninner) {
-    const int rows = (nouter + kTN - 1) / kTN;
+    const long rows = (nouter + kTN - 1) / kTN;
+    auto fill = [&](long split) {
+        const long b = rows * split, rounds = (b + kSlots - 1) / kSlots;
+        return (double)b / (double)(rounds * kSlots);
+    };
     int split = 1;
-    while (rows * split < 2048 && (ninner + split * 2 - 1) / (split * 2) >= 2 * kTM) split *= 2;
+    while ((rows * split < 2048 || fill(split) < 0.98) &&
+           (ninner + split * 2 - 1) / (split * 2) >= 2 * kTM)
+        split *= 2;
     return split;
 }
 
