@@ -186,8 +186,9 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  *                      device's 256 MB last-level cache (solves grouped by
  *                      grid and length); waves where fewer than
  *                      "cache_chunk_min_solves" solves would fit are not
- *                      split.  0: never split for the cache.  Results do not
- *                      depend on it.
+ *                      split.  Solves taking four steps per launch do not
+ *                      count (they run as one wave through HBM).  0: never
+ *                      split for the cache.  Results do not depend on it.
  *   "cache_chunk_min_solves" 16 (default): see "wave_cache_bytes"; >= 1
  *   "coef_interleave"  8 (default): in nodal media, up to this many
  *                      consecutive solves of a wave on one medium and grid
@@ -215,9 +216,10 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
 int eig_ctx_set_option(eig_ctx* ctx, const char* name, int64_t value);
 /* Reads an option back; "last_variant" gives the stencil variant of the most
  * recent launch.  "temporal_blocking": leapfrog steps per launch for media
- * with rigid edges, 2 (default; 1 also selects 2), 3 (depth-only media; nodal
- * media then take two), or 0 for one step; two and three steps per launch
- * keep four field buffers per solve.  The serving engine takes two steps per
+ * with rigid edges, 4 (default: the tile and its halo in LDS for four steps,
+ * variants 23 depth-only, 24 and 25 nodal), 2 (1 also selects 2), 3
+ * (depth-only media; nodal media then take two), or 0 for one step; two to
+ * four steps per launch keep four field buffers per solve.  The serving engine takes two steps per
  * launch for depth-only media and one for nodal media. */
 int eig_ctx_get_option(const eig_ctx* ctx, const char* name, int64_t* value);
 

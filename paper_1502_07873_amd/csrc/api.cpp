@@ -60,12 +60,25 @@ bool resident_ok(const eig_ctx* c, const eig_grid& g, int kind) {
 constexpr int kResidentSpan = 1 << 28;
 
 // Leapfrog steps per launch of the kernels a solve class runs: absorbing
-// edges and dual solves one; depth-only media temporal_blocking (1, 2 or 3);
-// nodal media two unless temporal_blocking is 1.
+// edges and dual solves one; depth-only media temporal_blocking (1, 2, 3 or
+// 4); nodal media two unless temporal_blocking is 1 or 4.
 int family_steps_of(const eig_ctx* c, int kind, bool one_step) {
     if (one_step) return 1;
-    if (kind == EIG_MEDIUM_LAYERED) return c->temporal_blocking;
+    if (kind == EIG_MEDIUM_LAYERED || c->temporal_blocking == 4) return c->temporal_blocking;
     return std::min(c->temporal_blocking, 2);
+}
+
+// Leapfrog steps per launch of a tiled solve (a forced variant's, else its
+// family's).
+int tiled_steps_of(const eig_ctx* c, const SolveSpec& sp, const eig_grid& g,
+                   const MediumKey& mk) {
+    const bool one_step = g.bc == EIG_BC_ABSORBING || sp.rforce != nullptr;
+    int steps = family_steps_of(c, mk.kind, one_step);
+    if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == mk.kind &&
+        !kVariants[c->forced_variant].resident &&
+        !(one_step && kVariants[c->forced_variant].steps != 1))
+        steps = kVariants[c->forced_variant].steps;
+    return steps;
 }
 
 // Field bytes one solve keeps live from launch to launch: four buffers when
@@ -75,13 +88,7 @@ size_t live_field_bytes(const eig_ctx* c, const SolveSpec& sp, const eig_grid& g
                         const MediumKey& mk) {
     if (resident_ok(c, g, mk.kind)) return 0;  // fields in LDS
     const size_t field = (size_t)g.nz * pitch_of(g.nx) * sizeof(float2);
-    const bool one_step = g.bc == EIG_BC_ABSORBING || sp.rforce != nullptr;
-    int steps = family_steps_of(c, mk.kind, one_step);
-    if (c->forced_variant >= 0 && kVariants[c->forced_variant].medium_kind == mk.kind &&
-        !kVariants[c->forced_variant].resident &&
-        !(one_step && kVariants[c->forced_variant].steps != 1))
-        steps = kVariants[c->forced_variant].steps;
-    return (steps >= 2 ? 4 : 2) * field;
+    return (tiled_steps_of(c, sp, g, mk) >= 2 ? 4 : 2) * field;
 }
 
 // A wave's solves advance together, but not necessarily in one set of
@@ -92,8 +99,12 @@ size_t live_field_bytes(const eig_ctx* c, const SolveSpec& sp, const eig_grid& g
 // the same workspace in stream order.  For the split the solves are ordered
 // by kind, grid and length, so that each chunk is one or two uniform groups
 // of launches.  Waves where fewer than cache_chunk_min_solves solves would
-// fit are not split for the cache (too few tiles per launch to pay).  A
-// chunk also holds at most max_wave_solves solves when that is set.
+// fit are not split for the cache (too few tiles per launch to pay).  Solves
+// that take four steps per launch with the tile in LDS move a quarter of the
+// two-step kernels' field bytes per step and run faster as one wave through
+// HBM (all their tiles in every launch) than in cache-sized chunks, so their
+// fields do not count towards the limit.  A chunk also holds at most
+// max_wave_solves solves when that is set.
 
 int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
              const std::vector<eig_grid>& grids, const std::vector<MediumKey>& media,
@@ -103,7 +114,10 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
     std::vector<size_t> live(n), order(n);
     double total = 0.0;
     for (size_t i = 0; i < n; ++i) {
-        live[i] = live_field_bytes(c, solves[i], grids[solves[i].grid], media[solves[i].medium]);
+        const SolveSpec& sp = solves[i];
+        const eig_grid& g = grids[sp.grid];
+        const MediumKey& mk = media[sp.medium];
+        live[i] = tiled_steps_of(c, sp, g, mk) == 4 ? 0 : live_field_bytes(c, sp, g, mk);
         total += (double)live[i];
         order[i] = i;
     }
@@ -133,7 +147,7 @@ int run_wave(eig_ctx* c, const std::vector<SolveSpec>& solves,
             size_t q1 = q0 + 1;
             double seg = (double)live[order[q0]];
             while (q1 < n && uniform(order[q0], order[q1])) seg += (double)live[order[q1++]];
-            const size_t nch = (size_t)std::ceil(seg / lim);
+            const size_t nch = std::max<size_t>(1, (size_t)std::ceil(seg / lim));
             const double span = seg / (double)nch;
             double acc = 0.0;
             size_t made = 1;

@@ -111,6 +111,50 @@ __device__ __forceinline__ int blk_rec(const BlkTile& tl, const BlkLane& ln) {
     return -1;
 }
 
+// Loads the region's two field levels (and, for nodal media, lambda, mu and
+// s at its nodes) into LDS rows RW nodes apart.  Each thread issues all of
+// its loads before its first LDS store, so a workgroup waits for memory once
+// rather than once per row.
+template <int NT, int RW, int NQ, bool NODAL>
+__device__ __forceinline__ void blk_load(const BlkTile& tl, const float2* prev, const float2* cur,
+                                         float2* Fp, float2* Fc, float* C0, float* C1,
+                                         float* C2) {
+    const int n = tl.rh * tl.rw, rw = tl.rw, pitch = tl.d->pitch;
+    const size_t plane = (size_t)tl.d->nz * pitch;
+    const float* coef = tl.d->coef;
+    float2 a[NQ], b[NQ];
+    float cl[NODAL ? NQ : 1], cm[NODAL ? NQ : 1], cs[NODAL ? NQ : 1];
+    int off[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int e = (int)threadIdx.x + q * NT;
+        off[q] = -1;
+        if (e < n) {
+            const int r = e / rw, c = e - r * rw;
+            const size_t g = (size_t)(tl.rz0 + r) * pitch + tl.rx0 + c;
+            a[q] = ld2(prev, g);
+            b[q] = ld2(cur, g);
+            if constexpr (NODAL) {
+                cl[q] = ld1(coef, g);
+                cm[q] = ld1(coef, plane + g);
+                cs[q] = ld1(coef, 2 * plane + g);
+            }
+            off[q] = r * RW + c;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (off[q] < 0) continue;
+        Fp[off[q]] = a[q];
+        Fc[off[q]] = b[q];
+        if constexpr (NODAL) {
+            C0[off[q]] = cl[q];
+            C1[off[q]] = cm[q];
+            C2[off[q]] = cs[q];
+        }
+    }
+}
+
 // The K steps of one tile whose region, coefficient rows, forcing weights and
 // series values are in LDS (barrier before the first step is the caller's).
 template <int TW, int TH, int K, int NT, int RW>
@@ -222,22 +266,27 @@ stencil_layered_lds(const SolveDesc* __restrict__ descs, const int2* __restrict_
     BlkTile tl;
     if (!blk_setup<TW, TH, K>(descs, tiles[b], pass, tl)) return;  // uniform
     const SolveDesc* d = tl.d;
-    const int pitch = d->pitch, m = tl.m;
+    const int m = tl.m;
     const float2* prev = blk_buf(d, tl.pin + ((m - 1) & 1));  // u^{m-1}
     const float2* cur = blk_buf(d, tl.pin + (m & 1));         // u^m
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int r = wave; r < tl.rh; r += NT / 64) {
-        const size_t g = (size_t)(tl.rz0 + r) * pitch + tl.rx0;
-        for (int c = lane; c < tl.rw; c += 64) {
-            fld[(m - 1) & 1][r * RW + c] = ld2(prev, g + c);
-            fld[m & 1][r * RW + c] = ld2(cur, g + c);
-        }
-    }
-    for (int j = threadIdx.x; j < tl.rh * kCoefStride; j += NT)
-        cf_lds[j] = ld1(d->coef, (size_t)tl.rz0 * kCoefStride + j);
-    for (int j = threadIdx.x; j < 2 * kSrcW * kSrcW; j += NT) sw_lds[j] = ld1(d->srcw, j);
-    if ((int)threadIdx.x < tl.nst) sv_lds[threadIdx.x] = ld1(d->srcs, m + threadIdx.x);
+    // the small tables' loads go out with the region's (stored after it)
+    constexpr int NCF = (RH * kCoefStride + NT - 1) / NT;
+    static_assert(NT >= 2 * kSrcW * kSrcW && NT >= K, "one table entry per thread");
+    const int t = threadIdx.x;
+    float cfv[NCF], swv = 0.f, svv = 0.f;
+#pragma unroll
+    for (int q = 0; q < NCF; ++q)
+        if (t + q * NT < tl.rh * kCoefStride)
+            cfv[q] = ld1(d->coef, (size_t)tl.rz0 * kCoefStride + t + q * NT);
+    if (t < 2 * kSrcW * kSrcW) swv = ld1(d->srcw, t);
+    if (t < tl.nst) svv = ld1(d->srcs, m + t);
+    blk_load<NT, RW, (RH * RW + NT - 1) / NT, false>(tl, prev, cur, fld[(m - 1) & 1], fld[m & 1],
+                                                     nullptr, nullptr, nullptr);
+#pragma unroll
+    for (int q = 0; q < NCF; ++q)
+        if (t + q * NT < tl.rh * kCoefStride) cf_lds[t + q * NT] = cfv[q];
+    if (t < 2 * kSrcW * kSrcW) sw_lds[t] = swv;
+    if (t < tl.nst) sv_lds[t] = svv;
     const BlkLane ln = blk_lane<K, NT>(tl);
     const int rec = blk_rec(tl, ln);
     __syncthreads();
@@ -245,12 +294,245 @@ stencil_layered_lds(const SolveDesc* __restrict__ descs, const int2* __restrict_
     blk_store<TH, K, NT, RW>(tl, fld);
 }
 
+// u, v, lambda and mu of one row at columns i-1, i, i+1.
+struct NodalRow3 {
+    float2 ul, uc, ur;
+    float ll, lc, lr, ml, mc, mr;
+};
+
+// Step j of a tile whose region, medium and forcing are in LDS, each thread
+// streaming down its band of one column (variant 24).
+template <int K, int RW, class FLD, class CL>
+__device__ __forceinline__ void nodal_lds_stream(const BlkTile& tl, const BlkLane& ln, int rec,
+                                                 int j, FLD fld, CL cl, const float* sw_lds,
+                                                 float sval) {
+    const SolveDesc* d = tl.d;
+    const int nx = d->nx, nz = d->nz;
+    const int lvl = tl.m + j;
+    const float2* Q = fld[(lvl - 1) & 1];
+    float2* P = fld[lvl & 1];
+    const int gq = K - j;
+    const int cj0 = max(tl.x0 - gq, 1), cj1 = min(tl.x1 + gq, nx - 1);
+    const int rj0 = max(tl.z0 - gq, 0), rj1 = min(tl.z1 + gq, nz - 1);
+    const int col = ln.col;
+    const int ka = max(ln.kb, rj0), kz = min(ln.ke, rj1);
+    if (!(ln.active && col >= cj0 && col < cj1 && ka < kz)) return;
+    const int lc = col - tl.rx0, rz0 = tl.rz0;
+    const int sk0 = d->src_k0, di = col - d->src_i0;
+    const bool src_col = (unsigned)di < (unsigned)kSrcW;
+    const float h2 = d->h2;
+    auto row = [&](int k) {
+        const int o = (k - rz0) * RW + lc;
+        NodalRow3 r;
+        r.ul = Q[o - 1];
+        r.uc = Q[o];
+        r.ur = Q[o + 1];
+        r.ll = cl[0][o - 1];
+        r.lc = cl[0][o];
+        r.lr = cl[0][o + 1];
+        r.ml = cl[1][o - 1];
+        r.mc = cl[1][o];
+        r.mr = cl[1][o + 1];
+        return r;
+    };
+    // node (col, k) from rows k-1 (a), k (b), k+1 (c)
+    auto update = [&](auto row_kind, int k, const NodalRow3& a, const NodalRow3& b,
+                      const NodalRow3& c) {
+        constexpr int RK = decltype(row_kind)::value;
+        auto pick = [&](int kk) -> const NodalRow3& { return kk < k ? a : (kk == k ? b : c); };
+        auto U = [&](int ii, int kk) {
+            const NodalRow3& r = pick(kk);
+            return ii < col ? r.ul : (ii == col ? r.uc : r.ur);
+        };
+        auto L = [&](int ii, int kk) {
+            const NodalRow3& r = pick(kk);
+            return ii < col ? r.ll : (ii == col ? r.lc : r.lr);
+        };
+        auto M = [&](int ii, int kk) {
+            const NodalRow3& r = pick(kk);
+            return ii < col ? r.ml : (ii == col ? r.mc : r.mr);
+        };
+        const int o = (k - rz0) * RW + lc;
+        auto S = [&]() { return cl[2][o]; };
+        const int wk = k - sk0;
+        int inj = 0;
+        float w0 = 0.f, w1 = 0.f;
+        if (src_col && (unsigned)wk < (unsigned)kSrcW) {
+            inj = 2;
+            w0 = sw_lds[(0 * kSrcW + wk) * kSrcW + di];
+            w1 = sw_lds[(1 * kSrcW + wk) * kSrcW + di];
+        }
+        const float2 nw = nodal_node_gen<RK>(U, L, M, S, P[o], col, k, inj, h2, sval, w0, w1);
+        P[o] = nw;
+        if (RK == 2 && rec >= 0) st2(d->traces, (size_t)lvl * d->nrec + rec, nw);
+    };
+    constexpr std::integral_constant<int, 1> below{};
+    NodalRow3 ra, rb;
+    int k = ka;
+    if (k == 0) {
+        rb = row(0);
+        const NodalRow3 r1 = row(1);
+        update(std::integral_constant<int, 2>(), 0, rb, rb, r1);
+        ra = rb;
+        rb = r1;
+        k = 1;
+    } else {
+        ra = row(k - 1);
+        rb = row(k);
+    }
+    for (; k + 3 <= kz; k += 3) {
+        const NodalRow3 r2 = row(k + 1);
+        update(below, k, ra, rb, r2);
+        const NodalRow3 r3 = row(k + 2);
+        update(below, k + 1, rb, r2, r3);
+        const NodalRow3 r4 = row(k + 3);
+        update(below, k + 2, r2, r3, r4);
+        ra = r3;
+        rb = r4;
+    }
+    for (; k < kz; ++k) {
+        const NodalRow3 r2 = row(k + 1);
+        update(below, k, ra, rb, r2);
+        ra = rb;
+        rb = r2;
+    }
+}
+
+// Nodal media, K steps per launch (variants 24, 25: 64 x 24 tiles, two
+// 512-thread workgroups per CU).  Same passes, buffer pairs, regions and
+// receiver ownership as the depth-only kernel above; LDS also holds lambda,
+// mu and dt^2/(rho h^2) over the region (28 B per region node with both
+// field levels: 63 KB at 72 x 32).  Variant 24 (STREAM) packs threads over
+// (band, column) pairs as the depth-only kernel does and streams down its
+// rows with u, v, lambda and mu of rows k-1, k, k+1 and columns i-1, i, i+1
+// in registers; variant 25 gives thread t the nodes t, t + NT, ... of a
+// step's region in row-major order and reads every operand from LDS.  Both
+// form each node through nodal_node_gen, the per-node update every nodal
+// kernel uses, with the surface row's branch chosen at compile time; its
+// fused products are explicit, so the fields are bitwise those of every
+// nodal variant.  Rigid edges only, no receiver injection.
+template <int TW, int TH, int K, int NT, int WPC, bool STREAM>
+__global__ void __launch_bounds__(NT, NT / 256 * WPC)
+stencil_nodal_lds(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
+                  int ntiles, int pass) {
+    constexpr int RW = TW + 2 * K, RH = TH + 2 * K;  // largest region
+    __shared__ float2 fld[2][RH * RW];
+    __shared__ float cl[3][RH * RW];  // lambda, mu, s
+    __shared__ float sw_lds[2 * kSrcW * kSrcW];
+    __shared__ float sv_lds[K];
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (b >= ntiles) return;
+    BlkTile tl;
+    if (!blk_setup<TW, TH, K>(descs, tiles[b], pass, tl)) return;  // uniform
+    const SolveDesc* d = tl.d;
+    const int m = tl.m, nx = d->nx, nz = d->nz;
+    const float2* prev = blk_buf(d, tl.pin + ((m - 1) & 1));  // u^{m-1}
+    const float2* cur = blk_buf(d, tl.pin + (m & 1));         // u^m
+    static_assert(NT >= 2 * kSrcW * kSrcW && NT >= K, "one table entry per thread");
+    const int t = threadIdx.x;
+    float swv = 0.f, svv = 0.f;
+    if (t < 2 * kSrcW * kSrcW) swv = ld1(d->srcw, t);
+    if (t < tl.nst) svv = ld1(d->srcs, m + t);
+    blk_load<NT, RW, (RH * RW + NT - 1) / NT, true>(tl, prev, cur, fld[(m - 1) & 1], fld[m & 1],
+                                                    cl[0], cl[1], cl[2]);
+    if (t < 2 * kSrcW * kSrcW) sw_lds[t] = swv;
+    if (t < tl.nst) sv_lds[t] = svv;
+    const BlkLane ln = blk_lane<K, NT>(tl);
+    const int rec = STREAM ? blk_rec(tl, ln) : -1;
+    __syncthreads();
+    const int si0 = d->src_i0, sk0 = d->src_k0;
+    float2* traces = d->traces;
+    const int nrec = d->nrec;
+    const float h2 = d->h2;
+    for (int j = 1; j <= tl.nst; ++j) {
+        if constexpr (STREAM) {
+            nodal_lds_stream<K, RW>(tl, ln, rec, j, fld, cl, sw_lds, sv_lds[j - 1]);
+            __syncthreads();
+            continue;
+        }
+        const int lvl = m + j;
+        const float2* Q = fld[(lvl - 1) & 1];
+        float2* P = fld[lvl & 1];
+        const int gq = K - j;  // this step's region: the tile grown by gq
+        const int cj0 = max(tl.x0 - gq, 1), cj1 = min(tl.x1 + gq, nx - 1);
+        const int rj0 = max(tl.z0 - gq, 0), rj1 = min(tl.z1 + gq, nz - 1);
+        const int w = cj1 - cj0;
+        const float sval = sv_lds[j - 1];
+        // the surface row first (its own branch of the update), then the rows
+        // below it, thread t taking nodes t, t + NT, ... in row-major order
+        auto node = [&](auto row_kind, int i, int k, int o) {
+            constexpr int RK = decltype(row_kind)::value;
+            const float2* Qo = Q + o;
+            const float* Lo = cl[0] + o;
+            const float* Mo = cl[1] + o;
+            auto U = [&](int ii, int kk) { return Qo[(kk - k) * RW + (ii - i)]; };
+            auto L = [&](int ii, int kk) { return Lo[(kk - k) * RW + (ii - i)]; };
+            auto M = [&](int ii, int kk) { return Mo[(kk - k) * RW + (ii - i)]; };
+            auto S = [&]() { return cl[2][o]; };
+            const int wk = k - sk0, wi = i - si0;
+            int inj = 0;
+            float w0 = 0.f, w1 = 0.f;
+            if ((unsigned)wk < (unsigned)kSrcW && (unsigned)wi < (unsigned)kSrcW) {
+                inj = 2;
+                w0 = sw_lds[(0 * kSrcW + wk) * kSrcW + wi];
+                w1 = sw_lds[(1 * kSrcW + wk) * kSrcW + wi];
+            }
+            const float2 nw = nodal_node_gen<RK>(U, L, M, S, P[o], i, k, inj, h2, sval, w0, w1);
+            P[o] = nw;
+            return nw;
+        };
+        int r0 = rj0;
+        if (w > 0 && rj0 == 0 && rj1 > 0) {
+            for (int i = cj0 + (int)threadIdx.x; i < cj1; i += NT) {
+                const float2 nw = node(std::integral_constant<int, 2>(), i, 0, i - tl.rx0 - tl.rz0 * RW);
+                if (i >= tl.x0 && i < tl.x1) {
+                    const int rec = ldi(d->recmap, i);
+                    if (rec >= 0) st2(traces, (size_t)lvl * nrec + rec, nw);
+                }
+            }
+            r0 = 1;
+        }
+        if (w > 0 && rj1 > r0) {
+            const int dk = NT / w, di = NT - dk * w;
+            const int t0 = (int)threadIdx.x / w;
+            int k = r0 + t0, i = cj0 + ((int)threadIdx.x - t0 * w);
+            int o = (k - tl.rz0) * RW + (i - tl.rx0);
+            const int dox = dk * RW + di, dow = RW - w;
+            while (k < rj1) {
+                node(std::integral_constant<int, 1>(), i, k, o);
+                i += di;
+                k += dk;
+                o += dox;
+                if (i >= cj1) {
+                    i -= w;
+                    ++k;
+                    o += dow;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    blk_store<TH, K, NT, RW>(tl, fld);
+}
+
 }  // namespace
 
 void launch_blocked_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int pass,
                             int variant, hipStream_t s) {
-    (void)variant;
-    stencil_layered_lds<64, 56, 4, 512, 2><<<ntiles, 512, 0, s>>>(descs, tiles, ntiles, pass);
+    switch (variant) {
+        case 24:
+            stencil_nodal_lds<64, 24, 4, 512, 2, true><<<ntiles, 512, 0, s>>>(descs, tiles,
+                                                                              ntiles, pass);
+            break;
+        case 25:
+            stencil_nodal_lds<64, 24, 4, 512, 2, false><<<ntiles, 512, 0, s>>>(descs, tiles,
+                                                                               ntiles, pass);
+            break;
+        default:
+            stencil_layered_lds<64, 56, 4, 512, 2><<<ntiles, 512, 0, s>>>(descs, tiles, ntiles,
+                                                                          pass);
+            break;
+    }
 }
 
 }  // namespace eig

@@ -59,7 +59,7 @@ struct eig_ctx {
     int default_variant = 4;      // one step per launch
     int default_variant_tb = 11;  // two steps per launch
     int default_variant_tb3 = 15; // three steps per launch
-    int temporal_blocking = 2;    // steps per launch for depth-only media: 1, 2 or 3
+    int temporal_blocking = 4;    // steps per launch for rigid edges: 1, 2, 3 or 4
     bool autotune = true;
     std::map<std::tuple<int, int, int, int, int>, int> tuned;
     int last_variant = -1;  // variant of the most recent stencil launch

@@ -144,7 +144,7 @@ void launch_source_tables(const SourceJob* jobs, int njobs, int max_nsteps,
 // bitwise-identical results; they differ only in speed.
 struct StencilVariant {
     int cols, rows, medium_kind;
-    int steps;  // leapfrog steps per launch (2, 3: four field buffers per solve)
+    int steps;  // leapfrog steps per launch (2, 3, 4: four field buffers per solve)
     int edges;  // 1: runs edge tiles (absorbing edges in the same launch)
     int resident;  // 1: one workgroup per solve, fields in LDS, all steps in one launch
 };
@@ -155,7 +155,7 @@ constexpr int kEdgeTileNodes = 128;
 inline int edge_tiles_of(int nx, int nz) {
     return (2 * nz + nx - 2 + kEdgeTileNodes - 1) / kEdgeTileNodes;
 }
-constexpr int kNumVariants = 24;
+constexpr int kNumVariants = 26;
 extern const StencilVariant kVariants[kNumVariants];
 // tiles: (solve index, strip << 16 | chunk) per wavefront
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
@@ -163,8 +163,8 @@ void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int s
 // Tiled depth-only variants (0..5, 7..16) of launch_stencil.
 void launch_layered_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                             int variant, hipStream_t s);
-// Depth-only variant 23 (K steps per launch, tile in LDS) of launch_stencil:
-// one workgroup per tile.
+// Variants 23 (depth-only) and 24, 25 (nodal) of launch_stencil: K steps
+// per launch with the tile in LDS, one workgroup per tile.
 void launch_blocked_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int pass,
                             int variant, hipStream_t s);
 // Nodal-media variants (6, 17..20) of launch_stencil.

@@ -106,6 +106,13 @@ __device__ __forceinline__ float2 layered_update(const LayerCoef& c, const NodeR
     return nw;
 }
 
+// An opaque copy: the compiler may not fuse the product that made x into a
+// later addition, so x enters every use rounded, as it does after a DPP move.
+__device__ __forceinline__ float pinned(float x) {
+    __asm__ volatile("" : "+v"(x));
+    return x;
+}
+
 // Nodal media: coef = three planes (lambda, mu, s = dt^2/(rho h^2)).
 //
 // Operands of the nodal operator at one node (i, k): the node's own values,
@@ -122,26 +129,34 @@ struct NodalView {
     float pR, pL, qR, qL;                  // the x-neighbours' p and q
 };
 
-// Acceleration terms at one node, before the scaling by s.
+// Acceleration terms at one node, before the scaling by s.  Every product
+// that is fused into a sum is written as an fmaf and nothing else is fused
+// (contraction off here), so the rounding does not depend on how the caller's
+// code around it is laid out: a kernel that knows the row's branch at compile
+// time rounds exactly as one that branches at run time.
 __device__ __forceinline__ float2 nodal_accel(const NodalView& n, bool top) {
-    const float ac = n.lam + 2.f * n.mu;
-    const float an = n.lamn + 2.f * n.mun;
-    float au = 0.5f * ((ac + n.aR) * (n.uR - n.u) - (n.aL + ac) * (n.u - n.uL));
-    float av = 0.5f * ((n.mu + n.mR) * (n.vR - n.v) - (n.mL + n.mu) * (n.v - n.vL));
+#pragma clang fp contract(off)
+    const float ac = __builtin_fmaf(2.f, n.mu, n.lam);
+    const float an = __builtin_fmaf(2.f, n.mun, n.lamn);
+    // a b - c d as fma(a, b, -(c d)).  The factors 1/2 and 1/4 are exact, so
+    // c (x + y) = c x + c y and c x + z = fma(c, x, z) bit for bit.
+    const float xu = __builtin_fmaf(ac + n.aR, n.uR - n.u, -((n.aL + ac) * (n.u - n.uL)));
+    const float xv = __builtin_fmaf(n.mu + n.mR, n.vR - n.v, -((n.mL + n.mu) * (n.v - n.vL)));
+    float au, av;
     if (top) {
         const float dxu_c = n.uR - n.uL, dxv_c = n.vR - n.vL;
-        au += (n.mu + n.mun) * (n.un - n.u);
-        av += (ac + an) * (n.vn - n.v);
+        au = __builtin_fmaf(n.mu + n.mun, n.un - n.u, 0.5f * xu);
+        av = __builtin_fmaf(ac + an, n.vn - n.v, 0.5f * xv);
         // 1/2 [lam_{i+1,0} (v_{i+1,1}-v_{i+1,0}) - lam_{i-1,0} (...)]
-        au += 0.5f * (n.pR - n.pL) + 0.5f * (n.mu * dxv_c + n.mun * n.dxvn);
-        av += 0.5f * (n.lam * dxu_c + n.lamn * n.dxun) + 0.5f * (n.qR - n.qL);
+        au = __builtin_fmaf(0.5f, (n.pR - n.pL) + __builtin_fmaf(n.mu, dxv_c, n.mun * n.dxvn), au);
+        av = __builtin_fmaf(0.5f, __builtin_fmaf(n.lam, dxu_c, n.lamn * n.dxun) + (n.qR - n.qL), av);
     } else {
-        const float am = n.lamm + 2.f * n.mum;
-        au += 0.5f * ((n.mu + n.mun) * (n.un - n.u) - (n.mum + n.mu) * (n.u - n.um));
-        av += 0.5f * ((ac + an) * (n.vn - n.v) - (am + ac) * (n.v - n.vm));
+        const float am = __builtin_fmaf(2.f, n.mum, n.lamm);
+        au = 0.5f * (xu + __builtin_fmaf(n.mu + n.mun, n.un - n.u, -((n.mum + n.mu) * (n.u - n.um))));
+        av = 0.5f * (xv + __builtin_fmaf(ac + an, n.vn - n.v, -((am + ac) * (n.v - n.vm))));
         // 1/4 [lam_{i+1,k} Dz v_{i+1} - lam_{i-1,k} Dz v_{i-1}], Dz w = w_{k+1} - w_{k-1}
-        au += 0.25f * (n.pR - n.pL) + 0.25f * (n.mun * n.dxvn - n.mum * n.dxvm);
-        av += 0.25f * (n.lamn * n.dxun - n.lamm * n.dxum) + 0.25f * (n.qR - n.qL);
+        au = __builtin_fmaf(0.25f, (n.pR - n.pL) + __builtin_fmaf(n.mun, n.dxvn, -(n.mum * n.dxvm)), au);
+        av = __builtin_fmaf(0.25f, __builtin_fmaf(n.lamn, n.dxun, -(n.lamm * n.dxum)) + (n.qR - n.qL), av);
     }
     return make_float2(au, av);
 }
@@ -149,17 +164,19 @@ __device__ __forceinline__ float2 nodal_accel(const NodalView& n, bool top) {
 // u^{m+1} from the acceleration terms, s, u^m, u^{m-1} and the forcing:
 // inj 1 adds a receiver force density (w0, w1) (dual solves), inj 2 the
 // source window weights (w0, w1) times the series value; dt^2/rho f = s h^2 f.
+// Fused products explicit, as in nodal_accel.
 __device__ __forceinline__ float2 nodal_new(float2 acc, float sc, float u, float v, float upu,
                                            float upv, int inj, float h2, float sval,
                                            float w0, float w1) {
+#pragma clang fp contract(off)
     float au = acc.x * sc, av = acc.y * sc;
     if (inj == 1) {
-        au += sc * h2 * w0;
-        av += sc * h2 * w1;
+        au = __builtin_fmaf(sc * h2, w0, au);
+        av = __builtin_fmaf(sc * h2, w1, av);
     } else if (inj == 2) {
         const float f = sc * h2 * sval;
-        au += f * w0;
-        av += f * w1;
+        au = __builtin_fmaf(f, w0, au);
+        av = __builtin_fmaf(f, w1, av);
     }
     float2 nw;
     nw.x = u + ((u - upu) + au);
@@ -167,23 +184,15 @@ __device__ __forceinline__ float2 nodal_new(float2 acc, float sc, float u, float
     return nw;
 }
 
-// An opaque copy: the compiler may not fuse the product that made x into a
-// later addition, so x enters every use rounded, as it does after a DPP move.
-__device__ __forceinline__ float pinned(float x) {
-    __asm__ volatile("" : "+v"(x));
-    return x;
-}
-
-// U(i, k) gives u^m (from device memory or LDS); up is u^{m-1} at the node;
-// the coefficient planes have row pitch `pitch`.
-template <class UF>
-__device__ __forceinline__ float2 nodal_node_at(UF U, float2 up, const float* LAM,
-                                                const float* MU, const float* SC, int pitch,
-                                                int i, int k, int inj, float h2, float sval,
-                                                float w0, float w1) {
-    auto L = [&](int ii, int kk) { return ld1(LAM, (size_t)kk * pitch + ii); };
-    auto M = [&](int ii, int kk) { return ld1(MU, (size_t)kk * pitch + ii); };
-    const bool top = k == 0;
+// U(i, k) gives u^m, L(i, k) and M(i, k) lambda and mu, S() the node's
+// dt^2/(rho h^2) (each from device memory or LDS); up is u^{m-1} at the node.
+// ROW: 0 any row, 1 a row below the surface, 2 the surface row (a caller
+// that knows which drops the other branch; the arithmetic is the same).
+template <int ROW = 0, class UF, class LF, class MF, class SF>
+__device__ __forceinline__ float2 nodal_node_gen(UF U, LF L, MF M, SF S, float2 up, int i, int k,
+                                                 int inj, float h2, float sval, float w0,
+                                                 float w1) {
+    const bool top = ROW == 0 ? k == 0 : ROW == 2;
     NodalView n;
     const float2 c = U(i, k), l = U(i - 1, k), r = U(i + 1, k);
     n.u = c.x;
@@ -231,8 +240,19 @@ __device__ __forceinline__ float2 nodal_node_at(UF U, float2 up, const float* LA
     n.qR = pinned(qR);
     n.qL = pinned(qL);
     const float2 acc = nodal_accel(n, top);
-    return nodal_new(acc, ld1(SC, (size_t)k * pitch + i), n.u, n.v, up.x, up.y, inj, h2, sval,
-                     w0, w1);
+    return nodal_new(acc, S(), n.u, n.v, up.x, up.y, inj, h2, sval, w0, w1);
+}
+
+// The same with the coefficient planes in device memory, row pitch `pitch`.
+template <class UF>
+__device__ __forceinline__ float2 nodal_node_at(UF U, float2 up, const float* LAM,
+                                                const float* MU, const float* SC, int pitch,
+                                                int i, int k, int inj, float h2, float sval,
+                                                float w0, float w1) {
+    auto L = [&](int ii, int kk) { return ld1(LAM, (size_t)kk * pitch + ii); };
+    auto M = [&](int ii, int kk) { return ld1(MU, (size_t)kk * pitch + ii); };
+    auto S = [&]() { return ld1(SC, (size_t)k * pitch + i); };
+    return nodal_node_gen(U, L, M, S, up, i, k, inj, h2, sval, w0, w1);
 }
 
 }  // namespace

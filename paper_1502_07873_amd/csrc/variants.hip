@@ -1,7 +1,7 @@
 // The stencil variants the host may run and their launcher.  All give
 // bitwise-identical fields; they differ in tile shape, steps per launch and
 // speed (tiled depth-only kernels: stencil.hip; nodal: nodal.hip; tile in LDS
-// over several steps: blocked.hip; whole solves in LDS: resident.hip).
+// over several steps, both media: blocked.hip; whole solves in LDS: resident.hip).
 #include "internal.h"
 
 namespace eig {
@@ -31,15 +31,17 @@ const StencilVariant kVariants[kNumVariants] = {
     {0, 0, EIG_MEDIUM_LAYERED, 1, 1, 1},  // 21: resident in LDS, every step in one launch
     {0, 0, EIG_MEDIUM_NODAL, 1, 1, 1},    // 22: resident in LDS, every step in one launch
     {64, 56, EIG_MEDIUM_LAYERED, 4},   // 23: four steps per launch, tile in LDS
+    {64, 24, EIG_MEDIUM_NODAL, 4},     // 24: nodal, four steps, tile and medium in LDS
+    {64, 24, EIG_MEDIUM_NODAL, 4},     // 25: the same, operands read per node
 };
 
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,
                     int variant, hipStream_t s) {
     if (ntiles <= 0) return;
-    if (kVariants[variant].medium_kind == EIG_MEDIUM_NODAL)
-        launch_nodal_stencil(descs, tiles, ntiles, step, variant, s);
-    else if (kVariants[variant].steps == 4)
+    if (kVariants[variant].steps == 4)
         launch_blocked_stencil(descs, tiles, ntiles, step, variant, s);
+    else if (kVariants[variant].medium_kind == EIG_MEDIUM_NODAL)
+        launch_nodal_stencil(descs, tiles, ntiles, step, variant, s);
     else
         launch_layered_stencil(descs, tiles, ntiles, step, variant, s);
 }

@@ -463,12 +463,14 @@ def test_stencil_variants_bitwise_identical(variant, nsteps, monkeypatch):
 
 
 @pytest.mark.parametrize("variant,nsteps", [(17, 333), (18, 333), (19, 333), (19, 334),
-                                            (20, 333), (20, 334)])
+                                            (20, 333), (20, 334), (24, 333), (24, 334),
+                                            (24, 335), (24, 336), (25, 333), (25, 336)])
 def test_nodal_variants_bitwise_identical(variant, nsteps, monkeypatch):
     # the two-nodes-per-lane nodal kernels (one step per launch: 17, 18; two
-    # steps: 19, 20, with odd and even step counts) hand the per-node update
-    # the same operands as the one-node kernel (variant 6): bit-for-bit equal
-    # traces, across strip boundaries and a ragged last strip, and the oracle's
+    # steps: 19, 20, with odd and even step counts) and the four-step kernels
+    # with the tile in LDS (24, 25: every step count mod 4) hand the per-node
+    # update the same operands as the one-node kernel (variant 6): bit-for-bit
+    # equal traces, across strip and tile boundaries, a ragged last strip, and the oracle's
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     from paper_1502_07873_amd import Context
@@ -496,7 +498,7 @@ def test_nodal_variants_bitwise_identical(variant, nsteps, monkeypatch):
         check_receivers(outs[variant][s], ref, TRACE_TOL, what=f"variant {variant} solve {s}")
 
 
-@pytest.mark.parametrize("variant", [20, 18])
+@pytest.mark.parametrize("variant", [20, 18, 24])
 def test_nodal_tile_interleave_is_bitwise_neutral(variant, monkeypatch):
     # tiles of consecutive solves on one nodal medium run position-major in
     # sets of coef_interleave; the sets here are ragged (5 solves of one
@@ -546,8 +548,8 @@ def test_nodal_tile_interleave_is_bitwise_neutral(variant, monkeypatch):
         check_receivers(outs[3][s], ref, TRACE_TOL, what=f"interleaved solve {s}")
 
 
-@pytest.mark.parametrize("tb", [3, 4])
-def test_multi_step_family_with_mixed_lengths_matches_one_step(tb):
+@pytest.mark.parametrize("tb,kind", [(3, "layered"), (4, "layered"), (4, "nodal")])
+def test_multi_step_family_with_mixed_lengths_matches_one_step(tb, kind):
     # temporal_blocking = 3 or 4 through the normal (tuned) path: solves of
     # different lengths in one wave (running prefixes of tiles and halo
     # tiles), tails of every shorter length; bitwise equal to one step per
@@ -558,7 +560,10 @@ def test_multi_step_family_with_mixed_lengths_matches_one_step(tb):
     from paper_1502_07873_amd.query import grid_tuple
     rng = np.random.default_rng(33)
     nx, nz, h = 300, 141, 10.0
-    med = synthetic.random_layers_medium(rng, nz, h, 3)
+    if kind == "nodal":
+        med = synthetic.nodal_perturbed_medium(rng, nz, nx, h, nlayers=3, corr_len=70.0)
+    else:
+        med = synthetic.random_layers_medium(rng, nz, h, 3)
     dt = synthetic.cfl_dt(h, med.vp_max())
     lens = [600, 431, 302, 601]
     grids = [synthetic.Grid(nx, nz, h, dt, n) for n in lens]
@@ -566,7 +571,7 @@ def test_multi_step_family_with_mixed_lengths_matches_one_step(tb):
     th = synthetic.draw_uniform(rng, lo, hi, len(lens))
     th[:, 2] = 0.08
     rec = np.array([1, 127, 128, 129, 255, 256, nx - 2], dtype=np.int32)
-    _say(f"{tb}-step family, mixed lengths")
+    _say(f"{tb}-step family, mixed lengths ({kind})")
     dm = _dev_medium(med)
     outs = []
     for t in (tb, 0):
@@ -663,9 +668,11 @@ def test_cache_sized_wave_chunks_match_one_wave():
     _say("cache-sized wave chunks vs one wave (40 mixed solves)")
     outs, launches = [], []
     # ~24 MB of live fields, mean 0.6 MB: a 10 MiB limit fits 16 solves,
-    # giving three chunks (solves regrouped by kind, grid and length)
+    # giving three chunks (solves regrouped by kind, grid and length); two
+    # steps per launch (four-step solves are never split for the cache)
     for lim in (0, 10 << 20):
         with Context(0, 2 << 30) as c:
+            c.set_option("temporal_blocking", 2)
             c.set_option("wave_cache_bytes", lim)
             assert c.get_option("wave_cache_bytes") == lim
             tr = [torch.empty((g.nsteps + 1, len(r), 2), dtype=torch.float32, device="cuda")

@@ -48,8 +48,8 @@ def _mix(seed, n):
     return cases
 
 
-@pytest.mark.parametrize("seed", [101, 202])
-def test_random_mix_in_small_chunks_matches_oracle(seed):
+@pytest.mark.parametrize("seed,tb", [(101, 2), (202, 2), (303, 4)])
+def test_random_mix_in_small_chunks_matches_oracle(seed, tb):
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     from paper_1502_07873_amd import Context
@@ -66,13 +66,17 @@ def test_random_mix_in_small_chunks_matches_oracle(seed):
     lim = int(16.5 * np.mean(live))
     assert sum(live) > 2 * lim
     with Context(0, 2 << 30) as c:
+        # two steps per launch: every rigid solve counts towards the limit;
+        # four (the default): rigid solves run unsplit, the rest in chunks
+        c.set_option("temporal_blocking", tb)
         c.set_option("wave_cache_bytes", lim)
         c.stencil_stats(reset=True)
         c.forward_solve_batch([grid_tuple(g) for g, _, _, _ in cases], dms,
                               np.stack([t for _, _, t, _ in cases]), [r for _, _, _, r in cases],
                               tr)
         torch.cuda.synchronize()
-        assert c.stencil_stats()["launches"] > max(g.nsteps for g, _, _, _ in cases)
+        if tb == 2:
+            assert c.stencil_stats()["launches"] > max(g.nsteps for g, _, _, _ in cases)
     for s, (g, m, th, r) in enumerate(cases):
         ref = elastic.forward(g, m, th, r)
         out = tr[s].cpu().numpy().astype(np.float64)
