@@ -43,6 +43,7 @@ CSRC = os.path.join(ROOT, "paper_1502_07873_amd", "csrc")
 # the kernel sources each counter record was taken on
 LAYERED_SOURCES = ("stencil.hip", "node_update.h", "tile.h")
 NODAL_SOURCES = ("nodal.hip", "node_update.h", "tile.h")
+BLOCKED_SOURCES = ("blocked.hip", "node_update.h", "tile.h")   # variants 23, 24, 25
 RESIDENT_SOURCES = ("resident.hip", "node_update.h", "ce.h")
 
 
@@ -74,9 +75,30 @@ def _measured_traffic(solves_per_launch, wave_cache_bytes, variant):
     """Bytes per stencil launch past the L2 caches (served by the last-level
     cache or HBM) from the committed rocprofv3 counter record, only if it was
     taken on these kernel sources, workload and wave size."""
-    rec = _counter_record(TRAFFIC_RECORD, LAYERED_SOURCES, solves_per_launch=solves_per_launch,
-                          variant=variant, wave_cache_bytes=wave_cache_bytes)
+    rec = _counter_record(TRAFFIC_RECORD, _kernel_sources(variant, LAYERED_SOURCES),
+                          solves_per_launch=solves_per_launch, variant=variant,
+                          wave_cache_bytes=wave_cache_bytes)
     return rec["traffic_bytes_per_launch"] if rec else None
+
+
+# fields the four-step kernel (variant 23: 64 x 56 tiles, a 4-node halo)
+# moves per update: the region's two levels in, the tile's two levels out
+BLOCKED_FLOOR_B = (72 * 64 + 64 * 56) * 16 / (64 * 56 * 4)
+
+
+def _kernel_sources(variant, tiled):
+    """The sources of a stencil variant's kernel: `tiled` unless it is one of
+    the four-step kernels with the tile in LDS."""
+    return BLOCKED_SOURCES if variant in (23, 24, 25) else tiled
+
+
+def _steps_per_launch(variant):
+    """Leapfrog steps one launch of a stencil variant takes."""
+    if variant in (15, 16):
+        return 3
+    if variant in (23, 24, 25):
+        return 4
+    return 2 if (9 <= variant <= 14 or variant in (19, 20)) else 1
 
 
 CPU_SHARE = 16   # host cores a one-GPU box grants a process
@@ -369,12 +391,16 @@ def _bench_c3(nsample=4096, oracle_check=True):
            "solves": 15 * nsample, "seconds": t, "sample_eig_evals_per_s": nsample / t,
            "grid_pt_updates_per_s": updates / t, "variant_last": variant,
            "workspace_GB": ws / 1e9, "flagged": int((status != 0).sum())}
-    out.update(_leg_roofline(st, "24 B per grid-point update (read u^m, u^{m-1}, write "
-                                 "u^{m+1}) over the stencil launch time, against the 8 TB/s "
-                                 "HBM peak; the waves run as cache-sized chunks, so the "
-                                 "launches read and write the 256 MB last-level cache (bound "
-                                 "'llc', as for c2) and achieved may approach or pass the HBM "
-                                 "figure", bound="llc"))
+    four = _steps_per_launch(variant) == 4
+    out.update(_leg_roofline(
+        st, "24 B per grid-point update (read u^m, u^{m-1}, write u^{m+1}) over the stencil "
+            "launch time, against the 8 TB/s HBM peak; " +
+            ("four steps per launch with the tile in LDS, one wave per grid and length "
+             "through HBM: the kernel moves about 9.1 B per update, so achieved can pass "
+             "the peak" if four else
+             "the waves run as cache-sized chunks, so the launches read and write the "
+             "256 MB last-level cache (bound 'llc') and achieved may approach or pass the "
+             "HBM figure"), bound="hbm" if four else "llc"))
     Hg = H1.cpu().numpy()
     seen = [k for k in picks if (np.diag(Hg[k]) > 0).all()]
     if oracle_check and seen:
@@ -470,8 +496,9 @@ def _bench_c5(reduced_grid=(512, 256, 1000), full_nodes=2, kmax=40, pipeline=Tru
           "projected_full_query_minutes": len(w) * t / full_nodes / 60}
     leg = _leg_roofline(st, "")
     avg_ms = leg["avg_launch_ms"]
-    solves_per_launch = round(st["updates"] / max(st["launches"], 1) / (pts * 2))
-    rec = _counter_record(NODAL_TRAFFIC_RECORD, NODAL_SOURCES,
+    solves_per_launch = round(st["updates"] / max(st["launches"], 1) /
+                              (pts * _steps_per_launch(variant)))
+    rec = _counter_record(NODAL_TRAFFIC_RECORD, _kernel_sources(variant, NODAL_SOURCES),
                           variant=variant, solves_per_launch=solves_per_launch,
                           coef_interleave=coef_interleave)
     traffic = rec["traffic_bytes_per_launch"] if rec else None
@@ -1124,8 +1151,7 @@ def main():
     total_ms = ev[0].elapsed_time(ev[-1])
     st = jac_stats
     variant = ctx.get_option("last_variant")
-    steps_per_launch = 3 if variant in (15, 16) else (2 if (9 <= variant <= 14 or
-                                                             variant in (19, 20)) else 1)
+    steps_per_launch = _steps_per_launch(variant)
     S = len(wl.theta)
     value = S * args.steps / (total_ms / 1e3)
     avg_launch_ms = st["ms"] / max(st["launches"], 1)
@@ -1140,6 +1166,8 @@ def main():
     traffic = _measured_traffic(round(solves_per_launch), ctx.get_option("wave_cache_bytes"),
                                 variant)
     traffic_rate = traffic / (avg_launch_ms * 1e-3) / 1e9 if traffic else None
+    in_cache = steps_per_launch < 4   # two or three steps: cache-sized chunks
+    floor_b = {1: 24.0, 2: 16.0, 3: 32.0 / 3.0, 4: BLOCKED_FLOOR_B}[steps_per_launch]
     status_ok = int(out["status"].abs().sum()) == 0 and int(out["chol_status"].abs().sum()) == 0
     line = {
         "metric": METRIC,
@@ -1167,48 +1195,61 @@ def main():
         "stencil": {"launches": st["launches"], "avg_launch_ms": avg_launch_ms,
                     "variant": variant, "steps_per_launch": steps_per_launch,
                     "bytes_per_launch": bytes_per_launch,
-                    "kernel_floor_bytes_per_update": 16 if steps_per_launch == 2 else 24,
-                    "achieved_at_kernel_floor_GBs":
-                        achieved * (16 if steps_per_launch == 2 else 24) / 24,
+                    "kernel_floor_bytes_per_update": floor_b,
+                    "achieved_at_kernel_floor_GBs": achieved * floor_b / 24,
                     "time_frac_of_step": st["ms"] / total_ms,
                     "solves_per_launch": solves_per_launch,
-                    "note": "launches of the 15*S-solve jacobian_fd wave, run as chunks "
-                            "whose fields (4 buffers per solve) fit wave_cache_bytes, so "
-                            "they stay in the 256 MB last-level cache between launches; "
-                            "bytes_per_launch and roofline.achieved count 24 B per "
-                            "grid-point update (read u^m, u^{m-1}, write u^{m+1}); a "
-                            "two-steps-per-launch kernel needs only 16 B per update "
-                            "(achieved_at_kernel_floor_GBs)"},
+                    "note": ("launches of the 15*S-solve jacobian_fd wave, every solve in "
+                             "every launch (four steps per launch with each 64x56 tile and "
+                             "its 4-node halo in LDS: the fields stream through HBM)"
+                             if not in_cache else
+                             "launches of the 15*S-solve jacobian_fd wave, run as chunks "
+                             "whose fields (4 buffers per solve) fit wave_cache_bytes, so "
+                             "they stay in the 256 MB last-level cache between launches") +
+                            "; bytes_per_launch and roofline.achieved count 24 B per "
+                            "grid-point update (read u^m, u^{m-1}, write u^{m+1}); "
+                            "kernel_floor_bytes_per_update: what the kernel itself must "
+                            "move per update (achieved_at_kernel_floor_GBs)"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)),
                        "p99": float(np.percentile(lat, 99))},
-        "roofline": {"bound": "llc", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "roofline": {"bound": "llc" if in_cache else "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "traffic_rate_GBs": traffic_rate,
                      "llc_copy_GBs_measured": llc_copy_gbs,
-                     "frac_of_llc_copy": (traffic_rate / llc_copy_gbs if traffic_rate
-                                          else None),
+                     "frac_of_llc_copy": (traffic_rate / llc_copy_gbs
+                                          if traffic_rate and in_cache else None),
                      "copy_GBs_measured": copy_gbs,
+                     "frac_of_copy": (traffic_rate / copy_gbs
+                                      if traffic_rate and not in_cache else None),
                      "wave_cache_bytes": ctx.get_option("wave_cache_bytes"),
-                     "note": "the headline launches work in the 256 MB last-level cache "
-                             "(cache-sized chunks), so the bound is that cache, not HBM. "
-                             "achieved: 24 B per update (algorithmic) over the launch time; "
-                             "frac: achieved / the 8 TB/s HBM peak (the only published "
-                             "figure; achieved can pass it since the cache serves the "
-                             "fields). traffic: bytes per launch past L2 from the counter "
-                             "record; frac_of_llc_copy: that traffic rate over a plain "
-                             "96 MiB copy measured in this run (llc_copy_GBs_measured). "
-                             "hbm_streamed: the same query as one unsplit wave, whose "
-                             "launches stream every field through HBM"},
+                     "note": "achieved: 24 B per update (algorithmic: read u^m, u^{m-1}, "
+                             "write u^{m+1}) over the launch time; frac: achieved / the "
+                             "8 TB/s HBM peak. " + (
+                                 "The kernel takes four steps per launch with the tile in "
+                                 "LDS, so it moves about 9.1 B per update, not 24: "
+                                 "achieved can pass the peak. traffic: bytes per launch "
+                                 "past L2 from the counter record; frac_of_copy: that "
+                                 "traffic rate over a plain 2 x 4 GiB copy measured in "
+                                 "this run (copy_GBs_measured). two_step_llc: the same "
+                                 "query with two steps per launch in cache-sized chunks"
+                                 if not in_cache else
+                                 "The launches work in the 256 MB last-level cache "
+                                 "(cache-sized chunks), so the bound is that cache; "
+                                 "traffic: bytes per launch past L2 from the counter record; "
+                                 "frac_of_llc_copy: that rate over a plain 96 MiB copy "
+                                 "measured in this run")},
         "wall_s": wall,
     }
     if args.headline_only:
         print(json.dumps(line), flush=True)
         ctx.close()
         return
-    # the same query as one unsplit wave: every launch streams all fields
-    # through HBM
-    print("[bench] unsplit wave (fields streamed through HBM)", flush=True)
-    ctx.set_option("wave_cache_bytes", 0)
+    # the same query with the other temporal-blocking family: two steps per
+    # launch in cache-sized chunks (or four steps, if two ran above)
+    other_tb = 2 if not in_cache else 4
+    print(f"[bench] same query, temporal_blocking {other_tb}", flush=True)
+    tb0 = ctx.get_option("temporal_blocking")
+    ctx.set_option("temporal_blocking", other_tb)
     one_step()
     torch.cuda.synchronize()
     ctx.stencil_stats(reset=True)
@@ -1219,19 +1260,18 @@ def main():
     torch.cuda.synchronize()
     stu = ctx.stencil_stats(reset=True)
     tu = e0.elapsed_time(e1) / 1e3
-    ctx.set_option("wave_cache_bytes", args.wave_cache_mib << 20)
-    hbm_ach = stu["bytes"] / (stu["ms"] * 1e-3) / 1e9
-    line["unsplit_wave"] = {
-        "value": S / tu, "unit": "sample-EIG evals/s",
+    vu = ctx.get_option("last_variant")
+    ctx.set_option("temporal_blocking", tb0)
+    ach_u = stu["bytes"] / (stu["ms"] * 1e-3) / 1e9
+    line["two_step_llc" if other_tb == 2 else "four_step_hbm"] = {
+        "value": S / tu, "unit": "sample-EIG evals/s", "variant": vu,
+        "steps_per_launch": _steps_per_launch(vu),
         "avg_launch_ms": stu["ms"] / max(stu["launches"], 1),
-        "achieved_GBs": hbm_ach,
-        "speedup_of_chunked": value / (S / tu),
+        "launches": stu["launches"],
+        "grid_pt_updates_per_s_stencil": stu["updates"] / (stu["ms"] * 1e-3),
+        "achieved_GBs": ach_u, "frac": ach_u / HBM_PEAK_GBS,
+        "headline_speedup": value / (S / tu),
         "dkl_match": bool(np.array_equal(ou["dkl"].cpu().numpy(), dkl))}
-    line["roofline"]["hbm_streamed"] = {
-        "bound": "hbm", "achieved": hbm_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": hbm_ach / HBM_PEAK_GBS, "frac_of_copy": hbm_ach / copy_gbs,
-        "note": "24 B per update over the launch time of the unsplit 3840-solve wave (two "
-                "steps per launch: the kernel itself moves 16 B per update)"}
     # the plain GPU path: the same kernels, one solve per launch
     print("[bench] one-solve-per-launch GPU baseline (2 samples)", flush=True)
     ctx1 = Context(0, 8 << 30)

@@ -203,7 +203,7 @@ void stencil_candidates(const eig_ctx* c, int kind, bool one_step, std::vector<i
     const int steps = family_steps_of(c, kind, one_step);
     for (int v = 1; v < kNumVariants; ++v)
         if (kVariants[v].medium_kind == kind && kVariants[v].steps == steps &&
-            !kVariants[v].resident)
+            !kVariants[v].resident && !kVariants[v].forced_only)
             out.push_back(v);
     if (out.empty()) out.push_back(kind == EIG_MEDIUM_NODAL ? 6 : 0);
     if (!c->autotune) {

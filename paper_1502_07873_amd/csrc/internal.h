@@ -147,6 +147,7 @@ struct StencilVariant {
     int steps;  // leapfrog steps per launch (2, 3, 4: four field buffers per solve)
     int edges;  // 1: runs edge tiles (absorbing edges in the same launch)
     int resident;  // 1: one workgroup per solve, fields in LDS, all steps in one launch
+    int forced_only;  // 1: runs only when forced (not a tuning candidate)
 };
 // Tile entries (solve, kEdgeStrip << 16 | part) of a variant with `edges`:
 // absorbing edge nodes part * kEdgeTileNodes .. +kEdgeTileNodes of a solve.

@@ -32,7 +32,7 @@ const StencilVariant kVariants[kNumVariants] = {
     {0, 0, EIG_MEDIUM_NODAL, 1, 1, 1},    // 22: resident in LDS, every step in one launch
     {64, 56, EIG_MEDIUM_LAYERED, 4},   // 23: four steps per launch, tile in LDS
     {64, 24, EIG_MEDIUM_NODAL, 4},     // 24: nodal, four steps, tile and medium in LDS
-    {64, 24, EIG_MEDIUM_NODAL, 4},     // 25: the same, operands read per node
+    {64, 24, EIG_MEDIUM_NODAL, 4, 0, 0, 1},  // 25: the same, operands read per node (forced only)
 };
 
 void launch_stencil(const SolveDesc* descs, const int2* tiles, int ntiles, int step,

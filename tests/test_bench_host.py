@@ -43,18 +43,31 @@ def test_traffic_reported_only_for_the_recorded_kernel_and_launch(tmp_path):
     assert bench._measured_traffic(24, 192 << 20, 9) is None
     bench.TRAFFIC_RECORD = str(tmp_path / "missing.json")
     assert bench._measured_traffic(24, 192 << 20, 9) is None
+    # the four-step kernel's record is keyed to its own sources
+    rec = {"kernel_source_sha256": bench._sources_sha(*bench.BLOCKED_SOURCES),
+           "solves_per_launch": 3840, "variant": 23, "wave_cache_bytes": 192 << 20,
+           "traffic_bytes_per_launch": 3.9e10}
+    path.write_text(json.dumps(rec))
+    bench.TRAFFIC_RECORD = str(path)
+    assert bench._measured_traffic(3840, 192 << 20, 23) == 3.9e10
+    rec["kernel_source_sha256"] = sha                             # the tiled kernels' hash
+    path.write_text(json.dumps(rec))
+    assert bench._measured_traffic(3840, 192 << 20, 23) is None
 
 
-@pytest.mark.parametrize("record,sources", [("stencil_layered_c2_traffic.json", "LAYERED_SOURCES"),
-                                            ("stencil_nodal_c5_traffic.json", "NODAL_SOURCES"),
-                                            ("stencil_resident_model_problem.json",
-                                             "RESIDENT_SOURCES")])
-def test_committed_counter_records_match_the_kernel_sources(record, sources):
-    # each record under profiles/ must describe its kernel's sources as they
-    # are (else the bench reports its traffic as null)
+@pytest.mark.parametrize("record,tiled", [("stencil_layered_c2_traffic.json", "LAYERED_SOURCES"),
+                                          ("stencil_nodal_c5_traffic.json", "NODAL_SOURCES"),
+                                          ("stencil_resident_model_problem.json",
+                                           "RESIDENT_SOURCES")])
+def test_committed_counter_records_match_the_kernel_sources(record, tiled):
+    # each record under profiles/ names the sources of its variant's kernel
+    # (the ones bench.py hashes for that variant) and must describe them as
+    # they are (else the bench reports its traffic as null)
     bench = _bench_module()
     rec = json.load(open(os.path.join(ROOT, "profiles", record)))
-    if rec["kernel_source_sha256"] != bench._sources_sha(*getattr(bench, sources)):
+    sources = bench._kernel_sources(rec["variant"], getattr(bench, tiled))
+    assert tuple(rec["sources"]) == sources
+    if rec["kernel_source_sha256"] != bench._sources_sha(*sources):
         pytest.xfail(f"{sources} changed since the counters of {record} were taken: bench "
                      "reports their figures as null until they are taken again")
     traffic = rec.get("traffic_bytes_per_launch", rec.get("traffic_bytes_per_update"))
