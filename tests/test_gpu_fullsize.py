@@ -239,9 +239,9 @@ def test_c5_full_size_node_against_oracle():
     assert np.max(np.abs((Hr.sum(axis=0) - Ha) / sc)) <= 1e-12
     assert np.linalg.eigvalsh(Ha / sc).min() > 0
     assert np.max(np.abs((Hs - Ha) / sc)) <= 1e-3
-    _say("c5 full size: nodal kernels 6, 17, 18, 19, 20 on one solve")
+    _say("c5 full size: nodal kernels 6, 17, 18, 19, 20, 24, 25 on one solve")
     outs = []
-    for v in (6, 17, 18, 19, 20):
+    for v in (6, 17, 18, 19, 20, 24, 25):
         tr = [torch.empty((wl.grid.nsteps + 1, R, 2), dtype=torch.float32, device="cuda")]
         with Context(0, 16 << 30) as ctx:
             ctx.set_option("stencil_variant", v)
