@@ -203,9 +203,11 @@ int eig_ctx_stencil_stats(eig_ctx* ctx, int32_t reset, double* ms, int64_t* laun
  *                      all such admitted groups stay within it (groups shrink
  *                      to fit; at least one group is always admitted), and
  *                      use 16-row tiles, so their launches work in the
- *                      last-level cache; queries with larger samples are
- *                      admitted by memory alone.  0: admit whatever memory
- *                      and slots allow.  Results do not depend on it.
+ *                      last-level cache; queries with larger samples, and
+ *                      every query of a kind that takes four steps per
+ *                      launch ("temporal_blocking" 4), are admitted by
+ *                      memory alone.  0: admit whatever memory and slots
+ *                      allow.  Results do not depend on it.
  *   "fused_edges"      1 (default): the two-nodes-per-lane one-step kernels
  *                      update absorbing edge nodes in extra wavefronts of
  *                      their own launch; 0: a separate edge kernel after each
@@ -219,8 +221,9 @@ int eig_ctx_set_option(eig_ctx* ctx, const char* name, int64_t value);
  * with rigid edges, 4 (default: the tile and its halo in LDS for four steps,
  * variants 23 depth-only, 24 and 25 nodal), 2 (1 also selects 2), 3
  * (depth-only media; nodal media then take two), or 0 for one step; two to
- * four steps per launch keep four field buffers per solve.  The serving engine takes two steps per
- * launch for depth-only media and one for nodal media. */
+ * four steps per launch keep four field buffers per solve.  Serving engines
+ * created while it is 4 take four steps per launch for both media (variants
+ * 23, 24); otherwise two for depth-only media and one for nodal media. */
 int eig_ctx_get_option(const eig_ctx* ctx, const char* name, int64_t* value);
 
 /*

@@ -12,8 +12,8 @@
 // at which a launch already keeps the device busy.  A short query that
 // arrives behind a long one therefore runs at once, alone or beside other
 // short ones, and the long one resumes when it is done.  Every launch
-// advances each scheduled solve by one leapfrog step (two for the two-step
-// kernel): a solve with `done` launches behind it that is scheduled at
+// advances each scheduled solve by one leapfrog step (two or four for the
+// multi-step kernels): a solve with `done` launches behind it that is scheduled at
 // launch L has SolveDesc::start = L - done, rewritten when a paused group
 // resumes.  Segment boundaries also fall where a scheduled group finishes;
 // there finished groups get their Hessian kernels and free their memory and
@@ -159,7 +159,7 @@ struct eig_server {
     // that cache instead of HBM; 0: admit whatever memory and slots allow
     size_t cache_bytes = 0;
     size_t live = 0;
-    int spl = 1;  // leapfrog steps per launch of the layered variant
+    int spl_layered = 1, spl_nodal = 1;  // leapfrog steps per launch of each kind's variant
     std::deque<SrvQuery*> queue;
     std::map<int64_t, std::unique_ptr<SrvQuery>> queries;
     std::vector<SrvGroup> groups;
@@ -172,6 +172,10 @@ struct eig_server {
 
 namespace {
 
+int spl_of(const eig_server* v, int kind) {
+    return kind == EIG_MEDIUM_NODAL ? v->spl_nodal : v->spl_layered;
+}
+
 // Admits one sample group of queued query q if memory, slots and the cache
 // limit allow (*ok), else leaves everything as it was.
 int srv_admit_group(eig_server* v, SrvQuery& q, hipStream_t s, bool* ok) {
@@ -180,12 +184,13 @@ int srv_admit_group(eig_server* v, SrvQuery& q, hipStream_t s, bool* ok) {
     {
         int G = std::min(v->group_samples, q.nsample - q.next_sample);
         G = std::min<int>(G, (int)(v->nslot_cap / 15));
-        const bool four_buf = q.medium.kind == EIG_MEDIUM_LAYERED && v->spl == 2;
-        const size_t sample_live = (size_t)15 * (four_buf ? 4 : 2) * q.grid.nz *
+        const int spl = spl_of(v, q.medium.kind);
+        const size_t sample_live = (size_t)15 * (spl >= 2 ? 4 : 2) * q.grid.nz *
                                    pitch_of(q.grid.nx) * sizeof(float2);
         // the cache limit applies to queries one of whose samples fits it;
-        // larger ones gain nothing from it and are admitted by memory alone
-        const bool cached = v->cache_bytes && sample_live <= v->cache_bytes;
+        // larger ones gain nothing from it and are admitted by memory alone,
+        // and so are four-step kinds, which stream HBM at their floor
+        const bool cached = v->cache_bytes && spl < 4 && sample_live <= v->cache_bytes;
         if (cached) {
             G = std::min<int>(G, (int)(v->cache_bytes / sample_live));
             if (!v->groups.empty() && v->live + (size_t)G * sample_live > v->cache_bytes)
@@ -224,7 +229,7 @@ int srv_admit_group(eig_server* v, SrvQuery& q, hipStream_t s, bool* ok) {
         gr.live = cached ? (size_t)G * sample_live : 0;
         gr.start = v->launch;
         gr.nsteps = q.grid.nsteps;
-        const bool four = q.medium.kind == EIG_MEDIUM_LAYERED && v->spl == 2;
+        const bool four = spl >= 2;
         // carve the group's region
         char* base = v->mem + off;
         const eig_grid& g = q.grid;
@@ -430,7 +435,7 @@ int srv_finish_query(eig_server* v, SrvQuery& q, hipStream_t s) {
 
 // launches a group needs in total
 int64_t group_launches(const eig_server* v, const SrvGroup& gr) {
-    const int spl = gr.q->medium.kind == EIG_MEDIUM_LAYERED ? v->spl : 1;
+    const int spl = spl_of(v, gr.q->medium.kind);
     return (gr.nsteps + spl - 1) / spl;
 }
 
@@ -471,7 +476,7 @@ double query_work_left(const eig_server* v, const SrvQuery& q) {
     double w = 15.0 * (q.nsample - q.next_sample) * pts * q.grid.nsteps;
     for (const auto& gr : v->groups) {
         if (gr.q != &q) continue;
-        const int spl = q.medium.kind == EIG_MEDIUM_LAYERED ? v->spl : 1;
+        const int spl = spl_of(v, q.medium.kind);
         w += (double)gr.nslot * pts * std::max<int64_t>(0, gr.nsteps - spl * gr.done);
     }
     return w;
@@ -580,20 +585,30 @@ int eig_server_create(eig_ctx* c, size_t budget, int32_t group_samples, eig_serv
     v->ctx = c;
     v->group_samples = group_samples > 0 ? group_samples : 16;
     // the server advances groups launch by launch: resident variants (a
-    // whole time loop per launch) are not used here
-    const bool forced = c->forced_variant >= 0 && !kVariants[c->forced_variant].resident;
-    v->variant_layered = forced &&
-                                 kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_LAYERED
-                             ? c->forced_variant
-                             : (c->temporal_blocking >= 2 ? c->default_variant_tb : c->default_variant);
+    // whole time loop per launch) are not used here.  Rigid edges only, so
+    // with temporal_blocking 4 (the default) both kinds take four steps per
+    // launch with the tile in LDS (variants 23, 24); otherwise depth-only
+    // media take two steps (16-row tiles under the cache limit) and nodal
+    // media one, with two nodes per lane
+    const int fv = c->forced_variant;
+    const bool forced = fv >= 0 && !kVariants[fv].resident;
+    const bool forced_layered = forced && kVariants[fv].medium_kind == EIG_MEDIUM_LAYERED;
+    const bool forced_nodal = forced && kVariants[fv].medium_kind == EIG_MEDIUM_NODAL;
     v->cache_bytes = c->serve_cache_bytes;
-    if (v->cache_bytes && !(forced &&
-                            kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_LAYERED))
+    if (forced_layered)
+        v->variant_layered = fv;
+    else if (c->temporal_blocking == 4)
+        v->variant_layered = 23;
+    else if (v->cache_bytes)
         v->variant_layered = c->temporal_blocking >= 2 ? 9 : c->default_variant;
-    v->spl = kVariants[v->variant_layered].steps;
-    // nodal media: two nodes per lane unless a nodal variant is forced
-    if (forced && kVariants[c->forced_variant].medium_kind == EIG_MEDIUM_NODAL)
-        v->variant_nodal = c->forced_variant;
+    else
+        v->variant_layered = c->temporal_blocking >= 2 ? c->default_variant_tb : c->default_variant;
+    if (forced_nodal)
+        v->variant_nodal = fv;
+    else if (c->temporal_blocking == 4)
+        v->variant_nodal = 24;
+    v->spl_layered = kVariants[v->variant_layered].steps;
+    v->spl_nodal = kVariants[v->variant_nodal].steps;
     v->nslot_cap = 1 << 17;
     if (hipMalloc((void**)&v->mem, budget) != hipSuccess) {
         (void)hipGetLastError();
@@ -729,7 +744,7 @@ int eig_server_step(eig_server* v, int32_t max_launches, void* stream, int32_t* 
             double upd = 0.0;
             for (auto& gr : v->groups) {
                 if (!gr.on) continue;
-                const int spl = gr.q->medium.kind == EIG_MEDIUM_LAYERED ? v->spl : 1;
+                const int spl = spl_of(v, gr.q->medium.kind);
                 const int64_t left = gr.nsteps - spl * gr.done;
                 upd += (double)gr.q->grid.nx * gr.q->grid.nz * gr.nslot *
                        (double)std::min<int64_t>(spl, left);

@@ -690,15 +690,21 @@ def test_cache_sized_wave_chunks_match_one_wave():
     assert max(np.max(np.abs(a)) for a in outs[0]) > 0
 
 
-@pytest.mark.parametrize("cache_bytes", [0, 3 << 20, 192 << 20])
-def test_server_alone_equals_mix_and_matches_jacobian_path(ctx, cache_bytes):
+@pytest.mark.parametrize("cache_bytes,tb", [(0, 4), (3 << 20, 4), (192 << 20, 4),
+                                           (0, 2), (3 << 20, 2), (192 << 20, 2)])
+def test_server_alone_equals_mix_and_matches_jacobian_path(ctx, cache_bytes, tb):
     # cache_bytes > 0: admission limited to that many live field bytes
-    # (groups shrink to fit, queries wait for room) - the same results
+    # (groups shrink to fit, queries wait for room) for kinds that take one
+    # or two steps per launch (tb 2); tb 4: both kinds take four steps per
+    # launch and are admitted by memory alone - the same results
     from paper_1502_07873_amd import eigseis, make_prior
     from paper_1502_07873_amd.query import grid_tuple, run_query
-    _say(f"serving engine: alone vs mix (serve_cache_bytes {cache_bytes})")
+    _say(f"serving engine: alone vs mix (serve_cache_bytes {cache_bytes}, "
+         f"temporal_blocking {tb})")
     default_cache = ctx.get_option("serve_cache_bytes")
+    default_tb = ctx.get_option("temporal_blocking")
     ctx.set_option("serve_cache_bytes", cache_bytes)
+    ctx.set_option("temporal_blocking", tb)
     wlA = synthetic.config("c1", nsample=5)[0]
     rng = np.random.default_rng(3)
     medB = synthetic.random_layers_medium(rng, 70, 15.0, 3)
@@ -751,13 +757,15 @@ def test_server_alone_equals_mix_and_matches_jacobian_path(ctx, cache_bytes):
     torch.cuda.synchronize()
     assert torch.equal(ref["H1"], alone[0]["H1"])
     assert torch.equal(ref["dkl"], alone[0]["dkl"])
-    # a nodal-medium query in the mix (the server's two-node nodal kernel)
+    # a nodal-medium query in the mix (the server's four-step or two-node
+    # nodal kernel)
     refN = run_query(ctx, grid_tuple(gN), dN, recN, loN, hiN, thN, np.full(3, 1.0 / 3),
                      sigma=0.9)
     torch.cuda.synchronize()
     assert torch.equal(refN["H1"], mix[3]["H1"])
     assert torch.equal(refN["dkl"], mix[3]["dkl"])
     ctx.set_option("serve_cache_bytes", default_cache)
+    ctx.set_option("temporal_blocking", default_tb)
 
 
 def test_sparse_quadrature_greedy_pipeline_c5_shape(ctx):
