@@ -498,6 +498,54 @@ def test_nodal_variants_bitwise_identical(variant, nsteps, monkeypatch):
         check_receivers(outs[variant][s], ref, TRACE_TOL, what=f"variant {variant} solve {s}")
 
 
+@pytest.mark.parametrize("kind,nx,nz", [("layered", 65, 20), ("layered", 257, 113),
+                                         ("nodal", 65, 26), ("nodal", 193, 50)])
+def test_four_step_kernels_on_ragged_grids(kind, nx, nz, monkeypatch):
+    # the four-step kernels (tile and halo in LDS) on grids that are not
+    # multiples of their tiles: a last strip one column wide (nx = 65, 257,
+    # 193), fewer free rows than a tile (nz = 20, 26) and a ragged last row
+    # band; sources at the corners of the source box (near the sides and the
+    # bottom), receivers on tile edges; every step count mod 4; bitwise equal
+    # to the one-step kernel and the oracle's traces
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1502_07873_amd import Context
+    rng = np.random.default_rng(nx * 1000 + nz)
+    h = 10.0
+    if kind == "nodal":
+        med = synthetic.nodal_perturbed_medium(rng, nz, nx, h, nlayers=2, corr_len=40.0)
+        fours, one = (24, 25), 6
+    else:
+        med = synthetic.random_layers_medium(rng, nz, h, 2)
+        fours, one = (23,), 0
+    rec = np.unique(np.r_[1, 56, 63, 64, 65, 127, 128, nx - 2])
+    rec = rec[rec <= nx - 2].astype(np.int32)
+    for nsteps in (201, 202, 203, 204):
+        grid = synthetic.Grid(nx, nz, h, synthetic.cfl_dt(h, med.vp_max()), nsteps)
+        lo, hi = synthetic.prior_box(grid)
+        th = synthetic.draw_uniform(rng, lo, hi, 4)
+        th[:, 0] = [lo[0], hi[0], lo[0], hi[0]]   # both sides
+        th[:, 1] = [lo[1], hi[1], hi[1], lo[1]]   # mid-depth and the bottom
+        th[:, 2] = 0.08
+        _say(f"four-step kernels {fours} on {kind} {nx}x{nz}x{nsteps}")
+        outs = {}
+        for v in (one,) + fours:
+            monkeypatch.setenv("EIG_STENCIL_VARIANT", str(v))
+            c = Context(0, 1 << 30)
+            outs[v] = _forward(c, grid, med, th, rec)
+            assert c.get_option("last_variant") == v
+            c.close()
+        for v in fours:
+            for s in range(len(th)):
+                assert np.array_equal(outs[one][s], outs[v][s]), (v, nsteps, s)
+        if nsteps == 203:
+            for s in (1, 2):
+                ref = elastic.forward(grid, med, th[s], rec)
+                assert np.max(np.abs(ref)) > 0
+                check_receivers(outs[fours[0]][s], ref, TRACE_TOL,
+                                what=f"{kind} {nx}x{nz} solve {s}")
+
+
 @pytest.mark.parametrize("variant", [20, 18, 24])
 def test_nodal_tile_interleave_is_bitwise_neutral(variant, monkeypatch):
     # tiles of consecutive solves on one nodal medium run position-major in
