@@ -1189,7 +1189,7 @@ int nested_mc_eig(eig_ctx* c, int32_t nouter, int32_t ninner, int32_t nobs,
         return set_error(EIG_EINVAL, "NULL array argument");
     if (!(sigma > 0) || !std::isfinite(sigma)) return set_error(EIG_EINVAL, "sigma");
     HIP_TRY(hipSetDevice(c->device));
-    const int rc = ensure_ws(c, nested_workspace(nouter, ninner));
+    const int rc = ensure_ws(c, nested_workspace(nouter, ninner, nobs));
     if (rc) return rc;
     launch_nested(g_outer, noise, g_inner, nouter, ninner, nobs, sigma, logratio, eig,
                   (double*)c->ws, (hipStream_t)stream);

@@ -191,9 +191,10 @@ void launch_resident(const SolveDesc* descs, const int2* tiles, int ntiles, int 
 void launch_tb3_halo(const SolveDesc* descs, const int2* htiles, int nhtiles, int pass,
                      hipStream_t s);
 // Nested Monte Carlo log ratios (and their mean when eig != NULL); work
-// holds nested_workspace() bytes: per-split partial sums, squared norms.
+// holds nested_workspace() bytes: per-split partial sums, squared norms, and
+// FP64 k-major copies of the outer data and inner outputs.
 int nested_splits(int nouter, int ninner);
-size_t nested_workspace(int nouter, int ninner);
+size_t nested_workspace(int nouter, int ninner, int nobs);
 void launch_nested(const float* gout, const float* noise, const float* gin, int nouter,
                    int ninner, int nobs, double sigma, double* logratio, double* eig,
                    double* work, hipStream_t s);

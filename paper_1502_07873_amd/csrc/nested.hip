@@ -20,10 +20,12 @@
 // Work decomposition: a 512-thread block (8 waves, 4 x 2) owns 128 outer rows
 // and a range of inner samples (the range is split over several blocks when
 // the rows alone cannot fill the chip), swept in tiles of 128 columns; each
-// wave accumulates 2 x 4 MFMA tiles (32 rows x 64 columns).  k is staged
-// through LDS in chunks of 16 (y in FP64, g as FP64 copies of the FP32
-// inputs), double buffered, with the global loads of the chunk after next in
-// flight while the current one is multiplied: one barrier per chunk.  After a
+// wave accumulates 2 x 4 MFMA tiles (32 rows x 64 columns).  A first pass
+// writes y and g as FP64, k-major and zero-padded to whole tiles and chunks
+// (Yt[k][n], Gt[k][m]); k is then staged through LDS in chunks of 16 with
+// 16-byte copies and nothing else (no conversion, no bounds), double
+// buffered, with the global loads of the chunk after next in flight while
+// the current one is multiplied: one barrier per chunk.  After a
 // tile's last chunk every lane folds its 32 distances into an online
 // log-sum-exp per row: the running maximum and the rescaling of the running
 // sum in FP64, the terms within 40 nats of the maximum as FP32 exponentials
@@ -44,13 +46,15 @@ constexpr int kWR = 2, kWC = 4, kGR = 4, kGC = 2, kKC = 16;
 constexpr int kThreads = 64 * kGR * kGC;          // 512
 constexpr int kTN = 16 * kGR * kWR;               // 128 outer rows per block
 constexpr int kTM = 16 * kGC * kWC;               // 128 inner columns per tile
-constexpr int kLY = kTN + 1, kLB = kTM + 1;       // padded LDS rows (conflict-free stores)
-constexpr int kQY = kKC * kTN / kThreads;         // y values staged per thread and chunk
-constexpr int kQB = kKC * kTM / kThreads;         // g values staged per thread and chunk
+constexpr int kLY = kTN + 2, kLB = kTM + 2;       // padded LDS rows (16-byte aligned pairs)
+constexpr int kQY = kKC * kTN / (2 * kThreads);   // y pairs staged per thread and chunk
+constexpr int kQB = kKC * kTM / (2 * kThreads);   // g pairs staged per thread and chunk
 constexpr int kNP = 16 * kGC;                     // per-row partials in a block
 constexpr int kBuf = kKC * (kLY + kLB);
 constexpr int kLds = 2 * kBuf > 2 * kNP * kTN ? 2 * kBuf : 2 * kNP * kTN;
-static_assert(kQY * kThreads == kKC * kTN && kQB * kThreads == kKC * kTM, "staging split");
+static_assert(2 * kQY * kThreads == kKC * kTN && 2 * kQB * kThreads == kKC * kTM,
+              "staging split");
+typedef double dv2 __attribute__((ext_vector_type(2)));
 constexpr double kDrop = -40.0;                   // terms below max - 40 nats are dropped
 
 // Squared norms of y_n = g_n + sigma e_n (noise != NULL) or of g_m, one
@@ -70,15 +74,41 @@ nested_sqnorm_kernel(const float* __restrict__ g, const float* __restrict__ nois
     if (l == 0) out[row] = s;
 }
 
+// out[k][r] (rows rpad apart, k < kpad) = y_r[k] = g_r[k] + sigma e_r[k]
+// (noise != NULL) or g_r[k], in FP64 (the same fma as the norms), zero for
+// r >= rows or k >= nobs.  32 x 32 tiles transposed through LDS.
+__global__ void __launch_bounds__(256)
+nested_pack_kernel(const float* __restrict__ g, const float* __restrict__ noise, int rows,
+                   int nobs, double sigma, int rpad, int kpad, double* __restrict__ out) {
+    __shared__ double tile[32][33];
+    const int r0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int j = ty; j < 32; j += 8) {
+        const int r = r0 + j, k = k0 + tx;
+        double v = 0.0;
+        if (r < rows && k < nobs) {
+            v = (double)g[(size_t)r * nobs + k];
+            if (noise) v = fma(sigma, (double)noise[(size_t)r * nobs + k], v);
+        }
+        tile[j][tx] = v;
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+        const int k = k0 + j, r = r0 + tx;
+        if (k < kpad) out[(size_t)k * rpad + r] = tile[tx][j];
+    }
+}
+
 // Partial log-sum-exp of rows [n0, n0+128) over inner samples [mb, me):
-// part_max / part_sum [split][nouter].
+// part_max / part_sum [split][nouter].  Yt, Gt: the packed y and g (rows
+// npad and mpad apart).
 __global__ void __launch_bounds__(kThreads)
-nested_lse_kernel(const float* __restrict__ gout, const float* __restrict__ noise,
-                  const float* __restrict__ gin, const double* __restrict__ ynorm,
+nested_lse_kernel(const double* __restrict__ Yt, const double* __restrict__ Gt, int npad,
+                  int mpad, const double* __restrict__ ynorm,
                   const double* __restrict__ gnorm, int nouter, int ninner, int nobs,
-                  double sigma, double inv2s2, int mchunk, double* __restrict__ part_max,
+                  double inv2s2, int mchunk, double* __restrict__ part_max,
                   double* __restrict__ part_sum) {
-    __shared__ double smem[kLds];
+    __shared__ __attribute__((aligned(16))) double smem[kLds];
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wr = w / kGC, wc = w % kGC;
     // MFMA lane layout: operand lane (li, lk) holds row/column li of k-slice
@@ -101,41 +131,37 @@ nested_lse_kernel(const float* __restrict__ gout, const float* __restrict__ nois
             sm[x][v] = 0.0;
         }
 
-    // chunk c = (column tile c / nk, k chunk c % nk); loads clamp their
-    // indices into the arrays, the LDS stores zero what lies outside
-    float rg[2][kQY], re[2][kQY], rb[2][kQB];
-    auto fetch = [&](int c, float* g, float* e, float* b) {
+    // chunk c = (column tile c / nk, k chunk c % nk); thread t copies the
+    // pairs q * kThreads + t: k row (pair / 64), columns 2 (pair % 64), +1
+    dv2 ry[2][kQY], rb[2][kQB];
+    auto fetch = [&](int c, dv2* y, dv2* b) {
         if (c >= nchunks) return;
         const int m0 = mb + (c / nk) * kTM, k0 = (c % nk) * kKC;
 #pragma unroll
         for (int q = 0; q < kQY; ++q) {
             const int i = t + kThreads * q;
-            const int n = min(n0 + i / kKC, nouter - 1), k = min(k0 + i % kKC, nobs - 1);
-            g[q] = gout[(size_t)n * nobs + k];
-            e[q] = noise[(size_t)n * nobs + k];
+            y[q] = *(const dv2*)(Yt + (size_t)(k0 + i / (kTN / 2)) * npad + n0 +
+                                 2 * (i % (kTN / 2)));
         }
 #pragma unroll
         for (int q = 0; q < kQB; ++q) {
             const int i = t + kThreads * q;
-            const int m = min(m0 + i / kKC, me - 1), k = min(k0 + i % kKC, nobs - 1);
-            b[q] = gin[(size_t)m * nobs + k];
+            b[q] = *(const dv2*)(Gt + (size_t)(k0 + i / (kTM / 2)) * mpad + m0 +
+                                 2 * (i % (kTM / 2)));
         }
     };
-    auto store = [&](int c, const float* g, const float* e, const float* b) {
+    auto store = [&](int c, const dv2* y, const dv2* b) {
         double* sY = smem + (c & 1) * kBuf;
         double* sB = sY + kKC * kLY;
-        const int m0 = mb + (c / nk) * kTM, k0 = (c % nk) * kKC;
 #pragma unroll
         for (int q = 0; q < kQY; ++q) {
             const int i = t + kThreads * q;
-            const bool in = k0 + i % kKC < nobs && n0 + i / kKC < nouter;
-            sY[(i % kKC) * kLY + i / kKC] = in ? fma(sigma, (double)e[q], (double)g[q]) : 0.0;
+            *(dv2*)(sY + (i / (kTN / 2)) * kLY + 2 * (i % (kTN / 2))) = y[q];
         }
 #pragma unroll
         for (int q = 0; q < kQB; ++q) {
             const int i = t + kThreads * q;
-            const bool in = k0 + i % kKC < nobs && m0 + i / kKC < me;
-            sB[(i % kKC) * kLB + i / kKC] = in ? (double)b[q] : 0.0;
+            *(dv2*)(sB + (i / (kTM / 2)) * kLB + 2 * (i % (kTM / 2))) = b[q];
         }
     };
     dv4 acc[kWR][kWC];
@@ -199,17 +225,17 @@ nested_lse_kernel(const float* __restrict__ gout, const float* __restrict__ nois
             }
     };
 
-    fetch(0, rg[0], re[0], rb[0]);
-    fetch(1, rg[1], re[1], rb[1]);
+    fetch(0, ry[0], rb[0]);
+    fetch(1, ry[1], rb[1]);
     for (int c = 0; c < nchunks; c += 2) {
-        store(c, rg[0], re[0], rb[0]);
+        store(c, ry[0], rb[0]);
         __syncthreads();
-        fetch(c + 2, rg[0], re[0], rb[0]);
+        fetch(c + 2, ry[0], rb[0]);
         compute(c);
         if (c + 1 < nchunks) {
-            store(c + 1, rg[1], re[1], rb[1]);
+            store(c + 1, ry[1], rb[1]);
             __syncthreads();
-            fetch(c + 3, rg[1], re[1], rb[1]);
+            fetch(c + 3, ry[1], rb[1]);
             compute(c + 1);
         }
     }
@@ -274,11 +300,18 @@ __global__ void mean_kernel(const double* __restrict__ x, int n, double* __restr
 
 }  // namespace
 
-// Partials (max, sum) per split and outer sample, then the squared norms of
-// the y_n and of the g_m.
-size_t nested_workspace(int nouter, int ninner) {
-    return (2 * (size_t)nested_splits(nouter, ninner) * nouter + nouter + ninner) *
-           sizeof(double);
+// Rows and k of the packed copies: whole tiles and whole k chunks.
+static int nested_rpad(int rows, int tile) { return (rows + tile - 1) / tile * tile; }
+static int nested_kpad(int nobs) { return (nobs + kKC - 1) / kKC * kKC; }
+
+// Partials (max, sum) per split and outer sample, the squared norms of the
+// y_n and of the g_m, then the packed Yt and Gt (256-byte aligned).
+size_t nested_workspace(int nouter, int ninner, int nobs) {
+    const size_t head = (2 * (size_t)nested_splits(nouter, ninner) * nouter + nouter + ninner) *
+                        sizeof(double);
+    const size_t kp = (size_t)nested_kpad(nobs);
+    return (head + 255) / 256 * 256 +
+           kp * ((size_t)nested_rpad(nouter, kTN) + nested_rpad(ninner, kTM)) * sizeof(double);
 }
 
 // Inner-range splits, each at least two column tiles long: enough blocks to
@@ -311,12 +344,21 @@ void launch_nested(const float* gout, const float* noise, const float* gin, int 
     double* psum = work + (size_t)split * nouter;
     double* ynorm = psum + (size_t)split * nouter;
     double* gnorm = ynorm + nouter;
+    const size_t head = (2 * (size_t)split * nouter + nouter + ninner) * sizeof(double);
+    const int npad = nested_rpad(nouter, kTN), mpad = nested_rpad(ninner, kTM);
+    const int kpad = nested_kpad(nobs);
+    double* Yt = (double*)((char*)work + (head + 255) / 256 * 256);
+    double* Gt = Yt + (size_t)kpad * npad;
     nested_sqnorm_kernel<<<(nouter + 3) / 4, 256, 0, s>>>(gout, noise, nouter, nobs, sigma, ynorm);
     nested_sqnorm_kernel<<<(ninner + 3) / 4, 256, 0, s>>>(gin, nullptr, ninner, nobs, 0.0, gnorm);
+    nested_pack_kernel<<<dim3(npad / 32, (kpad + 31) / 32), 256, 0, s>>>(
+        gout, noise, nouter, nobs, sigma, npad, kpad, Yt);
+    nested_pack_kernel<<<dim3(mpad / 32, (kpad + 31) / 32), 256, 0, s>>>(
+        gin, nullptr, ninner, nobs, 0.0, mpad, kpad, Gt);
     const dim3 grid((nouter + kTN - 1) / kTN, split);
-    nested_lse_kernel<<<grid, kThreads, 0, s>>>(gout, noise, gin, ynorm, gnorm, nouter, ninner,
-                                                nobs, sigma, 1.0 / (2.0 * sigma * sigma), mchunk,
-                                                pmax, psum);
+    nested_lse_kernel<<<grid, kThreads, 0, s>>>(Yt, Gt, npad, mpad, ynorm, gnorm, nouter, ninner,
+                                                nobs, 1.0 / (2.0 * sigma * sigma), mchunk, pmax,
+                                                psum);
     nested_merge_kernel<<<(nouter + 255) / 256, 256, 0, s>>>(noise, nouter, ninner, nobs,
                                                              split, pmax, psum, logratio);
     if (eig) mean_kernel<<<1, 256, 0, s>>>(logratio, nouter, eig);
