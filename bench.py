@@ -81,9 +81,10 @@ def _measured_traffic(solves_per_launch, wave_cache_bytes, variant):
     return rec["traffic_bytes_per_launch"] if rec else None
 
 
-# fields the four-step kernel (variant 23: 64 x 56 tiles, a 4-node halo)
-# moves per update: the region's two levels in, the tile's two levels out
-BLOCKED_FLOOR_B = (72 * 64 + 64 * 56) * 16 / (64 * 56 * 4)
+# fields a four-step launch must move per update: each node's two levels
+# read once and written once per four steps (the tiles' halos, which
+# neighbouring tiles share, come mostly from L2)
+BLOCKED_FLOOR_B = 32.0 / 4
 
 
 def _kernel_sources(variant, tiled):
@@ -396,7 +397,7 @@ def _bench_c3(nsample=4096, oracle_check=True):
         st, "24 B per grid-point update (read u^m, u^{m-1}, write u^{m+1}) over the stencil "
             "launch time, against the 8 TB/s HBM peak; " +
             ("four steps per launch with the tile in LDS, one wave per grid and length "
-             "through HBM: the kernel moves about 9.1 B per update, so achieved can pass "
+             "through HBM: the kernel moves about 8 B per update, so achieved can pass "
              "the peak" if four else
              "the waves run as cache-sized chunks, so the launches read and write the "
              "256 MB last-level cache (bound 'llc') and achieved may approach or pass the "
@@ -1200,7 +1201,7 @@ def main():
                     "time_frac_of_step": st["ms"] / total_ms,
                     "solves_per_launch": solves_per_launch,
                     "note": ("launches of the 15*S-solve jacobian_fd wave, every solve in "
-                             "every launch (four steps per launch with each 64x56 tile and "
+                             "every launch (four steps per launch with each 58x58 tile and "
                              "its 4-node halo in LDS: the fields stream through HBM)"
                              if not in_cache else
                              "launches of the 15*S-solve jacobian_fd wave, run as chunks "
@@ -1226,7 +1227,7 @@ def main():
                              "write u^{m+1}) over the launch time; frac: achieved / the "
                              "8 TB/s HBM peak. " + (
                                  "The kernel takes four steps per launch with the tile in "
-                                 "LDS, so it moves about 9.1 B per update, not 24: "
+                                 "LDS, so it moves about 8 B per update, not 24: "
                                  "achieved can pass the peak. traffic: bytes per launch "
                                  "past L2 from the counter record; frac_of_copy: that "
                                  "traffic rate over a plain 2 x 4 GiB copy measured in "

@@ -1,5 +1,6 @@
 // Depth-only media, K leapfrog steps per launch with the tile kept in LDS
-// (variant 23: 64 x 56 tiles, K = 4; the temporal_blocking 4 family).
+// (variant 23: 58 x 58 tiles, K = 4; the temporal_blocking 4 family, the
+// default for rigid edges).
 //
 // A workgroup of 512 threads owns a TW x TH tile of one solve (two share a
 // CU).  It loads u^{m-1} and u^m on the tile and a K-node halo around it
@@ -13,30 +14,29 @@
 // levels to the other pair, slot = level & 1, so no workgroup overwrites a
 // value another one still loads.
 //
-// Per update a launch moves (tile + halo) x 2 levels in and the tile x 2
-// levels out: (72 x 64 + 64 x 56) x 16 B / (64 x 56 x 4) = 9.1 B, against
-// 16 for the two-step kernels; the halo costs 10 % more updates (the region
-// of step j is (64 + 2(K-j)) x (56 + 2(K-j))).  Measured on the 512^2 Monte
-// Carlo query: 3.31-3.36e11 updates/s in cache-sized chunks, the same as the
-// two-step kernel (3.34e11), and 3.26e11 as one unsplit wave, where the
-// two-step kernel streams HBM at 2.85e11.  Its vector issue runs at 0.59
-// (68.7 lane-instructions per update); smaller tiles with four workgroups
-// per CU (64 x 24, 32 x 40) and a persistent form that prefetches the next
-// tile into registers (two 8-wave or one 16-wave workgroup per CU, 64 x 56
-// or 64 x 120) were slower (2.5-3.3e11), so the tile's loads are not what
-// holds it back.  Opt-in (temporal_blocking 4), not the default.
+// Per update a workgroup loads (tile + halo) x 2 levels and stores the tile
+// x 2 levels: (66 x 66 + 58 x 58) x 16 B / (58 x 58 x 4) = 9.2 B; the halos
+// neighbouring tiles share come from L2, so past L2 a launch moves each
+// node's two levels once in and once out, 8 B per update (16 for the
+// two-step kernels).  The halo costs 11 % more updates (the region of step j
+// is (58 + 2(K-j))^2).  All loads of a thread are issued before its first
+// LDS store (blk_load), so a workgroup waits for memory once; loading row by
+// row, a wave waited for each row's loads in turn, and the kernel ran no
+// faster than the two-step one (3.3e11 updates/s on the 512^2 Monte Carlo
+// query, against 4.4-4.5e11 now).
 //
 // Work split: threads are packed over (band, column) pairs of the first
-// step's region as in the resident kernel (thread t: column t mod W of band
-// t div W, W the region's free columns), fixed for a tile; at step j a
-// thread clips its column and band to that step's region.  A thread streams
-// down its rows keeping rows k-1, k, k+1 in registers.  Coefficient rows,
-// forcing weights and the forcing series values sit in LDS.  Receivers are
-// recorded by the tile that owns their column; forcing is added at every
-// computed node of the window, halo included, so every tile that computes a
-// node computes it alike.  The per-node arithmetic is layered_update, so the
-// fields are bitwise those of every variant.  Rigid edges only, no receiver
-// injection (dual solves run one step per launch).
+// step's region, fixed for a tile; at step j a thread clips its column and
+// band to that step's region.  With 58-column tiles the first region is 64
+// columns wide, so each wave is one band (blk_lane) and its lanes share their
+// rows.  A thread streams down its rows keeping rows k-1, k, k+1 in
+// registers.  Coefficient rows, forcing weights and the forcing series
+// values sit in LDS.  Receivers are recorded by the tile that owns their
+// column; forcing is added at every computed node of the window, halo
+// included, so every tile that computes a node computes it alike.  The
+// per-node arithmetic is layered_update, so the fields are bitwise those of
+// every variant.  Rigid edges only, no receiver injection (dual solves run
+// one step per launch).
 #include "internal.h"
 #include "node_update.h"
 #include "tile.h"
@@ -81,7 +81,10 @@ __device__ __forceinline__ const float2* blk_buf(const SolveDesc* d, int i) {
     return i == 0 ? d->buf0 : (i == 1 ? d->buf1 : (i == 2 ? d->buf2 : d->buf3));
 }
 
-// The thread's (band, column) of a tile's first-step region.
+// The thread's (band, column) of a tile's first-step region.  A region at
+// most 64 columns wide (tiles of 64 - 2 (K - 1) columns) gives each wave one
+// band: lane l takes column c0 + l, so a wave's lanes share their rows and
+// every lane of an interior tile's wave is busy in the first step.
 struct BlkLane {
     int col, kb, ke;
     bool active;
@@ -93,11 +96,13 @@ __device__ __forceinline__ BlkLane blk_lane(const BlkTile& tl) {
     const int c0 = max(tl.x0 - (K - 1), 1), c1 = min(tl.x1 + (K - 1), nx - 1);
     const int r0 = max(tl.z0 - (K - 1), 0), r1 = min(tl.z1 + (K - 1), nz - 1);
     const int W = c1 - c0, nrow = r1 - r0;
-    const int nb = max(1, NT / W);
-    const int band = (int)threadIdx.x / W;
+    const int Wl = W <= 64 ? 64 : W;  // lanes per band
+    const int nb = max(1, NT / Wl);
+    const int band = (int)threadIdx.x / Wl;
+    const int lane = (int)threadIdx.x - band * Wl;
     BlkLane ln;
-    ln.active = band < nb;
-    ln.col = c0 + ((int)threadIdx.x - band * W);
+    ln.active = band < nb && lane < W;
+    ln.col = c0 + lane;
     ln.kb = r0 + band * nrow / nb;
     ln.ke = r0 + (band + 1) * nrow / nb;
     return ln;
@@ -398,19 +403,19 @@ __device__ __forceinline__ void nodal_lds_stream(const BlkTile& tl, const BlkLan
     }
 }
 
-// Nodal media, K steps per launch (variants 24, 25: 64 x 24 tiles, two
-// 512-thread workgroups per CU).  Same passes, buffer pairs, regions and
-// receiver ownership as the depth-only kernel above; LDS also holds lambda,
-// mu and dt^2/(rho h^2) over the region (28 B per region node with both
-// field levels: 63 KB at 72 x 32).  Variant 24 (STREAM) packs threads over
-// (band, column) pairs as the depth-only kernel does and streams down its
-// rows with u, v, lambda and mu of rows k-1, k, k+1 and columns i-1, i, i+1
-// in registers; variant 25 gives thread t the nodes t, t + NT, ... of a
-// step's region in row-major order and reads every operand from LDS.  Both
-// form each node through nodal_node_gen, the per-node update every nodal
-// kernel uses, with the surface row's branch chosen at compile time; its
-// fused products are explicit, so the fields are bitwise those of every
-// nodal variant.  Rigid edges only, no receiver injection.
+// Nodal media, K steps per launch (variant 24: 58 x 26 tiles; the
+// forced-only variant 25: 64 x 24; two 512-thread workgroups per CU).  Same
+// passes, buffer pairs, regions and receiver ownership as the depth-only
+// kernel above; LDS also holds lambda, mu and dt^2/(rho h^2) over the region
+// (28 B per region node with both field levels: 63 KB at 66 x 34).  Variant
+// 24 (STREAM) gives each wave one band of the 64-column first region and
+// streams down its rows with u, v, lambda and mu of rows k-1, k, k+1 and
+// columns i-1, i, i+1 in registers; variant 25 gives thread t the nodes t,
+// t + NT, ... of a step's region in row-major order and reads every operand
+// from LDS.  Both form each node through nodal_node_gen, the per-node update
+// every nodal kernel uses, with the surface row's branch chosen at compile
+// time; its fused products are explicit, so the fields are bitwise those of
+// every nodal variant.  Rigid edges only, no receiver injection.
 template <int TW, int TH, int K, int NT, int WPC, bool STREAM>
 __global__ void __launch_bounds__(NT, NT / 256 * WPC)
 stencil_nodal_lds(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
@@ -521,7 +526,7 @@ void launch_blocked_stencil(const SolveDesc* descs, const int2* tiles, int ntile
                             int variant, hipStream_t s) {
     switch (variant) {
         case 24:
-            stencil_nodal_lds<64, 24, 4, 512, 2, true><<<ntiles, 512, 0, s>>>(descs, tiles,
+            stencil_nodal_lds<58, 26, 4, 512, 2, true><<<ntiles, 512, 0, s>>>(descs, tiles,
                                                                               ntiles, pass);
             break;
         case 25:
@@ -529,7 +534,7 @@ void launch_blocked_stencil(const SolveDesc* descs, const int2* tiles, int ntile
                                                                                ntiles, pass);
             break;
         default:
-            stencil_layered_lds<64, 56, 4, 512, 2><<<ntiles, 512, 0, s>>>(descs, tiles, ntiles,
+            stencil_layered_lds<58, 58, 4, 512, 2><<<ntiles, 512, 0, s>>>(descs, tiles, ntiles,
                                                                           pass);
             break;
     }
