@@ -167,12 +167,15 @@ __device__ __forceinline__ void blk_steps(const BlkTile& tl, const BlkLane& ln, 
                                           float2 (*fld)[RW * (TH + 2 * K)],
                                           const float* cf_lds, const float* sw_lds,
                                           const float* sv_lds) {
+    static_assert(TW + 2 * (K - 1) <= 64, "one band per wave");
     const SolveDesc* d = tl.d;
     const int nx = d->nx, nz = d->nz;
     const int m = tl.m, x0 = tl.x0, x1 = tl.x1, z0 = tl.z0, z1 = tl.z1;
     const int rz0 = tl.rz0;
     const bool active = ln.active;
-    const int col = ln.col, kb = ln.kb, ke = ln.ke;
+    // a wave is one band: its rows are wave-uniform
+    const int col = ln.col, kb = __builtin_amdgcn_readfirstlane(ln.kb),
+              ke = __builtin_amdgcn_readfirstlane(ln.ke);
     const int si0 = d->src_i0, sk0 = d->src_k0;
     const int di = col - si0;
     const bool src_lane = di >= 0 && di < kSrcW;
@@ -320,7 +323,10 @@ __device__ __forceinline__ void nodal_lds_stream(const BlkTile& tl, const BlkLan
     const int cj0 = max(tl.x0 - gq, 1), cj1 = min(tl.x1 + gq, nx - 1);
     const int rj0 = max(tl.z0 - gq, 0), rj1 = min(tl.z1 + gq, nz - 1);
     const int col = ln.col;
-    const int ka = max(ln.kb, rj0), kz = min(ln.ke, rj1);
+    // a wave is one band (the caller's tiles keep the first region within
+    // 64 columns): its rows are wave-uniform
+    const int ka = max(__builtin_amdgcn_readfirstlane(ln.kb), rj0);
+    const int kz = min(__builtin_amdgcn_readfirstlane(ln.ke), rj1);
     if (!(ln.active && col >= cj0 && col < cj1 && ka < kz)) return;
     const int lc = col - tl.rx0, rz0 = tl.rz0;
     const int sk0 = d->src_k0, di = col - d->src_i0;
@@ -421,6 +427,7 @@ __global__ void __launch_bounds__(NT, NT / 256 * WPC)
 stencil_nodal_lds(const SolveDesc* __restrict__ descs, const int2* __restrict__ tiles,
                   int ntiles, int pass) {
     constexpr int RW = TW + 2 * K, RH = TH + 2 * K;  // largest region
+    static_assert(!STREAM || TW + 2 * (K - 1) <= 64, "one band per wave");
     __shared__ float2 fld[2][RH * RW];
     __shared__ float cl[3][RH * RW];  // lambda, mu, s
     __shared__ float sw_lds[2 * kSrcW * kSrcW];
