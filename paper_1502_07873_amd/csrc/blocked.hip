@@ -409,11 +409,13 @@ __device__ __forceinline__ void nodal_lds_stream(const BlkTile& tl, const BlkLan
     }
 }
 
-// Nodal media, K steps per launch (variant 24: 58 x 26 tiles; the
+// Nodal media, K steps per launch (variant 24: 58 x 34 tiles; the
 // forced-only variant 25: 64 x 24; two 512-thread workgroups per CU).  Same
 // passes, buffer pairs, regions and receiver ownership as the depth-only
 // kernel above; LDS also holds lambda, mu and dt^2/(rho h^2) over the region
-// (28 B per region node with both field levels: 63 KB at 66 x 34).  Variant
+// (28 B per region node with both field levels: 78 KB at 66 x 42, the
+// tallest region two workgroups per CU can hold: each wave's band gets 5
+// rows of the first step, 4 with 26-row tiles, which ran 8 % slower).  Variant
 // 24 (STREAM) gives each wave one band of the 64-column first region and
 // streams down its rows with u, v, lambda and mu of rows k-1, k, k+1 and
 // columns i-1, i, i+1 in registers; variant 25 gives thread t the nodes t,
@@ -533,7 +535,7 @@ void launch_blocked_stencil(const SolveDesc* descs, const int2* tiles, int ntile
                             int variant, hipStream_t s) {
     switch (variant) {
         case 24:
-            stencil_nodal_lds<58, 26, 4, 512, 2, true><<<ntiles, 512, 0, s>>>(descs, tiles,
+            stencil_nodal_lds<58, 34, 4, 512, 2, true><<<ntiles, 512, 0, s>>>(descs, tiles,
                                                                               ntiles, pass);
             break;
         case 25:
