@@ -343,9 +343,14 @@ int jacobian_sensitivity(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
  * ratio; log-sum-exp with its maximum and rescaling in FP64 and the terms
  * within 40 nats of the maximum as FP32 exponentials (at most ~3e-6 nats),
  * terms further down dropped.  Context workspace: 16 bytes per outer sample
- * per inner-range split (splits only when nouter is small) plus 8 bytes per
- * outer and per inner sample.  Errors: EIG_EINVAL for non-positive sizes or
- * sigma, NULL arrays.
+ * per inner-range split (the inner range is split so that the launch fills
+ * whole rounds of the device), 8 bytes per outer and per inner sample, and
+ * FP64 copies of the y_n and g_m, k-major and padded to whole tiles:
+ * 8 kpad (npad + mpad) bytes, kpad = nobs rounded up to a multiple of 16,
+ * npad and mpad = nouter and ninner rounded up to multiples of 128 (1.4 GB
+ * at nouter = ninner = 4e5, nobs = 204).  Errors: EIG_EINVAL for
+ * non-positive sizes or sigma, NULL arrays; EIG_EBUDGET when the workspace
+ * would exceed the context's budget.
  */
 int nested_mc_eig(eig_ctx* ctx, int32_t nouter, int32_t ninner, int32_t nobs,
                   const float* g_outer, const float* noise, const float* g_inner,
