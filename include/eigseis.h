@@ -347,7 +347,7 @@ int jacobian_sensitivity(eig_ctx* ctx, int32_t nsample, const eig_grid* grid,
  * whole rounds of the device), 8 bytes per outer and per inner sample, and
  * FP64 copies of the y_n and g_m, k-major and padded to whole tiles:
  * 8 kpad (npad + mpad) bytes, kpad = nobs rounded up to a multiple of 16,
- * npad and mpad = nouter and ninner rounded up to multiples of 128 (1.4 GB
+ * npad and mpad = nouter and ninner rounded up to multiples of 128 (1.3 GB
  * at nouter = ninner = 4e5, nobs = 204).  Errors: EIG_EINVAL for
  * non-positive sizes or sigma, NULL arrays; EIG_EBUDGET when the workspace
  * would exceed the context's budget.
