@@ -73,3 +73,19 @@ def test_committed_counter_records_match_the_kernel_sources(record, tiled):
     traffic = rec.get("traffic_bytes_per_launch", rec.get("traffic_bytes_per_update"))
     assert traffic > 0
     assert traffic >= rec.get("kernel_floor_bytes_per_launch", 0)
+
+
+def test_variant_steps_and_kernel_sources():
+    # the bench labels a launch by its variant: steps per launch for the
+    # solves-per-launch and floor arithmetic, and the kernel's own source
+    # files for the counter-record hash
+    bench = _bench_module()
+    assert [bench._steps_per_launch(v) for v in (0, 6, 8, 9, 14, 15, 16, 18, 19, 20)] == \
+        [1, 1, 1, 2, 2, 3, 3, 1, 2, 2]
+    assert [bench._steps_per_launch(v) for v in (23, 24, 25)] == [4, 4, 4]
+    for v in (23, 24, 25):
+        assert bench._kernel_sources(v, bench.LAYERED_SOURCES) == bench.BLOCKED_SOURCES
+        assert bench._kernel_sources(v, bench.NODAL_SOURCES) == bench.BLOCKED_SOURCES
+    assert bench._kernel_sources(9, bench.LAYERED_SOURCES) == bench.LAYERED_SOURCES
+    assert bench._kernel_sources(20, bench.NODAL_SOURCES) == bench.NODAL_SOURCES
+    assert bench.BLOCKED_FLOOR_B == 8.0
